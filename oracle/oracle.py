@@ -1,0 +1,289 @@
+"""ctypes binding of the CPU oracle (``qmc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg.  The GPU library never imports it.
+
+Family and transform names map to the oracle's own integer codes below; the
+GPU library numbers its own codes independently.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "qmc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+FAMILIES = {
+    "const": 0, "trig": 1, "p2kernel": 2, "genz_product_peak": 3, "genz_oscillatory": 4,
+    "genz_gaussian": 5, "genz_continuous": 6, "genz_corner_peak": 7, "sector": 8,
+}
+TRANSFORMS = {"none": 0, "korobov": 1, "baker": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain gcc (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", SRC, "-o", LIB + ".tmp", "-lm", "-lpthread"]
+        subprocess.check_call(cmd)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("family", C.c_int32),
+        ("c", C.c_double),
+        ("n_terms", C.c_uint32),
+        ("c0", C.c_double),
+        ("h", C.c_void_p),
+        ("ch", C.c_void_p),
+        ("phi", C.c_void_p),
+        ("a", C.c_void_p),
+        ("u", C.c_void_p),
+        ("n_u", C.c_uint32),
+        ("n_f", C.c_uint32),
+        ("coef_u", C.c_void_p),
+        ("exp_u", C.c_void_p),
+        ("coef_f", C.c_void_p),
+        ("exp_f", C.c_void_p),
+        ("nu", C.c_void_p),
+        ("pow_u", C.c_double),
+        ("pow_f", C.c_double),
+        ("delta_im", C.c_double),
+        ("is_complex", C.c_int32),
+        ("cv_w", C.c_void_p),
+        ("cv_c", C.c_void_p),
+        ("cv_r", C.c_uint32),
+        ("cv_k", C.c_uint32),
+        ("point_mode", C.c_int32),
+    ]
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        L = C.CDLL(LIB)
+        vp, u64, u32, i32, dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32, C.c_double
+        L.or_lattice_index.restype = u64
+        L.or_lattice_index.argtypes = [u64, u64, u64]
+        L.or_lattice_indices.argtypes = [u32, u64, vp, vp, u64, vp]
+        L.or_point.argtypes = [u32, u64, vp, u64, vp, i32, vp]
+        L.or_transform.argtypes = [i32, i32, dbl, vp, vp]
+        L.or_poly.restype = dbl
+        L.or_poly.argtypes = [u32, u32, vp, vp, vp]
+        L.or_legendre.argtypes = [u32, dbl, vp]
+        L.or_cv_g.restype = dbl
+        L.or_cv_g.argtypes = [u32, u32, u32, vp, vp, vp]
+        L.or_cv_integral.restype = dbl
+        L.or_cv_integral.argtypes = [u32, u32, u32, vp, vp]
+        L.or_integrand.argtypes = [vp, u32, vp, vp, vp]
+        L.or_fhat.argtypes = [vp, u32, i32, i32, vp, vp, vp]
+        L.or_estimate.restype = C.c_int
+        L.or_estimate.argtypes = [u32, u64, vp, u32, vp, i32, i32, vp, i32, vp, vp, vp]
+        L.or_mean_error.argtypes = [u32, vp, vp]
+        L.or_korobov_vector.argtypes = [u64, u32, u64, vp]
+        L.or_p2.restype = dbl
+        L.or_p2.argtypes = [u32, u64, vp, i32]
+        L.or_korobov_search.restype = C.c_int
+        L.or_korobov_search.argtypes = [u64, u32, vp, u32, i32, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Params:
+    """Integrand description; keeps the numpy arrays alive for the call."""
+
+    def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
+                 sector=None, cv=None, point_mode: int = 0):
+        self.keep = []
+        p = _Params()
+        p.family = FAMILIES[family]
+        p.c = float(c)
+        p.point_mode = int(point_mode)
+
+        def arr(x, dt):
+            v = np.ascontiguousarray(np.asarray(x, dtype=dt))
+            self.keep.append(v)
+            return v
+
+        if a is not None:
+            p.a = _ptr(arr(a, np.float64))
+        if u is not None:
+            p.u = _ptr(arr(u, np.float64))
+        if trig is not None:
+            c0, h, ch, phi = trig
+            h = arr(h, np.int64).reshape(-1, d)
+            p.n_terms = h.shape[0]
+            p.c0 = float(c0)
+            p.h = _ptr(h)
+            p.ch = _ptr(arr(ch, np.float64))
+            p.phi = _ptr(arr(phi, np.float64))
+        if sector is not None:
+            s = sector
+            p.n_u, p.n_f = s.n_u, s.n_f
+            p.coef_u = _ptr(arr(s.coef_u, np.float64))
+            p.exp_u = _ptr(arr(s.exp_u, np.uint8))
+            p.coef_f = _ptr(arr(s.coef_f, np.float64))
+            p.exp_f = _ptr(arr(s.exp_f, np.uint8))
+            p.nu = _ptr(arr(s.nu, np.uint8))
+            p.pow_u, p.pow_f = float(s.pow_u), float(s.pow_f)
+            p.delta_im = float(s.delta_im)
+            p.is_complex = int(bool(s.is_complex))
+        if cv is not None:
+            W, cc = cv
+            W = arr(W, np.float64)
+            p.cv_w = _ptr(W)
+            p.cv_c = _ptr(arr(cc, np.float64))
+            p.cv_r, p.cv_k = W.shape[0], W.shape[2]
+        self.struct = p
+
+    @property
+    def ref(self):
+        return C.byref(self.struct)
+
+
+def lattice_index(j: int, gi: int, n: int) -> int:
+    return int(lib().or_lattice_index(j, gi, n))
+
+
+def lattice_indices(n: int, g, js) -> np.ndarray:
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.uint64))
+    js = np.ascontiguousarray(np.asarray(js, dtype=np.uint64))
+    out = np.zeros((js.size, g.size), dtype=np.uint64)
+    lib().or_lattice_indices(g.size, n, _ptr(g), _ptr(js), js.size, _ptr(out))
+    return out
+
+
+def point(n: int, g, j: int, shift, mode: int = 0) -> np.ndarray:
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.uint64))
+    sh = np.ascontiguousarray(np.asarray(shift, dtype=np.float64))
+    x = np.zeros(g.size)
+    lib().or_point(g.size, n, _ptr(g), j, _ptr(sh), mode, _ptr(x))
+    return x
+
+
+def transform(kind: str, alpha: int, x: float):
+    z, w = C.c_double(), C.c_double()
+    lib().or_transform(TRANSFORMS[kind], alpha, float(x), C.byref(z), C.byref(w))
+    return z.value, w.value
+
+
+def poly(coef, exps, z) -> float:
+    coef = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
+    exps = np.ascontiguousarray(np.asarray(exps, dtype=np.uint8))
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    return float(lib().or_poly(z.size, coef.size, _ptr(coef), _ptr(exps), _ptr(z)))
+
+
+def legendre(K: int, x: float) -> np.ndarray:
+    out = np.zeros(K)
+    lib().or_legendre(K, float(x), _ptr(out))
+    return out
+
+
+def cv_g(W, c, z) -> float:
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.float64))
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    R, d, K = W.shape
+    return float(lib().or_cv_g(d, R, K, _ptr(W), _ptr(c), _ptr(z)))
+
+
+def cv_integral(W, c) -> float:
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.float64))
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+    R, d, K = W.shape
+    return float(lib().or_cv_integral(d, R, K, _ptr(W), _ptr(c)))
+
+
+def integrand(params: Params, z) -> complex:
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    re, im = C.c_double(), C.c_double()
+    lib().or_integrand(params.ref, z.size, _ptr(z), C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+def fhat(params: Params, x, tkind: str = "none", alpha: int = 0) -> complex:
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    re, im = C.c_double(), C.c_double()
+    lib().or_fhat(params.ref, x.size, TRANSFORMS[tkind], alpha, _ptr(x), C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+class Estimate:
+    def __init__(self, q_re, q_im, q_abs, status):
+        self.q_re, self.q_im, self.q_abs, self.status = q_re, q_im, q_abs, status
+
+    @property
+    def q(self) -> np.ndarray:
+        return self.q_re + 1j * self.q_im
+
+    def mean_error(self):
+        mr, er = mean_error(self.q_re)
+        mi, ei = mean_error(self.q_im)
+        return complex(mr, mi), er, ei
+
+
+def estimate(n: int, g, shifts, params: Params, tkind: str = "none", alpha: int = 0,
+             threads: int = 0) -> Estimate:
+    """Per-shift Q_k of eq. (2) for every shift row."""
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.uint64))
+    sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
+    m, d = sh.shape
+    assert d == g.size
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    q_re, q_im, q_abs = np.zeros(m), np.zeros(m), np.zeros(m)
+    st = lib().or_estimate(d, n, _ptr(g), m, _ptr(sh), TRANSFORMS[tkind], alpha, params.ref,
+                           threads, _ptr(q_re), _ptr(q_im), _ptr(q_abs))
+    return Estimate(q_re, q_im, q_abs, st)
+
+
+def mean_error(q) -> tuple:
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+    out = np.zeros(2)
+    lib().or_mean_error(q.size, _ptr(q), _ptr(out))
+    return float(out[0]), float(out[1])
+
+
+def korobov_vector(n: int, d: int, a: int) -> np.ndarray:
+    g = np.zeros(d, dtype=np.uint64)
+    lib().or_korobov_vector(n, d, a, _ptr(g))
+    return g
+
+
+def p2(n: int, g, threads: int = 0) -> float:
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.uint64))
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    return float(lib().or_p2(g.size, n, _ptr(g), threads))
+
+
+def korobov_search(n: int, d: int, cand, threads: int = 0):
+    cand = np.ascontiguousarray(np.asarray(cand, dtype=np.uint64))
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    a = C.c_uint64()
+    pb = C.c_double()
+    allp = np.zeros(cand.size)
+    st = lib().or_korobov_search(n, d, _ptr(cand), cand.size, threads, C.byref(a), C.byref(pb),
+                                 _ptr(allp))
+    if st != 0:
+        raise ValueError("bad korobov search arguments")
+    return int(a.value), float(pb.value), allp

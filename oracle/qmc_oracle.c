@@ -1,0 +1,604 @@
+/*
+ * CPU ORACLE for the randomly shifted rank-1 lattice estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark load this file's library.  It shares no
+ * source, header, table or helper with the GPU library: it is the estimator
+ * written out from its definition, slowly and plainly, so that the GPU
+ * results can be compared against it.
+ *
+ * What it computes (arXiv:1811.11722, Sec. 2):
+ *   eq. (2):  Q_k = (1/n) sum_{j=1..n} fhat( {(j-1) g / n + Delta_k} ),
+ *             Qbar = (1/m) sum_k Q_k
+ *   eq. (3):  sigma^2 = sum_k (Q_k - Qbar)^2 / (m (m - 1))
+ *   eq. (4):  Korobov transform z(x) = int_0^x w, w(u) = u^a (1-u)^a / B
+ *   eq. (5):  baker's transform z(x) = 1 - |2x - 1|
+ *   fhat(x) = f(z(x)) * prod_i z_i'(x_i)   (substitution x -> z(x), Sec. 2)
+ *
+ * Readings taken where the paper is silent (each also listed in the design
+ * notes):
+ *   - the shift index runs over k = 1..m (the text's upper limit n is a typo);
+ *   - points are numbered j' = j - 1 = 0..n-1, the index (j' g_i) mod n is an
+ *     exact integer, the coordinate is idx/n + Delta rounded to double, and
+ *     {.} subtracts 1 when that sum is >= 1;
+ *   - the baker's transform is 2-to-1 with |z'| = 2, so its integrand weight is
+ *     1 (the constant is integrated exactly, Sec. 2, Fig. 3 discussion);
+ *   - complex integrands carry separate variances for the real and imaginary
+ *     parts;
+ *   - sums over points are accumulated in long double with Neumaier's
+ *     compensation; the integrand itself is evaluated in double with libm.
+ *
+ * Threads split each shift's points into NCHUNK fixed chunks; chunk partials
+ * are merged in chunk order, so results do not depend on the thread count.
+ */
+#include <complex.h>
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_NCHUNK 256
+
+/* family codes used by this oracle */
+enum {
+    OR_F_CONST = 0,
+    OR_F_TRIG = 1,
+    OR_F_P2KERNEL = 2,
+    OR_F_GENZ_PRODUCT_PEAK = 3,
+    OR_F_GENZ_OSCILLATORY = 4,
+    OR_F_GENZ_GAUSSIAN = 5,
+    OR_F_GENZ_CONTINUOUS = 6,
+    OR_F_GENZ_CORNER_PEAK = 7,
+    OR_F_SECTOR = 8
+};
+
+/* transform codes used by this oracle */
+enum { OR_T_NONE = 0, OR_T_KOROBOV = 1, OR_T_BAKER = 2 };
+
+typedef struct {
+    int32_t family;
+    /* CONST */
+    double c;
+    /* TRIG: f = c0 + sum_t ch[t] cos(2 pi h_t . z + phi_t), h row-major (n_terms, d) */
+    uint32_t n_terms;
+    double c0;
+    const int64_t *h;
+    const double *ch;
+    const double *phi;
+    /* GENZ */
+    const double *a;
+    const double *u;
+    /* SECTOR: prod z^nu * U^pow_u * (F - i delta)^pow_f */
+    uint32_t n_u, n_f;
+    const double *coef_u;
+    const uint8_t *exp_u; /* (n_u, d) */
+    const double *coef_f;
+    const uint8_t *exp_f; /* (n_f, d) */
+    const uint8_t *nu;    /* d */
+    double pow_u, pow_f, delta_im;
+    int32_t is_complex;
+    /* control variate: when cv_w != NULL the integrand becomes f - g with
+       g(z) = sum_r c_r prod_i sum_k W[r,i,k] P~_k(z_i), W row-major (R, d, K) */
+    const double *cv_w;
+    const double *cv_c;
+    uint32_t cv_r, cv_k;
+    /* coordinate rounding: 0 -> idx / n (IEEE division), 1 -> idx * (1/n) */
+    int32_t point_mode;
+} or_params;
+
+/* ------------------------------------------------------------------ */
+/* Lattice index and point, eq. (2)                                     */
+/* ------------------------------------------------------------------ */
+uint64_t or_lattice_index(uint64_t j, uint64_t gi, uint64_t n)
+{
+    unsigned __int128 p = (unsigned __int128)j * (unsigned __int128)gi;
+    return (uint64_t)(p % n);
+}
+
+void or_lattice_indices(uint32_t d, uint64_t n, const uint64_t *g, const uint64_t *js,
+                        uint64_t count, uint64_t *out)
+{
+    for (uint64_t t = 0; t < count; ++t)
+        for (uint32_t i = 0; i < d; ++i)
+            out[t * d + i] = or_lattice_index(js[t], g[i], n);
+}
+
+static double or_coord(uint64_t idx, uint64_t n, double shift, int mode)
+{
+    double y = (mode == 1) ? (double)idx * (1.0 / (double)n) : (double)idx / (double)n;
+    double x = y + shift;
+    if (x >= 1.0)
+        x -= 1.0;
+    return x;
+}
+
+void or_point(uint32_t d, uint64_t n, const uint64_t *g, uint64_t j, const double *shift,
+              int32_t mode, double *x)
+{
+    for (uint32_t i = 0; i < d; ++i)
+        x[i] = or_coord(or_lattice_index(j, g[i], n), n, shift[i], mode);
+}
+
+/* ------------------------------------------------------------------ */
+/* Periodising transforms, eqs. (4) and (5)                             */
+/* ------------------------------------------------------------------ */
+static long double or_binom(int n, int k)
+{
+    long double r = 1.0L;
+    for (int t = 1; t <= k; ++t)
+        r = r * (long double)(n - k + t) / (long double)t;
+    return r;
+}
+
+/* z(x) for the Korobov weight alpha: the integral of u^a (1-u)^a from 0 to x,
+   divided by its value at x = 1.  Repeated integration by parts turns it into
+   the binomial tail sum_{k=a+1}^{2a+1} C(2a+1,k) x^k (1-x)^(2a+1-k), which is
+   what is evaluated here.  w(x) = x^a (1-x)^a / B(a+1, a+1). */
+void or_transform(int32_t kind, int32_t alpha, double x, double *z, double *w)
+{
+    if (kind == OR_T_KOROBOV) {
+        int a = alpha, nn = 2 * alpha + 1;
+        long double xl = x, yl = 1.0L - (long double)x, s = 0.0L;
+        for (int k = a + 1; k <= nn; ++k)
+            s += or_binom(nn, k) * powl(xl, k) * powl(yl, nn - k);
+        /* B(a+1, a+1) = a! a! / (2a+1)! */
+        long double beta = 1.0L;
+        for (int t = 1; t <= a; ++t)
+            beta *= (long double)t;
+        beta = beta * beta;
+        for (int t = 1; t <= nn; ++t)
+            beta /= (long double)t;
+        *z = (double)s;
+        *w = (double)(powl(xl, a) * powl(yl, a) / beta);
+    } else if (kind == OR_T_BAKER) {
+        *z = 1.0 - fabs(2.0 * x - 1.0);
+        *w = 1.0;
+    } else {
+        *z = x;
+        *w = 1.0;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Integrands                                                           */
+/* ------------------------------------------------------------------ */
+static double or_ipow(double v, int e)
+{
+    double r = 1.0;
+    for (int t = 0; t < e; ++t)
+        r *= v;
+    return r;
+}
+
+/* sparse polynomial sum_t coef[t] prod_i z_i^exp[t,i] */
+double or_poly(uint32_t d, uint32_t nt, const double *coef, const uint8_t *ex, const double *z)
+{
+    double s = 0.0;
+    for (uint32_t t = 0; t < nt; ++t) {
+        double mono = coef[t];
+        for (uint32_t i = 0; i < d; ++i)
+            mono *= or_ipow(z[i], ex[t * d + i]);
+        s += mono;
+    }
+    return s;
+}
+
+/* orthonormal shifted Legendre P~_k(x) = sqrt(2k+1) P_k(2x-1), k = 0..K-1,
+   from Bonnet's recurrence (k+1) P_{k+1} = (2k+1) t P_k - k P_{k-1} */
+void or_legendre(uint32_t K, double x, double *out)
+{
+    double t = 2.0 * x - 1.0, pm = 1.0, p = t;
+    for (uint32_t k = 0; k < K; ++k) {
+        double pk;
+        if (k == 0)
+            pk = 1.0;
+        else if (k == 1)
+            pk = t;
+        else {
+            double pn = ((2.0 * (k - 1) + 1.0) * t * p - (double)(k - 1) * pm) / (double)k;
+            pm = p;
+            p = pn;
+            pk = pn;
+        }
+        out[k] = sqrt(2.0 * k + 1.0) * pk;
+    }
+}
+
+/* control-variate model g(z) = sum_r c_r prod_i sum_k W[r,i,k] P~_k(z_i) */
+double or_cv_g(uint32_t d, uint32_t R, uint32_t K, const double *W, const double *c, const double *z)
+{
+    double leg[64 * 32];
+    for (uint32_t i = 0; i < d; ++i)
+        or_legendre(K, z[i], leg + i * K);
+    double g = 0.0;
+    for (uint32_t r = 0; r < R; ++r) {
+        double prod = c[r];
+        for (uint32_t i = 0; i < d; ++i) {
+            double h = 0.0;
+            for (uint32_t k = 0; k < K; ++k)
+                h += W[((size_t)r * d + i) * K + k] * leg[i * K + k];
+            prod *= h;
+        }
+        g += prod;
+    }
+    return g;
+}
+
+/* integral of g over [0,1]^d: only P~_0 = 1 has a nonzero integral */
+double or_cv_integral(uint32_t d, uint32_t R, uint32_t K, const double *W, const double *c)
+{
+    double s = 0.0;
+    for (uint32_t r = 0; r < R; ++r) {
+        double prod = c[r];
+        for (uint32_t i = 0; i < d; ++i)
+            prod *= W[((size_t)r * d + i) * K + 0];
+        s += prod;
+    }
+    return s;
+}
+
+/* f(z) for the family in p; returns the value in (re, im) */
+void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, double *im)
+{
+    const double PI = 3.14159265358979323846;
+    double vr = 0.0, vi = 0.0;
+    switch (p->family) {
+    case OR_F_CONST:
+        vr = p->c;
+        break;
+    case OR_F_TRIG: {
+        long double s = p->c0;
+        for (uint32_t t = 0; t < p->n_terms; ++t) {
+            long double arg = 0.0L;
+            for (uint32_t i = 0; i < d; ++i)
+                arg += (long double)p->h[(size_t)t * d + i] * (long double)z[i];
+            arg -= floorl(arg);
+            s += (long double)p->ch[t] * cosl(2.0L * 3.14159265358979323846264338327950288L * arg +
+                                              (long double)p->phi[t]);
+        }
+        vr = (double)s;
+        break;
+    }
+    case OR_F_P2KERNEL: {
+        double prod = 1.0;
+        for (uint32_t i = 0; i < d; ++i) {
+            double b2 = z[i] * z[i] - z[i] + 1.0 / 6.0;
+            prod *= 1.0 + 2.0 * PI * PI * b2;
+        }
+        vr = prod;
+        break;
+    }
+    case OR_F_GENZ_PRODUCT_PEAK: {
+        double prod = 1.0;
+        for (uint32_t i = 0; i < d; ++i) {
+            double t = z[i] - p->u[i];
+            prod *= 1.0 / (1.0 / (p->a[i] * p->a[i]) + t * t);
+        }
+        vr = prod;
+        break;
+    }
+    case OR_F_GENZ_OSCILLATORY: {
+        double s = 2.0 * PI * p->u[0];
+        for (uint32_t i = 0; i < d; ++i)
+            s += p->a[i] * z[i];
+        vr = cos(s);
+        break;
+    }
+    case OR_F_GENZ_GAUSSIAN: {
+        double s = 0.0;
+        for (uint32_t i = 0; i < d; ++i) {
+            double t = z[i] - p->u[i];
+            s += p->a[i] * p->a[i] * t * t;
+        }
+        vr = exp(-s);
+        break;
+    }
+    case OR_F_GENZ_CONTINUOUS: {
+        double s = 0.0;
+        for (uint32_t i = 0; i < d; ++i)
+            s += p->a[i] * fabs(z[i] - p->u[i]);
+        vr = exp(-s);
+        break;
+    }
+    case OR_F_GENZ_CORNER_PEAK: {
+        double s = 1.0;
+        for (uint32_t i = 0; i < d; ++i)
+            s += p->a[i] * z[i];
+        vr = pow(s, -(double)(d + 1));
+        break;
+    }
+    case OR_F_SECTOR: {
+        double mono = 1.0;
+        for (uint32_t i = 0; i < d; ++i)
+            mono *= or_ipow(z[i], p->nu[i]);
+        double U = or_poly(d, p->n_u, p->coef_u, p->exp_u, z);
+        double F = or_poly(d, p->n_f, p->coef_f, p->exp_f, z);
+        double pre = mono * pow(U, p->pow_u);
+        if (p->is_complex) {
+            double complex Fc = F - I * p->delta_im;
+            double complex v = pre * cpow(Fc, p->pow_f);
+            vr = creal(v);
+            vi = cimag(v);
+        } else {
+            vr = pre * pow(F, p->pow_f);
+        }
+        break;
+    }
+    default:
+        vr = NAN;
+        vi = NAN;
+    }
+    if (p->cv_w != NULL)
+        vr -= or_cv_g(d, p->cv_r, p->cv_k, p->cv_w, p->cv_c, z);
+    *re = vr;
+    *im = vi;
+}
+
+/* fhat(x) = f(z(x)) * prod_i z_i'(x_i) */
+void or_fhat(const or_params *p, uint32_t d, int32_t tkind, int32_t alpha, const double *x,
+             double *re, double *im)
+{
+    double z[64], wprod = 1.0;
+    for (uint32_t i = 0; i < d; ++i) {
+        double w;
+        or_transform(tkind, alpha, x[i], &z[i], &w);
+        wprod *= w;
+    }
+    double vr, vi;
+    or_integrand(p, d, z, &vr, &vi);
+    *re = vr * wprod;
+    *im = vi * wprod;
+}
+
+/* ------------------------------------------------------------------ */
+/* Compensated long-double accumulation                                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    long double s, c;
+} or_acc;
+
+static void or_acc_add(or_acc *a, long double v)
+{
+    long double t = a->s + v;
+    if (fabsl(a->s) >= fabsl(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+/* ------------------------------------------------------------------ */
+/* Estimator, eq. (2)                                                   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t d, m;
+    uint64_t n;
+    const uint64_t *g;
+    const double *shifts;
+    int32_t tkind, alpha;
+    const or_params *p;
+    or_acc *part_re, *part_im, *part_abs; /* [m][NCHUNK] */
+    int next;                             /* next work item, guarded by lock */
+    pthread_mutex_t lock;
+} or_job;
+
+static void or_work_item(or_job *jb, int item)
+{
+    uint32_t k = (uint32_t)(item / OR_NCHUNK);
+    uint64_t c = (uint64_t)(item % OR_NCHUNK);
+    uint64_t j0 = jb->n * c / OR_NCHUNK, j1 = jb->n * (c + 1) / OR_NCHUNK;
+    or_acc re = {0, 0}, im = {0, 0}, ab = {0, 0};
+    double x[64];
+    const double *sh = jb->shifts + (size_t)k * jb->d;
+    for (uint64_t j = j0; j < j1; ++j) {
+        or_point(jb->d, jb->n, jb->g, j, sh, jb->p->point_mode, x);
+        double vr, vi;
+        or_fhat(jb->p, jb->d, jb->tkind, jb->alpha, x, &vr, &vi);
+        or_acc_add(&re, vr);
+        or_acc_add(&im, vi);
+        or_acc_add(&ab, sqrt(vr * vr + vi * vi));
+    }
+    jb->part_re[item] = re;
+    jb->part_im[item] = im;
+    jb->part_abs[item] = ab;
+}
+
+static void *or_worker(void *arg)
+{
+    or_job *jb = (or_job *)arg;
+    int total = (int)jb->m * OR_NCHUNK;
+    for (;;) {
+        pthread_mutex_lock(&jb->lock);
+        int item = jb->next++;
+        pthread_mutex_unlock(&jb->lock);
+        if (item >= total)
+            break;
+        or_work_item(jb, item);
+    }
+    return NULL;
+}
+
+/* Per-shift estimates Q_k (re, im) and sum_j |fhat| / n (for the condition
+   number).  Returns 0, or 5 when a per-shift sum is not finite, or 1 on bad
+   arguments. */
+int or_estimate(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
+                int32_t tkind, int32_t alpha, const or_params *p, int32_t nthreads, double *q_re,
+                double *q_im, double *q_abs)
+{
+    if (d == 0 || d > 64 || n < 1 || m < 1)
+        return 1;
+    or_job jb;
+    jb.d = d;
+    jb.m = m;
+    jb.n = n;
+    jb.g = g;
+    jb.shifts = shifts;
+    jb.tkind = tkind;
+    jb.alpha = alpha;
+    jb.p = p;
+    size_t items = (size_t)m * OR_NCHUNK;
+    jb.part_re = (or_acc *)calloc(items, sizeof(or_acc));
+    jb.part_im = (or_acc *)calloc(items, sizeof(or_acc));
+    jb.part_abs = (or_acc *)calloc(items, sizeof(or_acc));
+    jb.next = 0;
+    pthread_mutex_init(&jb.lock, NULL);
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    pthread_t th[256];
+    for (int t = 1; t < nthreads; ++t)
+        pthread_create(&th[t], NULL, or_worker, &jb);
+    or_worker(&jb);
+    for (int t = 1; t < nthreads; ++t)
+        pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&jb.lock);
+
+    int status = 0;
+    for (uint32_t k = 0; k < m; ++k) {
+        or_acc re = {0, 0}, im = {0, 0}, ab = {0, 0};
+        for (int c = 0; c < OR_NCHUNK; ++c) {
+            or_acc *pr = &jb.part_re[(size_t)k * OR_NCHUNK + c];
+            or_acc *pi = &jb.part_im[(size_t)k * OR_NCHUNK + c];
+            or_acc *pa = &jb.part_abs[(size_t)k * OR_NCHUNK + c];
+            or_acc_add(&re, pr->s);
+            or_acc_add(&re, pr->c);
+            or_acc_add(&im, pi->s);
+            or_acc_add(&im, pi->c);
+            or_acc_add(&ab, pa->s);
+            or_acc_add(&ab, pa->c);
+        }
+        q_re[k] = (double)((re.s + re.c) / (long double)n);
+        q_im[k] = (double)((im.s + im.c) / (long double)n);
+        if (q_abs)
+            q_abs[k] = (double)((ab.s + ab.c) / (long double)n);
+        if (!isfinite(q_re[k]) || !isfinite(q_im[k]))
+            status = 5;
+    }
+    free(jb.part_re);
+    free(jb.part_im);
+    free(jb.part_abs);
+    return status;
+}
+
+/* Mean and error of eq. (2)/(3) for one real sequence: out[0] = Qbar,
+   out[1] = sqrt(sum_k (Q_k - Qbar)^2 / (m (m - 1))).  Two passes. */
+void or_mean_error(uint32_t m, const double *q, double *out)
+{
+    or_acc s = {0, 0};
+    for (uint32_t k = 0; k < m; ++k)
+        or_acc_add(&s, q[k]);
+    long double mean = (s.s + s.c) / (long double)m;
+    or_acc v = {0, 0};
+    for (uint32_t k = 0; k < m; ++k) {
+        long double dlt = (long double)q[k] - mean;
+        or_acc_add(&v, dlt * dlt);
+    }
+    out[0] = (double)mean;
+    out[1] = (m > 1) ? (double)sqrtl((v.s + v.c) / ((long double)m * (long double)(m - 1))) : NAN;
+}
+
+/* ------------------------------------------------------------------ */
+/* Generating vector: Korobov form and the P_2 criterion                */
+/* ------------------------------------------------------------------ */
+void or_korobov_vector(uint64_t n, uint32_t d, uint64_t a, uint64_t *g)
+{
+    uint64_t v = 1 % n;
+    for (uint32_t i = 0; i < d; ++i) {
+        g[i] = v;
+        v = or_lattice_index(v, a, n);
+    }
+}
+
+typedef struct {
+    uint32_t d;
+    uint64_t n;
+    const uint64_t *g;
+    or_acc *part;
+    int next;
+    pthread_mutex_t lock;
+} or_p2job;
+
+static void *or_p2_worker(void *arg)
+{
+    const double PI = 3.14159265358979323846;
+    or_p2job *jb = (or_p2job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&jb->lock);
+        int c = jb->next++;
+        pthread_mutex_unlock(&jb->lock);
+        if (c >= OR_NCHUNK)
+            break;
+        uint64_t j0 = jb->n * (uint64_t)c / OR_NCHUNK, j1 = jb->n * (uint64_t)(c + 1) / OR_NCHUNK;
+        or_acc a = {0, 0};
+        for (uint64_t j = j0; j < j1; ++j) {
+            double prod = 1.0;
+            for (uint32_t i = 0; i < jb->d; ++i) {
+                double x = (double)or_lattice_index(j, jb->g[i], jb->n) / (double)jb->n;
+                double b2 = x * x - x + 1.0 / 6.0;
+                prod *= 1.0 + 2.0 * PI * PI * b2;
+            }
+            or_acc_add(&a, prod);
+        }
+        jb->part[c] = a;
+    }
+    return NULL;
+}
+
+/* P_2(g) = -1 + (1/n) sum_{j=0}^{n-1} prod_i (1 + 2 pi^2 B_2({j g_i / n})),
+   B_2(x) = x^2 - x + 1/6: the worst-case error of the unshifted rule for
+   the unit-weight Korobov space of smoothness 2 (Sloan and Joe). */
+double or_p2(uint32_t d, uint64_t n, const uint64_t *g, int32_t nthreads)
+{
+    or_p2job jb;
+    jb.d = d;
+    jb.n = n;
+    jb.g = g;
+    jb.part = (or_acc *)calloc(OR_NCHUNK, sizeof(or_acc));
+    jb.next = 0;
+    pthread_mutex_init(&jb.lock, NULL);
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    pthread_t th[256];
+    for (int t = 1; t < nthreads; ++t)
+        pthread_create(&th[t], NULL, or_p2_worker, &jb);
+    or_p2_worker(&jb);
+    for (int t = 1; t < nthreads; ++t)
+        pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&jb.lock);
+    or_acc s = {0, 0};
+    for (int c = 0; c < OR_NCHUNK; ++c) {
+        or_acc_add(&s, jb.part[c].s);
+        or_acc_add(&s, jb.part[c].c);
+    }
+    free(jb.part);
+    return (double)(-1.0L + (s.s + s.c) / (long double)n);
+}
+
+/* argmin over candidates of P_2(korobov_vector(a)); ties go to the smaller
+   P_2 value, then to the smaller a.  p2_all (nullable) receives every value. */
+int or_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint32_t ncand,
+                      int32_t nthreads, uint64_t *a_best, double *p2_best, double *p2_all)
+{
+    if (ncand == 0 || d == 0 || d > 64 || n < 2)
+        return 1;
+    uint64_t g[64];
+    double best = INFINITY;
+    uint64_t abest = 0;
+    for (uint32_t c = 0; c < ncand; ++c) {
+        or_korobov_vector(n, d, cand[c], g);
+        double v = or_p2(d, n, g, nthreads);
+        if (p2_all)
+            p2_all[c] = v;
+        if (v < best || (v == best && cand[c] < abest)) {
+            best = v;
+            abest = cand[c];
+        }
+    }
+    *a_best = abest;
+    *p2_best = best;
+    return 0;
+}

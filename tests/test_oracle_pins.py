@@ -1,0 +1,534 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: exact
+integer arithmetic, closed-form integrals, library quadrature, textbook
+identities (Raabe's multiplication theorem, the dual-lattice character sum),
+statistical properties of eqs. (2)-(3), or an exact-rational brute force.
+Citations refer to arXiv:1811.11722.
+"""
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import oracle as O
+from paper_1811_11722_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build(force=False)
+
+
+# ---------------------------------------------------------------- inputs
+def test_philox_known_answers():
+    """Philox4x32-10 known-answer vectors of the Random123 distribution."""
+    cases = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+             ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF),
+              (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+             ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+              (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, want in cases:
+        got = synth.philox4x32_10(np.array([ctr], dtype=np.uint64), key)[0]
+        assert tuple(int(v) for v in got) == want
+
+
+def test_prime_ladder():
+    assert synth.N_LADDER[14] == 16381 and synth.N_LADDER[17] == 131071
+    assert synth.N_LADDER[24] == 16777213 and synth.N_LADDER[30] == 1073741789
+    for k, n in synth.N_LADDER.items():
+        assert all(not synth.is_prime(v) for v in range(n + 1, 1 << k))
+
+
+# ---------------------------------------------------- lattice index, eq. (2)
+def test_lattice_index_exact_big_integers():
+    """(j' g_i) mod n against Python's exact integers, including n near 2^32."""
+    rng = np.random.default_rng(1)
+    for n in (7, 1021, 131071, 1073741789, 4294967291):
+        for _ in range(200):
+            j = int(rng.integers(0, n))
+            gi = int(rng.integers(1, n))
+            assert O.lattice_index(j, gi, n) == (j * gi) % n
+
+
+def test_lattice_is_a_permutation():
+    """For gcd(g_i, n) = 1 each coordinate visits every residue exactly once."""
+    for n in (7, 31, 127, 1021):
+        g = O.korobov_vector(n, 3, 5 % n)
+        idx = O.lattice_indices(n, g, np.arange(n))
+        for i in range(3):
+            assert np.array_equal(np.sort(idx[:, i]), np.arange(n, dtype=np.uint64))
+
+
+def test_korobov_vector_powers():
+    n, a = 131071, 48724
+    g = O.korobov_vector(n, 6, a)
+    assert [int(v) for v in g] == [pow(a, i, n) for i in range(6)]
+
+
+def test_point_rounding_and_wrap():
+    """x = {idx/n + Delta} against exact rationals; at most one rounding of slack."""
+    rng = np.random.default_rng(2)
+    for n in (7, 127, 1021, 131071):
+        g = O.korobov_vector(n, 4, 3)
+        for _ in range(50):
+            j = int(rng.integers(0, n))
+            sh = rng.random(4)
+            x = O.point(n, g, j, sh)
+            for i in range(4):
+                exact = Fraction((j * int(g[i])) % n, n) + Fraction(float(sh[i]))
+                exact -= math.floor(exact)
+                assert 0.0 <= x[i] < 1.0
+                assert abs(x[i] - float(exact)) <= 2.0 ** -52
+    # a sum that rounds to exactly 1.0 wraps to 0.0
+    x = O.point(3, np.array([1], dtype=np.uint64), 1, np.array([1.0 - 1.0 / 3.0]))
+    assert 1.0 / 3.0 + (1.0 - 1.0 / 3.0) == 1.0 and x[0] == 0.0
+
+
+# ------------------------------------------------ transforms, eqs. (4)-(5)
+@pytest.mark.parametrize("alpha", [1, 2, 3, 6])
+def test_korobov_transform_against_quadrature(alpha):
+    """z(x) is the normalised integral of u^a (1-u)^a (eq. 4): compare with
+    scipy quadrature and the Beta function; check symmetry and z' = w."""
+    B = special.beta(alpha + 1, alpha + 1)
+    for x in (0.0, 0.013, 0.25, 0.5, 0.77, 0.999, 1.0):
+        z, w = O.transform("korobov", alpha, x)
+        zq, _ = integrate.quad(lambda t: t ** alpha * (1 - t) ** alpha / B, 0.0, x,
+                               epsabs=1e-15, epsrel=1e-13)
+        assert abs(z - zq) < 1e-13
+        assert abs(w - x ** alpha * (1 - x) ** alpha / B) <= 1e-13 * max(1.0, w)
+        z2, _ = O.transform("korobov", alpha, 1.0 - x)
+        assert abs(z2 - (1.0 - z)) < 1e-14
+    for x in (0.1, 0.4, 0.6):
+        h = 1e-6
+        zp, _ = O.transform("korobov", alpha, x + h)
+        zm, _ = O.transform("korobov", alpha, x - h)
+        _, w = O.transform("korobov", alpha, x)
+        assert abs((zp - zm) / (2 * h) - w) < 1e-7 * max(1.0, w)
+
+
+def test_korobov3_expanded_polynomial():
+    """For weight 3: w = 140 x^3 (1-x)^3 and z = 35x^4 - 84x^5 + 70x^6 - 20x^7."""
+    for x in np.linspace(0, 1, 41):
+        z, w = O.transform("korobov", 3, x)
+        q = Fraction(float(x))
+        zx = 35 * q**4 - 84 * q**5 + 70 * q**6 - 20 * q**7
+        wx = 140 * q**3 * (1 - q) ** 3
+        assert abs(z - float(zx)) <= 2.0 ** -52
+        assert abs(w - float(wx)) <= 2.0 ** -52 * max(1.0, float(wx))
+    _, w6 = O.transform("korobov", 6, 0.5)
+    assert abs(w6 - 12012 * 0.25**6) < 1e-12
+
+
+def test_baker_transform():
+    """eq. (5): z = 1 - |2x - 1|; the 2-to-1 map keeps integrals, so weight 1."""
+    for x in (0.0, 0.1, 0.5, 0.75, 0.999):
+        z, w = O.transform("baker", 0, x)
+        assert z == 1.0 - abs(2.0 * x - 1.0) and w == 1.0
+    f = lambda t: math.exp(3 * t) * math.cos(t)
+    lhs, _ = integrate.quad(lambda x: f(O.transform("baker", 0, x)[0]), 0, 1, points=[0.5],
+                            epsabs=1e-14)
+    rhs, _ = integrate.quad(f, 0, 1, epsabs=1e-14)
+    assert abs(lhs - rhs) < 1e-12
+
+
+# -------------------------------------------------------- estimator eq. (2)
+def _cfg(n, d, a=3):
+    return O.korobov_vector(n, d, a)
+
+
+def test_constant_exact_for_none_and_baker():
+    """A constant is integrated exactly by the plain rule and under the
+    baker's transform for any lattice (Sec. 2, discussion of Fig. 3)."""
+    n, d, m = 1021, 5, 8
+    g = _cfg(n, d, 76)
+    sh = synth.shifts(7, m, d)
+    for tk in ("none", "baker"):
+        est = O.estimate(n, g, sh, O.Params("const", d, c=2.75), tk)
+        assert np.all(np.abs(est.q_re - 2.75) <= 2 * np.spacing(2.75))
+        assert est.mean_error()[1] <= 1e-15
+
+
+def test_constant_under_korobov_decays():
+    """Fig. 3: integrating 1 with Korobov weight 3 in d = 6 leaves a nonzero
+    error that decreases with n (a band, not a fitted slope)."""
+    d, m = 6, 8
+    errs = []
+    for n in (1021, 16381, 262139):
+        a, _, _ = O.korobov_search(n, d, synth.korobov_candidates(11, n, 16))
+        g = O.korobov_vector(n, d, a)
+        est = O.estimate(n, g, synth.shifts(11, m, d), O.Params("const", d, c=1.0), "korobov", 3)
+        errs.append(np.sqrt(np.mean((est.q_re - 1.0) ** 2)))
+    assert errs[0] > 1e-9
+    assert errs[2] < errs[0] / 100.0
+
+
+def _genz_closed(family, a, u):
+    d = len(a)
+    if family == "genz_product_peak":
+        return float(np.prod([ai * (math.atan(ai * (1 - ui)) + math.atan(ai * ui))
+                              for ai, ui in zip(a, u)]))
+    if family == "genz_oscillatory":
+        v = np.exp(2j * math.pi * u[0]) * np.prod([(np.exp(1j * ai) - 1) / (1j * ai) for ai in a])
+        return float(v.real)
+    if family == "genz_gaussian":
+        return float(np.prod([math.sqrt(math.pi) / (2 * ai) *
+                              (math.erf(ai * (1 - ui)) + math.erf(ai * ui))
+                              for ai, ui in zip(a, u)]))
+    if family == "genz_continuous":
+        return float(np.prod([(2 - math.exp(-ai * ui) - math.exp(-ai * (1 - ui))) / ai
+                              for ai, ui in zip(a, u)]))
+    if family == "genz_corner_peak":
+        s = 0.0
+        for v in itertools.product((0, 1), repeat=d):
+            s += (-1) ** sum(v) / (1 + float(np.dot(a, v)))
+        return s / (math.factorial(d) * float(np.prod(a)))
+    raise KeyError(family)
+
+
+@pytest.mark.parametrize("family", ["genz_product_peak", "genz_oscillatory", "genz_gaussian",
+                                    "genz_continuous", "genz_corner_peak"])
+def test_genz_closed_forms(family):
+    """Genz (1984) test integrals against their closed forms, Korobov 3."""
+    d, n, m = 3, 65521, 16
+    a, u = synth.genz_params(5, d)
+    if family in ("genz_oscillatory", "genz_corner_peak"):
+        a = a / 4.0
+    ab, _, _ = O.korobov_search(n, d, synth.korobov_candidates(5, n, 16))
+    g = O.korobov_vector(n, d, ab)
+    est = O.estimate(n, g, synth.shifts(5, m, d), O.Params(family, d, a=a, u=u), "korobov", 3)
+    mean, err, _ = est.mean_error()
+    exact = _genz_closed(family, a, u)
+    assert abs(mean.real - exact) <= 5 * err + 1e-13 * abs(exact)
+    assert abs(mean.real - exact) <= 1e-6 * abs(exact)
+
+
+def test_genz_closed_forms_against_quadrature():
+    """The closed forms used above agree with scipy quadrature in d = 2."""
+    a, u = np.array([1.3, 0.7]), np.array([0.3, 0.6])
+    fs = {
+        "genz_product_peak": lambda y, x: 1 / ((a[0] ** -2 + (x - u[0]) ** 2) * (a[1] ** -2 + (y - u[1]) ** 2)),
+        "genz_oscillatory": lambda y, x: math.cos(2 * math.pi * u[0] + a[0] * x + a[1] * y),
+        "genz_gaussian": lambda y, x: math.exp(-(a[0] ** 2 * (x - u[0]) ** 2 + a[1] ** 2 * (y - u[1]) ** 2)),
+        "genz_continuous": lambda y, x: math.exp(-(a[0] * abs(x - u[0]) + a[1] * abs(y - u[1]))),
+        "genz_corner_peak": lambda y, x: (1 + a[0] * x + a[1] * y) ** -3,
+    }
+    for fam, f in fs.items():
+        q, _ = integrate.dblquad(f, 0, 1, 0, 1, epsabs=1e-12, epsrel=1e-12)
+        assert abs(q - _genz_closed(fam, a, u)) < 1e-8, fam
+
+
+def test_trig_polynomial_dual_lattice():
+    """Character sums: a frequency h outside the dual lattice
+    L^perp = {h : h.g = 0 mod n} averages to zero over the shifted lattice,
+    one inside it contributes c_h cos(2 pi h.Delta + phi) to every Q_k."""
+    n, d, m = 1021, 3, 6
+    g = [int(v) for v in O.korobov_vector(n, d, 76)]
+    sh = synth.shifts(9, m, d)
+    hs_out = [(1, 0, 0), (0, 2, -1), (3, 1, 1), (1, -1, 2)]
+    for h in hs_out:
+        assert sum(hi * gi for hi, gi in zip(h, g)) % n != 0
+    h_in = (-g[1], 1, 0)
+    assert sum(hi * gi for hi, gi in zip(h_in, g)) % n == 0
+    c0 = 0.5
+    ch = [0.7, -0.3, 0.25, 0.4]
+    phi = [0.1, 1.2, -0.4, 2.0]
+    est = O.estimate(n, np.array(g, dtype=np.uint64), sh,
+                     O.Params("trig", d, trig=(c0, hs_out, ch, phi)), "none")
+    assert np.all(np.abs(est.q_re - c0) < 1e-13)
+    hs = hs_out + [h_in]
+    est = O.estimate(n, np.array(g, dtype=np.uint64), sh,
+                     O.Params("trig", d, trig=(c0, hs, ch + [0.9], phi + [0.3])), "none")
+    want = c0 + 0.9 * np.cos(2 * np.pi * (sh @ np.array(h_in, dtype=float)) + 0.3)
+    assert np.all(np.abs(est.q_re - want) < 1e-11)
+
+
+def test_raabe_identity_one_dimension():
+    """(1/n) sum_j B2({j/n + D}) = B2({n D}) / n^2 (multiplication theorem),
+    seen through the P2 kernel 1 + 2 pi^2 B2(x) in d = 1."""
+    n = 131071
+    for D in (0.123456789, 0.5, 0.9876):
+        est = O.estimate(n, np.array([1], dtype=np.uint64), np.array([[D]]),
+                         O.Params("p2kernel", 1), "none")
+        t = Fraction(n) * Fraction(D)
+        t -= math.floor(t)
+        t = float(t)
+        want = 2 * math.pi ** 2 * (t * t - t + 1 / 6) / n ** 2
+        assert abs((est.q_re[0] - 1.0) - want) < 2e-15
+
+
+def test_p2_against_truncated_dual_lattice_sum():
+    """P2(g) equals the sum over nonzero dual-lattice h of prod r(h_i)^-2
+    (Fourier series of B2); truncation converges from below."""
+    n, g = 101, (1, 37)
+    p2 = O.p2(n, np.array(g, dtype=np.uint64))
+    H = 400
+    h1 = np.arange(-H, H + 1)
+    tot = 0.0
+    for a in h1:
+        # h2 with a*1 + h2*37 = 0 mod 101
+        h2 = h1[(a + h1 * 37) % n == 0]
+        r1 = max(1, abs(int(a)))
+        r2 = np.maximum(1, np.abs(h2))
+        tot += float(np.sum(1.0 / (r1 ** 2 * r2.astype(float) ** 2)))
+    tot -= 1.0  # h = 0
+    assert tot < p2 < tot * 1.05
+
+
+def test_p2_symmetries():
+    """a and n - a (reflection) and, for d = 2, a and a^-1 mod n (coordinate
+    swap) give the same P2."""
+    n = 1021
+    for a in (3, 76, 400):
+        v = O.p2(n, O.korobov_vector(n, 3, a))
+        assert abs(v - O.p2(n, O.korobov_vector(n, 3, n - a))) <= 1e-13 * v
+        ainv = pow(a, -1, n)
+        v2 = O.p2(n, O.korobov_vector(n, 2, a))
+        assert abs(v2 - O.p2(n, O.korobov_vector(n, 2, ainv))) <= 1e-13 * v2
+
+
+def test_korobov_search_brute_force():
+    """The search returns the argmin of P2 over its candidates."""
+    n, d = 1021, 3
+    cand = np.arange(2, 60, dtype=np.uint64)
+    a, p, allp = O.korobov_search(n, d, cand)
+    vals = [O.p2(n, O.korobov_vector(n, d, int(c))) for c in cand]
+    assert p == min(vals) and a == int(cand[int(np.argmin(vals))])
+    assert np.array_equal(allp, np.array(vals))
+
+
+# ------------------------------------------------------- mean and eq. (3)
+def test_mean_error_against_numpy():
+    q = synth.uniforms(3, 0, 32) * 5 + 1
+    mean, err = O.mean_error(q)
+    assert abs(mean - np.mean(q)) < 1e-15 * 6
+    assert abs(err - np.std(q, ddof=1) / math.sqrt(q.size)) < 1e-14
+
+
+def test_unbiased_and_error_calibrated():
+    """Random shifts make each Q_k unbiased (eq. 2) and sigma^2 of eq. (3)
+    estimates Var(Qbar): checked over many independent shift sets."""
+    d, n = 2, 127
+    a, u = np.array([3.0, 5.0]), np.array([0.3, 0.7])
+    exact = _genz_closed("genz_product_peak", a, u)
+    g = O.korobov_vector(n, d, 47)
+    M = 4096
+    est = O.estimate(n, g, synth.shifts(21, M, d), O.Params("genz_product_peak", d, a=a, u=u),
+                     "none")
+    q = est.q_re
+    assert abs(q.mean() - exact) < 4 * q.std() / math.sqrt(M)
+    m = 8
+    sets = q.reshape(-1, m)
+    means = sets.mean(axis=1)
+    sig2 = np.array([O.mean_error(s)[1] ** 2 for s in sets])
+    ratio = sig2.mean() / means.var(ddof=1)
+    assert 0.85 < ratio < 1.15
+
+
+# ----------------------------------------------------------- convergence
+def test_convergence_bands():
+    """Sec. 2: Korobov 3 gives O(n^-3), the baker's transform O(n^-2)
+    (Fig. 2 saw ~n^-1.5).  The paper warns the curves are noisy, so only
+    a band on the overall decay is asserted."""
+    d = 2
+    a, u = np.array([4.0, 6.0]), np.array([0.35, 0.6])
+    exact = _genz_closed("genz_product_peak", a, u)
+    res = {}
+    for tk, al, ns in (("korobov", 3, (1021, 16381)), ("baker", 0, (1021, 262139))):
+        errs = []
+        for n in ns:
+            ab, _, _ = O.korobov_search(n, d, synth.korobov_candidates(13, n, 16))
+            est = O.estimate(n, O.korobov_vector(n, d, ab), synth.shifts(13, 16, d),
+                             O.Params("genz_product_peak", d, a=a, u=u), tk, al)
+            errs.append(np.sqrt(np.mean((est.q_re - exact) ** 2)) / exact)
+        assert min(errs) > 0.0
+        res[tk] = np.log(errs[-1] / errs[0]) / np.log(ns[-1] / ns[0])
+    assert res["korobov"] < -2.5
+    assert res["baker"] < -1.4
+
+
+# ------------------------------------------------------- sector family
+def test_eq10_polynomial_vanishes():
+    """eq. (10): F of the Zbb vertex is zero at (1, 1, 1, 1/2, 1, 1)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "eq10_zbb_vertex_F.txt"))
+    coef, exps = rows[:, 0], rows[:, 1:].astype(np.uint8)
+    assert coef.size == 16
+    assert O.poly(coef, exps, [1, 1, 1, 0.5, 1, 1]) == 0.0
+    assert O.poly(coef, exps, [1, 1, 1, 1, 1, 1]) == 6.0
+
+
+def _sector(d, coef_u, exp_u, coef_f, exp_f, nu, pow_u=-2.0, pow_f=-1.3, delta=0.0, cplx=False):
+    return synth.SectorTables(d=d, coef_u=np.array(coef_u, float), exp_u=np.array(exp_u, np.uint8),
+                              coef_f=np.array(coef_f, float), exp_f=np.array(exp_f, np.uint8),
+                              nu=np.array(nu, np.uint8), pow_u=pow_u, pow_f=pow_f,
+                              delta_im=delta, is_complex=cplx)
+
+
+def test_sector_constant_polynomials():
+    """U = c_U, F = c_F: I = c_U^-2 c_F^-1.3 prod_i 1/(nu_i + 1)."""
+    d, n = 3, 65521
+    s = _sector(d, [2.5], [[0, 0, 0]], [0.4], [[0, 0, 0]], [0, 1, 2])
+    g = O.korobov_vector(n, d, 17364)
+    est = O.estimate(n, g, synth.shifts(4, 8, d), O.Params("sector", d, sector=s), "baker")
+    want = 2.5 ** -2 * 0.4 ** -1.3 / 6.0
+    mean, err, _ = est.mean_error()
+    assert abs(mean.real - want) < 1e-7 * want
+
+
+def test_sector_linear_F():
+    """F = c0 + c1 x1 (x2 absent), nu = 0: I = c_U^-2 [(c0+c1)^-e - c0^-e] / (-e c1)."""
+    d, n = 2, 65521
+    c0, c1, cu, e = 0.5, 3.0, 1.7, 0.3
+    s = _sector(d, [cu], [[0, 0]], [c0, c1], [[0, 0], [1, 0]], [0, 0], pow_f=-1 - e)
+    g = O.korobov_vector(n, d, 17364)
+    est = O.estimate(n, g, synth.shifts(4, 8, d), O.Params("sector", d, sector=s), "baker")
+    want = cu ** -2 * ((c0 + c1) ** -e - c0 ** -e) / (-e * c1)
+    q, _ = integrate.quad(lambda x: cu ** -2 * (c0 + c1 * x) ** (-1 - e), 0, 1, epsabs=1e-14)
+    assert abs(q - want) < 1e-12
+    mean, err, _ = est.mean_error()
+    assert abs(mean.real - want) < 1e-7 * abs(want)
+
+
+def _xmy_closed(eps, delta):
+    """Finite-delta value of the toy integral of eq. (7):
+    [(1-i d)^e + (-1-i d)^e - 2(-i d)^e] / (e (e - 1)), principal branch."""
+    p = lambda z: complex(z) ** eps
+    return (p(1 - 1j * delta) + p(-1 - 1j * delta) - 2 * p(-1j * delta)) / (eps * (eps - 1))
+
+
+def test_xmy_closed_form_against_quadrature():
+    """The closed form of eq. (7) at finite delta against 1-d quadrature of
+    the inner integral's antiderivative (a larger delta keeps quad cheap)."""
+    eps, delta = 0.3, 0.2
+    h1 = lambda t: (t - 1j * delta) ** (eps - 1) / (eps - 1)
+    inner = lambda x: h1(x) - h1(x - 1)
+    re, _ = integrate.quad(lambda x: inner(x).real, 0, 1, epsabs=1e-13)
+    im, _ = integrate.quad(lambda x: inner(x).imag, 0, 1, epsabs=1e-13)
+    assert abs(complex(re, im) - _xmy_closed(eps, delta)) < 1e-11
+    v = _xmy_closed(0.3, 1e-2)
+    assert abs(v - (-5.440988031190133 + 2.772321872285986j)) < 1e-12
+
+
+def test_xmy_integral_estimate():
+    """eq. (7) as a complex sector integrand: U = 1, F = x1 - x2,
+    (F - i delta)^(-2 + eps) with delta = 1e-2; baker periodisation."""
+    d, n, eps, delta = 2, 262139, 0.3, 1e-2
+    s = _sector(d, [1.0], [[0, 0]], [1.0, -1.0], [[1, 0], [0, 1]], [0, 0], pow_u=-2.0,
+                pow_f=-2.0 + eps, delta=delta, cplx=True)
+    a, _, _ = O.korobov_search(n, d, synth.korobov_candidates(8, n, 16))
+    g = O.korobov_vector(n, d, a)
+    est = O.estimate(n, g, synth.shifts(8, 16, d), O.Params("sector", d, sector=s), "baker")
+    mean, er, ei = est.mean_error()
+    want = _xmy_closed(eps, delta)
+    assert abs(mean.real - want.real) < 6 * er + 1e-9
+    assert abs(mean.imag - want.imag) < 6 * ei + 1e-9
+    assert abs(mean - want) < 2e-3 * abs(want)
+
+
+# ------------------------------------------------- exact brute force
+def _brute(n, g, shift, f, w_of):
+    vals = []
+    for j in range(n):
+        x = []
+        for i, gi in enumerate(g):
+            t = Fraction((j * gi) % n, n) + Fraction(float(shift[i]))
+            t -= math.floor(t)
+            x.append(float(t))
+        z, w = zip(*[w_of(xi) for xi in x])
+        vals.append(f(z) * math.prod(w))
+    return math.fsum(vals) / n
+
+
+def test_brute_force_tiny_lattices():
+    """Exact-rational points and an exactly rounded sum (math.fsum) in
+    Python, for tiny n, against the oracle's per-shift values."""
+    d = 3
+    a, u = np.array([3.0, 5.0, 2.5]), np.array([0.3, 0.7, 0.1])
+    s = synth.sector_tables(31, d, 5, 7)
+
+    def kor3(x):
+        return 35 * x**4 - 84 * x**5 + 70 * x**6 - 20 * x**7, 140 * x**3 * (1 - x) ** 3
+
+    def baker(x):
+        return 1 - abs(2 * x - 1), 1.0
+
+    def peak(z):
+        return math.prod(1 / (ai ** -2 + (zi - ui) ** 2) for zi, ai, ui in zip(z, a, u))
+
+    def sect(z):
+        U = sum(c * math.prod(zi ** int(e) for zi, e in zip(z, ex)) for c, ex in zip(s.coef_u, s.exp_u))
+        F = sum(c * math.prod(zi ** int(e) for zi, e in zip(z, ex)) for c, ex in zip(s.coef_f, s.exp_f))
+        return math.prod(zi ** int(v) for zi, v in zip(z, s.nu)) * U ** -2 * F ** -1.3
+
+    for n in (7, 31, 127):
+        g = O.korobov_vector(n, d, 3)
+        sh = synth.shifts(n, 3, d)
+        e1 = O.estimate(n, g, sh, O.Params("genz_product_peak", d, a=a, u=u), "korobov", 3)
+        e2 = O.estimate(n, g, sh, O.Params("sector", d, sector=s), "baker")
+        for k in range(3):
+            b1 = _brute(n, [int(v) for v in g], sh[k], peak, kor3)
+            b2 = _brute(n, [int(v) for v in g], sh[k], sect, baker)
+            assert abs(e1.q_re[k] - b1) <= 1e-13 * abs(b1)
+            assert abs(e2.q_re[k] - b2) <= 1e-13 * abs(b2)
+
+
+def test_thread_count_does_not_change_results():
+    w = synth.product_peak_workload(n=16381, m=4)
+    g = O.korobov_vector(w.n, w.d, 1234)
+    p = O.Params("genz_product_peak", w.d, a=w.genz_a, u=w.genz_u)
+    e1 = O.estimate(w.n, g, w.shifts, p, "korobov", 3, threads=1)
+    e8 = O.estimate(w.n, g, w.shifts, p, "korobov", 3, threads=8)
+    assert np.array_equal(e1.q_re, e8.q_re)
+
+
+# ------------------------------------------------------- control variate
+def test_legendre_orthonormal_against_numpy():
+    from numpy.polynomial import legendre as L
+    for x in (0.0, 0.2, 0.5, 0.93, 1.0):
+        got = O.legendre(12, x)
+        for k in range(12):
+            c = np.zeros(k + 1)
+            c[k] = 1
+            assert abs(got[k] - math.sqrt(2 * k + 1) * L.legval(2 * x - 1, c)) < 1e-12
+
+
+def test_cv_integral_against_gauss_legendre():
+    """int g over [0,1]^d = sum_r c_r prod_i W[r,i,0]; checked with a tensor
+    Gauss-Legendre rule exact for the model's degree."""
+    from numpy.polynomial import legendre as L
+    rng = np.random.default_rng(5)
+    for d, R, K in ((1, 3, 5), (2, 4, 6), (3, 2, 4)):
+        W = rng.normal(size=(R, d, K))
+        c = rng.normal(size=R)
+        xs, ws = L.leggauss(K)
+        xs, ws = (xs + 1) / 2, ws / 2
+        tot = 0.0
+        for idx in itertools.product(range(K), repeat=d):
+            z = [xs[t] for t in idx]
+            tot += math.prod(ws[t] for t in idx) * O.cv_g(W, c, z)
+        assert abs(tot - O.cv_integral(W, c)) < 1e-12 * max(1.0, abs(tot))
+
+
+def test_cv_residual_estimate():
+    """With W = 0 the residual f - g is f; if f is itself a separable
+    Legendre model, f - g = 0 and every Q_k of the residual is 0."""
+    d, n = 2, 1021
+    a, u = np.array([3.0, 5.0]), np.array([0.3, 0.7])
+    g = O.korobov_vector(n, d, 47)
+    sh = synth.shifts(3, 4, d)
+    W = np.zeros((2, d, 4))
+    plain = O.estimate(n, g, sh, O.Params("genz_product_peak", d, a=a, u=u), "baker")
+    zero = O.estimate(n, g, sh, O.Params("genz_product_peak", d, a=a, u=u, cv=(W, np.ones(2))),
+                      "baker")
+    assert np.array_equal(plain.q_re, zero.q_re)
+    # constant c = 1 modelled exactly by W[0,:,0] = 1, c_0 = 1
+    W = np.zeros((1, d, 3))
+    W[0, :, 0] = 1.0
+    res = O.estimate(n, g, sh, O.Params("const", d, c=1.0, cv=(W, np.ones(1))), "baker")
+    assert np.all(res.q_re == 0.0)
