@@ -1,0 +1,215 @@
+/*
+ * qmc.h -- randomly shifted rank-1 lattice quasi-Monte Carlo estimator on
+ * AMD Instinct MI355X (gfx950), FP64 throughout.
+ *
+ * The method (arXiv:1811.11722, Sec. 2):
+ *   I_d[f] = integral of f over [0,1]^d, f real or complex            eq. (1)
+ *   Q_k    = (1/n) sum_{j=1..n} fhat({(j-1) g / n + Delta_k}),
+ *   Qbar   = (1/m) sum_{k=1..m} Q_k                                   eq. (2)
+ *   sigma^2 = sum_k (Q_k - Qbar)^2 / (m (m - 1))                       eq. (3)
+ *   fhat(x) = f(z(x)) prod_i z_i'(x_i) with the Korobov transform      eq. (4)
+ *             or the baker's transform                                eq. (5)
+ * The sector integrand family follows eq. (6) with two polynomials
+ * (U and F of Sec. 3) and an optional -i*delta prescription as in eq. (7).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a qmc_status; nothing throws across the ABI.
+ *   - Arguments are validated on the host before any device call; on an
+ *     argument error nothing is launched and the outputs are untouched.
+ *   - Input pointers are host pointers, borrowed for the duration of the
+ *     call only (the library copies what it keeps).  Output pointers are
+ *     caller-owned host memory.
+ *   - A plan owns its device memory (allocated at create, freed at destroy).
+ *     A plan must not be used from two host threads at once; separate plans
+ *     may run concurrently on separate streams.
+ *   - qmc_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qmc_plan_s *qmc_plan_t;
+
+typedef enum {
+    QMC_OK = 0,
+    QMC_EINVAL = 1,        /* invalid argument */
+    QMC_EUNSUPPORTED = 2,  /* valid but outside what this build supports */
+    QMC_ENOMEM = 3,        /* device or host allocation failed */
+    QMC_EDEVICE = 4,       /* HIP runtime error; detail in qmc_last_error() */
+    QMC_ENONFINITE = 5     /* a per-shift sum is not finite; means/errors set to NaN */
+} qmc_status;
+
+/* Periodising transforms, eqs. (4) and (5).  QMC_T_TENT is the same map as
+   the baker's transform, read as a modification of the lattice (Sec. 2). */
+typedef enum {
+    QMC_T_NONE = 0,
+    QMC_T_KOROBOV = 1,  /* weight alpha in 1..6 */
+    QMC_T_BAKER = 2,
+    QMC_T_TENT = 2
+} qmc_transform_kind;
+
+typedef struct {
+    int32_t kind;   /* qmc_transform_kind */
+    int32_t alpha;  /* Korobov weight; ignored otherwise */
+} qmc_transform;
+
+/* Integrand families f(z), z in [0,1]^d. */
+typedef enum {
+    QMC_F_CONST = 0,              /* qmc_const_params */
+    QMC_F_TRIG = 1,               /* qmc_trig_params */
+    QMC_F_P2KERNEL = 2,           /* prod_i (1 + 2 pi^2 B2(z_i)); params NULL */
+    QMC_F_GENZ_PRODUCT_PEAK = 3,  /* prod_i 1/(a_i^-2 + (z_i - u_i)^2) */
+    QMC_F_GENZ_OSCILLATORY = 4,   /* cos(2 pi u_1 + sum_i a_i z_i) */
+    QMC_F_GENZ_GAUSSIAN = 5,      /* exp(-sum_i a_i^2 (z_i - u_i)^2) */
+    QMC_F_GENZ_CONTINUOUS = 6,    /* exp(-sum_i a_i |z_i - u_i|) */
+    QMC_F_GENZ_CORNER_PEAK = 7,   /* (1 + sum_i a_i z_i)^-(d+1) */
+    QMC_F_SECTOR = 8              /* qmc_sector_params */
+} qmc_family;
+
+typedef struct {
+    double c;
+} qmc_const_params;
+
+/* f = c0 + sum_t c[t] cos(2 pi h_t . z + phi[t]); h row-major (n_terms, d). */
+typedef struct {
+    uint32_t n_terms;
+    double c0;
+    const int64_t *h;
+    const double *c;
+    const double *phi;
+} qmc_trig_params;
+
+/* Genz parameters, length d each. */
+typedef struct {
+    const double *a;
+    const double *u;
+} qmc_genz_params;
+
+/* Sector integrand  prod_i z_i^nu_i * U(z)^pow_u * (F(z) - i delta_im)^pow_f,
+   U(z) = sum_t coef_u[t] prod_i z_i^exp_u[t*d+i]  (row-major (n_u, d)), F alike.
+   Exponents and nu are 0..2; a monomial may have total degree <= 12.
+   Real form (is_complex = 0) needs U > 0 and F > 0 on the domain; complex form
+   uses the principal branch.  pow_u, pow_f, delta_im are plain doubles. */
+typedef struct {
+    uint32_t n_u, n_f;
+    const double *coef_u;
+    const uint8_t *exp_u;
+    const double *coef_f;
+    const uint8_t *exp_f;
+    const uint8_t *nu;
+    double pow_u, pow_f;
+    double delta_im;
+    int32_t is_complex;
+} qmc_sector_params;
+
+/* Result of eqs. (2)-(3).  err = sqrt(sigma^2); complex integrands carry
+   separate errors for the real and imaginary parts. */
+typedef struct {
+    double mean_re, mean_im;
+    double err_re, err_im;
+    int32_t is_complex;
+    int32_t used_cv;  /* 1 when a control-variate estimate was returned */
+} qmc_result;
+
+/* Launch shape of the lattice kernel.  shift_tile is the number of shifts
+   each thread evaluates per lattice point (1, 2, 4 or 8); blocks_per_cu sets
+   the grid size (workgroups of 256 threads per compute unit and per shift
+   tile).  Zero fields mean "use the tuned or default choice". */
+typedef struct {
+    uint32_t shift_tile;
+    uint32_t blocks_per_cu;
+} qmc_launch;
+
+/* Create a plan for the rule of eq. (2).
+   d       dimension, 1..32
+   n       number of lattice points, 2..2^31
+   g       generating vector, length d; every g_i mod n must be nonzero
+   m       number of shifts, >= 2 (eq. (3) divides by m - 1)
+   shifts  m*d doubles, row-major (shift k is shifts[k*d .. k*d+d-1]), each in [0,1)
+   t       periodising transform
+   Errors: EINVAL on a bad argument, EUNSUPPORTED for d > 32, n > 2^31 or a
+   Korobov weight above 6, ENOMEM / EDEVICE from the device. */
+qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m,
+                           const double *shifts, qmc_transform t, qmc_plan_t *out);
+
+/* Run the plan's kernels on this HIP stream (a hipStream_t; NULL = default). */
+qmc_status qmc_plan_set_stream(qmc_plan_t plan, void *hip_stream);
+
+/* Fix the launch shape for later calls (zero fields restore the default). */
+qmc_status qmc_plan_set_launch(qmc_plan_t plan, const qmc_launch *cfg);
+
+/* Evaluate eqs. (2)-(3) for the integrand (family, params).
+   params     the family's parameter struct (NULL for QMC_F_P2KERNEL)
+   out        mean and error
+   per_shift  nullable; receives Q_k for k = 0..m-1 (real) or 2m doubles
+              (re, im interleaved) for a complex sector integrand.
+   Errors: EINVAL for a bad family/params, ENONFINITE if any Q_k is not
+   finite (then means and errors are NaN), EDEVICE on a HIP error. */
+qmc_status qmc_integrate(qmc_plan_t plan, qmc_family family, const void *params, qmc_result *out,
+                         double *per_shift);
+
+/* Device time of the lattice kernels launched through this plan since the
+   last reset, measured with HIP events on the plan's stream.  Timing is off
+   until qmc_plan_set_timing(plan, 1). */
+qmc_status qmc_plan_set_timing(qmc_plan_t plan, int32_t enable);
+qmc_status qmc_plan_kernel_time(qmc_plan_t plan, double *total_ms, uint64_t *launches, int32_t reset);
+
+/* Exact lattice indices idx_{j,i} = (j g_i) mod n for j = j_lo .. j_lo+count-1
+   (j counts from 0, i.e. j = (paper's j) - 1), written row-major into idx_out
+   (count*d uint32), produced by the same index walk the lattice kernel runs.
+   sums_out (nullable, 2*d uint64) receives, over all n points, sum_j idx and
+   sum_j idx^2 (mod 2^64) per dimension.  count <= 2^24. */
+qmc_status qmc_lattice_dump(qmc_plan_t plan, uint64_t j_lo, uint64_t count, uint32_t *idx_out,
+                            uint64_t *sums_out);
+
+/* Korobov generating vector g_i = a^i mod n, i = 0..d-1. */
+qmc_status qmc_korobov_vector(uint64_t n, uint32_t d, uint64_t a, uint64_t *g);
+
+/* P_2 criterion P2(g) = -1 + (1/n) sum_j prod_i (1 + 2 pi^2 B2({j g_i / n}))
+   for the Korobov vector of every candidate multiplier, evaluated on the GPU
+   as an unshifted lattice rule; returns the minimiser (ties: smaller P2, then
+   smaller a).  p2_all (nullable) receives all ncand values.  The generating
+   vector itself is not fixed by the paper (Sec. 2 only names it); this is
+   the standard worst-case-error choice.  n <= 2^31, d <= 32, ncand <= 4096. */
+qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint32_t ncand,
+                              uint64_t *a_best, double *p2_best, double *p2_all);
+
+/* Many independent estimates in one launch: plan p of `count` plans is
+   evaluated with family and params[p].  All plans must share the transform;
+   each plan keeps its own d, n, g, m and shifts.  The work is cut into tiles
+   ordered longest first and run by a persistent kernel; when use_graph is
+   set, the launch sequence is captured once into a HIP graph and replayed
+   on later calls with the same plans.  out receives count results.
+   Supported families: QMC_F_SECTOR (real) and the Genz families. */
+typedef struct {
+    int32_t use_graph;         /* capture/replay through a HIP graph */
+    int32_t per_plan_launches; /* 1 = one launch per plan instead (for comparison) */
+    uint32_t tile_points;      /* lattice points per tile (0 = default) */
+} qmc_batch_opts;
+
+qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_family family,
+                               const void *const *params, const qmc_batch_opts *opts,
+                               qmc_result *out);
+
+/* Pick a launch shape for (plan, family, params) by timing candidate shapes
+   on the device; the choice is stored in the plan and in the tuning cache
+   file named by the QMC_TUNE_CACHE environment variable (if set).  best
+   (nullable) receives the choice. */
+qmc_status qmc_autotune(qmc_plan_t plan, qmc_family family, const void *params, qmc_launch *best);
+
+/* Release a plan and its device memory (NULL is ignored). */
+void qmc_plan_destroy(qmc_plan_t plan);
+
+const char *qmc_status_string(qmc_status s);
+const char *qmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMC_H */

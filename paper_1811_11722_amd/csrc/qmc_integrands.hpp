@@ -1,0 +1,414 @@
+// Periodising transforms (arXiv:1811.11722 Sec. 2, eqs. (4)-(5)) and
+// integrand families, fused so that each thread evaluates
+// fhat(x) = f(z(x)) * prod_i z_i'(x_i) for T shifts of one lattice point.
+//
+// Parameter blobs are arrays of 8-byte words written by the host packer
+// (qmc_runtime.cpp).  They are read through uniform addresses, so the
+// compiler keeps them in scalar registers / the scalar cache.
+#pragma once
+
+#include "qmc_device.hpp"
+
+namespace qmc {
+
+// ------------------------------------------------------------ transforms
+// Identity: z = x.
+struct TrNone {
+    static constexpr bool kJac = false;
+    __device__ static double z(double x) { return x; }
+};
+
+// Baker's transform, eq. (5): z = 1 - |2x - 1|.  The map is 2-to-1 with
+// |z'| = 2 on each half, so the integrand weight is 1.
+struct TrBaker {
+    static constexpr bool kJac = false;
+    __device__ static double z(double x) { return 1.0 - __builtin_fabs(fma_(2.0, x, -1.0)); }
+};
+
+constexpr double cfact(int k) { return k <= 1 ? 1.0 : k * cfact(k - 1); }
+constexpr double cbinom(int n, int k) { return cfact(n) / (cfact(k) * cfact(n - k)); }
+constexpr double cpow4(int e) {  // 4^e for e <= 0
+    return e == 0 ? 1.0 : 0.25 * cpow4(e + 1);
+}
+
+// Korobov transform of weight A, eq. (4): w(x) = C_A x^A (1-x)^A with
+// C_A = (2A+1)!/(A!)^2, z(x) = int_0^x w.  With t = x - 1/2 the weight is
+// C_A (1/4 - t^2)^A and z = 1/2 + t * sum_j c_j t^(2j), where expanding the
+// binomial and integrating term by term gives
+// c_j = C_A binom(A, j) 4^(j-A) (-1)^j / (2j + 1).  This odd polynomial in t
+// has small coefficients, so it avoids the cancellation of the expanded form
+// in x near x = 1.  The constant C_A^d of prod_i w_i is applied once to
+// the final sums.
+template <int A>
+struct TrKorobov {
+    static_assert(A >= 1 && A <= 6, "Korobov weight 1..6");
+    static constexpr bool kJac = true;
+    static constexpr double kC = cfact(2 * A + 1) / (cfact(A) * cfact(A));
+    static constexpr double coef(int j) {
+        return kC * cbinom(A, j) * cpow4(j - A) * ((j & 1) ? -1.0 : 1.0) / (2 * j + 1);
+    }
+    // h(t^2) = sum_j c_j t^(2j), Horner from the top coefficient
+    __device__ static double h(double t2) {
+        double r = coef(A);
+#pragma unroll
+        for (int j = A - 1; j >= 0; --j) r = fma_(r, t2, coef(j));
+        return r;
+    }
+    // z and u = x (1 - x) = 1/4 - t^2
+    __device__ static double z(double x, double &u) {
+        const double t = x - 0.5;
+        const double t2 = t * t;
+        u = fma_(-t, t, 0.25);
+        return fma_(t, h(t2), 0.5);
+    }
+    // z - c, given hmc = 1/2 - c, and u
+    __device__ static double z_minus(double x, double hmc, double &u) {
+        const double t = x - 0.5;
+        const double t2 = t * t;
+        u = fma_(-t, t, 0.25);
+        return fma_(t, h(t2), hmc);
+    }
+    // prod_i w_i / C_A^d = (prod_i u_i)^A
+    __device__ static double jac(double pu) {
+        double r = pu;
+#pragma unroll
+        for (int a = 1; a < A; ++a) r *= pu;
+        return r;
+    }
+};
+
+// z for all D coordinates of T shifts, and the Jacobian (without C_A^d)
+template <class Tr, int D, int T>
+__device__ __forceinline__ void apply_transform(const double (&x)[T][D], double (&z)[T][D],
+                                                double (&jac)[T]) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        if constexpr (Tr::kJac) {
+            double pu = 1.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double u;
+                z[k][i] = Tr::z(x[k][i], u);
+                pu = (i == 0) ? u : pu * u;
+            }
+            jac[k] = Tr::jac(pu);
+        } else {
+#pragma unroll
+            for (int i = 0; i < D; ++i) z[k][i] = Tr::z(x[k][i]);
+            jac[k] = 1.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------ families
+// Every family provides NP (1 real, 2 complex) and
+//   eval<Tr, D, T>(p, x, v): v[k][.] = fhat(x[k]) / (transform constant).
+
+// constant c.  blob: [c]
+struct FamConst {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        const double c = p[0];
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+#pragma unroll
+        for (int k = 0; k < T; ++k) v[k][0] = Tr::kJac ? c * jac[k] : c;
+    }
+};
+
+// prod_i (1 + 2 pi^2 B2(z_i)), B2(z) = z^2 - z + 1/6, i.e. the quadratic
+// 2pi^2 z^2 - 2pi^2 z + (1 + pi^2/3) per coordinate.  No blob.
+struct FamP2 {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        constexpr double c2 = 2.0 * 9.869604401089358;  // 2 pi^2
+        constexpr double c0 = 1.0 + 9.869604401089358 / 3.0;
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            double prod = 1.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const double q = fma_(fma_(c2, z[k][i], -c2), z[k][i], c0);
+                prod = (i == 0) ? q : prod * q;
+            }
+            v[k][0] = Tr::kJac ? prod * jac[k] : prod;
+        }
+    }
+};
+
+// c0 + sum_t c_t cos(2 pi (h_t . z) + phi_t).
+// blob: [n_terms, c0, then per term: c_t, phi_t / (2 pi), h_t[0..D-1] as doubles]
+struct FamTrig {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+        const uint32_t nt = (uint32_t)__double_as_longlong(p[0]);
+        const double c0 = p[1];
+        double acc[T];
+#pragma unroll
+        for (int k = 0; k < T; ++k) acc[k] = c0;
+        const double *q = p + 2;
+        for (uint32_t t = 0; t < nt; ++t, q += 2 + D) {
+            const double c = q[0], ph = q[1];
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                double arg = ph;
+#pragma unroll
+                for (int i = 0; i < D; ++i) arg = fma_(q[2 + i], z[k][i], arg);
+                acc[k] = fma_(c, cospi(2.0 * fract(arg)), acc[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < T; ++k) v[k][0] = Tr::kJac ? acc[k] * jac[k] : acc[k];
+    }
+};
+
+// Genz product peak prod_i 1/(a_i^-2 + (z_i - u_i)^2).
+// blob: [a^-2 (D), u (D), 1/2 - u (D)]
+struct FamGenzProductPeak {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            double den = 1.0, pu = 1.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s;
+                if constexpr (Tr::kJac) {
+                    double u;
+                    s = Tr::z_minus(x[k][i], p[2 * D + i], u);
+                    pu = (i == 0) ? u : pu * u;
+                } else {
+                    s = Tr::z(x[k][i]) - p[D + i];
+                }
+                const double q = fma_(s, s, p[i]);
+                den = (i == 0) ? q : den * q;
+            }
+            if constexpr (Tr::kJac)
+                v[k][0] = Tr::jac(pu) * recip(den);
+            else
+                v[k][0] = recip(den);
+        }
+    }
+};
+
+// Genz oscillatory cos(2 pi u_1 + sum_i a_i z_i).  blob: [a (D), 2 pi u_1]
+struct FamGenzOscillatory {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            double s = p[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) s = fma_(p[i], z[k][i], s);
+            const double c = cos(s);
+            v[k][0] = Tr::kJac ? c * jac[k] : c;
+        }
+    }
+};
+
+// Genz Gaussian exp(-sum_i a_i^2 (z_i - u_i)^2).  blob: [a^2 (D), u (D)]
+struct FamGenzGaussian {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const double t = z[k][i] - p[D + i];
+                s = fma_(p[i] * t, t, s);
+            }
+            const double e = exp(-s);
+            v[k][0] = Tr::kJac ? e * jac[k] : e;
+        }
+    }
+};
+
+// Genz continuous exp(-sum_i a_i |z_i - u_i|).  blob: [a (D), u (D)]
+struct FamGenzContinuous {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) s = fma_(p[i], __builtin_fabs(z[k][i] - p[D + i]), s);
+            const double e = exp(-s);
+            v[k][0] = Tr::kJac ? e * jac[k] : e;
+        }
+    }
+};
+
+// Genz corner peak (1 + sum_i a_i z_i)^-(d+1).  blob: [a (D)]
+struct FamGenzCornerPeak {
+    static constexpr int NP = 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            double s = 1.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) s = fma_(p[i], z[k][i], s);
+            const double r = recip(s);
+            double q = r;
+#pragma unroll
+            for (int i = 0; i < D; ++i) q *= r;
+            v[k][0] = Tr::kJac ? q * jac[k] : q;
+        }
+    }
+};
+
+// ---------------------------------------------------- sparse polynomials
+// A monomial is coded as a 64-bit word: bits 0..3 hold the number of
+// factors c (<= 12), bits 4+5f..8+5f the variable of factor f; z_i^2 is two
+// factors of variable i.  The code and the coefficient are wave-uniform, so
+// the factor loop and the variable selection below become scalar branches;
+// only the multiplications run on the vector unit, once per shift.
+template <int D, int T>
+__device__ __forceinline__ void mul_var(double (&q)[T], const double (&z)[T][D], uint32_t v) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (v == (uint32_t)i) {
+#pragma unroll
+            for (int k = 0; k < T; ++k) q[k] *= z[k][i];
+        }
+    }
+}
+
+template <int D, int T>
+__device__ __forceinline__ void scale_var(double (&q)[T], double c, const double (&z)[T][D],
+                                          uint32_t v) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (v == (uint32_t)i) {
+#pragma unroll
+            for (int k = 0; k < T; ++k) q[k] = c * z[k][i];
+        }
+    }
+}
+
+// out[k] = sum_t coef[t] * prod_f z[k][var_f(t)]
+template <int D, int T>
+__device__ __forceinline__ void poly_eval(const double *__restrict__ coef,
+                                          const uint64_t *__restrict__ code, uint32_t nt,
+                                          const double (&z)[T][D], double (&out)[T]) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) out[k] = 0.0;
+    for (uint32_t t = 0; t < nt; ++t) {
+        uint64_t c = code[t];
+        const double cf = coef[t];
+        const uint32_t cnt = (uint32_t)(c & 15u);
+        if (cnt == 0) {
+#pragma unroll
+            for (int k = 0; k < T; ++k) out[k] += cf;
+            continue;
+        }
+        c >>= 4;
+        double q[T];
+        scale_var<D, T>(q, cf, z, (uint32_t)(c & 31u));
+        for (uint32_t f = 1; f < cnt; ++f) {
+            c >>= 5;
+            mul_var<D, T>(q, z, (uint32_t)(c & 31u));
+        }
+#pragma unroll
+        for (int k = 0; k < T; ++k) out[k] += q[k];
+    }
+}
+
+// out[k] = init[k] * prod_f z[k][var_f] for one coded monomial
+template <int D, int T>
+__device__ __forceinline__ void mono_eval(uint64_t c, const double (&init)[T],
+                                          const double (&z)[T][D], double (&out)[T]) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) out[k] = init[k];
+    const uint32_t cnt = (uint32_t)(c & 15u);
+    for (uint32_t f = 0; f < cnt; ++f) {
+        c >>= (f == 0) ? 4 : 5;
+        mul_var<D, T>(out, z, (uint32_t)(c & 31u));
+    }
+}
+
+// Sector integrand prod_i z_i^nu_i * U^pow_u * (F - i delta)^pow_f (eq. (6)
+// with the two Symanzik-type polynomials; -i delta as in eq. (7)).
+// blob: [n_u, n_f, flags, pow_u, pow_f, delta, nu_code,
+//        coef_u (n_u), code_u (n_u), coef_f (n_f), code_f (n_f)]
+// flags bit 0: complex, bit 1: pow_u == -2 (U^-2 by reciprocal).
+enum : uint32_t { kSectorComplex = 1u, kSectorPowUm2 = 2u };
+constexpr int kSectorHeader = 7;
+
+template <bool Complex>
+struct FamSector {
+    static constexpr int NP = Complex ? 2 : 1;
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],
+                                double (&v)[T][NP]) {
+        double z[T][D], jac[T];
+        apply_transform<Tr, D, T>(x, z, jac);
+        const uint32_t nu = (uint32_t)__double_as_longlong(p[0]);
+        const uint32_t nf = (uint32_t)__double_as_longlong(p[1]);
+        const uint32_t flags = (uint32_t)__double_as_longlong(p[2]);
+        const double pow_u = p[3], pow_f = p[4], delta = p[5];
+        const uint64_t *nucode = reinterpret_cast<const uint64_t *>(p + 6);
+        const double *cu = p + kSectorHeader;
+        const uint64_t *eu = reinterpret_cast<const uint64_t *>(cu + nu);
+        const double *cf = cu + 2 * nu;
+        const uint64_t *ef = reinterpret_cast<const uint64_t *>(cf + nf);
+        double U[T], F[T], mono[T];
+        poly_eval<D, T>(cu, eu, nu, z, U);
+        poly_eval<D, T>(cf, ef, nf, z, F);
+        mono_eval<D, T>(nucode[0], jac, z, mono);
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            double pre = mono[k];
+            double lu = 0.0;
+            if (flags & kSectorPowUm2) {
+                const double r = recip(U[k]);
+                pre = pre * (r * r);
+            } else {
+                lu = pow_u * log(U[k]);
+            }
+            if constexpr (!Complex) {
+                v[k][0] = pre * exp(fma_(pow_f, log(F[k]), lu));
+            } else {
+                // principal branch: log(F - i delta) = ln|.| + i atan2(-delta, F)
+                const double mod2 = fma_(F[k], F[k], delta * delta);
+                const double e = fma_(0.5 * pow_f, log(mod2), lu);
+                const double ph = pow_f * atan2(-delta, F[k]);
+                double s, c;
+                sincos(ph, &s, &c);
+                const double mag = pre * exp(e);
+                v[k][0] = mag * c;
+                v[k][1] = mag * s;
+            }
+        }
+    }
+};
+
+}  // namespace qmc

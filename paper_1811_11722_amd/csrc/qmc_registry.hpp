@@ -1,0 +1,50 @@
+// Registry of compiled lattice-kernel instantiations.
+//
+// Each (family, transform, dimension, shift tile) combination is a separate
+// template instantiation, compiled in its own translation unit; those units
+// register a launcher here when the library is loaded.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <tuple>
+
+#include "qmc_kernels.hpp"
+
+namespace qmc {
+
+// internal family codes: the public qmc_family values, plus the complex
+// sector integrand as its own code
+enum : int { kFamSectorComplex = 100 };
+
+struct KernelKey {
+    int family;  // qmc_family value or kFamSectorComplex
+    int tkind;   // 0 none, 1 Korobov, 2 baker
+    int alpha;   // Korobov weight (0 otherwise)
+    int d;
+    int T;
+    bool operator<(const KernelKey &o) const {
+        return std::tie(family, tkind, alpha, d, T) < std::tie(o.family, o.tkind, o.alpha, o.d, o.T);
+    }
+};
+
+using LatticeLaunch = hipError_t (*)(const LatticeArgs &, dim3 grid, hipStream_t);
+
+std::map<KernelKey, LatticeLaunch> &lattice_registry();
+
+struct LatticeRegistrar {
+    LatticeRegistrar(KernelKey k, LatticeLaunch f) { lattice_registry()[k] = f; }
+};
+
+template <class Fam, class Tr, int D, int T>
+hipError_t launch_lattice(const LatticeArgs &a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_lattice<Fam, Tr, D, T>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// launchers of the non-templated helper kernels (qmc_common.hip)
+hipError_t launch_finalize(const FinalizeArgs &a, uint32_t ninst, hipStream_t s);
+hipError_t launch_dump(const DumpArgs &a, uint32_t blocks, hipStream_t s);
+
+}  // namespace qmc

@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libqmc.so (declarations in include/qmc.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library.  Importing this module loads the library and raises if it has not
+been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqmc.so")
+
+# status codes
+QMC_OK, QMC_EINVAL, QMC_EUNSUPPORTED, QMC_ENOMEM, QMC_EDEVICE, QMC_ENONFINITE = range(6)
+# transforms
+QMC_T_NONE, QMC_T_KOROBOV, QMC_T_BAKER = 0, 1, 2
+QMC_T_TENT = QMC_T_BAKER
+# families
+(QMC_F_CONST, QMC_F_TRIG, QMC_F_P2KERNEL, QMC_F_GENZ_PRODUCT_PEAK, QMC_F_GENZ_OSCILLATORY,
+ QMC_F_GENZ_GAUSSIAN, QMC_F_GENZ_CONTINUOUS, QMC_F_GENZ_CORNER_PEAK, QMC_F_SECTOR) = range(9)
+
+FAMILY = {
+    "const": QMC_F_CONST, "trig": QMC_F_TRIG, "p2kernel": QMC_F_P2KERNEL,
+    "genz_product_peak": QMC_F_GENZ_PRODUCT_PEAK, "genz_oscillatory": QMC_F_GENZ_OSCILLATORY,
+    "genz_gaussian": QMC_F_GENZ_GAUSSIAN, "genz_continuous": QMC_F_GENZ_CONTINUOUS,
+    "genz_corner_peak": QMC_F_GENZ_CORNER_PEAK, "sector": QMC_F_SECTOR,
+}
+TRANSFORM = {"none": QMC_T_NONE, "korobov": QMC_T_KOROBOV, "baker": QMC_T_BAKER,
+             "tent": QMC_T_TENT}
+
+
+class qmc_transform(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("alpha", C.c_int32)]
+
+
+class qmc_const_params(C.Structure):
+    _fields_ = [("c", C.c_double)]
+
+
+class qmc_trig_params(C.Structure):
+    _fields_ = [("n_terms", C.c_uint32), ("c0", C.c_double), ("h", C.c_void_p),
+                ("c", C.c_void_p), ("phi", C.c_void_p)]
+
+
+class qmc_genz_params(C.Structure):
+    _fields_ = [("a", C.c_void_p), ("u", C.c_void_p)]
+
+
+class qmc_sector_params(C.Structure):
+    _fields_ = [("n_u", C.c_uint32), ("n_f", C.c_uint32), ("coef_u", C.c_void_p),
+                ("exp_u", C.c_void_p), ("coef_f", C.c_void_p), ("exp_f", C.c_void_p),
+                ("nu", C.c_void_p), ("pow_u", C.c_double), ("pow_f", C.c_double),
+                ("delta_im", C.c_double), ("is_complex", C.c_int32)]
+
+
+class qmc_result(C.Structure):
+    _fields_ = [("mean_re", C.c_double), ("mean_im", C.c_double), ("err_re", C.c_double),
+                ("err_im", C.c_double), ("is_complex", C.c_int32), ("used_cv", C.c_int32)]
+
+
+class qmc_launch(C.Structure):
+    _fields_ = [("shift_tile", C.c_uint32), ("blocks_per_cu", C.c_uint32)]
+
+
+class qmc_batch_opts(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("per_plan_launches", C.c_int32),
+                ("tile_points", C.c_uint32)]
+
+
+# every symbol include/qmc.h declares, with its ctypes signature
+_vp, _u32, _u64, _i32, _dbl = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_double
+SIGNATURES = {
+    "qmc_plan_create": (C.c_int, [_u32, _u64, _vp, _u32, _vp, qmc_transform, _vp]),
+    "qmc_plan_set_stream": (C.c_int, [_vp, _vp]),
+    "qmc_plan_set_launch": (C.c_int, [_vp, _vp]),
+    "qmc_integrate": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "qmc_plan_set_timing": (C.c_int, [_vp, _i32]),
+    "qmc_plan_kernel_time": (C.c_int, [_vp, _vp, _vp, _i32]),
+    "qmc_lattice_dump": (C.c_int, [_vp, _u64, _u64, _vp, _vp]),
+    "qmc_korobov_vector": (C.c_int, [_u64, _u32, _u64, _vp]),
+    "qmc_korobov_search": (C.c_int, [_u64, _u32, _vp, _u32, _vp, _vp, _vp]),
+    "qmc_integrate_batch": (C.c_int, [_u32, _vp, C.c_int, _vp, _vp, _vp]),
+    "qmc_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "qmc_plan_destroy": (None, [_vp]),
+    "qmc_status_string": (C.c_char_p, [C.c_int]),
+    "qmc_last_error": (C.c_char_p, []),
+}
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1811_11722_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class QMCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().qmc_last_error().decode(errors="replace")
+        name = lib().qmc_status_string(status).decode()
+        super().__init__(f"{where}: {name} ({status}): {msg}")
+
+
+def check(status: int, where: str):
+    if status != QMC_OK:
+        raise QMCError(status, where)
+
+
+def _arr(x, dt):
+    return np.ascontiguousarray(np.asarray(x, dtype=dt))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Params:
+    """Family parameter struct plus the arrays it points into."""
+
+    def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
+                 sector=None):
+        self.family = FAMILY[family]
+        self.keep = []
+
+        def keep(x, dt):
+            v = _arr(x, dt)
+            self.keep.append(v)
+            return v
+
+        if self.family == QMC_F_CONST:
+            self.struct = qmc_const_params(float(c))
+        elif self.family == QMC_F_TRIG:
+            c0, h, ch, phi = trig
+            h = keep(h, np.int64).reshape(-1, d)
+            self.struct = qmc_trig_params(h.shape[0], float(c0), _p(h), _p(keep(ch, np.float64)),
+                                          _p(keep(phi, np.float64)))
+        elif self.family == QMC_F_P2KERNEL:
+            self.struct = None
+        elif self.family == QMC_F_SECTOR:
+            s = sector
+            self.struct = qmc_sector_params(
+                s.n_u, s.n_f, _p(keep(s.coef_u, np.float64)), _p(keep(s.exp_u, np.uint8)),
+                _p(keep(s.coef_f, np.float64)), _p(keep(s.exp_f, np.uint8)),
+                _p(keep(s.nu, np.uint8)), float(s.pow_u), float(s.pow_f), float(s.delta_im),
+                int(bool(s.is_complex)))
+        else:
+            self.struct = qmc_genz_params(_p(keep(a, np.float64)), _p(keep(u, np.float64)))
+
+    @property
+    def ptr(self):
+        return None if self.struct is None else C.cast(C.pointer(self.struct), C.c_void_p)
+
+    @property
+    def is_complex(self) -> bool:
+        return self.family == QMC_F_SECTOR and bool(self.struct.is_complex)
+
+
+class Plan:
+    """Owner of a qmc_plan_t."""
+
+    def __init__(self, d: int, n: int, g: Sequence[int], shifts, transform: str = "none",
+                 alpha: int = 0):
+        g = _arr(g, np.uint64)
+        sh = _arr(shifts, np.float64)
+        self.d, self.n, self.m = int(d), int(n), int(sh.shape[0])
+        self.handle = C.c_void_p()
+        check(lib().qmc_plan_create(self.d, self.n, _p(g), self.m, _p(sh),
+                                    qmc_transform(TRANSFORM[transform], alpha),
+                                    C.byref(self.handle)), "qmc_plan_create")
+
+    def close(self):
+        if self.handle:
+            lib().qmc_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_handle: int):
+        check(lib().qmc_plan_set_stream(self.handle, C.c_void_p(stream_handle)), "set_stream")
+
+    def set_launch(self, shift_tile: int = 0, blocks_per_cu: int = 0):
+        cfg = qmc_launch(shift_tile, blocks_per_cu)
+        check(lib().qmc_plan_set_launch(self.handle, C.byref(cfg)), "set_launch")
+
+    def set_timing(self, on: bool = True):
+        check(lib().qmc_plan_set_timing(self.handle, int(on)), "set_timing")
+
+    def kernel_time(self, reset: bool = False):
+        ms, cnt = C.c_double(), C.c_uint64()
+        check(lib().qmc_plan_kernel_time(self.handle, C.byref(ms), C.byref(cnt), int(reset)),
+              "kernel_time")
+        return ms.value, cnt.value
+
+    def integrate(self, params: Params):
+        """Returns (qmc_result, per-shift array: real (m,) or complex (m,))."""
+        res = qmc_result()
+        per = np.zeros(2 * self.m)
+        check(lib().qmc_integrate(self.handle, params.family, params.ptr, C.byref(res), _p(per)),
+              "qmc_integrate")
+        if res.is_complex:
+            return res, per[0::2] + 1j * per[1::2]
+        return res, per[: self.m].copy()
+
+    def integrate_status(self, params: Params):
+        """Like integrate but returns (status, result, per_shift) without raising."""
+        res = qmc_result()
+        per = np.zeros(2 * self.m)
+        st = lib().qmc_integrate(self.handle, params.family, params.ptr, C.byref(res), _p(per))
+        return st, res, per
+
+    def lattice_dump(self, j_lo: int, count: int):
+        idx = np.zeros((count, self.d), dtype=np.uint32)
+        sums = np.zeros(2 * self.d, dtype=np.uint64)
+        check(lib().qmc_lattice_dump(self.handle, j_lo, count, _p(idx), _p(sums)), "lattice_dump")
+        return idx, sums.reshape(self.d, 2)
+
+    def autotune(self, params: Params):
+        best = qmc_launch()
+        check(lib().qmc_autotune(self.handle, params.family, params.ptr, C.byref(best)),
+              "qmc_autotune")
+        return best.shift_tile, best.blocks_per_cu
+
+
+def korobov_vector(n: int, d: int, a: int) -> np.ndarray:
+    g = np.zeros(d, dtype=np.uint64)
+    check(lib().qmc_korobov_vector(n, d, a, _p(g)), "qmc_korobov_vector")
+    return g
+
+
+def korobov_search(n: int, d: int, cand):
+    cand = _arr(cand, np.uint64)
+    a = C.c_uint64()
+    p2 = C.c_double()
+    allp = np.zeros(cand.size)
+    check(lib().qmc_korobov_search(n, d, _p(cand), cand.size, C.byref(a), C.byref(p2), _p(allp)),
+          "qmc_korobov_search")
+    return int(a.value), float(p2.value), allp
+
+
+def integrate_batch(plans: Sequence[Plan], params: Sequence[Params], use_graph: bool = True,
+                    per_plan_launches: bool = False, tile_points: int = 0):
+    fam = params[0].family
+    handles = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+    pp = (C.c_void_p * len(params))(*[p.ptr for p in params])
+    opts = qmc_batch_opts(int(use_graph), int(per_plan_launches), tile_points)
+    out = (qmc_result * len(plans))()
+    check(lib().qmc_integrate_batch(len(plans), handles, fam, pp, C.byref(opts), out),
+          "qmc_integrate_batch")
+    return list(out)

