@@ -143,6 +143,19 @@ qmc_status qmc_plan_set_stream(qmc_plan_t plan, void *hip_stream);
 /* Fix the launch shape for later calls (zero fields restore the default). */
 qmc_status qmc_plan_set_launch(qmc_plan_t plan, const qmc_launch *cfg);
 
+/* How sector integrands are evaluated: 0 = interpret the sparse polynomial
+   tables in the kernel; 1 (default) = compile a kernel specialised to the
+   exponent structure on first use (hipRTC; about a second, cached per
+   structure for the process) and fall back to the tables if compilation
+   fails; 2 = always specialise and return EUNSUPPORTED if that fails.
+   Results agree to rounding either way. */
+qmc_status qmc_plan_set_jit(qmc_plan_t plan, int32_t mode);
+
+/* Launch shape of the plan's last estimate: shift_tile = tile used,
+   blocks_per_cu = workgroups per shift tile along the lattice points;
+   used_jit (nullable) = 1 if it ran a specialised sector kernel. */
+qmc_status qmc_plan_get_launch(qmc_plan_t plan, qmc_launch *cfg, int32_t *used_jit);
+
 /* Evaluate eqs. (2)-(3) for the integrand (family, params).
    params     the family's parameter struct (NULL for QMC_F_P2KERNEL)
    out        mean and error
@@ -201,6 +214,11 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
    file named by the QMC_TUNE_CACHE environment variable (if set).  best
    (nullable) receives the choice. */
 qmc_status qmc_autotune(qmc_plan_t plan, qmc_family family, const void *params, qmc_launch *best);
+
+/* The library's device FP64 logarithm (fn = 0, argument > 0) or exponential
+   (fn = 1) on count host values x, results in y; for checking the device
+   math the sector integrand uses against a host reference. */
+qmc_status qmc_math_eval(int32_t fn, uint64_t count, const double *x, double *y);
 
 /* Release a plan and its device memory (NULL is ignored). */
 void qmc_plan_destroy(qmc_plan_t plan);

@@ -284,10 +284,21 @@ qmc_status plan_set_gstep(qmc_plan_s *p, uint32_t S) {
 // Enqueue the lattice kernel and the finalize kernel of one estimate.
 qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32_t bpc) {
     uint32_t T = 0;
-    LatticeLaunch fn = find_kernel(pk.key_family, p->tr, p->d, want_T ? want_T : default_tile(pk.key_family), T);
-    if (!fn)
-        return fail(QMC_EUNSUPPORTED, "no kernel for family %d, transform %d/%d, d = %u", pk.key_family,
-                    p->tr.kind, p->tr.alpha, p->d);
+    LatticeLaunch fn = nullptr;
+    hipFunction_t jfn = nullptr;
+    const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
+    if (sector && p->jit_mode != 0) {
+        T = want_T ? want_T : (pk.np == 2 ? 1u : 2u);
+        std::string err;
+        jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.np == 2, p->device, err);
+        if (!jfn && p->jit_mode == 2) return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
+    }
+    if (!jfn) {
+        fn = find_kernel(pk.key_family, p->tr, p->d, want_T ? want_T : default_tile(pk.key_family), T);
+        if (!fn)
+            return fail(QMC_EUNSUPPORTED, "no kernel for family %d, transform %d/%d, d = %u", pk.key_family,
+                        p->tr.kind, p->tr.alpha, p->d);
+    }
     if (p->m * pk.np > kMaxRows) return fail(QMC_EUNSUPPORTED, "m * parts > %u", kMaxRows);
     qmc_status st = plan_upload_params(p, pk);
     if (st) return st;
@@ -311,7 +322,7 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     a.np = pk.np;
     a.partials = p->d_partials;
     if (p->timing) hipEventRecord(p->ev0, p->stream);
-    hipError_t e = fn(a, dim3(bx, tiles), p->stream);
+    hipError_t e = jfn ? jit_launch(jfn, a, dim3(bx, tiles), p->stream) : fn(a, dim3(bx, tiles), p->stream);
     if (e != hipSuccess) return hip_fail(e, "launch lattice kernel");
     if (p->timing) hipEventRecord(p->ev1, p->stream);
 
@@ -329,6 +340,7 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     if (e != hipSuccess) return hip_fail(e, "launch finalize kernel");
     p->last_T = T;
     p->last_bx = bx;
+    p->last_jit = jfn != nullptr;
     return QMC_OK;
 }
 
@@ -481,6 +493,21 @@ qmc_status qmc_plan_set_launch(qmc_plan_t p, const qmc_launch *cfg) {
     return QMC_OK;
 }
 
+qmc_status qmc_plan_set_jit(qmc_plan_t p, int32_t mode) {
+    if (!p) return fail(QMC_EINVAL, "plan is NULL");
+    if (mode < 0 || mode > 2) return fail(QMC_EINVAL, "jit mode must be 0, 1 or 2");
+    p->jit_mode = mode;
+    return QMC_OK;
+}
+
+qmc_status qmc_plan_get_launch(qmc_plan_t p, qmc_launch *cfg, int32_t *used_jit) {
+    if (!p || !cfg) return fail(QMC_EINVAL, "null argument");
+    cfg->shift_tile = p->last_T;
+    cfg->blocks_per_cu = p->last_bx;
+    if (used_jit) *used_jit = p->last_jit ? 1 : 0;
+    return QMC_OK;
+}
+
 qmc_status qmc_plan_set_timing(qmc_plan_t p, int32_t enable) {
     if (!p) return fail(QMC_EINVAL, "plan is NULL");
     p->timing = enable != 0;
@@ -507,6 +534,21 @@ qmc_status qmc_integrate(qmc_plan_t p, qmc_family family, const void *params, qm
     if (st) return st;
     if ((st = plan_enqueue(p, pk, p->launch.shift_tile, p->launch.blocks_per_cu))) return st;
     return plan_collect(p, pk.np, out, per_shift);
+}
+
+qmc_status qmc_math_eval(int32_t fn, uint64_t count, const double *x, double *y) {
+    if (fn != 0 && fn != 1) return fail(QMC_EINVAL, "fn must be 0 (log) or 1 (exp)");
+    if (count && (!x || !y)) return fail(QMC_EINVAL, "null array");
+    if (count > (1ull << 28)) return fail(QMC_EINVAL, "count > 2^28");
+    if (count == 0) return QMC_OK;
+    DeviceScratch s;
+    qmc_status st;
+    if ((st = s.alloc(count * 8)) || (st = s.alloc(count * 8))) return st;
+    hipError_t e = hipMemcpy(s.ptr[0], x, count * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_math(fn, count, (const double *)s.ptr[0], (double *)s.ptr[1], nullptr);
+    if (e == hipSuccess) e = hipMemcpy(y, s.ptr[1], count * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "math eval");
+    return QMC_OK;
 }
 
 qmc_status qmc_korobov_vector(uint64_t n, uint32_t d, uint64_t a, uint64_t *g) {

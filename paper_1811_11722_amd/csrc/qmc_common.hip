@@ -84,6 +84,18 @@ std::map<KernelKey, LatticeLaunch> &lattice_registry() {
     return reg;
 }
 
+// device math on an array: fn 0 = qlog, 1 = qexp
+__global__ __launch_bounds__(kBlock) void k_math(int fn, uint64_t count, const double *x, double *y) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) y[i] = fn == 0 ? qlog(x[i]) : qexp(x[i]);
+}
+
+hipError_t launch_math(int fn, uint64_t count, const double *x, double *y, hipStream_t s) {
+    const uint64_t blocks = (count + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_math, dim3((uint32_t)blocks), dim3(kBlock), 0, s, fn, count, x, y);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t ninst, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(ninst), dim3(kBlock), 0, s, a);
     return hipGetLastError();

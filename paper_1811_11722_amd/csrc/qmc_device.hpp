@@ -5,8 +5,16 @@
 // below is written explicitly, so the rounding of each step is the one shown.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else  // compiled at run time by hipRTC (specialised sector kernels)
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+using __hip_internal::uint8_t;
+#endif
 
 namespace qmc {
 
@@ -57,6 +65,70 @@ __device__ __forceinline__ double divide(double a, double b) {
     const double q = a * r;
     const double res = fma_(-b, q, a);
     return fma_(res, r, q);
+}
+
+// ------------------------------------------------- FP64 exp and log
+// gfx950 has no FP64 exponential or logarithm instruction.  These two are
+// written for the sector integrand's U^a F^b = exp(a ln U + b ln F): finite
+// arguments, no errno or special-case branches.
+
+// exp(x), Cody & Waite argument reduction: k = rint(x / ln 2),
+// r = x - k ln2_hi - k ln2_lo with ln2_hi holding 32 significant bits (so
+// k * ln2_hi is exact for |k| < 2^21) and |r| <= ln2 / 2; exp(r) by its
+// Taylor series to degree 13 (truncation < 5e-18 relative), scaled by 2^k
+// with v_ldexp (overflow gives inf, underflow 0).
+__device__ __forceinline__ double qexp(double x) {
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;  // 0x3FE62E42FEE00000
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
+    const double k = __builtin_rint(x * kLog2e);
+    double r = fma_(-k, kLn2Hi, x);
+    r = fma_(-k, kLn2Lo, r);
+    // 1/i! for i = 13 .. 1, Horner from the top
+    double p = 1.0 / 6227020800.0;  // 1/13!
+    p = fma_(p, r, 1.0 / 479001600.0);
+    p = fma_(p, r, 1.0 / 39916800.0);
+    p = fma_(p, r, 1.0 / 3628800.0);
+    p = fma_(p, r, 1.0 / 362880.0);
+    p = fma_(p, r, 1.0 / 40320.0);
+    p = fma_(p, r, 1.0 / 5040.0);
+    p = fma_(p, r, 1.0 / 720.0);
+    p = fma_(p, r, 1.0 / 120.0);
+    p = fma_(p, r, 1.0 / 24.0);
+    p = fma_(p, r, 1.0 / 6.0);
+    p = fma_(p, r, 0.5);
+    p = fma_(p, r, 1.0);
+    p = fma_(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
+// ln(x) for x > 0 (NaN for x <= 0 or NaN).  x = m 2^e with m in [1/2, 1);
+// with y = m sqrt(2) in [0.707, 1.414), ln x = (e - 1/2) ln 2 + ln y and
+// ln y = 2 atanh(s) = 2 sum_k s^(2k+1) / (2k+1), s = (y - 1)/(y + 1),
+// |s| <= 0.1716; eleven terms leave a truncation below 1e-18 relative.  The
+// absolute error is a few 1e-16, which is what exp(a ln x) needs.
+__device__ __forceinline__ double qlog(double x) {
+    constexpr double kSqrt2 = 1.4142135623730951;
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const double e = (double)__builtin_amdgcn_frexp_exp(x) - 0.5;
+    const double y = m * kSqrt2;
+    const double s = (y - 1.0) * recip(y + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+    p = fma_(p, s2, 1.0 / 19.0);
+    p = fma_(p, s2, 1.0 / 17.0);
+    p = fma_(p, s2, 1.0 / 15.0);
+    p = fma_(p, s2, 1.0 / 13.0);
+    p = fma_(p, s2, 1.0 / 11.0);
+    p = fma_(p, s2, 1.0 / 9.0);
+    p = fma_(p, s2, 1.0 / 7.0);
+    p = fma_(p, s2, 1.0 / 5.0);
+    p = fma_(p, s2, 1.0 / 3.0);
+    const double ly = 2.0 * s * fma_(p, s2, 1.0);
+    const double r = fma_(e, kLn2Hi, fma_(e, kLn2Lo, ly));
+    return x > 0.0 ? r : __builtin_nan("");
 }
 
 // Knuth's TwoSum: s + e == a + b exactly.

@@ -238,7 +238,7 @@ struct FamGenzGaussian {
                 const double t = z[k][i] - p[D + i];
                 s = fma_(p[i] * t, t, s);
             }
-            const double e = exp(-s);
+            const double e = qexp(-s);
             v[k][0] = Tr::kJac ? e * jac[k] : e;
         }
     }
@@ -257,7 +257,7 @@ struct FamGenzContinuous {
             double s = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) s = fma_(p[i], __builtin_fabs(z[k][i] - p[D + i]), s);
-            const double e = exp(-s);
+            const double e = qexp(-s);
             v[k][0] = Tr::kJac ? e * jac[k] : e;
         }
     }
@@ -363,6 +363,35 @@ __device__ __forceinline__ void mono_eval(uint64_t c, const double (&init)[T],
 enum : uint32_t { kSectorComplex = 1u, kSectorPowUm2 = 2u };
 constexpr int kSectorHeader = 7;
 
+// fhat from the polynomial values: mono = jac * prod z^nu, then
+// mono * U^pow_u * (F - i delta)^pow_f with the principal branch.
+template <bool Complex>
+__device__ __forceinline__ void sector_finish(double mono, double U, double F, uint32_t flags,
+                                              double pow_u, double pow_f, double delta,
+                                              double (&v)[Complex ? 2 : 1]) {
+    double pre = mono;
+    double lu = 0.0;
+    if (flags & kSectorPowUm2) {
+        const double r = recip(U);
+        pre = pre * (r * r);
+    } else {
+        lu = pow_u * qlog(U);
+    }
+    if constexpr (!Complex) {
+        v[0] = pre * qexp(fma_(pow_f, qlog(F), lu));
+    } else {
+        // log(F - i delta) = ln|F - i delta| + i atan2(-delta, F)
+        const double mod2 = fma_(F, F, delta * delta);
+        const double e = fma_(0.5 * pow_f, qlog(mod2), lu);
+        const double ph = pow_f * atan2(-delta, F);
+        double s, c;
+        sincos(ph, &s, &c);
+        const double mag = pre * qexp(e);
+        v[0] = mag * c;
+        v[1] = mag * s;
+    }
+}
+
 template <bool Complex>
 struct FamSector {
     static constexpr int NP = Complex ? 2 : 1;
@@ -385,29 +414,7 @@ struct FamSector {
         poly_eval<D, T>(cf, ef, nf, z, F);
         mono_eval<D, T>(nucode[0], jac, z, mono);
 #pragma unroll
-        for (int k = 0; k < T; ++k) {
-            double pre = mono[k];
-            double lu = 0.0;
-            if (flags & kSectorPowUm2) {
-                const double r = recip(U[k]);
-                pre = pre * (r * r);
-            } else {
-                lu = pow_u * log(U[k]);
-            }
-            if constexpr (!Complex) {
-                v[k][0] = pre * exp(fma_(pow_f, log(F[k]), lu));
-            } else {
-                // principal branch: log(F - i delta) = ln|.| + i atan2(-delta, F)
-                const double mod2 = fma_(F[k], F[k], delta * delta);
-                const double e = fma_(0.5 * pow_f, log(mod2), lu);
-                const double ph = pow_f * atan2(-delta, F[k]);
-                double s, c;
-                sincos(ph, &s, &c);
-                const double mag = pre * exp(e);
-                v[k][0] = mag * c;
-                v[k][1] = mag * s;
-            }
-        }
+        for (int k = 0; k < T; ++k) sector_finish<Complex>(mono[k], U[k], F[k], flags, pow_u, pow_f, delta, v[k]);
     }
 };
 

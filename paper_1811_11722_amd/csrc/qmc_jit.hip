@@ -1,0 +1,227 @@
+// Run-time specialisation of the sector integrand (hipRTC).
+//
+// The table-driven sector functor reads each monomial's factor list from
+// wave-uniform memory and dispatches on it with scalar branches; on gfx950
+// that dispatch costs more scalar-unit issue than the FP64 work it selects.
+// For a single large sector the exponent structure is fixed for the whole
+// estimate, so this module writes it out as straight-line FP64 code and
+// compiles it once per structure: the monomials of U, F and z^nu become a
+// shared-prefix product trie (each trie edge one multiply, each monomial one
+// fused multiply-add with its coefficient), followed by the same tail as the
+// table-driven functor.  Coefficients and powers are still read from the
+// parameter blob, so one compiled kernel serves every coefficient set with
+// the same exponents.  The kernel body is the same k_lattice template,
+// compiled from the same headers (embedded into the library at build time).
+#include <hip/hiprtc.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+
+#include "qmc_jit_headers.inc"
+#include "qmc_runtime.hpp"
+
+namespace qmc {
+
+namespace {
+
+struct JitEntry {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    std::string error;  // non-empty when compilation failed
+};
+
+std::mutex g_jit_mu;
+std::map<std::string, JitEntry> g_jit_cache;
+
+uint64_t word(const std::vector<double> &b, size_t i) {
+    uint64_t v;
+    std::memcpy(&v, &b[i], sizeof v);
+    return v;
+}
+
+std::vector<int> factors_of(uint64_t code) {
+    std::vector<int> f;
+    const uint32_t cnt = (uint32_t)(code & 15u);
+    for (uint32_t k = 0; k < cnt; ++k) f.push_back((int)((code >> (4 + 5 * k)) & 31u));
+    return f;
+}
+
+// product trie over sorted factor lists
+struct Trie {
+    std::vector<std::pair<int, int>> node;  // (parent, variable); parent -1 = root
+    std::map<std::pair<int, int>, int> index;
+    int insert(const std::vector<int> &f) {
+        int cur = -1;
+        for (int v : f) {
+            auto key = std::make_pair(cur, v);
+            auto it = index.find(key);
+            if (it == index.end()) {
+                node.push_back(key);
+                it = index.emplace(key, (int)node.size() - 1).first;
+            }
+            cur = it->second;
+        }
+        return cur;  // -1 for the empty product
+    }
+};
+
+const char *transform_type(const qmc_transform &t) {
+    static const char *kor[] = {"", "TrKorobov<1>", "TrKorobov<2>", "TrKorobov<3>",
+                                "TrKorobov<4>", "TrKorobov<5>", "TrKorobov<6>"};
+    if (t.kind == QMC_T_KOROBOV) return kor[t.alpha];
+    return t.kind == QMC_T_BAKER ? "TrBaker" : "TrNone";
+}
+
+}  // namespace
+
+// Source of the specialised functor + the kernel instantiation; `structure`
+// receives a canonical description of what the code depends on.
+static std::string jit_source(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr,
+                              uint32_t T, bool cplx, std::string &name_expr, std::string &structure) {
+    const uint32_t nu = (uint32_t)word(blob, 0), nf = (uint32_t)word(blob, 1);
+    Trie trie;
+    std::vector<int> mu(nu), mf(nf);
+    std::ostringstream st;
+    st << "d" << d << "T" << T << "c" << cplx << "t" << tr.kind << "a" << tr.alpha << "|";
+    for (uint32_t t = 0; t < nu; ++t) {
+        const uint64_t c = word(blob, kSectorHeader + nu + t);
+        mu[t] = trie.insert(factors_of(c));
+        st << c << ",";
+    }
+    st << "|";
+    for (uint32_t t = 0; t < nf; ++t) {
+        const uint64_t c = word(blob, kSectorHeader + 2 * nu + nf + t);
+        mf[t] = trie.insert(factors_of(c));
+        st << c << ",";
+    }
+    const uint64_t nuc = word(blob, 6);
+    const int mnu = trie.insert(factors_of(nuc));
+    st << "|" << nuc;
+    structure = st.str();
+
+    std::ostringstream s;
+    s << "#include \"qmc_kernels.hpp\"\nnamespace qmc {\nstruct FamJit {\n"
+      << "    static constexpr int NP = " << (cplx ? 2 : 1) << ";\n"
+      << "    template <class Tr, int D, int T>\n"
+      << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
+         " double (&v)[T][NP]) {\n"
+      << "        double z[T][D], jac[T];\n"
+      << "        apply_transform<Tr, D, T>(x, z, jac);\n"
+      << "        const uint32_t flags = (uint32_t)__double_as_longlong(p[2]);\n"
+      << "        const double pow_u = p[3], pow_f = p[4], delta = p[5];\n"
+      << "        const double *cu = p + kSectorHeader;\n"
+      << "        asm volatile(\"\" : \"+s\"(cu));  // keep coefficient loads in the point loop\n"
+      << "        const double *cf = cu + " << 2 * nu << ";\n"
+      << "#pragma unroll\n"
+      << "        for (int k = 0; k < T; ++k) {\n";
+    auto ref = [&](int id) {
+        std::ostringstream r;
+        if (trie.node[id].first < 0) r << "z[k][" << trie.node[id].second << "]";
+        else r << "m" << id;
+        return r.str();
+    };
+    for (size_t id = 0; id < trie.node.size(); ++id) {
+        const auto &nd = trie.node[id];
+        if (nd.first < 0) continue;
+        s << "            const double m" << id << " = " << ref(nd.first) << " * z[k][" << nd.second << "];\n";
+    }
+    auto poly = [&](const char *name, const char *coef, const std::vector<int> &mono) {
+        for (size_t t = 0; t < mono.size(); ++t) {
+            s << "            ";
+            if (t == 0) s << "double " << name << " = ";
+            else s << name << " = ";
+            if (mono[t] < 0) s << (t == 0 ? "" : std::string(name) + " + ") << coef << "[" << t << "];\n";
+            else if (t == 0) s << coef << "[" << t << "] * " << ref(mono[t]) << ";\n";
+            else s << "fma_(" << coef << "[" << t << "], " << ref(mono[t]) << ", " << name << ");\n";
+        }
+    };
+    poly("U", "cu", mu);
+    poly("F", "cf", mf);
+    s << "            const double mono = " << (mnu < 0 ? std::string("jac[k]") : "jac[k] * " + ref(mnu))
+      << ";\n"
+      << "            sector_finish<" << (cplx ? "true" : "false")
+      << ">(mono, U, F, flags, pow_u, pow_f, delta, v[k]);\n"
+      << "        }\n    }\n};\n";
+    std::ostringstream ne;
+    ne << "qmc::k_lattice<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ", " << T << ">";
+    name_expr = ne.str();
+    s << "template __global__ void k_lattice<FamJit, " << transform_type(tr) << ", " << d << ", " << T
+      << ">(const LatticeArgs);\n}  // namespace qmc\n";
+    return s.str();
+}
+
+static std::string device_arch(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "gfx950";
+    std::string a = prop.gcnArchName;
+    return a.empty() ? std::string("gfx950") : a;
+}
+
+// Compile (or fetch) the specialised kernel for this blob; returns nullptr
+// and sets `err` when compilation fails.
+hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
+                         bool cplx, int dev, std::string &err) {
+    std::string name_expr, structure;
+    const std::string src = jit_source(blob, d, tr, T, cplx, name_expr, structure);
+    const std::string key = std::to_string(dev) + "#" + structure;
+    if (const char *dump = std::getenv("QMC_JIT_DUMP")) {  // write the generated source for inspection
+        std::ofstream(std::string(dump) + "/" + std::to_string(std::hash<std::string>()(structure)) + ".hip") << src;
+    }
+    std::lock_guard<std::mutex> lock(g_jit_mu);
+    auto it = g_jit_cache.find(key);
+    if (it != g_jit_cache.end()) {
+        err = it->second.error;
+        return it->second.fn;
+    }
+    JitEntry e;
+    hiprtcProgram prog = nullptr;
+    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "qmc_sector_jit.hip", kJitHeaderCount, kJitHeaderText,
+                                         kJitHeaderName);
+    if (r == HIPRTC_SUCCESS) r = hiprtcAddNameExpression(prog, name_expr.c_str());
+    const std::string arch = "--offload-arch=" + device_arch(dev);
+    const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops"};
+    if (r == HIPRTC_SUCCESS) r = hiprtcCompileProgram(prog, 8, opts);
+    if (r != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        std::string log;
+        if (prog && hiprtcGetProgramLogSize(prog, &ls) == HIPRTC_SUCCESS && ls > 1) {
+            log.resize(ls);
+            hiprtcGetProgramLog(prog, &log[0]);
+        }
+        e.error = std::string("hipRTC: ") + hiprtcGetErrorString(r) + ": " + log.substr(0, 2000);
+    } else {
+        const char *lowered = nullptr;
+        size_t cs = 0;
+        std::vector<char> code;
+        if (hiprtcGetLoweredName(prog, name_expr.c_str(), &lowered) != HIPRTC_SUCCESS || !lowered ||
+            hiprtcGetCodeSize(prog, &cs) != HIPRTC_SUCCESS) {
+            e.error = "hipRTC: no lowered name / code";
+        } else {
+            code.resize(cs);
+            hiprtcGetCode(prog, code.data());
+            std::string low = lowered;
+            hipError_t he = hipModuleLoadData(&e.mod, code.data());
+            if (he == hipSuccess) he = hipModuleGetFunction(&e.fn, e.mod, low.c_str());
+            if (he != hipSuccess) {
+                e.error = std::string("module load: ") + hipGetErrorString(he);
+                e.fn = nullptr;
+            }
+        }
+    }
+    if (prog) hiprtcDestroyProgram(&prog);
+    err = e.error;
+    g_jit_cache[key] = e;
+    return e.fn;
+}
+
+hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s) {
+    LatticeArgs copy = a;
+    void *args[] = {&copy};
+    return hipModuleLaunchKernel(fn, grid.x, grid.y, 1, kBlock, 1, 1, 0, s, args, nullptr);
+}
+
+}  // namespace qmc

@@ -46,5 +46,6 @@ hipError_t launch_lattice(const LatticeArgs &a, dim3 grid, hipStream_t s) {
 // launchers of the non-templated helper kernels (qmc_common.hip)
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t ninst, hipStream_t s);
 hipError_t launch_dump(const DumpArgs &a, uint32_t blocks, hipStream_t s);
+hipError_t launch_math(int fn, uint64_t count, const double *x, double *y, hipStream_t s);
 
 }  // namespace qmc

@@ -41,6 +41,8 @@ struct qmc_plan_s {
     uint32_t cur_S = 0;  // thread stride that d_gstep was computed for
     qmc_launch launch{0, 0};
     uint32_t last_T = 0, last_bx = 0;
+    int32_t jit_mode = 1;   // 0 tables only, 1 specialise when possible, 2 always specialise
+    bool last_jit = false;  // the last sector estimate ran a specialised kernel
     // timing
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -72,6 +74,9 @@ qmc_status plan_set_gstep(qmc_plan_s *p, uint32_t S);
 qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32_t blocks_per_cu);
 qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift);
 void plan_release_extra(qmc_plan_s *p);
+hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
+                         bool cplx, int dev, std::string &err);
+hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s);
 
 // device allocations released together when the object goes out of scope
 struct DeviceScratch {
@@ -84,7 +89,7 @@ struct DeviceScratch {
         return QMC_OK;
     }
     ~DeviceScratch() {
-        for (void *q : ptr) hipFree(q);
+        for (void *q : ptr) (void)hipFree(q);
     }
 };
 

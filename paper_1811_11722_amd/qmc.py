@@ -79,6 +79,8 @@ SIGNATURES = {
     "qmc_plan_set_stream": (C.c_int, [_vp, _vp]),
     "qmc_plan_set_launch": (C.c_int, [_vp, _vp]),
     "qmc_integrate": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "qmc_plan_set_jit": (C.c_int, [_vp, _i32]),
+    "qmc_plan_get_launch": (C.c_int, [_vp, _vp, _vp]),
     "qmc_plan_set_timing": (C.c_int, [_vp, _i32]),
     "qmc_plan_kernel_time": (C.c_int, [_vp, _vp, _vp, _i32]),
     "qmc_lattice_dump": (C.c_int, [_vp, _u64, _u64, _vp, _vp]),
@@ -86,6 +88,7 @@ SIGNATURES = {
     "qmc_korobov_search": (C.c_int, [_u64, _u32, _vp, _u32, _vp, _vp, _vp]),
     "qmc_integrate_batch": (C.c_int, [_u32, _vp, C.c_int, _vp, _vp, _vp]),
     "qmc_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "qmc_math_eval": (C.c_int, [_i32, _u64, _vp, _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
     "qmc_last_error": (C.c_char_p, []),
@@ -202,6 +205,15 @@ class Plan:
         cfg = qmc_launch(shift_tile, blocks_per_cu)
         check(lib().qmc_plan_set_launch(self.handle, C.byref(cfg)), "set_launch")
 
+    def set_jit(self, mode: int):
+        """0 tables, 1 specialise when possible (default), 2 always specialise."""
+        check(lib().qmc_plan_set_jit(self.handle, int(mode)), "set_jit")
+
+    def last_launch(self):
+        cfg, used = qmc_launch(), C.c_int32()
+        check(lib().qmc_plan_get_launch(self.handle, C.byref(cfg), C.byref(used)), "get_launch")
+        return cfg.shift_tile, cfg.blocks_per_cu, bool(used.value)
+
     def set_timing(self, on: bool = True):
         check(lib().qmc_plan_set_timing(self.handle, int(on)), "set_timing")
 
@@ -239,6 +251,14 @@ class Plan:
         check(lib().qmc_autotune(self.handle, params.family, params.ptr, C.byref(best)),
               "qmc_autotune")
         return best.shift_tile, best.blocks_per_cu
+
+
+def math_eval(fn: str, x) -> np.ndarray:
+    """Device qlog ('log') or qexp ('exp') on an array."""
+    x = _arr(x, np.float64)
+    y = np.zeros_like(x)
+    check(lib().qmc_math_eval({"log": 0, "exp": 1}[fn], x.size, _p(x), _p(y)), "qmc_math_eval")
+    return y
 
 
 def korobov_vector(n: int, d: int, a: int) -> np.ndarray:
