@@ -209,6 +209,12 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
                                const void *const *params, const qmc_batch_opts *opts,
                                qmc_result *out);
 
+/* Per-shift values Q_k of the last qmc_integrate_batch call with exactly these
+   plans: per_shift[i] (nullable entries) receives m_i doubles, or 2 m_i
+   interleaved (re, im) for complex sectors.  Not filled by the per-plan
+   comparison mode. */
+qmc_status qmc_batch_per_shift(uint32_t count, const qmc_plan_t *plans, double *const *per_shift);
+
 /* Pick a launch shape for (plan, family, params) by timing candidate shapes
    on the device; the choice is stored in the plan and in the tuning cache
    file named by the QMC_TUNE_CACHE environment variable (if set).  best

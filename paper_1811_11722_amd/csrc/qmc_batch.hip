@@ -1,22 +1,354 @@
-// Batched estimates and the autotuner (filled in below).
+// Batched estimates: many plans (sectors of different d, n, m) in one
+// persistent, graph-replayed launch.
+//
+// The batch context concatenates every plan's generating vector, stride
+// steps, shifts and parameter blob into device arrays once, cuts the work
+// into tiles of tile_points lattice points times one shift tile, orders the
+// tiles longest first (a cost model per plan: points times an evaluation
+// cost from d and the polynomial sizes) and captures {counter reset,
+// persistent kernel, per-plan finalize} into a HIP graph that later calls with
+// the same plans and parameters replay.  The comparison mode launches each
+// plan's own lattice and finalize kernels instead, all on one stream with a
+// single synchronisation at the end.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+
 #include "qmc_runtime.hpp"
 
 namespace qmc {
+
 struct qmc_plan_extra {};
+
+std::map<BatchKey, BatchLaunch> &batch_registry() {
+    static std::map<BatchKey, BatchLaunch> reg;
+    return reg;
+}
+
+namespace {
+
+struct BatchCtx {
+    std::vector<qmc_plan_s *> plans;
+    std::vector<std::vector<double>> blobs;
+    int key_family = 0;
+    uint32_t np = 1, T = 4, dmax = 16, tile_points = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    BatchLaunch fn = nullptr;
+    DeviceScratch dev;  // sectors, tiles, g, gstep, shifts, params, counter, partials, q, res
+    BatchArgs args{};
+    FinalizeBatchArgs fargs{};
+    std::vector<BatchSector> hs;
+    size_t nq = 0;
+    double *h_q = nullptr, *h_res = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t blocks = 0;
+    ~BatchCtx() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (h_q) (void)hipHostFree(h_q);
+        if (h_res) (void)hipHostFree(h_res);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchCtx>> g_batch;
+constexpr size_t kMaxContexts = 8;
+
+// evaluation cost of one point and shift, in arbitrary units
+double plan_cost(int key_family, uint32_t d, const std::vector<double> &blob) {
+    if (key_family == QMC_F_SECTOR || key_family == kFamSectorComplex) {
+        uint64_t nu, nf;
+        std::memcpy(&nu, &blob[0], 8);
+        std::memcpy(&nf, &blob[1], 8);
+        double factors = 0.0;
+        for (uint64_t t = 0; t < nu + nf; ++t) {
+            uint64_t c;
+            const size_t at = t < nu ? kSectorHeader + nu + t : kSectorHeader + 2 * nu + (t - nu) + nf;
+            std::memcpy(&c, &blob[at], 8);
+            factors += (double)(c & 15u);
+        }
+        return 60.0 + 4.0 * d + 8.0 * (double)(nu + nf) + 8.0 * factors + (key_family == kFamSectorComplex ? 80 : 0);
+    }
+    return 20.0 + 12.0 * d;
+}
+
+qmc_status build_ctx(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk,
+                     uint32_t tile_points) {
+    qmc_plan_s *p0 = plans[0];
+    c.plans.assign(plans, plans + count);
+    c.key_family = pk[0].key_family;
+    c.np = pk[0].np;
+    c.device = p0->device;
+    c.tile_points = tile_points;
+    uint32_t maxd = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        c.blobs.push_back(pk[i].blob);
+        maxd = std::max(maxd, plans[i]->d);
+    }
+    const int alpha = p0->tr.kind == QMC_T_KOROBOV ? p0->tr.alpha : 0;
+    auto &reg = batch_registry();
+    for (int T : {4, 2, 1}) {
+        for (int dm : {9, 16}) {
+            if ((uint32_t)dm < maxd) continue;
+            auto it = reg.find(BatchKey{c.key_family, p0->tr.kind, alpha, T, dm});
+            if (it != reg.end()) {
+                c.fn = it->second;
+                c.T = (uint32_t)T;
+                c.dmax = (uint32_t)dm;
+                break;
+            }
+        }
+        if (c.fn) break;
+    }
+    if (!c.fn)
+        return fail(QMC_EUNSUPPORTED, "no batch kernel for family %d, transform %d/%d, d <= %u", c.key_family,
+                    p0->tr.kind, p0->tr.alpha, maxd);
+    const uint32_t T = c.T;
+
+    std::vector<uint32_t> g, gs;
+    std::vector<double> sh, prm;
+    struct Work {
+        double cost;
+        BatchTile t;
+    };
+    std::vector<Work> work;
+    uint32_t slot = 0;
+    size_t qoff = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const qmc_plan_s *p = plans[i];
+        BatchSector s{};
+        s.n = p->n;
+        s.d = p->d;
+        s.m = p->m;
+        s.jtiles = (p->n + tile_points - 1) / tile_points;
+        s.inv_n = p->inv_n;
+        s.scale = transform_scale(p->tr, p->d);
+        s.g_off = (uint32_t)g.size();
+        s.shift_off = (uint32_t)sh.size();
+        s.param_off = (uint32_t)prm.size();
+        s.slot_base = slot;
+        s.q_off = (uint32_t)qoff;
+        std::vector<uint32_t> step(p->d);
+        gstep_for(p->g.data(), p->d, p->n, kBlock, step.data());
+        g.insert(g.end(), p->g.begin(), p->g.end());
+        gs.insert(gs.end(), step.begin(), step.end());
+        sh.insert(sh.end(), p->shifts.begin(), p->shifts.end());
+        prm.insert(prm.end(), pk[i].blob.begin(), pk[i].blob.end());
+        const uint32_t ktiles = (p->m + T - 1) / T;
+        const double cpp = plan_cost(c.key_family, p->d, pk[i].blob) * T;
+        for (uint32_t kt = 0; kt < ktiles; ++kt)
+            for (uint32_t jt = 0; jt < s.jtiles; ++jt) {
+                const uint32_t pts = std::min(tile_points, p->n - jt * tile_points);
+                work.push_back(Work{cpp * pts, BatchTile{i, kt * T, jt, 0}});
+            }
+        slot += ktiles * s.jtiles;
+        qoff += (size_t)p->m * c.np;
+        c.hs.push_back(s);
+    }
+    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+    std::vector<BatchTile> tiles(work.size());
+    for (size_t t = 0; t < work.size(); ++t) tiles[t] = work[t].t;
+    c.nq = qoff;
+
+    qmc_status st;
+    const size_t psize = (size_t)slot * T * c.np * sizeof(double2);
+    if ((st = c.dev.alloc(c.hs.size() * sizeof(BatchSector))) || (st = c.dev.alloc(tiles.size() * sizeof(BatchTile))) ||
+        (st = c.dev.alloc(g.size() * 4)) || (st = c.dev.alloc(gs.size() * 4)) || (st = c.dev.alloc(sh.size() * 8)) ||
+        (st = c.dev.alloc(prm.size() * 8)) || (st = c.dev.alloc(64)) || (st = c.dev.alloc(psize)) ||
+        (st = c.dev.alloc(qoff * 8)) || (st = c.dev.alloc((size_t)count * 32)))
+        return st;
+    hipError_t e;
+    auto up = [&](int k, const void *src, size_t bytes) {
+        return bytes ? hipMemcpy(c.dev.ptr[k], src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    if ((e = up(0, c.hs.data(), c.hs.size() * sizeof(BatchSector))) != hipSuccess ||
+        (e = up(1, tiles.data(), tiles.size() * sizeof(BatchTile))) != hipSuccess ||
+        (e = up(2, g.data(), g.size() * 4)) != hipSuccess || (e = up(3, gs.data(), gs.size() * 4)) != hipSuccess ||
+        (e = up(4, sh.data(), sh.size() * 8)) != hipSuccess || (e = up(5, prm.data(), prm.size() * 8)) != hipSuccess)
+        return hip_fail(e, "batch upload");
+    if ((e = hipHostMalloc((void **)&c.h_q, std::max<size_t>(qoff, 1) * 8, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&c.h_res, (size_t)count * 32, hipHostMallocDefault)) != hipSuccess)
+        return fail(QMC_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    if ((e = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    c.args.sectors = (const BatchSector *)c.dev.ptr[0];
+    c.args.tiles = (const BatchTile *)c.dev.ptr[1];
+    c.args.ntiles = (uint32_t)tiles.size();
+    c.args.tile_points = tile_points;
+    c.args.g = (const uint32_t *)c.dev.ptr[2];
+    c.args.gstep = (const uint32_t *)c.dev.ptr[3];
+    c.args.shifts = (const double *)c.dev.ptr[4];
+    c.args.params = (const double *)c.dev.ptr[5];
+    c.args.counter = (uint32_t *)c.dev.ptr[6];
+    c.args.partials = (double2 *)c.dev.ptr[7];
+    c.fargs.sectors = c.args.sectors;
+    c.fargs.partials = c.args.partials;
+    c.fargs.T = T;
+    c.fargs.np = c.np;
+    c.fargs.q = (double *)c.dev.ptr[8];
+    c.fargs.res = (double *)c.dev.ptr[9];
+    c.blocks = (uint32_t)device_cu_count(c.device) * 8;
+    return QMC_OK;
+}
+
+hipError_t enqueue_batch(BatchCtx &c) {
+    hipError_t e = launch_zero_u32(c.args.counter, 1, c.stream);
+    if (e == hipSuccess) e = c.fn(c.args, c.blocks, c.stream);
+    if (e == hipSuccess) e = launch_finalize_batch(c.fargs, (uint32_t)c.plans.size(), c.stream);
+    return e;
+}
+
+qmc_status run_graph(BatchCtx &c, bool use_graph) {
+    hipError_t e;
+    if (!use_graph) {
+        e = enqueue_batch(c);
+        return e == hipSuccess ? QMC_OK : hip_fail(e, "batch launch");
+    }
+    if (!c.exec) {
+        e = hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        hipError_t le = enqueue_batch(c);
+        e = hipStreamEndCapture(c.stream, &c.graph);
+        if (le != hipSuccess) return hip_fail(le, "capture launches");
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        e = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    }
+    e = hipGraphLaunch(c.exec, c.stream);
+    return e == hipSuccess ? QMC_OK : hip_fail(e, "graph launch");
+}
+
+bool same_ctx(const BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk,
+              uint32_t tile_points) {
+    if (c.plans.size() != count || c.tile_points != tile_points || c.key_family != pk[0].key_family) return false;
+    for (uint32_t i = 0; i < count; ++i)
+        if (c.plans[i] != plans[i] || c.blobs[i] != pk[i].blob) return false;
+    return true;
+}
+
+}  // namespace
+
 void plan_release_extra(qmc_plan_s *p) {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    g_batch.erase(std::remove_if(g_batch.begin(), g_batch.end(),
+                                 [p](const std::unique_ptr<BatchCtx> &c) {
+                                     return std::find(c->plans.begin(), c->plans.end(), p) != c->plans.end();
+                                 }),
+                  g_batch.end());
     delete p->extra;
     p->extra = nullptr;
 }
+
 }  // namespace qmc
 
 using namespace qmc;
 
 extern "C" {
-qmc_status qmc_integrate_batch(uint32_t, const qmc_plan_t *, qmc_family, const void *const *,
-                               const qmc_batch_opts *, qmc_result *) {
-    return fail(QMC_EUNSUPPORTED, "batch not built yet");
+
+qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_family family, const void *const *params,
+                               const qmc_batch_opts *opts, qmc_result *out) {
+    if (count == 0) return fail(QMC_EINVAL, "count must be >= 1");
+    if (!plans || !params || !out) return fail(QMC_EINVAL, "null argument");
+    const qmc_batch_opts o = opts ? *opts : qmc_batch_opts{1, 0, 0};
+    uint32_t tile_points = o.tile_points ? o.tile_points : 8192;
+    if (tile_points % kBlock) return fail(QMC_EINVAL, "tile_points must be a multiple of %d", kBlock);
+    std::vector<Packed> pk(count);
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!plans[i]) return fail(QMC_EINVAL, "plan %u is NULL", i);
+        if (plans[i]->tr.kind != plans[0]->tr.kind || plans[i]->tr.alpha != plans[0]->tr.alpha)
+            return fail(QMC_EINVAL, "plan %u has a different transform", i);
+        if (plans[i]->device != plans[0]->device) return fail(QMC_EINVAL, "plans on different devices");
+        qmc_status st = pack_params((int)family, plans[i]->d, params[i], pk[i]);
+        if (st) return st;
+        if (pk[i].key_family != pk[0].key_family) return fail(QMC_EINVAL, "mixed real and complex sectors");
+        if (plans[i]->m * pk[i].np > kMaxRows) return fail(QMC_EUNSUPPORTED, "m * parts > %u", kMaxRows);
+    }
+
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    BatchCtx *c = nullptr;
+    for (auto &x : g_batch)
+        if (same_ctx(*x, count, plans, pk, tile_points)) c = x.get();
+    if (!c) {
+        auto fresh = std::make_unique<BatchCtx>();
+        qmc_status st = build_ctx(*fresh, count, plans, pk, tile_points);
+        if (st) return st;
+        if (g_batch.size() >= kMaxContexts) g_batch.erase(g_batch.begin());
+        g_batch.push_back(std::move(fresh));
+        c = g_batch.back().get();
+    }
+
+    hipError_t e;
+    bool any_nonfinite = false;
+    if (o.per_plan_launches) {
+        // comparison mode: each plan's own table-driven kernels, one stream
+        for (uint32_t i = 0; i < count; ++i) {
+            qmc_plan_s *p = plans[i];
+            hipStream_t keep = p->stream;
+            const int32_t jit = p->jit_mode;
+            p->stream = c->stream;
+            p->jit_mode = 0;
+            qmc_status st = plan_enqueue(p, pk[i], c->T, 0);
+            if (!st && (e = hipMemcpyAsync(p->h_out, p->d_out, (2 * p->m + 4) * sizeof(double),
+                                           hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+                st = hip_fail(e, "copy results");
+            p->stream = keep;
+            p->jit_mode = jit;
+            if (st) return st;
+        }
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "synchronize");
+        for (uint32_t i = 0; i < count; ++i) {
+            qmc_plan_s *p = plans[i];
+            const double *q = p->h_out, *res = p->h_out + 2 * p->m;
+            bool fin = true;
+            for (uint32_t k = 0; k < p->m * pk[i].np; ++k) fin = fin && std::isfinite(q[k]);
+            out[i] = qmc_result{res[0], pk[i].np == 2 ? res[1] : 0.0, res[2], pk[i].np == 2 ? res[3] : 0.0,
+                                (int32_t)(pk[i].np == 2), 0};
+            if (!fin) {
+                out[i].mean_re = out[i].mean_im = out[i].err_re = out[i].err_im = NAN;
+                any_nonfinite = true;
+            }
+        }
+    } else {
+        qmc_status st = run_graph(*c, o.use_graph != 0);
+        if (st) return st;
+        if ((e = hipMemcpyAsync(c->h_q, c->fargs.q, c->nq * 8, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(c->h_res, c->fargs.res, (size_t)count * 32, hipMemcpyDeviceToHost, c->stream)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+            return hip_fail(e, "batch results");
+        for (uint32_t i = 0; i < count; ++i) {
+            const BatchSector &s = c->hs[i];
+            bool fin = true;
+            for (uint32_t k = 0; k < s.m * c->np; ++k) fin = fin && std::isfinite(c->h_q[s.q_off + k]);
+            const double *r = c->h_res + 4 * i;
+            out[i] = qmc_result{r[0], c->np == 2 ? r[1] : 0.0, r[2], c->np == 2 ? r[3] : 0.0, (int32_t)(c->np == 2), 0};
+            if (!fin) {
+                out[i].mean_re = out[i].mean_im = out[i].err_re = out[i].err_im = NAN;
+                any_nonfinite = true;
+            }
+        }
+    }
+    if (any_nonfinite) return fail(QMC_ENONFINITE, "a per-shift sum of some plan is not finite");
+    return QMC_OK;
 }
-qmc_status qmc_autotune(qmc_plan_t, qmc_family, const void *, qmc_launch *) {
-    return fail(QMC_EUNSUPPORTED, "autotune not built yet");
+
+qmc_status qmc_batch_per_shift(uint32_t count, const qmc_plan_t *plans, double *const *per_shift) {
+    if (!plans || !per_shift) return fail(QMC_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    for (auto &x : g_batch) {
+        if (x->plans.size() != count || !std::equal(x->plans.begin(), x->plans.end(), plans)) continue;
+        for (uint32_t i = 0; i < count; ++i)
+            if (per_shift[i])
+                std::memcpy(per_shift[i], x->h_q + x->hs[i].q_off, (size_t)x->hs[i].m * x->np * sizeof(double));
+        return QMC_OK;
+    }
+    return fail(QMC_EINVAL, "no batch ran with these plans");
 }
-}
+
+}  // extern "C"

@@ -149,11 +149,12 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
         if (!std::isfinite(p->pow_u) || !std::isfinite(p->pow_f)) return fail(QMC_EINVAL, "power not finite");
         const bool cplx = p->is_complex != 0;
         if (cplx && (!std::isfinite(p->delta_im))) return fail(QMC_EINVAL, "delta_im not finite");
-        uint64_t nucode;
-        for (uint32_t i = 0; i < d; ++i)
+        uint64_t nucode = 0;
+        for (uint32_t i = 0; i < d; ++i) {
             if (p->nu[i] > 2) return fail(QMC_EINVAL, "nu_%u = %u > 2", i, (unsigned)p->nu[i]);
-        qmc_status st = monomial_code(p->nu, d, nucode);
-        if (st) return st;
+            nucode |= (uint64_t)p->nu[i] << (2 * i);
+        }
+        qmc_status st = QMC_OK;
         uint32_t flags = (cplx ? 1u : 0u) | (p->pow_u == -2.0 ? 2u : 0u);
         pk.blob = {bits(p->n_u), bits(p->n_f), bits(flags), p->pow_u, p->pow_f, cplx ? p->delta_im : 0.0,
                    bits(nucode)};
@@ -532,7 +533,13 @@ qmc_status qmc_integrate(qmc_plan_t p, qmc_family family, const void *params, qm
     Packed pk;
     qmc_status st = pack_params((int)family, p->d, params, pk);
     if (st) return st;
-    if ((st = plan_enqueue(p, pk, p->launch.shift_tile, p->launch.blocks_per_cu))) return st;
+    qmc_launch L = p->launch;
+    if (L.shift_tile == 0 && L.blocks_per_cu == 0) {
+        const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
+        qmc_launch tuned;
+        if (tune_lookup(p, pk, sector && p->jit_mode != 0, tuned)) L = tuned;
+    }
+    if ((st = plan_enqueue(p, pk, L.shift_tile, L.blocks_per_cu))) return st;
     return plan_collect(p, pk.np, out, per_shift);
 }
 

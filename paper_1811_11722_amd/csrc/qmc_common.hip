@@ -96,6 +96,62 @@ hipError_t launch_math(int fn, uint64_t count, const double *x, double *y, hipSt
     return hipGetLastError();
 }
 
+// Clears a small counter array (used inside captured graphs, where a memset
+// node is avoided).
+__global__ void k_zero_u32(uint32_t *p, uint32_t count) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((count + 63) / 64), dim3(64), 0, s, p, count);
+    return hipGetLastError();
+}
+
+// One block per plan of a batch: adds the plan's tile slots of every
+// (shift, part) row in slot order, then forms Q_k, the mean and the error.
+__global__ __launch_bounds__(kBlock) void k_finalize_batch(const FinalizeBatchArgs a) {
+    __shared__ double qs[kMaxRows];
+    const BatchSector sc = a.sectors[blockIdx.x];
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t rows = sc.m * a.np, width = a.T * a.np;
+    for (uint32_t r = wave; r < rows; r += kBlock / kWave) {
+        const uint32_t k = r / a.np, p = r - k * a.np;
+        const uint32_t kt = k / a.T, col = (k - kt * a.T) * a.np + p;
+        const double2 *src = a.partials + ((size_t)sc.slot_base + (size_t)kt * sc.jtiles) * width + col;
+        dd acc{0.0, 0.0};
+        for (uint32_t b = lane; b < sc.jtiles; b += kWave) acc = dd_add(acc, dd{src[(size_t)b * width].x, src[(size_t)b * width].y});
+        acc = wave_reduce(acc);
+        if (lane == 0) {
+            const double q = ((acc.hi + acc.lo) * sc.scale) / (double)sc.n;
+            qs[r] = q;
+            a.q[sc.q_off + r] = q;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double out[4] = {0.0, 0.0, 0.0, 0.0};
+        for (uint32_t p = 0; p < a.np; ++p) {
+            dd s{0.0, 0.0};
+            for (uint32_t k = 0; k < sc.m; ++k) dd_accumulate(s.hi, s.lo, qs[k * a.np + p]);
+            const double mean = (s.hi + s.lo) / (double)sc.m;
+            dd v{0.0, 0.0};
+            for (uint32_t k = 0; k < sc.m; ++k) {
+                const double t = qs[k * a.np + p] - mean;
+                dd_accumulate(v.hi, v.lo, t * t);
+            }
+            out[p] = mean;
+            out[2 + p] = sqrt((v.hi + v.lo) / ((double)sc.m * (double)(sc.m - 1)));
+        }
+        for (int t = 0; t < 4; ++t) a.res[(size_t)blockIdx.x * 4 + t] = out[t];
+    }
+}
+
+hipError_t launch_finalize_batch(const FinalizeBatchArgs &a, uint32_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_batch, dim3(count), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t ninst, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(ninst), dim3(kBlock), 0, s, a);
     return hipGetLastError();

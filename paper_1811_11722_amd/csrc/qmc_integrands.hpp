@@ -342,22 +342,30 @@ __device__ __forceinline__ void poly_eval(const double *__restrict__ coef,
     }
 }
 
-// out[k] = init[k] * prod_f z[k][var_f] for one coded monomial
+// out[k] = init[k] * prod_i z[k][i]^e_i with e_i = bits 2i..2i+1 of code
+// (the z^nu prefactor; e_i <= 2)
 template <int D, int T>
-__device__ __forceinline__ void mono_eval(uint64_t c, const double (&init)[T],
-                                          const double (&z)[T][D], double (&out)[T]) {
+__device__ __forceinline__ void nu_eval(uint32_t code, const double (&init)[T], const double (&z)[T][D],
+                                        double (&out)[T]) {
 #pragma unroll
     for (int k = 0; k < T; ++k) out[k] = init[k];
-    const uint32_t cnt = (uint32_t)(c & 15u);
-    for (uint32_t f = 0; f < cnt; ++f) {
-        c >>= (f == 0) ? 4 : 5;
-        mul_var<D, T>(out, z, (uint32_t)(c & 31u));
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const uint32_t e = (code >> (2 * i)) & 3u;
+        if (e >= 1) {
+#pragma unroll
+            for (int k = 0; k < T; ++k) out[k] *= z[k][i];
+        }
+        if (e == 2) {
+#pragma unroll
+            for (int k = 0; k < T; ++k) out[k] *= z[k][i];
+        }
     }
 }
 
 // Sector integrand prod_i z_i^nu_i * U^pow_u * (F - i delta)^pow_f (eq. (6)
 // with the two Symanzik-type polynomials; -i delta as in eq. (7)).
-// blob: [n_u, n_f, flags, pow_u, pow_f, delta, nu_code,
+// blob: [n_u, n_f, flags, pow_u, pow_f, delta, nu (2 bits per variable),
 //        coef_u (n_u), code_u (n_u), coef_f (n_f), code_f (n_f)]
 // flags bit 0: complex, bit 1: pow_u == -2 (U^-2 by reciprocal).
 enum : uint32_t { kSectorComplex = 1u, kSectorPowUm2 = 2u };
@@ -404,7 +412,7 @@ struct FamSector {
         const uint32_t nf = (uint32_t)__double_as_longlong(p[1]);
         const uint32_t flags = (uint32_t)__double_as_longlong(p[2]);
         const double pow_u = p[3], pow_f = p[4], delta = p[5];
-        const uint64_t *nucode = reinterpret_cast<const uint64_t *>(p + 6);
+        const uint32_t nucode = (uint32_t)__double_as_longlong(p[6]);
         const double *cu = p + kSectorHeader;
         const uint64_t *eu = reinterpret_cast<const uint64_t *>(cu + nu);
         const double *cf = cu + 2 * nu;
@@ -412,7 +420,7 @@ struct FamSector {
         double U[T], F[T], mono[T];
         poly_eval<D, T>(cu, eu, nu, z, U);
         poly_eval<D, T>(cf, ef, nf, z, F);
-        mono_eval<D, T>(nucode[0], jac, z, mono);
+        nu_eval<D, T>(nucode, jac, z, mono);
 #pragma unroll
         for (int k = 0; k < T; ++k) sector_finish<Complex>(mono[k], U[k], F[k], flags, pow_u, pow_f, delta, v[k]);
     }

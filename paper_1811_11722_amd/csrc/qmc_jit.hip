@@ -98,7 +98,10 @@ static std::string jit_source(const std::vector<double> &blob, uint32_t d, const
         st << c << ",";
     }
     const uint64_t nuc = word(blob, 6);
-    const int mnu = trie.insert(factors_of(nuc));
+    std::vector<int> nuf;
+    for (uint32_t i = 0; i < d; ++i)
+        for (uint64_t r = 0; r < ((nuc >> (2 * i)) & 3u); ++r) nuf.push_back((int)i);
+    const int mnu = trie.insert(nuf);
     st << "|" << nuc;
     structure = st.str();
 

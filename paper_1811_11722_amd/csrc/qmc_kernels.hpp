@@ -36,79 +36,75 @@ struct LatticeArgs {
 
 constexpr int kChunk = 8;  // points per plain-FP64 partial before the TwoSum fold
 
+// Adds fhat over the lattice points j = j, j + S, j + 2S, ... < j1 of one
+// thread into (hi, lo) for the T shifts dl.  gs holds (S g_i) mod n.
 template <class Fam, class Tr, int D, int T>
-__global__ __launch_bounds__(kBlock) void k_lattice(const LatticeArgs a) {
+__device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S, uint32_t n, double inv_n,
+                                            const uint32_t *__restrict__ g, const uint32_t *__restrict__ gs,
+                                            const double (&dl)[T][D], const double *__restrict__ prm,
+                                            double (&hi)[T][Fam::NP], double (&lo)[T][Fam::NP]) {
     constexpr int NP = Fam::NP;
-    const uint32_t inst = blockIdx.y / a.tiles;
-    const uint32_t k0 = (blockIdx.y - inst * a.tiles) * T;
-    const uint32_t *__restrict__ g = a.g + (size_t)inst * a.g_stride;
-    const uint32_t *__restrict__ gs = a.gstep + (size_t)inst * a.g_stride;
-    const double *__restrict__ sh = a.shifts + (size_t)inst * a.shift_stride;
-    const double *__restrict__ prm = a.params + (size_t)inst * a.param_stride;
-    const uint32_t n = a.n;
-    const uint32_t S = gridDim.x * kBlock;
-    const uint32_t t0 = blockIdx.x * kBlock + threadIdx.x;
-
-    double hi[T][NP], lo[T][NP];
+    if (j >= j1) return;
+    uint32_t idx[D], step[D], nms[D];
 #pragma unroll
-    for (int k = 0; k < T; ++k)
-#pragma unroll
-        for (int p = 0; p < NP; ++p) hi[k][p] = lo[k][p] = 0.0;
-
-    if (t0 < n) {
-        // shifts of this tile; rows past m repeat the last shift (discarded)
-        double dl[T][D];
-#pragma unroll
-        for (int k = 0; k < T; ++k) {
-            const uint32_t row = min(k0 + (uint32_t)k, a.m - 1u);
-#pragma unroll
-            for (int i = 0; i < D; ++i) dl[k][i] = sh[row * D + i];
-        }
-        uint32_t idx[D], step[D], nms[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            idx[i] = mulmod(t0, g[i], n, a.inv_n);
-            step[i] = gs[i];
-            nms[i] = n - gs[i];
-        }
-        uint32_t j = t0;
-#pragma unroll 1
-        while (j < n) {
-            double s[T][NP];
-#pragma unroll
-            for (int k = 0; k < T; ++k)
-#pragma unroll
-                for (int p = 0; p < NP; ++p) s[k][p] = 0.0;
-#pragma unroll 1
-            for (int c = 0; c < kChunk && j < n; ++c) {
-                double y[D];
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    y[i] = (double)idx[i] * a.inv_n;
-                    idx[i] = walk(idx[i], step[i], nms[i]);
-                }
-                double x[T][D];
-#pragma unroll
-                for (int k = 0; k < T; ++k)
-#pragma unroll
-                    for (int i = 0; i < D; ++i) x[k][i] = fract(y[i] + dl[k][i]);
-                double v[T][NP];
-                Fam::template eval<Tr, D, T>(prm, x, v);
-#pragma unroll
-                for (int k = 0; k < T; ++k)
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) s[k][p] += v[k][p];
-                j += S;
-            }
-#pragma unroll
-            for (int k = 0; k < T; ++k)
-#pragma unroll
-                for (int p = 0; p < NP; ++p) dd_accumulate(hi[k][p], lo[k][p], s[k][p]);
-        }
+    for (int i = 0; i < D; ++i) {
+        idx[i] = mulmod(j, g[i], n, inv_n);
+        step[i] = gs[i];
+        nms[i] = n - gs[i];
     }
+#pragma unroll 1
+    while (j < j1) {
+        double s[T][NP];
+#pragma unroll
+        for (int k = 0; k < T; ++k)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) s[k][p] = 0.0;
+#pragma unroll 1
+        for (int c = 0; c < kChunk && j < j1; ++c) {
+            double y[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                y[i] = (double)idx[i] * inv_n;
+                idx[i] = walk(idx[i], step[i], nms[i]);
+            }
+            double x[T][D];
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+#pragma unroll
+                for (int i = 0; i < D; ++i) x[k][i] = fract(y[i] + dl[k][i]);
+            double v[T][NP];
+            Fam::template eval<Tr, D, T>(prm, x, v);
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) s[k][p] += v[k][p];
+            j += S;
+        }
+#pragma unroll
+        for (int k = 0; k < T; ++k)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) dd_accumulate(hi[k][p], lo[k][p], s[k][p]);
+    }
+}
 
-    // block reduction: wave butterfly, then the 4 waves in order via LDS
-    __shared__ dd red[kBlock / kWave][T * NP];
+// shifts k0 .. k0+T-1 of an (m, D) row-major table; rows past m repeat the
+// last shift (their sums are discarded)
+template <int D, int T>
+__device__ __forceinline__ void load_shifts(const double *__restrict__ sh, uint32_t k0, uint32_t m,
+                                            double (&dl)[T][D]) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const uint32_t row = min(k0 + (uint32_t)k, m - 1u);
+#pragma unroll
+        for (int i = 0; i < D; ++i) dl[k][i] = sh[row * D + i];
+    }
+}
+
+// Block-wide double-double sum of every thread's (hi, lo)[k][p]: the wave
+// butterfly, then the 4 waves in order.  Thread r < T*NP returns row r.
+template <int T, int NP>
+__device__ __forceinline__ dd block_reduce(const double (&hi)[T][NP], const double (&lo)[T][NP],
+                                           dd (&red)[kBlock / kWave][T * NP]) {
     const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
     for (int k = 0; k < T; ++k)
@@ -118,17 +114,136 @@ __global__ __launch_bounds__(kBlock) void k_lattice(const LatticeArgs a) {
             if (lane == 0) red[wave][k * NP + p] = r;
         }
     __syncthreads();
+    dd r{0.0, 0.0};
     if (threadIdx.x < (uint32_t)(T * NP)) {
-        const uint32_t k = threadIdx.x / NP, p = threadIdx.x - k * NP;
-        dd r = red[0][threadIdx.x];
+        r = red[0][threadIdx.x];
 #pragma unroll
         for (int w = 1; w < kBlock / kWave; ++w) r = dd_add(r, red[w][threadIdx.x]);
+    }
+    return r;
+}
+
+template <class Fam, class Tr, int D, int T>
+__global__ __launch_bounds__(kBlock) void k_lattice(const LatticeArgs a) {
+    constexpr int NP = Fam::NP;
+    const uint32_t inst = blockIdx.y / a.tiles;
+    const uint32_t k0 = (blockIdx.y - inst * a.tiles) * T;
+    const uint32_t *__restrict__ g = a.g + (size_t)inst * a.g_stride;
+    const uint32_t *__restrict__ gs = a.gstep + (size_t)inst * a.g_stride;
+    const double *__restrict__ sh = a.shifts + (size_t)inst * a.shift_stride;
+    const double *__restrict__ prm = a.params + (size_t)inst * a.param_stride;
+
+    double hi[T][NP], lo[T][NP];
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) hi[k][p] = lo[k][p] = 0.0;
+    double dl[T][D];
+    load_shifts<D, T>(sh, k0, a.m, dl);
+    walk_points<Fam, Tr, D, T>(blockIdx.x * kBlock + threadIdx.x, a.n, gridDim.x * kBlock, a.n, a.inv_n, g, gs,
+                               dl, prm, hi, lo);
+
+    __shared__ dd red[kBlock / kWave][T * NP];
+    const dd r = block_reduce<T, NP>(hi, lo, red);
+    if (threadIdx.x < (uint32_t)(T * NP)) {
+        const uint32_t k = threadIdx.x / NP, p = threadIdx.x - k * NP;
         if (k0 + k < a.m) {
             const size_t o = (((size_t)inst * a.m + k0 + k) * a.np + p) * gridDim.x + blockIdx.x;
             a.partials[o] = make_double2(r.hi, r.lo);
         }
     }
 }
+
+// ------------------------------------------------------- batched estimates
+// Many plans (sectors) of different d, n, m in one persistent launch.  The
+// work is a list of tiles (plan, shift tile, range of tile_points lattice
+// points) ordered longest first; each workgroup takes the next tile from an
+// atomic counter until the list is exhausted and writes one (hi, lo) pair per
+// shift of the tile to that tile's slot.  k_finalize_batch then adds each
+// plan's slots in a fixed order, so results do not depend on which
+// workgroup ran which tile.
+struct BatchSector {
+    uint32_t n, d, m, jtiles;  // jtiles = ceil(n / tile_points)
+    double inv_n;
+    double scale;              // transform constant
+    uint32_t g_off, shift_off, param_off, slot_base;
+    uint32_t q_off, pad;
+};
+
+struct BatchTile {
+    uint32_t sector, k0, jt, pad;
+};
+
+struct BatchArgs {
+    const BatchSector *sectors;
+    const BatchTile *tiles;
+    uint32_t ntiles;
+    uint32_t tile_points;  // multiple of kBlock
+    const uint32_t *g;     // concatenated generating vectors
+    const uint32_t *gstep; // (kBlock g_i) mod n, same layout
+    const double *shifts;  // concatenated (m, d) tables
+    const double *params;  // concatenated parameter blobs
+    uint32_t *counter;     // next tile; zeroed before the launch
+    double2 *partials;     // (slot, T * np)
+};
+
+template <class Fam, class Tr, int D, int T>
+__device__ __forceinline__ void batch_tile(const BatchArgs &a, const BatchTile &tl, const BatchSector &sc,
+                                           dd (&red)[kBlock / kWave][T * Fam::NP]) {
+    constexpr int NP = Fam::NP;
+    double hi[T][NP], lo[T][NP];
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) hi[k][p] = lo[k][p] = 0.0;
+    double dl[T][D];
+    load_shifts<D, T>(a.shifts + sc.shift_off, tl.k0, sc.m, dl);
+    const uint32_t j0 = tl.jt * a.tile_points;
+    const uint32_t j1 = min(sc.n, j0 + a.tile_points);
+    walk_points<Fam, Tr, D, T>(j0 + threadIdx.x, j1, kBlock, sc.n, sc.inv_n, a.g + sc.g_off, a.gstep + sc.g_off,
+                               dl, a.params + sc.param_off, hi, lo);
+    const dd r = block_reduce<T, NP>(hi, lo, red);
+    if (threadIdx.x < (uint32_t)(T * NP)) {
+        const size_t slot = (size_t)sc.slot_base + (size_t)(tl.k0 / T) * sc.jtiles + tl.jt;
+        a.partials[slot * (T * NP) + threadIdx.x] = make_double2(r.hi, r.lo);
+    }
+}
+
+template <class Fam, class Tr, int T, int DMAX>
+__global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
+    __shared__ uint32_t s_tile;
+    __shared__ dd red[kBlock / kWave][T * Fam::NP];
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const uint32_t t = uniform(s_tile);
+        if (t >= a.ntiles) break;
+        const BatchTile tl = a.tiles[t];
+        const BatchSector sc = a.sectors[tl.sector];
+        switch (sc.d) {
+#define QMC_BATCH_CASE(DD) \
+    case DD:               \
+        if constexpr (DD <= DMAX) batch_tile<Fam, Tr, DD, T>(a, tl, sc, red); \
+        break;
+            QMC_BATCH_CASE(1) QMC_BATCH_CASE(2) QMC_BATCH_CASE(3) QMC_BATCH_CASE(4)
+            QMC_BATCH_CASE(5) QMC_BATCH_CASE(6) QMC_BATCH_CASE(7) QMC_BATCH_CASE(8)
+            QMC_BATCH_CASE(9) QMC_BATCH_CASE(10) QMC_BATCH_CASE(11) QMC_BATCH_CASE(12)
+            QMC_BATCH_CASE(13) QMC_BATCH_CASE(14) QMC_BATCH_CASE(15) QMC_BATCH_CASE(16)
+#undef QMC_BATCH_CASE
+        default:
+            break;
+        }
+        __syncthreads();
+    }
+}
+
+struct FinalizeBatchArgs {
+    const BatchSector *sectors;
+    const double2 *partials;
+    uint32_t T, np;
+    double *q;    // per sector at q_off: (m, np)
+    double *res;  // (sector, 4)
+};
 
 struct FinalizeArgs {
     const double2 *partials;  // (inst, m, np, nblk)

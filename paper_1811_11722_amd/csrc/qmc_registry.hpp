@@ -43,9 +43,32 @@ hipError_t launch_lattice(const LatticeArgs &a, dim3 grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+struct BatchKey {
+    int family, tkind, alpha, T, dmax;
+    bool operator<(const BatchKey &o) const {
+        return std::tie(family, tkind, alpha, T, dmax) < std::tie(o.family, o.tkind, o.alpha, o.T, o.dmax);
+    }
+};
+
+using BatchLaunch = hipError_t (*)(const BatchArgs &, uint32_t blocks, hipStream_t);
+
+std::map<BatchKey, BatchLaunch> &batch_registry();
+
+struct BatchRegistrar {
+    BatchRegistrar(BatchKey k, BatchLaunch f) { batch_registry()[k] = f; }
+};
+
+template <class Fam, class Tr, int T, int DMAX>
+hipError_t launch_batch(const BatchArgs &a, uint32_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch<Fam, Tr, T, DMAX>), dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 // launchers of the non-templated helper kernels (qmc_common.hip)
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t ninst, hipStream_t s);
 hipError_t launch_dump(const DumpArgs &a, uint32_t blocks, hipStream_t s);
 hipError_t launch_math(int fn, uint64_t count, const double *x, double *y, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t s);
+hipError_t launch_finalize_batch(const FinalizeBatchArgs &a, uint32_t count, hipStream_t s);
 
 }  // namespace qmc

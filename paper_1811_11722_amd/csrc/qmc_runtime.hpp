@@ -77,6 +77,8 @@ void plan_release_extra(qmc_plan_s *p);
 hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
                          bool cplx, int dev, std::string &err);
 hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s);
+std::string tune_key(const qmc_plan_s *p, const Packed &pk, bool jit);
+bool tune_lookup(const qmc_plan_s *p, const Packed &pk, bool jit, qmc_launch &out);
 
 // device allocations released together when the object goes out of scope
 struct DeviceScratch {

@@ -88,6 +88,7 @@ SIGNATURES = {
     "qmc_korobov_search": (C.c_int, [_u64, _u32, _vp, _u32, _vp, _vp, _vp]),
     "qmc_integrate_batch": (C.c_int, [_u32, _vp, C.c_int, _vp, _vp, _vp]),
     "qmc_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "qmc_batch_per_shift": (C.c_int, [_u32, _vp, _vp]),
     "qmc_math_eval": (C.c_int, [_i32, _u64, _vp, _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
@@ -287,3 +288,14 @@ def integrate_batch(plans: Sequence[Plan], params: Sequence[Params], use_graph: 
     check(lib().qmc_integrate_batch(len(plans), handles, fam, pp, C.byref(opts), out),
           "qmc_integrate_batch")
     return list(out)
+
+
+def batch_per_shift(plans: Sequence[Plan], complex_parts: bool = False):
+    """Per-shift Q_k of the last graph/persistent batch run over these plans."""
+    handles = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+    bufs = [np.zeros(p.m * (2 if complex_parts else 1)) for p in plans]
+    ptrs = (C.c_void_p * len(plans))(*[_p(b) for b in bufs])
+    check(lib().qmc_batch_per_shift(len(plans), handles, ptrs), "qmc_batch_per_shift")
+    if complex_parts:
+        return [b[0::2] + 1j * b[1::2] for b in bufs]
+    return bufs

@@ -1,0 +1,154 @@
+"""Batched persistent launch and autotuner on the GPU, against the oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1811_11722_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Q():
+    O.build(force=False)
+    from paper_1811_11722_amd import qmc
+    qmc.lib()
+    return qmc
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300)
+
+
+def _sector_plans(Q, count, seed, ns, m):
+    draws = synth.sector_batch_draws(seed, count)
+    tabs = synth.sector_batch(seed, count)
+    plans, params, cases = [], [], []
+    for s, ((d, _, _), tab) in enumerate(zip(draws, tabs)):
+        n = ns[s % len(ns)]
+        g = O.korobov_vector(n, d, 3 + 2 * s)
+        sh = synth.sector_batch_shifts(seed, s, m, d)
+        plans.append(Q.Plan(d, n, g, sh, "baker"))
+        params.append(Q.Params("sector", d, sector=tab))
+        cases.append((d, n, g, sh, tab))
+    return plans, params, cases
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_sector_batch_parity(Q, use_graph):
+    """Sectors of d = 2..9 and uneven n in one persistent launch."""
+    plans, params, cases = _sector_plans(Q, 24, 77, [1021, 4093, 16381, 257, 65521], 6)
+    _say(f"sector batch graph={use_graph}")
+    res = Q.integrate_batch(plans, params, use_graph=use_graph, tile_points=1024)
+    per = Q.batch_per_shift(plans)
+    for (d, n, g, sh, tab), q, r in zip(cases, per, res):
+        est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
+        assert np.all(_rel(q, est.q_re) < TOL), (d, n, _rel(q, est.q_re).max())
+        mean, err, _ = est.mean_error()
+        assert abs(r.mean_re - mean.real) <= TOL * abs(mean.real)
+
+
+def test_batch_graph_replay_and_per_plan_mode(Q):
+    plans, params, cases = _sector_plans(Q, 16, 78, [4093, 16381], 8)
+    _say("graph replays")
+    first = Q.integrate_batch(plans, params, use_graph=True)
+    q1 = Q.batch_per_shift(plans)
+    for rep in range(3):
+        again = Q.integrate_batch(plans, params, use_graph=True)
+        qa = Q.batch_per_shift(plans)
+        assert all(np.array_equal(a, b) for a, b in zip(q1, qa))
+        assert [r.mean_re for r in again] == [r.mean_re for r in first]
+    eager = Q.integrate_batch(plans, params, use_graph=False)
+    assert [r.mean_re for r in eager] == [r.mean_re for r in first]
+    _say("per-plan launches")
+    pp = Q.integrate_batch(plans, params, per_plan_launches=True)
+    for a, b in zip(pp, first):
+        assert abs(a.mean_re - b.mean_re) <= TOL * abs(b.mean_re)
+        assert abs(a.err_re - b.err_re) <= 1e-6 * abs(b.err_re) + 1e-300
+
+
+def test_genz_batch(Q):
+    """Product peak instances (shared g and shifts, own a and u), Korobov 3."""
+    d, n, m = 4, 16381, 16
+    g = O.korobov_vector(n, d, 1234)
+    sh = synth.shifts(5, m, d)
+    plans, params, cases = [], [], []
+    for b in range(12):
+        a, u = synth.genz_params(1000 + b, d)
+        plans.append(Q.Plan(d, n, g, sh, "korobov", 3))
+        params.append(Q.Params("genz_product_peak", d, a=a, u=u))
+        cases.append((a, u))
+    _say("genz batch")
+    Q.integrate_batch(plans, params, tile_points=2048)
+    for (a, u), q in zip(cases, Q.batch_per_shift(plans)):
+        est = O.estimate(n, g, sh, O.Params("genz_product_peak", d, a=a, u=u), "korobov", 3,
+                         threads=THREADS)
+        assert np.all(_rel(q, est.q_re) < TOL)
+
+
+def test_complex_batch(Q):
+    d, m = 4, 4
+    plans, params, cases = [], [], []
+    for s in range(5):
+        tab = synth.sector_tables(900 + s, d, 6, 9, complex_kinematics=True)
+        n = [1021, 2039][s % 2]
+        g = O.korobov_vector(n, d, 5 + s)
+        sh = synth.shifts(900 + s, m, d)
+        plans.append(Q.Plan(d, n, g, sh, "baker"))
+        params.append(Q.Params("sector", d, sector=tab))
+        cases.append((n, g, sh, tab))
+    _say("complex batch")
+    Q.integrate_batch(plans, params, tile_points=512)
+    for (n, g, sh, tab), q in zip(cases, Q.batch_per_shift(plans, complex_parts=True)):
+        est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
+        assert np.all(np.abs(q - est.q) <= 1e-11 * np.abs(est.q))
+
+
+def test_batch_validation(Q):
+    g = O.korobov_vector(1021, 2, 5)
+    p1 = Q.Plan(2, 1021, g, synth.shifts(1, 2, 2), "baker")
+    p2 = Q.Plan(2, 1021, g, synth.shifts(1, 2, 2), "korobov", 3)
+    prm = Q.Params("genz_gaussian", 2, a=[1.0, 2.0], u=[0.3, 0.4])
+    with pytest.raises(Q.QMCError) as e:
+        Q.integrate_batch([p1, p2], [prm, prm])
+    assert e.value.status == Q.QMC_EINVAL
+    with pytest.raises(Q.QMCError) as e:
+        Q.integrate_batch([p1], [prm], tile_points=100)
+    assert e.value.status == Q.QMC_EINVAL
+
+
+def test_autotune(Q, tmp_path, monkeypatch):
+    """The tuner picks a shape; estimates with it still match the oracle."""
+    w = synth.product_peak_workload(n=65521, m=16)
+    g = O.korobov_vector(w.n, w.d, 17364)
+    plan = Q.Plan(w.d, w.n, g, w.shifts, "korobov", 3)
+    p = Q.Params("genz_product_peak", w.d, a=w.genz_a, u=w.genz_u)
+    _say("autotune product peak")
+    T, bpc = plan.autotune(p)
+    assert T in (2, 4, 8) and bpc in (2, 4, 8, 16, 32)
+    _, q = plan.integrate(p)
+    assert plan.last_launch()[0] == T
+    est = O.estimate(w.n, g, w.shifts, O.Params("genz_product_peak", w.d, a=w.genz_a, u=w.genz_u),
+                     "korobov", 3, threads=THREADS)
+    assert np.all(_rel(q, est.q_re) < TOL)
+    ws = synth.sector_workload(n=65521, m=8)
+    gs = O.korobov_vector(ws.n, ws.d, 17364)
+    sp = Q.Plan(ws.d, ws.n, gs, ws.shifts, "baker")
+    _say("autotune sector")
+    T2, _ = sp.autotune(Q.Params("sector", ws.d, sector=ws.sector))
+    assert T2 in (1, 2, 4)
+    _, q2 = sp.integrate(Q.Params("sector", ws.d, sector=ws.sector))
+    est2 = O.estimate(ws.n, gs, ws.shifts, O.Params("sector", ws.d, sector=ws.sector), "baker",
+                      threads=THREADS)
+    assert np.all(_rel(q2, est2.q_re) < TOL)
