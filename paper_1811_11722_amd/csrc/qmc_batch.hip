@@ -33,10 +33,22 @@ struct BatchCtx {
     std::vector<qmc_plan_s *> plans;
     std::vector<std::vector<double>> blobs;
     int key_family = 0;
-    uint32_t np = 1, T = 4, dmax = 16, tile_points = 0;
+    uint32_t np = 1, T = 4, tile_points = 0;
     int device = 0;
     hipStream_t stream = nullptr;
-    BatchLaunch fn = nullptr;
+    struct Group {
+        uint32_t d;
+        BatchLaunch fn;
+        uint32_t tile_begin, ntiles;
+    };
+    std::vector<Group> groups;  // one persistent launch per dimension
+    // uniform batches (every plan with the same d, n and m): one launch of the
+    // lattice kernel with the plans as instances along grid.y
+    bool uniform = false;
+    LatticeLaunch lfn = nullptr;
+    LatticeArgs largs{};
+    FinalizeArgs lfargs{};
+    uint32_t lbx = 0, ltiles = 0;
     DeviceScratch dev;  // sectors, tiles, g, gstep, shifts, params, counter, partials, q, res
     BatchArgs args{};
     FinalizeBatchArgs fargs{};
@@ -78,6 +90,89 @@ double plan_cost(int key_family, uint32_t d, const std::vector<double> &blob) {
     return 20.0 + 12.0 * d;
 }
 
+qmc_status build_uniform(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk) {
+    qmc_plan_s *p0 = plans[0];
+    c.uniform = true;
+    c.plans.assign(plans, plans + count);
+    c.key_family = pk[0].key_family;
+    c.np = pk[0].np;
+    c.device = p0->device;
+    for (uint32_t i = 0; i < count; ++i) c.blobs.push_back(pk[i].blob);
+    uint32_t T = 0;
+    c.lfn = find_kernel(c.key_family, p0->tr, p0->d, default_tile(c.key_family) == 4 ? 8 : default_tile(c.key_family), T);
+    if (!c.lfn)
+        return fail(QMC_EUNSUPPORTED, "no kernel for family %d, transform %d/%d, d = %u", c.key_family, p0->tr.kind,
+                    p0->tr.alpha, p0->d);
+    const uint32_t d = p0->d, m = p0->m, n = p0->n, rows = padded_rows(m);
+    c.T = T;
+    c.ltiles = (m + T - 1) / T;
+    if ((uint64_t)count * c.ltiles > 65535) return fail(QMC_EUNSUPPORTED, "too many instances for one launch");
+    c.lbx = grid_x(n, count * c.ltiles, c.device, 8);
+    size_t pstride = 0;
+    for (auto &b : pk) pstride = std::max(pstride, b.blob.size());
+    std::vector<uint32_t> g((size_t)count * d), gs((size_t)count * d);
+    std::vector<double> sh((size_t)count * rows * d), prm(count * pstride, 0.0);
+    for (uint32_t i = 0; i < count; ++i) {
+        std::copy(plans[i]->g.begin(), plans[i]->g.end(), g.begin() + (size_t)i * d);
+        gstep_for(plans[i]->g.data(), d, n, (uint64_t)c.lbx * kBlock, &gs[(size_t)i * d]);
+        const std::vector<double> ps = padded_shifts(plans[i]->shifts, m, d, rows);
+        std::copy(ps.begin(), ps.end(), sh.begin() + (size_t)i * rows * d);
+        std::copy(pk[i].blob.begin(), pk[i].blob.end(), prm.begin() + (size_t)i * pstride);
+        BatchSector s{};
+        s.n = n;
+        s.d = d;
+        s.m = m;
+        s.q_off = i * m * c.np;
+        c.hs.push_back(s);
+    }
+    c.nq = (size_t)count * m * c.np;
+    qmc_status st;
+    if ((st = c.dev.alloc(g.size() * 4)) || (st = c.dev.alloc(gs.size() * 4)) || (st = c.dev.alloc(sh.size() * 8)) ||
+        (st = c.dev.alloc(prm.size() * 8)) ||
+        (st = c.dev.alloc((size_t)count * m * c.np * c.lbx * sizeof(double2))) || (st = c.dev.alloc(c.nq * 8)) ||
+        (st = c.dev.alloc((size_t)count * 32)))
+        return st;
+    hipError_t e;
+    if ((e = hipMemcpy(c.dev.ptr[0], g.data(), g.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c.dev.ptr[1], gs.data(), gs.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c.dev.ptr[2], sh.data(), sh.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c.dev.ptr[3], prm.data(), prm.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "batch upload");
+    if ((e = hipHostMalloc((void **)&c.h_q, c.nq * 8, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&c.h_res, (size_t)count * 32, hipHostMallocDefault)) != hipSuccess)
+        return fail(QMC_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    if ((e = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    LatticeArgs &a = c.largs;
+    a.n = n;
+    a.d = d;
+    a.m = m;
+    a.tiles = c.ltiles;
+    a.inv_n = p0->inv_n;
+    a.g = (const uint32_t *)c.dev.ptr[0];
+    a.gstep = (const uint32_t *)c.dev.ptr[1];
+    a.shifts = (const double *)c.dev.ptr[2];
+    a.params = (const double *)c.dev.ptr[3];
+    a.g_stride = d;
+    a.shift_stride = rows * d;
+    a.param_stride = (uint32_t)pstride;
+    a.np = c.np;
+    a.partials = (double2 *)c.dev.ptr[4];
+    FinalizeArgs &f = c.lfargs;
+    f.partials = a.partials;
+    f.nblk = c.lbx;
+    f.m = m;
+    f.np = c.np;
+    f.n = (double)n;
+    f.scale = transform_scale(p0->tr, d);
+    f.sub = 0.0;
+    f.q = (double *)c.dev.ptr[5];
+    f.res = (double *)c.dev.ptr[6];
+    c.fargs.q = f.q;
+    c.fargs.res = f.res;
+    return QMC_OK;
+}
+
 qmc_status build_ctx(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk,
                      uint32_t tile_points) {
     qmc_plan_s *p0 = plans[0];
@@ -86,35 +181,34 @@ qmc_status build_ctx(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const
     c.np = pk[0].np;
     c.device = p0->device;
     c.tile_points = tile_points;
-    uint32_t maxd = 0;
-    for (uint32_t i = 0; i < count; ++i) {
-        c.blobs.push_back(pk[i].blob);
-        maxd = std::max(maxd, plans[i]->d);
-    }
+    for (uint32_t i = 0; i < count; ++i) c.blobs.push_back(pk[i].blob);
     const int alpha = p0->tr.kind == QMC_T_KOROBOV ? p0->tr.alpha : 0;
     auto &reg = batch_registry();
-    for (int T : {4, 2, 1}) {
-        for (int dm : {9, 16}) {
-            if ((uint32_t)dm < maxd) continue;
-            auto it = reg.find(BatchKey{c.key_family, p0->tr.kind, alpha, T, dm});
-            if (it != reg.end()) {
-                c.fn = it->second;
-                c.T = (uint32_t)T;
-                c.dmax = (uint32_t)dm;
-                break;
-            }
+    // one shift tile for the whole batch: the largest compiled for plan 0's d
+    c.T = 0;
+    for (int T : {4, 2, 1})
+        if (reg.count(BatchKey{c.key_family, p0->tr.kind, alpha, (int)p0->d, T})) {
+            c.T = (uint32_t)T;
+            break;
         }
-        if (c.fn) break;
+    std::map<uint32_t, BatchLaunch> fn_of_d;
+    for (uint32_t i = 0; i < count && c.T; ++i) {
+        auto it = reg.find(BatchKey{c.key_family, p0->tr.kind, alpha, (int)plans[i]->d, (int)c.T});
+        if (it == reg.end())
+            return fail(QMC_EUNSUPPORTED, "no batch kernel for family %d, transform %d/%d, d = %u", c.key_family,
+                        p0->tr.kind, p0->tr.alpha, plans[i]->d);
+        fn_of_d[plans[i]->d] = it->second;
     }
-    if (!c.fn)
-        return fail(QMC_EUNSUPPORTED, "no batch kernel for family %d, transform %d/%d, d <= %u", c.key_family,
-                    p0->tr.kind, p0->tr.alpha, maxd);
+    if (!c.T)
+        return fail(QMC_EUNSUPPORTED, "no batch kernel for family %d, transform %d/%d, d = %u", c.key_family,
+                    p0->tr.kind, p0->tr.alpha, p0->d);
     const uint32_t T = c.T;
 
     std::vector<uint32_t> g, gs;
     std::vector<double> sh, prm;
     struct Work {
         double cost;
+        uint32_t d;
         BatchTile t;
     };
     std::vector<Work> work;
@@ -138,29 +232,42 @@ qmc_status build_ctx(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const
         gstep_for(p->g.data(), p->d, p->n, kBlock, step.data());
         g.insert(g.end(), p->g.begin(), p->g.end());
         gs.insert(gs.end(), step.begin(), step.end());
-        sh.insert(sh.end(), p->shifts.begin(), p->shifts.end());
+        const std::vector<double> psh = padded_shifts(p->shifts, p->m, p->d, (p->m + T - 1) / T * T);
+        sh.insert(sh.end(), psh.begin(), psh.end());
         prm.insert(prm.end(), pk[i].blob.begin(), pk[i].blob.end());
         const uint32_t ktiles = (p->m + T - 1) / T;
         const double cpp = plan_cost(c.key_family, p->d, pk[i].blob) * T;
         for (uint32_t kt = 0; kt < ktiles; ++kt)
             for (uint32_t jt = 0; jt < s.jtiles; ++jt) {
                 const uint32_t pts = std::min(tile_points, p->n - jt * tile_points);
-                work.push_back(Work{cpp * pts, BatchTile{i, kt * T, jt, 0}});
+                work.push_back(Work{cpp * pts, p->d, BatchTile{i, kt * T, jt, 0}});
             }
         slot += ktiles * s.jtiles;
         qoff += (size_t)p->m * c.np;
         c.hs.push_back(s);
     }
-    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+    // group by dimension (groups with more work first), longest tiles first
+    std::map<uint32_t, double> group_cost;
+    for (const Work &w : work) group_cost[w.d] += w.cost;
+    std::stable_sort(work.begin(), work.end(), [&](const Work &a, const Work &b) {
+        if (a.d != b.d) return group_cost[a.d] != group_cost[b.d] ? group_cost[a.d] > group_cost[b.d] : a.d > b.d;
+        return a.cost > b.cost;
+    });
     std::vector<BatchTile> tiles(work.size());
-    for (size_t t = 0; t < work.size(); ++t) tiles[t] = work[t].t;
+    for (size_t t = 0; t < work.size(); ++t) {
+        tiles[t] = work[t].t;
+        if (c.groups.empty() || c.groups.back().d != work[t].d)
+            c.groups.push_back(BatchCtx::Group{work[t].d, fn_of_d[work[t].d], (uint32_t)t, 0});
+        c.groups.back().ntiles += 1;
+    }
     c.nq = qoff;
 
     qmc_status st;
     const size_t psize = (size_t)slot * T * c.np * sizeof(double2);
     if ((st = c.dev.alloc(c.hs.size() * sizeof(BatchSector))) || (st = c.dev.alloc(tiles.size() * sizeof(BatchTile))) ||
         (st = c.dev.alloc(g.size() * 4)) || (st = c.dev.alloc(gs.size() * 4)) || (st = c.dev.alloc(sh.size() * 8)) ||
-        (st = c.dev.alloc(prm.size() * 8)) || (st = c.dev.alloc(64)) || (st = c.dev.alloc(psize)) ||
+        (st = c.dev.alloc(prm.size() * 8)) || (st = c.dev.alloc(4 * c.groups.size() + 64)) ||
+        (st = c.dev.alloc(psize)) ||
         (st = c.dev.alloc(qoff * 8)) || (st = c.dev.alloc((size_t)count * 32)))
         return st;
     hipError_t e;
@@ -198,8 +305,20 @@ qmc_status build_ctx(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const
 }
 
 hipError_t enqueue_batch(BatchCtx &c) {
-    hipError_t e = launch_zero_u32(c.args.counter, 1, c.stream);
-    if (e == hipSuccess) e = c.fn(c.args, c.blocks, c.stream);
+    if (c.uniform) {
+        hipError_t e = c.lfn(c.largs, dim3(c.lbx, (uint32_t)c.plans.size() * c.ltiles), c.stream);
+        if (e == hipSuccess) e = launch_finalize(c.lfargs, (uint32_t)c.plans.size(), c.stream);
+        return e;
+    }
+    hipError_t e = launch_zero_u32(c.args.counter, (uint32_t)c.groups.size(), c.stream);
+    for (size_t gi = 0; gi < c.groups.size() && e == hipSuccess; ++gi) {
+        BatchArgs a = c.args;
+        a.tiles = c.args.tiles + c.groups[gi].tile_begin;
+        a.ntiles = c.groups[gi].ntiles;
+        a.counter = c.args.counter + gi;
+        const uint32_t blocks = std::min<uint32_t>(c.blocks, a.ntiles);
+        e = c.groups[gi].fn(a, blocks, c.stream);
+    }
     if (e == hipSuccess) e = launch_finalize_batch(c.fargs, (uint32_t)c.plans.size(), c.stream);
     return e;
 }
@@ -276,7 +395,11 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
         if (same_ctx(*x, count, plans, pk, tile_points)) c = x.get();
     if (!c) {
         auto fresh = std::make_unique<BatchCtx>();
-        qmc_status st = build_ctx(*fresh, count, plans, pk, tile_points);
+        bool uniform = o.tile_points == 0 && count * ((plans[0]->m + 7) / 8) <= 65535;
+        for (uint32_t i = 1; i < count && uniform; ++i)
+            uniform = plans[i]->d == plans[0]->d && plans[i]->n == plans[0]->n && plans[i]->m == plans[0]->m;
+        qmc_status st = uniform ? build_uniform(*fresh, count, plans, pk)
+                                : build_ctx(*fresh, count, plans, pk, tile_points);
         if (st) return st;
         if (g_batch.size() >= kMaxContexts) g_batch.erase(g_batch.begin());
         g_batch.push_back(std::move(fresh));

@@ -237,6 +237,17 @@ void gstep_for(const uint32_t *g, uint32_t d, uint32_t n, uint64_t S, uint32_t *
     for (uint32_t i = 0; i < d; ++i) out[i] = (uint32_t)((s * (uint64_t)g[i]) % n);
 }
 
+// shift tables on the device hold whole tiles of up to kMaxTile rows; rows
+// past m repeat the last shift (their sums are never read)
+uint32_t padded_rows(uint32_t m) { return (m + kMaxTile - 1) / kMaxTile * kMaxTile; }
+
+std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows) {
+    std::vector<double> out((size_t)rows * d);
+    for (uint32_t r = 0; r < rows; ++r)
+        for (uint32_t i = 0; i < d; ++i) out[(size_t)r * d + i] = sh[(size_t)std::min(r, m - 1) * d + i];
+    return out;
+}
+
 // --------------------------------------------------------------- plan ops
 qmc_status plan_upload_params(qmc_plan_s *p, const Packed &pk) {
     if (pk.blob.size() > p->params_cap) {
@@ -437,7 +448,8 @@ qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m
     size_t cap = 0;
     if ((st = ensure_buffer((void **)&p->d_g, cap, d * sizeof(uint32_t), "g")) ||
         (cap = 0, st = ensure_buffer((void **)&p->d_gstep, cap, d * sizeof(uint32_t), "gstep")) ||
-        (cap = 0, st = ensure_buffer((void **)&p->d_shifts, cap, (size_t)m * d * sizeof(double), "shifts")) ||
+        (cap = 0, st = ensure_buffer((void **)&p->d_shifts, cap, (size_t)padded_rows(m) * d * sizeof(double),
+                                     "shifts")) ||
         (cap = 0, st = ensure_buffer((void **)&p->d_out, cap, (2 * (size_t)m + 4) * sizeof(double), "out"))) {
         qmc_plan_destroy(p);
         return st;
@@ -448,8 +460,8 @@ qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m
         return fail(QMC_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     }
     if ((e = hipMemcpy(p->d_g, p->g.data(), d * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->d_shifts, p->shifts.data(), (size_t)m * d * sizeof(double), hipMemcpyHostToDevice)) !=
-            hipSuccess ||
+        (e = hipMemcpy(p->d_shifts, padded_shifts(p->shifts, m, d, padded_rows(m)).data(),
+                       (size_t)padded_rows(m) * d * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipEventCreate(&p->ev0)) != hipSuccess || (e = hipEventCreate(&p->ev1)) != hipSuccess) {
         qmc_plan_destroy(p);
         return hip_fail(e, "plan setup");

@@ -181,4 +181,14 @@ __device__ __forceinline__ dd wave_reduce(dd v) {
 // Uniform (wave-invariant) value as seen by the scalar unit.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+template <class P>
+__device__ __forceinline__ const P *uniform_ptr(const P *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    // the builtin returns a signed int: widen through uint32_t so the low half
+    // is not sign-extended into the high half
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const P *>(lo | (hi << 32));
+}
+
 }  // namespace qmc

@@ -27,7 +27,8 @@ struct LatticeArgs {
     double inv_n;           // 1.0 / n
     const uint32_t *g;      // generating vectors, instance stride g_stride
     const uint32_t *gstep;  // (S * g_i) mod n, same layout as g
-    const double *shifts;   // shifts (m, d) row-major, instance stride shift_stride
+    const double *shifts;   // shifts (m, d) row-major, padded to whole shift tiles by
+                            // repeating the last row; instance stride shift_stride
     const double *params;   // parameter blobs, instance stride param_stride (words)
     uint32_t g_stride, shift_stride, param_stride;
     uint32_t np;            // 1 real, 2 complex
@@ -37,11 +38,16 @@ struct LatticeArgs {
 constexpr int kChunk = 8;  // points per plain-FP64 partial before the TwoSum fold
 
 // Adds fhat over the lattice points j = j, j + S, j + 2S, ... < j1 of one
-// thread into (hi, lo) for the T shifts dl.  gs holds (S g_i) mod n.
-template <class Fam, class Tr, int D, int T>
+// thread into (hi, lo) for the T shifts starting at row pointer dls (T rows
+// of D doubles; shift tables are padded to whole tiles).  gs holds
+// (S g_i) mod n.  With Reload the shifts are re-read through the scalar
+// cache at every point instead of being held in registers across the loop
+// (the persistent kernel, whose tile loop would otherwise keep them in
+// vector registers).
+template <class Fam, class Tr, int D, int T, bool Reload = false>
 __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S, uint32_t n, double inv_n,
                                             const uint32_t *__restrict__ g, const uint32_t *__restrict__ gs,
-                                            const double (&dl)[T][D], const double *__restrict__ prm,
+                                            const double *__restrict__ dls, const double *__restrict__ prm,
                                             double (&hi)[T][Fam::NP], double (&lo)[T][Fam::NP]) {
     constexpr int NP = Fam::NP;
     if (j >= j1) return;
@@ -67,11 +73,16 @@ __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S,
                 y[i] = (double)idx[i] * inv_n;
                 idx[i] = walk(idx[i], step[i], nms[i]);
             }
+            const double *dl = dls;
+            if constexpr (Reload) {
+                dl = uniform_ptr(dls);
+                asm volatile("" : "+s"(dl));  // keep the shift loads inside the loop
+            }
             double x[T][D];
 #pragma unroll
             for (int k = 0; k < T; ++k)
 #pragma unroll
-                for (int i = 0; i < D; ++i) x[k][i] = fract(y[i] + dl[k][i]);
+                for (int i = 0; i < D; ++i) x[k][i] = fract(y[i] + dl[k * D + i]);
             double v[T][NP];
             Fam::template eval<Tr, D, T>(prm, x, v);
 #pragma unroll
@@ -84,19 +95,6 @@ __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S,
         for (int k = 0; k < T; ++k)
 #pragma unroll
             for (int p = 0; p < NP; ++p) dd_accumulate(hi[k][p], lo[k][p], s[k][p]);
-    }
-}
-
-// shifts k0 .. k0+T-1 of an (m, D) row-major table; rows past m repeat the
-// last shift (their sums are discarded)
-template <int D, int T>
-__device__ __forceinline__ void load_shifts(const double *__restrict__ sh, uint32_t k0, uint32_t m,
-                                            double (&dl)[T][D]) {
-#pragma unroll
-    for (int k = 0; k < T; ++k) {
-        const uint32_t row = min(k0 + (uint32_t)k, m - 1u);
-#pragma unroll
-        for (int i = 0; i < D; ++i) dl[k][i] = sh[row * D + i];
     }
 }
 
@@ -138,10 +136,8 @@ __global__ __launch_bounds__(kBlock) void k_lattice(const LatticeArgs a) {
     for (int k = 0; k < T; ++k)
 #pragma unroll
         for (int p = 0; p < NP; ++p) hi[k][p] = lo[k][p] = 0.0;
-    double dl[T][D];
-    load_shifts<D, T>(sh, k0, a.m, dl);
     walk_points<Fam, Tr, D, T>(blockIdx.x * kBlock + threadIdx.x, a.n, gridDim.x * kBlock, a.n, a.inv_n, g, gs,
-                               dl, prm, hi, lo);
+                               sh + (size_t)k0 * D, prm, hi, lo);
 
     __shared__ dd red[kBlock / kWave][T * NP];
     const dd r = block_reduce<T, NP>(hi, lo, red);
@@ -181,9 +177,9 @@ struct BatchArgs {
     uint32_t tile_points;  // multiple of kBlock
     const uint32_t *g;     // concatenated generating vectors
     const uint32_t *gstep; // (kBlock g_i) mod n, same layout
-    const double *shifts;  // concatenated (m, d) tables
+    const double *shifts;  // concatenated (m, d) tables, each padded to whole tiles
     const double *params;  // concatenated parameter blobs
-    uint32_t *counter;     // next tile; zeroed before the launch
+    uint32_t *counter;     // next tile of this list; zeroed before the launch
     double2 *partials;     // (slot, T * np)
 };
 
@@ -196,12 +192,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const BatchTile &
     for (int k = 0; k < T; ++k)
 #pragma unroll
         for (int p = 0; p < NP; ++p) hi[k][p] = lo[k][p] = 0.0;
-    double dl[T][D];
-    load_shifts<D, T>(a.shifts + sc.shift_off, tl.k0, sc.m, dl);
     const uint32_t j0 = tl.jt * a.tile_points;
     const uint32_t j1 = min(sc.n, j0 + a.tile_points);
-    walk_points<Fam, Tr, D, T>(j0 + threadIdx.x, j1, kBlock, sc.n, sc.inv_n, a.g + sc.g_off, a.gstep + sc.g_off,
-                               dl, a.params + sc.param_off, hi, lo);
+    walk_points<Fam, Tr, D, T, true>(j0 + threadIdx.x, j1, kBlock, sc.n, sc.inv_n, a.g + sc.g_off, a.gstep + sc.g_off,
+                               a.shifts + sc.shift_off + (size_t)tl.k0 * D, a.params + sc.param_off, hi, lo);
     const dd r = block_reduce<T, NP>(hi, lo, red);
     if (threadIdx.x < (uint32_t)(T * NP)) {
         const size_t slot = (size_t)sc.slot_base + (size_t)(tl.k0 / T) * sc.jtiles + tl.jt;
@@ -209,7 +203,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const BatchTile &
     }
 }
 
-template <class Fam, class Tr, int T, int DMAX>
+// One persistent kernel per dimension: the tiles of the plans with d = D
+// are a contiguous run of the list (tiles, ntiles) with their own counter.
+template <class Fam, class Tr, int D, int T>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
     __shared__ uint32_t s_tile;
     __shared__ dd red[kBlock / kWave][T * Fam::NP];
@@ -220,19 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
         if (t >= a.ntiles) break;
         const BatchTile tl = a.tiles[t];
         const BatchSector sc = a.sectors[tl.sector];
-        switch (sc.d) {
-#define QMC_BATCH_CASE(DD) \
-    case DD:               \
-        if constexpr (DD <= DMAX) batch_tile<Fam, Tr, DD, T>(a, tl, sc, red); \
-        break;
-            QMC_BATCH_CASE(1) QMC_BATCH_CASE(2) QMC_BATCH_CASE(3) QMC_BATCH_CASE(4)
-            QMC_BATCH_CASE(5) QMC_BATCH_CASE(6) QMC_BATCH_CASE(7) QMC_BATCH_CASE(8)
-            QMC_BATCH_CASE(9) QMC_BATCH_CASE(10) QMC_BATCH_CASE(11) QMC_BATCH_CASE(12)
-            QMC_BATCH_CASE(13) QMC_BATCH_CASE(14) QMC_BATCH_CASE(15) QMC_BATCH_CASE(16)
-#undef QMC_BATCH_CASE
-        default:
-            break;
-        }
+        batch_tile<Fam, Tr, D, T>(a, tl, sc, red);
         __syncthreads();
     }
 }

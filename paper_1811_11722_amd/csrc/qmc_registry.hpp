@@ -44,9 +44,9 @@ hipError_t launch_lattice(const LatticeArgs &a, dim3 grid, hipStream_t s) {
 }
 
 struct BatchKey {
-    int family, tkind, alpha, T, dmax;
+    int family, tkind, alpha, d, T;
     bool operator<(const BatchKey &o) const {
-        return std::tie(family, tkind, alpha, T, dmax) < std::tie(o.family, o.tkind, o.alpha, o.T, o.dmax);
+        return std::tie(family, tkind, alpha, d, T) < std::tie(o.family, o.tkind, o.alpha, o.d, o.T);
     }
 };
 
@@ -58,9 +58,9 @@ struct BatchRegistrar {
     BatchRegistrar(BatchKey k, BatchLaunch f) { batch_registry()[k] = f; }
 };
 
-template <class Fam, class Tr, int T, int DMAX>
+template <class Fam, class Tr, int D, int T>
 hipError_t launch_batch(const BatchArgs &a, uint32_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_batch<Fam, Tr, T, DMAX>), dim3(blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_batch<Fam, Tr, D, T>), dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 namespace qmc {
 
 constexpr uint32_t kMaxDim = 16;
+constexpr uint32_t kMaxTile = 8;  // largest shift tile of any kernel
 
 struct qmc_plan_extra;  // batch / graph state, owned by qmc_batch.hip
 
@@ -74,6 +75,8 @@ qmc_status plan_set_gstep(qmc_plan_s *p, uint32_t S);
 qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32_t blocks_per_cu);
 qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift);
 void plan_release_extra(qmc_plan_s *p);
+uint32_t padded_rows(uint32_t m);
+std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows);
 hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
                          bool cplx, int dev, std::string &err);
 hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s);

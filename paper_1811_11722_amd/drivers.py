@@ -1,0 +1,153 @@
+"""Drivers above the estimator: batches of sectors with an error-goal lattice
+size rule, and throughput batches of small instances.
+
+Every estimate runs in the HIP library (qmc_integrate / qmc_integrate_batch);
+this module only chooses lattice sizes and generating vectors, builds plans
+and times calls.
+
+    python -m paper_1811_11722_amd.drivers sector_batch [--count 2000]
+    python -m paper_1811_11722_amd.drivers product_peak_batch [--count 512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+from . import qmc, synth
+
+LADDER = synth.prime_ladder(14, 24)  # largest prime below 2^k, k = 14..24
+
+
+class GeneratingVectors:
+    """Korobov generating vectors chosen on the GPU by the P2 criterion, one
+    per (n, d), cached."""
+
+    def __init__(self, seed: int, candidates: int = 64):
+        self.seed, self.candidates = seed, candidates
+        self.cache: Dict[Tuple[int, int], np.ndarray] = {}
+
+    def __call__(self, n: int, d: int) -> np.ndarray:
+        key = (n, d)
+        if key not in self.cache:
+            a, _, _ = qmc.korobov_search(n, d, synth.korobov_candidates(self.seed, n, self.candidates))
+            self.cache[key] = qmc.korobov_vector(n, d, a)
+        return self.cache[key]
+
+
+def allocate_n(rel_err0: float, n0: int, goal: float, rate: float = 2.0) -> int:
+    """Smallest ladder prime >= n0 (r0 / goal)^(1/rate), clamped to the ladder:
+    the error of the baker-transformed rule falls like n^-2 (Sec. 2)."""
+    if not np.isfinite(rel_err0) or rel_err0 <= goal:
+        return LADDER[0]
+    want = n0 * (rel_err0 / goal) ** (1.0 / rate)
+    for n in LADDER:
+        if n >= want:
+            return n
+    return LADDER[-1]
+
+
+def _timed(fn, reps: int):
+    fn()  # warm-up (uploads, graph capture)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t0)
+    return out, float(np.median(ts))
+
+
+def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int = synth.SEED_BASE + 3,
+                 tile_points: int = 8192, reps: int = 3, compare: bool = True) -> dict:
+    """Batched sectors: pilot estimates at n0 = 16381, the error-goal rule for
+    each sector's n, then one graph-replayed persistent launch against one
+    launch per sector."""
+    tabs = synth.sector_batch(seed, count)
+    gv = GeneratingVectors(seed)
+    n0 = LADDER[0]
+    params = [qmc.Params("sector", t.d, sector=t) for t in tabs]
+
+    pilots = [qmc.Plan(t.d, n0, gv(n0, t.d), synth.shifts(seed, m, t.d, stream=16 + s, sub=3),
+                       "baker") for s, t in enumerate(tabs)]
+    t0 = time.perf_counter()
+    pres = qmc.integrate_batch(pilots, params, tile_points=tile_points)
+    t_pilot = time.perf_counter() - t0
+    rel0 = [abs(r.err_re) / abs(r.mean_re) for r in pres]
+    ns = [allocate_n(r, n0, goal) for r in rel0]
+    for p in pilots:
+        p.close()
+
+    t0 = time.perf_counter()
+    plans = [qmc.Plan(t.d, n, gv(n, t.d), synth.sector_batch_shifts(seed, s, m, t.d), "baker")
+             for s, (t, n) in enumerate(zip(tabs, ns))]
+    t_setup = time.perf_counter() - t0
+    evals = int(sum(n * m for n in ns))
+    res, t_graph = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True,
+                                                     tile_points=tile_points), reps)
+    out = {
+        "sectors": count, "m": m, "goal": goal, "tile_points": tile_points,
+        "pilot_n": n0, "pilot_seconds": t_pilot,
+        "n_histogram": {str(n): int(sum(1 for v in ns if v == n)) for n in sorted(set(ns))},
+        "sectors_at_cap": int(sum(1 for v in ns if v == LADDER[-1])),
+        "evals": evals, "setup_seconds": t_setup,
+        "graph_seconds": t_graph, "graph_evals_per_s": evals / t_graph,
+        "rel_err_max": float(max(abs(r.err_re) / abs(r.mean_re) for r in res)),
+        "rel_err_median": float(np.median([abs(r.err_re) / abs(r.mean_re) for r in res])),
+    }
+    if compare:
+        res_pp, t_pp = _timed(lambda: qmc.integrate_batch(plans, params, per_plan_launches=True),
+                              reps)
+        out["per_plan_seconds"] = t_pp
+        out["per_plan_evals_per_s"] = evals / t_pp
+        out["speedup_graph_vs_per_plan"] = t_pp / t_graph
+        out["max_rel_diff_graph_vs_per_plan"] = float(max(
+            abs(a.mean_re - b.mean_re) / abs(b.mean_re) for a, b in zip(res, res_pp)))
+    for p in plans:
+        p.close()
+    return out
+
+
+def product_peak_batch(count: int = 512, n: int = 131071, m: int = 16, d: int = 4,
+                       seed: int = synth.SEED_BASE + 1, tile_points: int = 0, reps: int = 5) -> dict:
+    """Throughput on many Genz product-peak instances (Korobov weight 3):
+    shared generating vector and shifts, own a_i and u_i per instance."""
+    w = synth.product_peak_workload(n=n, m=m, d=d, seed=seed)
+    a, _, _ = qmc.korobov_search(n, d, w.candidates)
+    g = qmc.korobov_vector(n, d, a)
+    plans, params = [], []
+    for b in range(count):
+        aa, uu = synth.genz_params(seed, d, stream=16 + b)
+        plans.append(qmc.Plan(d, n, g, w.shifts, "korobov", 3))
+        params.append(qmc.Params("genz_product_peak", d, a=aa, u=uu))
+    res, t = _timed(lambda: qmc.integrate_batch(plans, params, tile_points=tile_points), reps)
+    evals = count * n * m
+    for p in plans:
+        p.close()
+    return {"instances": count, "n": n, "m": m, "d": d, "evals": evals, "seconds": t,
+            "evals_per_s": evals / t, "generator_a": a}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["sector_batch", "product_peak_batch"])
+    ap.add_argument("--count", type=int, default=0)
+    ap.add_argument("--tile-points", type=int, default=-1)
+    ap.add_argument("--no-compare", action="store_true")
+    args = ap.parse_args(argv)
+    if args.what == "sector_batch":
+        out = sector_batch(count=args.count or 2000,
+                           tile_points=8192 if args.tile_points < 0 else args.tile_points,
+                           compare=not args.no_compare)
+    else:
+        out = product_peak_batch(count=args.count or 512,
+                                 tile_points=0 if args.tile_points < 0 else args.tile_points)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

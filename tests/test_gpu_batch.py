@@ -97,6 +97,28 @@ def test_genz_batch(Q):
         assert np.all(_rel(q, est.q_re) < TOL)
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_uniform_batch_instances(Q, use_graph):
+    """Plans with one (d, n, m) run as instances of a single lattice launch."""
+    d, n, m = 4, 16381, 16
+    plans, params, cases = [], [], []
+    for b in range(40):
+        a, u = synth.genz_params(2000 + b, d)
+        g = O.korobov_vector(n, d, 76 + 2 * b)
+        sh = synth.shifts(2000 + b, m, d)
+        plans.append(Q.Plan(d, n, g, sh, "korobov", 3))
+        params.append(Q.Params("genz_product_peak", d, a=a, u=u))
+        cases.append((a, u, g, sh))
+    _say(f"uniform batch graph={use_graph}")
+    res = Q.integrate_batch(plans, params, use_graph=use_graph)
+    per = Q.batch_per_shift(plans)
+    for (a, u, g, sh), q, r in zip(cases, per, res):
+        est = O.estimate(n, g, sh, O.Params("genz_product_peak", d, a=a, u=u), "korobov", 3,
+                         threads=THREADS)
+        assert np.all(_rel(q, est.q_re) < TOL)
+        assert abs(r.mean_re - est.mean_error()[0].real) <= TOL * abs(r.mean_re)
+
+
 def test_complex_batch(Q):
     d, m = 4, 4
     plans, params, cases = [], [], []
