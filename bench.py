@@ -32,6 +32,12 @@ def flops_per_eval(workload: str) -> float:
     return {"sector": 280.0, "product_peak": 91.0}[workload]
 
 
+# HBM bytes per lattice-kernel launch from rocprofv3 FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0 (factors from a 256 MiB copy of known size); recorded for
+# the kernel as profiled (profiles/k_lattice_sector_jit_d6_n16777213_m32.md).
+TRAFFIC_BYTES = {"sector": 301466}
+
+
 def make_workload(name: str):
     from paper_1811_11722_amd import synth
     if name == "sector":
@@ -85,6 +91,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="shift tile override (0 = tuned/default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 4 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the estimator "
@@ -94,6 +102,15 @@ def main():
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "copies": 4}))
+        return
     from paper_1811_11722_amd import qmc
 
     w, tk, alpha = make_workload(args.workload)
@@ -143,7 +160,8 @@ def main():
                    "family": w.family, "evals_per_step": evals, "generator_a": a},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "k_lattice", "kernel_ms": avg_kernel_s * 1e3,
+                     "traffic": TRAFFIC_BYTES.get(args.workload), "kernel": "k_lattice",
+                     "kernel_ms": avg_kernel_s * 1e3,
                      "flops_per_eval": fpe},
         "result": {"mean": res.mean_re, "err": res.err_re},
     }
