@@ -126,13 +126,13 @@ typedef struct {
 } qmc_launch;
 
 /* Create a plan for the rule of eq. (2).
-   d       dimension, 1..32
+   d       dimension, 1..16
    n       number of lattice points, 2..2^31
    g       generating vector, length d; every g_i mod n must be nonzero
    m       number of shifts, >= 2 (eq. (3) divides by m - 1)
    shifts  m*d doubles, row-major (shift k is shifts[k*d .. k*d+d-1]), each in [0,1)
    t       periodising transform
-   Errors: EINVAL on a bad argument, EUNSUPPORTED for d > 32, n > 2^31 or a
+   Errors: EINVAL on a bad argument, EUNSUPPORTED for d > 16, n > 2^31 or a
    Korobov weight above 6, ENOMEM / EDEVICE from the device. */
 qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m,
                            const double *shifts, qmc_transform t, qmc_plan_t *out);
@@ -188,7 +188,7 @@ qmc_status qmc_korobov_vector(uint64_t n, uint32_t d, uint64_t a, uint64_t *g);
    as an unshifted lattice rule; returns the minimiser (ties: smaller P2, then
    smaller a).  p2_all (nullable) receives all ncand values.  The generating
    vector itself is not fixed by the paper (Sec. 2 only names it); this is
-   the standard worst-case-error choice.  n <= 2^31, d <= 32, ncand <= 4096. */
+   the standard worst-case-error choice.  n <= 2^31, d <= 16, ncand <= 4096. */
 qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint32_t ncand,
                               uint64_t *a_best, double *p2_best, double *p2_all);
 
@@ -223,6 +223,58 @@ qmc_status qmc_batch_per_shift(uint32_t count, const qmc_plan_t *plans, double *
    file named by the QMC_TUNE_CACHE environment variable (if set).  best
    (nullable) receives the choice. */
 qmc_status qmc_autotune(qmc_plan_t plan, qmc_family family, const void *params, qmc_launch *best);
+
+/* ---------------------------------------------------------------- control
+   variate.  A separable rank-R model on orthonormal shifted Legendre
+   polynomials P~_k(z) = sqrt(2k+1) P_k(2z - 1), k < K:
+     g(z) = sum_r c_r prod_i sum_k W[r,i,k] P~_k(z_i),   int g = sum_r c_r prod_i W[r,i,0],
+   W row-major (R, d, K).  The estimate int g + Qbar[f - g] keeps eqs. (2)-(3)
+   unbiased (g is fitted on an independent training lattice) and the m
+   shifts judge its error.  Built for real QMC_F_SECTOR integrands with
+   (R, K) in {(8,4), (8,8), (16,8), (16,12), (32,8), (32,12), (32,16), (64,12)}
+   and d <= 12. */
+typedef struct {
+    uint32_t max_sweeps;  /* alternating least-squares sweeps (0 = 12) */
+    double ridge;         /* ridge relative to the mean diagonal (0 = 1e-5) */
+    double tol;           /* stop when the relative loss improves less than this */
+    uint64_t seed;        /* initial-factor seed */
+} qmc_cv_train_opts;
+
+typedef struct {
+    uint32_t sweeps;      /* sweeps run */
+    double rel_loss;      /* sum (fhat - J g)^2 / sum fhat^2 on the training set */
+    double scale;         /* target scale (mean |fhat|), folded into c */
+    double seconds;       /* device time of the training */
+} qmc_cv_train_report;
+
+/* Fit W and c to the integrand sampled at the n points of train_plan's
+   lattice with its first shift (z, J and fhat are sampled by the GPU), by
+   minimising sum_j (fhat_j - J_j g(z_j))^2 + lam |W[., i, .]|^2 with
+   alternating least squares over the dimensions i.  Each step assembles its
+   normal equations with BF16 MFMA (FP32 accumulation), factorises them in
+   FP64 and refines the solution twice against the FP32 residual; a sweep
+   ends by balancing each rank's factor norms.  The control variate is an
+   addition to the paper's estimator (it does not appear in the paper); the
+   estimate it feeds stays unbiased because the training lattice is
+   independent of the estimation shifts.  QMC_F_SECTOR only, real
+   integrands, d <= 12, (R, K) in {(8,4), (8,8), (16,8), (16,12), (32,8),
+   (32,12), (32,16), (64,12)} (EUNSUPPORTED otherwise); ENONFINITE when the
+   loss is not finite.  w_out: R*d*K doubles (orthonormal-basis
+   coefficients), c_out: R doubles (caller-owned).  rep nullable. */
+qmc_status qmc_cv_train(qmc_plan_t train_plan, qmc_family family, const void *params, uint32_t R, uint32_t K,
+                        const qmc_cv_train_opts *opts, double *w_out, double *c_out, qmc_cv_train_report *rep);
+
+/* int g over [0,1]^d in closed form. */
+qmc_status qmc_cv_integral(uint32_t R, uint32_t d, uint32_t K, const double *w, const double *c, double *out);
+
+/* One pass over the plan's lattice evaluating fhat and the residual
+   fhat - J g (g in FP64).  plain_out (nullable): the plain estimate of the
+   same pass; out: int g + Qbar[f - g] with its error, or the plain estimate
+   (used_cv = 0) when the residual's error is not smaller.  per_shift
+   (nullable, 2m doubles): (plain Q_k, residual Q_k) interleaved. */
+qmc_status qmc_integrate_cv(qmc_plan_t plan, qmc_family family, const void *params, uint32_t R, uint32_t K,
+                            const double *w, const double *c, qmc_result *out, qmc_result *plain_out,
+                            double *per_shift);
 
 /* The library's device FP64 logarithm (fn = 0, argument > 0) or exponential
    (fn = 1) on count host values x, results in y; for checking the device

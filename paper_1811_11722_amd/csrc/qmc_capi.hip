@@ -293,24 +293,10 @@ qmc_status plan_set_gstep(qmc_plan_s *p, uint32_t S) {
     return QMC_OK;
 }
 
-// Enqueue the lattice kernel and the finalize kernel of one estimate.
-qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32_t bpc) {
-    uint32_t T = 0;
-    LatticeLaunch fn = nullptr;
-    hipFunction_t jfn = nullptr;
-    const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
-    if (sector && p->jit_mode != 0) {
-        T = want_T ? want_T : (pk.np == 2 ? 1u : 2u);
-        std::string err;
-        jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.np == 2, p->device, err);
-        if (!jfn && p->jit_mode == 2) return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
-    }
-    if (!jfn) {
-        fn = find_kernel(pk.key_family, p->tr, p->d, want_T ? want_T : default_tile(pk.key_family), T);
-        if (!fn)
-            return fail(QMC_EUNSUPPORTED, "no kernel for family %d, transform %d/%d, d = %u", pk.key_family,
-                        p->tr.kind, p->tr.alpha, p->d);
-    }
+// Enqueue the lattice kernel (a registry launcher or a specialised module
+// function) and the finalize kernel of one estimate.
+static qmc_status plan_launch(qmc_plan_s *p, const Packed &pk, LatticeLaunch fn, hipFunction_t jfn, uint32_t T,
+                              uint32_t bpc) {
     if (p->m * pk.np > kMaxRows) return fail(QMC_EUNSUPPORTED, "m * parts > %u", kMaxRows);
     qmc_status st = plan_upload_params(p, pk);
     if (st) return st;
@@ -354,6 +340,30 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     p->last_bx = bx;
     p->last_jit = jfn != nullptr;
     return QMC_OK;
+}
+
+qmc_status plan_enqueue_fn(qmc_plan_s *p, const Packed &pk, hipFunction_t jfn, uint32_t T) {
+    return plan_launch(p, pk, nullptr, jfn, T, p->launch.blocks_per_cu);
+}
+
+qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32_t bpc) {
+    uint32_t T = 0;
+    LatticeLaunch fn = nullptr;
+    hipFunction_t jfn = nullptr;
+    const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
+    if (sector && p->jit_mode != 0) {
+        T = want_T ? want_T : (pk.np == 2 ? 1u : 2u);
+        std::string err;
+        jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.np == 2, p->device, err);
+        if (!jfn && p->jit_mode == 2) return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
+    }
+    if (!jfn) {
+        fn = find_kernel(pk.key_family, p->tr, p->d, want_T ? want_T : default_tile(pk.key_family), T);
+        if (!fn)
+            return fail(QMC_EUNSUPPORTED, "no kernel for family %d, transform %d/%d, d = %u", pk.key_family,
+                        p->tr.kind, p->tr.alpha, p->d);
+    }
+    return plan_launch(p, pk, fn, jfn, T, bpc);
 }
 
 qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift) {

@@ -22,6 +22,7 @@
 
 #include "qmc_jit_headers.inc"
 #include "qmc_runtime.hpp"
+#include "qmc_cv.hpp"
 
 namespace qmc {
 
@@ -77,15 +78,14 @@ const char *transform_type(const qmc_transform &t) {
 
 }  // namespace
 
-// Source of the specialised functor + the kernel instantiation; `structure`
-// receives a canonical description of what the code depends on.
-static std::string jit_source(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr,
-                              uint32_t T, bool cplx, std::string &name_expr, std::string &structure) {
+// Source of the specialised functor FamJit; `structure` receives a
+// canonical description of what the code depends on.
+static std::string functor_source(const std::vector<double> &blob, uint32_t d, bool cplx, std::string &structure) {
     const uint32_t nu = (uint32_t)word(blob, 0), nf = (uint32_t)word(blob, 1);
     Trie trie;
     std::vector<int> mu(nu), mf(nf);
     std::ostringstream st;
-    st << "d" << d << "T" << T << "c" << cplx << "t" << tr.kind << "a" << tr.alpha << "|";
+    st << "d" << d << "c" << cplx << "|";
     for (uint32_t t = 0; t < nu; ++t) {
         const uint64_t c = word(blob, kSectorHeader + nu + t);
         mu[t] = trie.insert(factors_of(c));
@@ -106,7 +106,7 @@ static std::string jit_source(const std::vector<double> &blob, uint32_t d, const
     structure = st.str();
 
     std::ostringstream s;
-    s << "#include \"qmc_kernels.hpp\"\nnamespace qmc {\nstruct FamJit {\n"
+    s << "struct FamJit {\n"
       << "    static constexpr int NP = " << (cplx ? 2 : 1) << ";\n"
       << "    template <class Tr, int D, int T>\n"
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
@@ -148,11 +148,6 @@ static std::string jit_source(const std::vector<double> &blob, uint32_t d, const
       << "            sector_finish<" << (cplx ? "true" : "false")
       << ">(mono, U, F, flags, pow_u, pow_f, delta, v[k]);\n"
       << "        }\n    }\n};\n";
-    std::ostringstream ne;
-    ne << "qmc::k_lattice<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ", " << T << ">";
-    name_expr = ne.str();
-    s << "template __global__ void k_lattice<FamJit, " << transform_type(tr) << ", " << d << ", " << T
-      << ">(const LatticeArgs);\n}  // namespace qmc\n";
     return s.str();
 }
 
@@ -163,15 +158,12 @@ static std::string device_arch(int dev) {
     return a.empty() ? std::string("gfx950") : a;
 }
 
-// Compile (or fetch) the specialised kernel for this blob; returns nullptr
-// and sets `err` when compilation fails.
-hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
-                         bool cplx, int dev, std::string &err) {
-    std::string name_expr, structure;
-    const std::string src = jit_source(blob, d, tr, T, cplx, name_expr, structure);
-    const std::string key = std::to_string(dev) + "#" + structure;
+// Compile (or fetch from the process cache) `src`, returning the function
+// named by name_expr; nullptr and `err` on failure.
+static hipFunction_t compile_cached(const std::string &src, const std::string &name_expr, const std::string &key,
+                                    int dev, std::string &err) {
     if (const char *dump = std::getenv("QMC_JIT_DUMP")) {  // write the generated source for inspection
-        std::ofstream(std::string(dump) + "/" + std::to_string(std::hash<std::string>()(structure)) + ".hip") << src;
+        std::ofstream(std::string(dump) + "/" + std::to_string(std::hash<std::string>()(key)) + ".hip") << src;
     }
     std::lock_guard<std::mutex> lock(g_jit_mu);
     auto it = g_jit_cache.find(key);
@@ -219,6 +211,54 @@ hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_
     err = e.error;
     g_jit_cache[key] = e;
     return e.fn;
+}
+
+// The lattice kernel with the specialised sector functor.
+hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
+                         bool cplx, int dev, std::string &err) {
+    std::string structure;
+    const std::string fam = functor_source(blob, d, cplx, structure);
+    std::ostringstream ne, src, key;
+    ne << "qmc::k_lattice<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ", " << T << ">";
+    src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_lattice<FamJit, "
+        << transform_type(tr) << ", " << d << ", " << T << ">(const LatticeArgs);\n}  // namespace qmc\n";
+    key << dev << "#lattice#T" << T << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
+    return compile_cached(src.str(), ne.str(), key.str(), dev, err);
+}
+
+// The lattice kernel with the control-variate residual around the
+// specialised functor (parts: fhat, fhat - J g).
+hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint32_t d, const qmc_transform &tr,
+                            uint32_t R, uint32_t K, int dev, std::string &err) {
+    std::string structure;
+    const std::string fam = functor_source(blob, d, false, structure);
+    std::ostringstream ne, src, key, cvt;
+    cvt << "FamCvResidual<FamJit, " << R << ", " << K << ", " << cv_off << ">";
+    ne << "qmc::k_lattice<qmc::FamCvResidual<qmc::FamJit, " << R << ", " << K << ", " << cv_off << ">, qmc::"
+       << transform_type(tr) << ", " << d << ", 1>";
+    src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_lattice<" << cvt.str()
+        << ", " << transform_type(tr) << ", " << d << ", 1>(const LatticeArgs);\n}  // namespace qmc\n";
+    key << dev << "#cv#R" << R << "K" << K << "o" << cv_off << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
+    return compile_cached(src.str(), ne.str(), key.str(), dev, err);
+}
+
+// The training-lattice sampler with the specialised functor.
+hipFunction_t jit_sample_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, int dev,
+                                std::string &err) {
+    std::string structure;
+    const std::string fam = functor_source(blob, d, false, structure);
+    std::ostringstream ne, src, key;
+    ne << "qmc::k_cv_sample<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ">";
+    src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_cv_sample<FamJit, "
+        << transform_type(tr) << ", " << d << ">(const CvSampleArgs);\n}  // namespace qmc\n";
+    key << dev << "#sample#t" << tr.kind << "a" << tr.alpha << "#" << structure;
+    return compile_cached(src.str(), ne.str(), key.str(), dev, err);
+}
+
+hipError_t jit_launch_sample(hipFunction_t fn, const CvSampleArgs &a, uint32_t blocks, hipStream_t s) {
+    CvSampleArgs copy = a;
+    void *args[] = {&copy};
+    return hipModuleLaunchKernel(fn, blocks, 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
 }
 
 hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s) {

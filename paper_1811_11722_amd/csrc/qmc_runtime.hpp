@@ -80,6 +80,13 @@ std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uin
 hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
                          bool cplx, int dev, std::string &err);
 hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s);
+struct CvSampleArgs;
+hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint32_t d, const qmc_transform &tr,
+                            uint32_t R, uint32_t K, int dev, std::string &err);
+hipFunction_t jit_sample_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, int dev,
+                                std::string &err);
+hipError_t jit_launch_sample(hipFunction_t fn, const CvSampleArgs &a, uint32_t blocks, hipStream_t s);
+qmc_status plan_enqueue_fn(qmc_plan_s *p, const Packed &pk, hipFunction_t jfn, uint32_t T);
 std::string tune_key(const qmc_plan_s *p, const Packed &pk, bool jit);
 bool tune_lookup(const qmc_plan_s *p, const Packed &pk, bool jit, qmc_launch &out);
 

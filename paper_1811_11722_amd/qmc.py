@@ -63,6 +63,16 @@ class qmc_result(C.Structure):
                 ("err_im", C.c_double), ("is_complex", C.c_int32), ("used_cv", C.c_int32)]
 
 
+class qmc_cv_train_opts(C.Structure):
+    _fields_ = [("max_sweeps", C.c_uint32), ("ridge", C.c_double), ("tol", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class qmc_cv_train_report(C.Structure):
+    _fields_ = [("sweeps", C.c_uint32), ("rel_loss", C.c_double), ("scale", C.c_double),
+                ("seconds", C.c_double)]
+
+
 class qmc_launch(C.Structure):
     _fields_ = [("shift_tile", C.c_uint32), ("blocks_per_cu", C.c_uint32)]
 
@@ -90,6 +100,9 @@ SIGNATURES = {
     "qmc_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "qmc_batch_per_shift": (C.c_int, [_u32, _vp, _vp]),
     "qmc_math_eval": (C.c_int, [_i32, _u64, _vp, _vp]),
+    "qmc_cv_train": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp]),
+    "qmc_cv_integral": (C.c_int, [_u32, _u32, _u32, _vp, _vp, _vp]),
+    "qmc_integrate_cv": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
     "qmc_last_error": (C.c_char_p, []),
@@ -241,6 +254,29 @@ class Plan:
         st = lib().qmc_integrate(self.handle, params.family, params.ptr, C.byref(res), _p(per))
         return st, res, per
 
+    def cv_train(self, params: Params, R: int, K: int, max_sweeps: int = 0, ridge: float = 0.0,
+                 tol: float = 1e-4, seed: int = 1):
+        """Fit the Legendre control variate on this plan's lattice (first shift).
+        Returns (W (R, d, K), c (R,), report)."""
+        W = np.zeros((R, self.d, K))
+        c = np.zeros(R)
+        opts = qmc_cv_train_opts(max_sweeps, ridge, tol, seed)
+        rep = qmc_cv_train_report()
+        check(lib().qmc_cv_train(self.handle, params.family, params.ptr, R, K, C.byref(opts), _p(W),
+                                 _p(c), C.byref(rep)), "qmc_cv_train")
+        return W, c, rep
+
+    def integrate_cv(self, params: Params, W, c):
+        """Returns (result, plain result, per-shift (plain, residual) arrays)."""
+        W = _arr(W, np.float64)
+        c = _arr(c, np.float64)
+        R, d, K = W.shape
+        out, plain = qmc_result(), qmc_result()
+        per = np.zeros(2 * self.m)
+        check(lib().qmc_integrate_cv(self.handle, params.family, params.ptr, R, K, _p(W), _p(c),
+                                     C.byref(out), C.byref(plain), _p(per)), "qmc_integrate_cv")
+        return out, plain, per[0::2].copy(), per[1::2].copy()
+
     def lattice_dump(self, j_lo: int, count: int):
         idx = np.zeros((count, self.d), dtype=np.uint32)
         sums = np.zeros(2 * self.d, dtype=np.uint64)
@@ -260,6 +296,15 @@ def math_eval(fn: str, x) -> np.ndarray:
     y = np.zeros_like(x)
     check(lib().qmc_math_eval({"log": 0, "exp": 1}[fn], x.size, _p(x), _p(y)), "qmc_math_eval")
     return y
+
+
+def cv_integral(W, c) -> float:
+    W = _arr(W, np.float64)
+    c = _arr(c, np.float64)
+    R, d, K = W.shape
+    out = C.c_double()
+    check(lib().qmc_cv_integral(R, d, K, _p(W), _p(c), C.byref(out)), "qmc_cv_integral")
+    return out.value
 
 
 def korobov_vector(n: int, d: int, a: int) -> np.ndarray:
