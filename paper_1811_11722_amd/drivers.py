@@ -7,6 +7,8 @@ and times calls.
 
     python -m paper_1811_11722_amd.drivers sector_batch [--count 2000]
     python -m paper_1811_11722_amd.drivers product_peak_batch [--count 512]
+    python -m paper_1811_11722_amd.drivers time_to_error
+    python -m paper_1811_11722_amd.drivers convergence
 """
 from __future__ import annotations
 
@@ -132,9 +134,129 @@ def product_peak_batch(count: int = 512, n: int = 131071, m: int = 16, d: int = 
             "evals_per_s": evals / t, "generator_a": a}
 
 
+def _sync():
+    import torch
+    torch.cuda.synchronize()  # the library calls return synchronously; kept as a guard
+
+
+def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 4,
+                  goal: float = 1e-7, m: int = 32, R: int = 32, K: int = 12, n_train: int = 1048573,
+                  kmin: int = 14, kmax: int = 26, max_sweeps: int = 12, log=None) -> dict:
+    """Time to a relative error goal, plain estimator against the control
+    variate (real sector integrand, baker's transform).  Each form runs the
+    ladder of primes below 2^k upwards until err / |mean| <= goal; reported:
+    the wall time of the first lattice size that meets the goal (CV training
+    included for the CV form), the cumulative ladder time, and every rung.
+    Generating vectors are searched once per (n, d) beforehand (tabulated in
+    practice) and their time is reported on its own; the first call of each
+    form compiles its specialised kernel and is not timed."""
+    tab = synth.sector_tables(seed, d, n_u, n_f)
+    params = qmc.Params("sector", d, sector=tab)
+    ladder = synth.prime_ladder(kmin, kmax)
+    sh = synth.shifts(seed, m, d)
+    gv = GeneratingVectors(seed)
+    say = log or (lambda msg: None)
+    t0 = time.perf_counter()
+    for n in ladder:
+        gv(n, d)
+    t_search = time.perf_counter() - t0
+    say(f"generating vectors for {len(ladder)} rungs: {t_search:.2f} s")
+
+    warm = qmc.Plan(d, ladder[0], gv(ladder[0], d), sh, "baker")
+    warm.integrate(params)
+
+    def ladder_run(step):
+        rows, cum, hit = [], 0.0, None
+        for n in ladder:
+            plan = qmc.Plan(d, n, gv(n, d), sh, "baker")
+            _sync()
+            t = time.perf_counter()
+            res = step(plan)
+            _sync()
+            t = time.perf_counter() - t
+            plan.close()
+            cum += t
+            rel = abs(res.err_re) / abs(res.mean_re)
+            rows.append({"n": n, "mean": res.mean_re, "err": res.err_re, "rel_err": rel,
+                         "seconds": t, "used_cv": res.used_cv})
+            say(f"  n={n} mean={res.mean_re!r} rel_err={rel:.3e} used_cv={res.used_cv} {t * 1e3:.2f} ms")
+            if rel <= goal:
+                hit = rows[-1]
+                break
+        return rows, cum, hit
+
+    say("plain")
+    rows_p, cum_p, hit_p = ladder_run(lambda plan: plan.integrate(params)[0])
+
+    say("control variate: training")
+    train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), "baker")
+    _sync()
+    t = time.perf_counter()
+    W, c, rep = train.cv_train(params, R, K, max_sweeps=max_sweeps)
+    _sync()
+    t_train = time.perf_counter() - t
+    train.close()
+    say(f"  sweeps={rep.sweeps} rel_loss={rep.rel_loss:.3e} {t_train:.3f} s")
+    warm.integrate_cv(params, W, c)
+    warm.close()
+    say("control variate: ladder")
+    rows_c, cum_c, hit_c = ladder_run(lambda plan: plan.integrate_cv(params, W, c)[0])
+
+    def summary(rows, cum, hit, extra):
+        return {"goal_met": hit is not None, "n": (hit or rows[-1])["n"],
+                "rel_err": (hit or rows[-1])["rel_err"],
+                "seconds_at_n": (hit or rows[-1])["seconds"] + extra,
+                "ladder_seconds": cum + extra, "rungs": rows}
+
+    return {"d": d, "n_u": n_u, "n_f": n_f, "m": m, "goal": goal, "transform": "baker",
+            "generating_vector_search_seconds": t_search,
+            "plain": summary(rows_p, cum_p, hit_p, 0.0),
+            "cv": dict(summary(rows_c, cum_c, hit_c, t_train), R=R, K=K, n_train=n_train,
+                       train_seconds=t_train, train_sweeps=rep.sweeps, train_rel_loss=rep.rel_loss)}
+
+
+def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEED_BASE + 5, m: int = 32,
+                kmin: int = 16, kmax: int = 30, log=None) -> dict:
+    """Convergence table of the plain estimator on the complex sector
+    integrand (F - 0.01 i, mixed-sign F, baker's transform) over the ladder
+    of primes below 2^k: n, mean, error, relative error, wall time and
+    lattice-point evaluations per second for every rung."""
+    w = synth.sector_workload(n=synth.largest_prime_below(1 << kmax), m=m, d=d, n_u=n_u, n_f=n_f,
+                              seed=seed, complex_kinematics=True)
+    params = qmc.Params("sector", d, sector=w.sector)
+    gv = GeneratingVectors(seed, candidates=32)
+    say = log or (lambda msg: None)
+    rows = []
+    first = True
+    for n in synth.prime_ladder(kmin, kmax):
+        ts = time.perf_counter()
+        g = gv(n, d)
+        t_search = time.perf_counter() - ts
+        plan = qmc.Plan(d, n, g, w.shifts, "baker")
+        if first:
+            plan.integrate(params)  # compiles the specialised kernel
+            first = False
+        _sync()
+        t = time.perf_counter()
+        res, _ = plan.integrate(params)
+        _sync()
+        t = time.perf_counter() - t
+        plan.close()
+        mean = complex(res.mean_re, res.mean_im)
+        err = math.hypot(res.err_re, res.err_im)
+        rows.append({"n": n, "mean_re": res.mean_re, "mean_im": res.mean_im, "err_re": res.err_re,
+                     "err_im": res.err_im, "rel_err": err / abs(mean), "seconds": t,
+                     "evals_per_s": n * m / t, "search_seconds": t_search})
+        say(f"  n={n} mean={mean!r} rel_err={err / abs(mean):.3e} {t * 1e3:.2f} ms "
+            f"{n * m / t:.3e} evals/s")
+    return {"d": d, "n_u": n_u, "n_f": n_f, "m": m, "transform": "baker", "complex": True,
+            "name": w.name, "rows": rows}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sector_batch", "product_peak_batch"])
+    ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence"])
+    ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--count", type=int, default=0)
     ap.add_argument("--tile-points", type=int, default=-1)
     ap.add_argument("--no-compare", action="store_true")
@@ -143,9 +265,13 @@ def main(argv=None):
         out = sector_batch(count=args.count or 2000,
                            tile_points=8192 if args.tile_points < 0 else args.tile_points,
                            compare=not args.no_compare)
-    else:
+    elif args.what == "product_peak_batch":
         out = product_peak_batch(count=args.count or 512,
                                  tile_points=0 if args.tile_points < 0 else args.tile_points)
+    elif args.what == "time_to_error":
+        out = time_to_error(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+    else:
+        out = convergence(kmax=args.kmax or 30, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     print(json.dumps(out))
 
 

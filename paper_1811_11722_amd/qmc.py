@@ -117,6 +117,11 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1811_11722_amd.build` (no CPU fallback exists)")
+        # PyTorch ships its own HIP runtime under the same soname as the system
+        # one, and a process holds only the first one loaded.  Loading torch
+        # first makes the library share torch's runtime, so torch streams can
+        # be handed to it and torch keeps working in the same process.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
