@@ -251,9 +251,13 @@ typedef struct {
    lattice with its first shift (z, J and fhat are sampled by the GPU), by
    minimising sum_j (fhat_j - J_j g(z_j))^2 + lam |W[., i, .]|^2 with
    alternating least squares over the dimensions i.  Each step assembles its
-   normal equations with BF16 MFMA (FP32 accumulation), factorises them in
-   FP64 and refines the solution twice against the FP32 residual; a sweep
-   ends by balancing each rank's factor norms.  The control variate is an
+   normal equations with BF16 MFMA (each feature rounded once, FP32
+   accumulation), factorises them in FP64 and refines the solution twice
+   against the FP32 residual; a sweep ends by balancing each rank's factor
+   norms.  lam = ridge times the mean diagonal; it must stay above the
+   rounding of the assembled normal matrix for the refinement to converge.  Training stops when a sweep improves the
+   loss by less than tol (relative) and returns the factors of the lowest
+   loss seen.  The control variate is an
    addition to the paper's estimator (it does not appear in the paper); the
    estimate it feeds stays unbiased because the training lattice is
    independent of the estimation shifts.  QMC_F_SECTOR only, real

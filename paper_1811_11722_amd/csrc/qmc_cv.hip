@@ -192,102 +192,194 @@ struct CvSolveArgs {
     const double *tiles;    // (nslots, 32, 32)
     const uint32_t *pair_slot;  // (K, K): slot of the first (rb, cb) tile of pair (min, max)
     double *A;              // (F, F) scratch, F = R K
-    double *b;              // (F) scratch
     double *w64;            // (R, d, K) model, normalised basis
     float *ws32;            // (R, d, K) model times sqrt(2k+1)
     int *status;            // 0 ok, 1 not positive definite
 };
 
-// One workgroup: assemble the normal equations of dimension i, Cholesky
-// factorise A = L L^T in place (right-looking), solve, store W[., i, .].  A
-// factorisation that meets a non-positive pivot is redone with a 100x larger
-// ridge (up to three times).  A refinement call (refine = 1) reuses the
-// factor left in A, solves (A^T A + lam I) delta = A^T e - lam w for the
-// correction of the ridge-regularised problem and adds it to W[., i, .].
+// One workgroup solves the normal equations of dimension i.
+//
+// Assembly: the lower triangle of A (F x F, F = R K, row-major in HBM) is
+// gathered from the Gram tiles, plus the ridge lam = ridge * trace / F.
+// Factorisation: blocked right-looking Cholesky, A = L L^T in place.  Each
+// panel of kPanel columns is loaded into LDS and factorised there; the
+// trailing lower triangle is then updated by A -= P P^T, each thread owning
+// 4 x 4 blocks.  A non-positive pivot restarts the factorisation with a 100x
+// larger ridge (at most three times).  Solves: blocked forward and backward
+// substitution in LDS.  A refinement call (refine = 1) reuses the factor
+// left in A, solves (A + lam I) delta = A^T e - lam w and adds delta to
+// W[., i, .].
+constexpr uint32_t kPanel = 8;
+constexpr uint32_t kMaxF = 768;  // largest R K compiled: (64, 12)
+
+__device__ void cv_load_rhs(const CvSolveArgs &a, uint32_t F, double *y, double lam) {
+    for (uint32_t u = threadIdx.x; u < F; u += blockDim.x) {
+        const uint32_t r = u / a.K, k = u - r * a.K;
+        double v = a.tiles[((size_t)(a.rhs_slot0 + r / 32) << 10) + (r % 32) * 32 + k];
+        if (a.refine) v -= lam * a.w64[((size_t)r * a.d + a.i) * a.K + k];
+        y[u] = v;
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
     const uint32_t F = a.R * a.K, tid = threadIdx.x, nt = blockDim.x;
+    __shared__ double P[(kMaxF + 4) * kPanel];  // panel rows c0..F-1 (+4 rows of padding)
+    __shared__ double y[kMaxF];                 // right-hand side / solution
     __shared__ double s_ridge;
     __shared__ int s_bad;
-    double ridge = a.ridge;
-    if (a.refine) {
-        const double lam = *a.lam;
-        for (uint32_t u = tid; u < F; u += nt) {
-            const uint32_t r = u / a.K, k = u - r * a.K;
-            a.b[u] = a.tiles[((size_t)(a.rhs_slot0 + r / 32) << 10) + (r % 32) * 32 + k] -
-                     lam * a.w64[((size_t)r * a.d + a.i) * a.K + k];
-        }
-        __syncthreads();
-    }
-    for (int attempt = 0; attempt < 4 && !a.refine; ++attempt, ridge *= 100.0) {
-        for (uint32_t t = tid; t < F * F; t += nt) {
-            const uint32_t u = t / F, v = t - u * F;
-            const uint32_t r = u / a.K, k = u - r * a.K, rp = v / a.K, kp = v - rp * a.K;
-            double g;
-            if (k <= kp) {
-                const uint32_t slot = a.pair_slot[k * a.K + kp] + (r / 32) * a.RB + (rp / 32);
-                g = a.tiles[((size_t)slot << 10) + (r % 32) * 32 + (rp % 32)];
-            } else {
-                const uint32_t slot = a.pair_slot[kp * a.K + k] + (rp / 32) * a.RB + (r / 32);
-                g = a.tiles[((size_t)slot << 10) + (rp % 32) * 32 + (r % 32)];
+    double *A = a.A;
+
+    if (!a.refine) {
+        double ridge = a.ridge;
+        for (int attempt = 0; attempt < 4; ++attempt, ridge *= 100.0) {
+            // lower triangle of the normal matrix
+            for (uint32_t u = tid / 32; u < F; u += nt / 32) {
+                const uint32_t r = u / a.K, k = u - r * a.K;
+                for (uint32_t v = tid % 32; v <= u; v += 32) {
+                    const uint32_t rp = v / a.K, kp = v - rp * a.K;
+                    double g;
+                    if (k <= kp) {
+                        const uint32_t slot = a.pair_slot[k * a.K + kp] + (r / 32) * a.RB + (rp / 32);
+                        g = a.tiles[((size_t)slot << 10) + (r % 32) * 32 + (rp % 32)];
+                    } else {
+                        const uint32_t slot = a.pair_slot[kp * a.K + k] + (rp / 32) * a.RB + (r / 32);
+                        g = a.tiles[((size_t)slot << 10) + (rp % 32) * 32 + (r % 32)];
+                    }
+                    A[(size_t)u * F + v] = g;
+                }
             }
-            a.A[t] = g;
-        }
-        for (uint32_t u = tid; u < F; u += nt) {
-            const uint32_t r = u / a.K, k = u - r * a.K;
-            a.b[u] = a.tiles[((size_t)(a.rhs_slot0 + r / 32) << 10) + (r % 32) * 32 + k];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double tr = 0.0;
-            for (uint32_t u = 0; u < F; ++u) tr += a.A[(size_t)u * F + u];
-            s_ridge = ridge * tr / F + 1e-300;
-            s_bad = 0;
-        }
-        __syncthreads();
-        for (uint32_t u = tid; u < F; u += nt) a.A[(size_t)u * F + u] += s_ridge;
-        __syncthreads();
-        for (uint32_t c = 0; c < F; ++c) {
+            __syncthreads();
             if (tid == 0) {
-                const double p = a.A[(size_t)c * F + c];
-                if (!(p > 0.0)) s_bad = 1;
-                a.A[(size_t)c * F + c] = p > 0.0 ? sqrt(p) : 1.0;
+                double tr = 0.0;
+                for (uint32_t u = 0; u < F; ++u) tr += A[(size_t)u * F + u];
+                s_ridge = ridge * tr / F + 1e-300;
+                s_bad = 0;
             }
             __syncthreads();
-            const double lcc = a.A[(size_t)c * F + c];
-            for (uint32_t u = c + 1 + tid; u < F; u += nt) a.A[(size_t)u * F + c] /= lcc;
+            for (uint32_t u = tid; u < F; u += nt) A[(size_t)u * F + u] += s_ridge;
             __syncthreads();
-            const uint32_t m = F - c - 1;
-            for (uint32_t t = tid; t < m * m; t += nt) {
-                const uint32_t u = c + 1 + t / m, v = c + 1 + t % m;
-                if (v <= u) a.A[(size_t)u * F + v] -= a.A[(size_t)u * F + c] * a.A[(size_t)v * F + c];
+
+            for (uint32_t c0 = 0; c0 < F; c0 += kPanel) {
+                const uint32_t nb = min(kPanel, F - c0), rows = F - c0;
+                for (uint32_t t = tid; t < rows * kPanel; t += nt) {
+                    const uint32_t r = t / kPanel, q = t % kPanel;
+                    P[t] = (q < nb && q <= r) ? A[(size_t)(c0 + r) * F + c0 + q] : 0.0;
+                }
+                __syncthreads();
+                for (uint32_t q = 0; q < nb; ++q) {
+                    if (tid == 0) {
+                        const double piv = P[q * kPanel + q];
+                        if (!(piv > 0.0)) s_bad = 1;
+                        P[q * kPanel + q] = piv > 0.0 ? sqrt(piv) : 1.0;
+                    }
+                    __syncthreads();
+                    const double inv = 1.0 / P[q * kPanel + q];
+                    for (uint32_t r = q + 1 + tid; r < rows; r += nt) P[r * kPanel + q] *= inv;
+                    __syncthreads();
+                    for (uint32_t r = q + 1 + tid; r < rows; r += nt) {
+                        const double l = P[r * kPanel + q];
+                        for (uint32_t q2 = q + 1; q2 < nb && q2 <= r; ++q2)
+                            P[r * kPanel + q2] -= l * P[q2 * kPanel + q];
+                    }
+                    __syncthreads();
+                }
+                for (uint32_t t = tid; t < rows * kPanel; t += nt) {
+                    const uint32_t r = t / kPanel, q = t % kPanel;
+                    if (q < nb && q <= r) A[(size_t)(c0 + r) * F + c0 + q] = P[t];
+                }
+                // trailing update of rows / columns c1..F-1
+                const uint32_t c1 = c0 + nb;
+                if (c1 < F) {
+                    const uint32_t M = F - c1, nbk = (M + 3) / 4;
+                    for (uint32_t bu = tid / 32; bu < nbk; bu += nt / 32) {
+                        for (uint32_t bv = tid % 32; bv <= bu; bv += 32) {
+                            double acc[4][4] = {};
+                            for (uint32_t q = 0; q < nb; ++q) {
+                                double pu[4], pv[4];
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    pu[e] = P[(nb + 4 * bu + e) * kPanel + q];
+                                    pv[e] = P[(nb + 4 * bv + e) * kPanel + q];
+                                }
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                                    for (int f = 0; f < 4; ++f) acc[e][f] = fma(pu[e], pv[f], acc[e][f]);
+                            }
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const uint32_t u = c1 + 4 * bu + e;
+#pragma unroll
+                                for (int f = 0; f < 4; ++f) {
+                                    const uint32_t v = c1 + 4 * bv + f;
+                                    if (u < F && v <= u) A[(size_t)u * F + v] -= acc[e][f];
+                                }
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
             }
+            const int bad = s_bad;
             __syncthreads();
+            if (!bad) break;
         }
-        const int bad = s_bad;
-        __syncthreads();
-        if (!bad) break;
-    }
-    if (tid == 0) {
-        for (uint32_t u = 0; u < F; ++u) {  // L y = b
-            double s = a.b[u];
-            for (uint32_t v = 0; v < u; ++v) s -= a.A[(size_t)u * F + v] * a.b[v];
-            a.b[u] = s / a.A[(size_t)u * F + u];
-        }
-        for (uint32_t uu = F; uu-- > 0;) {  // L^T w = y
-            double s = a.b[uu];
-            for (uint32_t v = uu + 1; v < F; ++v) s -= a.A[(size_t)v * F + uu] * a.b[v];
-            a.b[uu] = s / a.A[(size_t)uu * F + uu];
-        }
-        if (!a.refine) {
+        if (tid == 0) {
             *a.status = s_bad;
             *a.lam = s_ridge;
         }
+        cv_load_rhs(a, F, y, 0.0);
+    } else {
+        cv_load_rhs(a, F, y, *a.lam);
     }
     __syncthreads();
+
+    // forward substitution L z = y, one panel at a time
+    for (uint32_t c0 = 0; c0 < F; c0 += kPanel) {
+        const uint32_t nb = min(kPanel, F - c0);
+        if (tid == 0) {
+            for (uint32_t q = 0; q < nb; ++q) {
+                double v = y[c0 + q];
+                for (uint32_t q2 = 0; q2 < q; ++q2) v -= A[(size_t)(c0 + q) * F + c0 + q2] * y[c0 + q2];
+                y[c0 + q] = v / A[(size_t)(c0 + q) * F + c0 + q];
+            }
+        }
+        __syncthreads();
+        for (uint32_t u = c0 + nb + tid; u < F; u += nt) {
+            double v = y[u];
+            for (uint32_t q = 0; q < nb; ++q) v -= A[(size_t)u * F + c0 + q] * y[c0 + q];
+            y[u] = v;
+        }
+        __syncthreads();
+    }
+    // backward substitution L^T w = z, panels from the last; P holds the
+    // per-column partial dot products (kPanel groups of nt / kPanel threads)
+    const uint32_t per = nt / kPanel, grp = tid / per, lane = tid % per;
+    for (uint32_t c0 = ((F - 1) / kPanel) * kPanel;; c0 -= kPanel) {
+        const uint32_t nb = min(kPanel, F - c0), c1 = c0 + nb;
+        double s = 0.0;
+        if (grp < nb)
+            for (uint32_t v = c1 + lane; v < F; v += per) s += A[(size_t)v * F + c0 + grp] * y[v];
+        P[tid] = s;
+        __syncthreads();
+        for (uint32_t h = per / 2; h > 0; h >>= 1) {
+            if (lane < h) P[tid] += P[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            for (uint32_t q = nb; q-- > 0;) {
+                double v = y[c0 + q] - P[q * per];
+                for (uint32_t q2 = q + 1; q2 < nb; ++q2) v -= A[(size_t)(c0 + q2) * F + c0 + q] * y[c0 + q2];
+                y[c0 + q] = v / A[(size_t)(c0 + q) * F + c0 + q];
+            }
+        }
+        __syncthreads();
+        if (c0 == 0) break;
+    }
     for (uint32_t u = tid; u < F; u += nt) {
         const uint32_t r = u / a.K, k = u - r * a.K;
         const size_t o = ((size_t)r * a.d + a.i) * a.K + k;
-        const double w = a.refine ? a.w64[o] + a.b[u] : a.b[u];
+        const double w = a.refine ? a.w64[o] + y[u] : y[u];
         a.w64[o] = w;
         a.ws32[o] = (float)(w * sqrt(2.0 * k + 1.0));
     }
@@ -586,14 +678,14 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
     so.tiles = (const double *)s.ptr[9];
     so.pair_slot = (const uint32_t *)s.ptr[10];
     so.A = (double *)s.ptr[11];
-    so.b = (double *)s.ptr[12];
     so.w64 = (double *)s.ptr[6];
     so.ws32 = (float *)s.ptr[5];
     so.status = (int *)s.ptr[13];
     so.lam = (double *)s.ptr[17];
 
     const uint32_t max_sweeps = o.max_sweeps ? o.max_sweeps : 12;
-    double prev = INFINITY, rel = INFINITY;
+    double prev = INFINITY, rel = INFINITY, best = INFINITY;
+    std::vector<double> w_best(w64.size());
     uint32_t sweeps = 0;
     const uint32_t gblocks = (ga.njobs + 3) / 4;
     const float inv_scale = (float)(1.0 / scale);
@@ -645,13 +737,22 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
             sy += part[2 * b + 1];
         }
         rel = se / sy;
-        if (!std::isfinite(rel)) return fail(QMC_ENONFINITE, "training diverged");
+        if (!std::isfinite(rel)) {
+            if (std::isfinite(best)) break;  // keep the best factors so far
+            return fail(QMC_ENONFINITE, "training diverged");
+        }
+        if (rel < best) {  // the factors of the lowest loss are the result
+            best = rel;
+            if ((e = hipMemcpy(w_best.data(), s.ptr[6], w_best.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+                return hip_fail(e, "training download");
+        }
         if (prev - rel < o.tol * prev) break;
         prev = rel;
     }
     (void)hipEventRecord(t1, stream);
-    if ((e = hipMemcpy(w64.data(), s.ptr[6], w64.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_fail(e, "training download");
+    (void)hipStreamSynchronize(stream);
+    w64 = w_best;
+    rel = best;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, t0, t1);
     (void)hipEventDestroy(t0);
@@ -688,14 +789,25 @@ qmc_status qmc_integrate_cv(qmc_plan_t p, qmc_family family, const void *params,
     if (st) return st;
     if (pk.np != 1) return fail(QMC_EUNSUPPORTED, "control variates are built for real integrands");
     const size_t base = pk.blob.size();
-    for (uint32_t r = 0; r < R; ++r) {
+    for (uint32_t r = 0; r < R; ++r)
         if (!std::isfinite(c[r])) return fail(QMC_EINVAL, "c not finite");
-        pk.blob.push_back(c[r]);
-    }
-    for (size_t t = 0; t < (size_t)R * p->d * K; ++t) {
+    for (size_t t = 0; t < (size_t)R * p->d * K; ++t)
         if (!std::isfinite(w[t])) return fail(QMC_EINVAL, "W not finite");
-        pk.blob.push_back(w[t] * std::sqrt(2.0 * (double)(t % K) + 1.0));
-    }
+    // weights in the lane order of the FP64 matrix instructions (FamCvResidual):
+    // fragment ((i * RB + rb) * KS + ks), lane l -> W[16 rb + l % 16, i, 4 ks + l / 16]
+    // * sqrt(2k + 1), times c_r in dimension 0, zero outside R x K
+    const uint32_t RB = (R + 15) / 16, KS = (K + 3) / 4;
+    pk.blob.resize(base + (size_t)p->d * RB * KS * kWave, 0.0);
+    for (uint32_t i = 0; i < p->d; ++i)
+        for (uint32_t rb = 0; rb < RB; ++rb)
+            for (uint32_t ks = 0; ks < KS; ++ks)
+                for (uint32_t l = 0; l < kWave; ++l) {
+                    const uint32_t r = 16 * rb + l % 16, k = 4 * ks + l / 16;
+                    if (r >= R || k >= K) continue;
+                    double v = w[((size_t)r * p->d + i) * K + k] * std::sqrt(2.0 * k + 1.0);
+                    if (i == 0) v *= c[r];
+                    pk.blob[base + (((size_t)i * RB + rb) * KS + ks) * kWave + l] = v;
+                }
     std::string err;
     hipFunction_t fn = jit_cv_kernel(pk.blob, base, p->d, p->tr, R, K, p->device, err);
     if (!fn) return fail(QMC_EUNSUPPORTED, "control-variate kernel: %s", err.c_str());

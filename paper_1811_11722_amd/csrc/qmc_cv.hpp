@@ -7,8 +7,9 @@
 // transform and lattice rule, so the estimator stays unbiased and the m
 // shifts judge its error exactly as for f.
 //
-// Device code: the Legendre basis, the FP64 model evaluation used inside the
-// lattice kernel, and the kernel that samples the training lattice.
+// Device code: the Legendre basis, the residual family whose FP64 model
+// evaluation runs inside the lattice kernel, and the kernel that samples the
+// training lattice.
 #pragma once
 
 #include "qmc_kernels.hpp"
@@ -30,55 +31,129 @@ __device__ __forceinline__ void legendre_raw(F z, F (&p)[K]) {
     }
 }
 
-// g(z) in FP64 for one point.  ws holds W[r,i,k] * sqrt(2k+1) row-major
-// (R, D, K); c holds c_r.  Both are wave-uniform (scalar loads).
-template <int D, int R, int K>
-__device__ __forceinline__ double cv_model(const double *__restrict__ c, const double *__restrict__ ws,
-                                           const double (&z)[D]) {
-    double prod[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) prod[r] = c[r];
-    // one dimension at a time (a rolled loop keeps a single basis live)
-#pragma unroll 1
-    for (int i = 0; i < D; ++i) {
-        double p[K];
-        legendre_raw<K, double>(z[i], p);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double *w = ws + (r * D + i) * K;
-            double h = w[K - 1] * p[K - 1];
-#pragma unroll
-            for (int k = K - 2; k >= 0; --k) h = fma_(w[k], p[k], h);
-            prod[r] *= h;
-        }
-    }
-    double g = prod[0];
-#pragma unroll
-    for (int r = 1; r < R; ++r) g += prod[r];
-    return g;
+typedef double cv_d4 __attribute__((ext_vector_type(4)));
+
+// One of four register values by lane group.  The values pass through an
+// empty asm statement so the compiler keeps the selects on registers rather
+// than turning them into an indexed load from a private array.
+__device__ __forceinline__ double cv_pick4(double a, double b, double c, double d, bool s1, bool s2, bool s3) {
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+    double t = a;
+    t = s1 ? b : t;
+    t = s2 ? c : t;
+    t = s3 ? d : t;
+    return t;
 }
 
 // Residual family: part 0 is the base integrand fhat, part 1 is
 // fhat - J g(z), both without the transform constant (applied to the sums).
-// cv points at [c (R), ws (R*D*K)] inside the parameter blob at word CvOff.
+//
+// g is evaluated for the wave's 64 points at once with FP64 matrix
+// instructions.  For dimension i, H_i[r][pt] = sum_k W'[r,i,k] P_k(z_pt,i) is
+// a (R x K) by (K x 64) product, done as 16 x 16 x 4 tiles by
+// v_mfma_f64_16x16x4f64 (A = weights: lane l holds row l % 16, inner index
+// l / 16; B = Legendre values: lane l holds column l % 16, inner index
+// l / 16; output element e of lane l is row 4e + l / 16, column l % 16).
+// The product over dimensions is taken elementwise on the output tiles and
+// the sum over ranks by two cross-lane adds.  Each lane gathers the z of the
+// 4 points its B columns stand for (one per 16-point block).
+//
+// cv points at the weights in fragment order at word CvOff of the parameter
+// blob: fragment ((i * RB + rb) * KS + ks) holds, for lane l,
+// W[r = 16 rb + l % 16, i, k = 4 ks + l / 16] * sqrt(2k + 1), times c_r for
+// i = 0, and 0 for r >= R or k >= K.
 template <class Base, int R, int K, int CvOff>
 struct FamCvResidual {
     static constexpr int NP = 2;
+    static constexpr bool kWaveUniform = true;  // the whole wave runs the matrix instructions
+    static constexpr int RB = (R + 15) / 16, KS = (K + 3) / 4;
     static_assert(Base::NP == 1, "control variate for real integrands");
     template <class Tr, int D, int T>
     __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D], double (&v)[T][NP]) {
-        double fb[T][1];
-        Base::template eval<Tr, D, T>(p, x, fb);
-        double z[T][D], jac[T];
-        apply_transform<Tr, D, T>(x, z, jac);
-        const double *cv = p + CvOff;
-        asm volatile("" : "+s"(cv));  // weights are re-read per point, not held in registers
+        static_assert(T == 1, "one shift per thread");
+        double fb[1][1];
+        Base::template eval<Tr, D, 1>(p, x, fb);
+        double z[1][D], jac[1];
+        apply_transform<Tr, D, 1>(x, z, jac);
+        const uint32_t lane = threadIdx.x & (kWave - 1), grp = lane >> 4, col = lane & 15;
+        // the wave's z values go through LDS (each wave uses its own rows;
+        // a wave's LDS accesses complete in order)
+        __shared__ double zs[kBlock * D];
+        double *zw = zs + (size_t)(threadIdx.x - lane) * D;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < T; ++k) {
-            const double g = cv_model<D, R, K>(cv, cv + R, z[k]);
-            v[k][0] = fb[k][0];
-            v[k][1] = Tr::kJac ? fma_(-jac[k], g, fb[k][0]) : fb[k][0] - g;
+        for (int i = 0; i < D; ++i) zw[lane * D + i] = z[0][i];
+        __builtin_amdgcn_wave_barrier();
+        const double *__restrict__ w = p + CvOff + lane;
+        const bool s1 = grp == 1, s2 = grp == 2, s3 = grp == 3;
+        cv_d4 prod[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) prod[rb][pb] = cv_d4{1.0, 1.0, 1.0, 1.0};
+        double wa[RB][KS];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) wa[rb][ks] = w[(rb * KS + ks) * kWave];
+#pragma unroll 1
+        for (int i = 0; i < D; ++i) {
+            // weights of the next dimension, loaded while this one computes
+            const int inext = i + 1 < D ? i + 1 : i;
+            double wn[RB][KS];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) wn[rb][ks] = w[((inext * RB + rb) * KS + ks) * kWave];
+            double bk[4][KS];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const double zp = zw[(16 * pb + col) * D + i];
+                double pk[4 * KS];
+                legendre_raw<4 * KS, double>(zp, pk);
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    bk[pb][ks] = cv_pick4(pk[4 * ks], pk[4 * ks + 1], pk[4 * ks + 2], pk[4 * ks + 3], s1, s2, s3);
+            }
+            // RB x 4 independent accumulation chains, interleaved over ks
+            cv_d4 acc[RB][4];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) acc[rb][pb] = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int pb = 0; pb < 4; ++pb)
+                        acc[rb][pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[rb][ks], bk[pb][ks], acc[rb][pb], 0, 0, 0);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) prod[rb][pb] *= acc[rb][pb];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) wa[rb][ks] = wn[rb][ks];
         }
+        __builtin_amdgcn_wave_barrier();
+        double s[4];
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            double t = 0.0;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) t += (prod[rb][pb][0] + prod[rb][pb][1]) + (prod[rb][pb][2] + prod[rb][pb][3]);
+            t += __shfl_xor(t, 16);
+            t += __shfl_xor(t, 32);
+            s[pb] = t;
+        }
+        double g = s[0];
+        g = grp == 1 ? s[1] : g;
+        g = grp == 2 ? s[2] : g;
+        g = grp == 3 ? s[3] : g;
+        v[0][0] = fb[0][0];
+        v[0][1] = Tr::kJac ? fma_(-jac[0], g, fb[0][0]) : fb[0][0] - g;
     }
 };
 

@@ -234,9 +234,11 @@ hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint
     const std::string fam = functor_source(blob, d, false, structure);
     std::ostringstream ne, src, key, cvt;
     cvt << "FamCvResidual<FamJit, " << R << ", " << K << ", " << cv_off << ">";
-    ne << "qmc::k_lattice<qmc::FamCvResidual<qmc::FamJit, " << R << ", " << K << ", " << cv_off << ">, qmc::"
+    // up to R = 32 the kernel fits two waves per SIMD without spills
+    const char *kern = R <= 32 ? "k_lattice_w2" : "k_lattice";
+    ne << "qmc::" << kern << "<qmc::FamCvResidual<qmc::FamJit, " << R << ", " << K << ", " << cv_off << ">, qmc::"
        << transform_type(tr) << ", " << d << ", 1>";
-    src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_lattice<" << cvt.str()
+    src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void " << kern << "<" << cvt.str()
         << ", " << transform_type(tr) << ", " << d << ", 1>(const LatticeArgs);\n}  // namespace qmc\n";
     key << dev << "#cv#R" << R << "K" << K << "o" << cv_off << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);

