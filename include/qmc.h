@@ -255,16 +255,21 @@ typedef struct {
    accumulation), factorises them in FP64 and refines the solution twice
    against the FP32 residual; a sweep ends by balancing each rank's factor
    norms.  lam = ridge times the mean diagonal; it must stay above the
-   rounding of the assembled normal matrix for the refinement to converge.  Training stops when a sweep improves the
-   loss by less than tol (relative) and returns the factors of the lowest
-   loss seen.  The control variate is an
-   addition to the paper's estimator (it does not appear in the paper); the
-   estimate it feeds stays unbiased because the training lattice is
-   independent of the estimation shifts.  QMC_F_SECTOR only, real
-   integrands, d <= 12, (R, K) in {(8,4), (8,8), (16,8), (16,12), (32,8),
-   (32,12), (32,16), (64,12)} (EUNSUPPORTED otherwise); ENONFINITE when the
-   loss is not finite.  w_out: R*d*K doubles (orthonormal-basis
-   coefficients), c_out: R doubles (caller-owned).  rep nullable. */
+   rounding of the assembled normal matrix for the refinement to converge.
+   Training stops when a sweep improves the loss by less than tol (relative)
+   and returns the factors of the lowest loss seen.
+
+   The control variate is an addition to the paper's estimator (it does not
+   appear in the paper); the estimate it feeds stays unbiased because the
+   training lattice is independent of the estimation shifts.  A complex
+   integrand gets one model for its real part and one for its imaginary
+   part, trained in turn.  QMC_F_SECTOR only, d <= 12, (R, K) in {(8,4),
+   (8,8), (16,8), (16,12), (32,8), (32,12), (32,16), (64,12)} (EUNSUPPORTED
+   otherwise); ENONFINITE when the loss is not finite.  w_out: nm*R*d*K
+   doubles (model-major, each (R, d, K) row-major, orthonormal-basis
+   coefficients), c_out: nm*R doubles, nm = 1 (real) or 2 (complex);
+   caller-owned.  rep (nullable): total sweeps, the larger relative loss,
+   the real part's target scale, total device time. */
 qmc_status qmc_cv_train(qmc_plan_t train_plan, qmc_family family, const void *params, uint32_t R, uint32_t K,
                         const qmc_cv_train_opts *opts, double *w_out, double *c_out, qmc_cv_train_report *rep);
 
@@ -272,10 +277,12 @@ qmc_status qmc_cv_train(qmc_plan_t train_plan, qmc_family family, const void *pa
 qmc_status qmc_cv_integral(uint32_t R, uint32_t d, uint32_t K, const double *w, const double *c, double *out);
 
 /* One pass over the plan's lattice evaluating fhat and the residual
-   fhat - J g (g in FP64).  plain_out (nullable): the plain estimate of the
-   same pass; out: int g + Qbar[f - g] with its error, or the plain estimate
-   (used_cv = 0) when the residual's error is not smaller.  per_shift
-   (nullable, 2m doubles): (plain Q_k, residual Q_k) interleaved. */
+   fhat - J g (g in FP64, W and c laid out as qmc_cv_train writes them).
+   plain_out (nullable): the plain estimate of the same pass; out:
+   int g + Qbar[f - g] with its error, or the plain estimate (used_cv = 0)
+   when the residual's error (complex modulus) is not smaller.  per_shift
+   (nullable): real integrands 2m doubles (plain Q_k, residual Q_k) per
+   shift; complex ones 4m doubles (Re, Im plain, Re, Im residual). */
 qmc_status qmc_integrate_cv(qmc_plan_t plan, qmc_family family, const void *params, uint32_t R, uint32_t K,
                             const double *w, const double *c, qmc_result *out, qmc_result *plain_out,
                             double *per_shift);

@@ -62,6 +62,8 @@ class _Params(C.Structure):
         ("cv_c", C.c_void_p),
         ("cv_r", C.c_uint32),
         ("cv_k", C.c_uint32),
+        ("cv_w_im", C.c_void_p),
+        ("cv_c_im", C.c_void_p),
         ("point_mode", C.c_int32),
     ]
 
@@ -146,11 +148,19 @@ class Params:
             p.delta_im = float(s.delta_im)
             p.is_complex = int(bool(s.is_complex))
         if cv is not None:
+            # (W (R, d, K), c (R,)) for the real part; a leading axis of 2
+            # adds the imaginary-part model of a complex integrand
             W, cc = cv
             W = arr(W, np.float64)
-            p.cv_w = _ptr(W)
-            p.cv_c = _ptr(arr(cc, np.float64))
-            p.cv_r, p.cv_k = W.shape[0], W.shape[2]
+            cc = arr(cc, np.float64)
+            if W.ndim == 3:
+                W, cc = W[None], cc[None]
+            p.cv_w = _ptr(arr(W[0], np.float64))
+            p.cv_c = _ptr(arr(cc[0], np.float64))
+            p.cv_r, p.cv_k = W.shape[1], W.shape[3]
+            if W.shape[0] == 2:
+                p.cv_w_im = _ptr(arr(W[1], np.float64))
+                p.cv_c_im = _ptr(arr(cc[1], np.float64))
         self.struct = p
 
     @property

@@ -79,10 +79,14 @@ typedef struct {
     double pow_u, pow_f, delta_im;
     int32_t is_complex;
     /* control variate: when cv_w != NULL the integrand becomes f - g with
-       g(z) = sum_r c_r prod_i sum_k W[r,i,k] P~_k(z_i), W row-major (R, d, K) */
+       g(z) = sum_r c_r prod_i sum_k W[r,i,k] P~_k(z_i), W row-major (R, d, K);
+       for a complex integrand cv_w / cv_c model the real part and
+       cv_w_im / cv_c_im (same shape) the imaginary part */
     const double *cv_w;
     const double *cv_c;
     uint32_t cv_r, cv_k;
+    const double *cv_w_im;
+    const double *cv_c_im;
     /* coordinate rounding: 0 -> idx / n (IEEE division), 1 -> idx * (1/n) */
     int32_t point_mode;
 } or_params;
@@ -331,6 +335,8 @@ void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, d
     }
     if (p->cv_w != NULL)
         vr -= or_cv_g(d, p->cv_r, p->cv_k, p->cv_w, p->cv_c, z);
+    if (p->cv_w_im != NULL)
+        vi -= or_cv_g(d, p->cv_r, p->cv_k, p->cv_w_im, p->cv_c_im, z);
     *re = vr;
     *im = vi;
 }

@@ -417,7 +417,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
             p->stream = c->stream;
             p->jit_mode = 0;
             qmc_status st = plan_enqueue(p, pk[i], c->T, 0);
-            if (!st && (e = hipMemcpyAsync(p->h_out, p->d_out, (2 * p->m + 4) * sizeof(double),
+            if (!st && (e = hipMemcpyAsync(p->h_out, p->d_out, out_doubles(p->m) * sizeof(double),
                                            hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
                 st = hip_fail(e, "copy results");
             p->stream = keep;
@@ -427,7 +427,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
         if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(e, "synchronize");
         for (uint32_t i = 0; i < count; ++i) {
             qmc_plan_s *p = plans[i];
-            const double *q = p->h_out, *res = p->h_out + 2 * p->m;
+            const double *q = p->h_out, *res = p->h_out + out_res_offset(p->m);
             bool fin = true;
             for (uint32_t k = 0; k < p->m * pk[i].np; ++k) fin = fin && std::isfinite(q[k]);
             out[i] = qmc_result{res[0], pk[i].np == 2 ? res[1] : 0.0, res[2], pk[i].np == 2 ? res[3] : 0.0,

@@ -333,7 +333,7 @@ static qmc_status plan_launch(qmc_plan_s *p, const Packed &pk, LatticeLaunch fn,
     f.scale = transform_scale(p->tr, p->d);
     f.sub = 0.0;
     f.q = p->d_out;
-    f.res = p->d_out + 2 * p->m;
+    f.res = p->d_out + out_res_offset(p->m);
     e = launch_finalize(f, 1, p->stream);
     if (e != hipSuccess) return hip_fail(e, "launch finalize kernel");
     p->last_T = T;
@@ -368,7 +368,7 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
 
 qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift) {
     const size_t nq = (size_t)p->m * np;
-    hipError_t e = hipMemcpyAsync(p->h_out, p->d_out, (2 * p->m + 4) * sizeof(double), hipMemcpyDeviceToHost,
+    hipError_t e = hipMemcpyAsync(p->h_out, p->d_out, out_doubles(p->m) * sizeof(double), hipMemcpyDeviceToHost,
                                   p->stream);
     if (e != hipSuccess) return hip_fail(e, "copy results");
     e = hipStreamSynchronize(p->stream);
@@ -380,20 +380,20 @@ qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per
             p->kernel_launches += 1;
         }
     }
-    const double *q = p->h_out, *res = p->h_out + 2 * p->m;
+    const double *q = p->h_out, *res = p->h_out + out_res_offset(p->m);
     bool finite = true;
     for (size_t i = 0; i < nq; ++i) finite = finite && std::isfinite(q[i]);
     if (per_shift) std::memcpy(per_shift, q, nq * sizeof(double));
-    out->is_complex = np == 2;
+    out->is_complex = np >= 2;
     out->used_cv = 0;
     if (!finite) {
         out->mean_re = out->mean_im = out->err_re = out->err_im = NAN;
         return fail(QMC_ENONFINITE, "a per-shift sum is not finite");
     }
     out->mean_re = res[0];
-    out->mean_im = np == 2 ? res[1] : 0.0;
+    out->mean_im = np >= 2 ? res[1] : 0.0;
     out->err_re = res[2];
-    out->err_im = np == 2 ? res[3] : 0.0;
+    out->err_im = np >= 2 ? res[3] : 0.0;
     return QMC_OK;
 }
 
@@ -460,11 +460,11 @@ qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m
         (cap = 0, st = ensure_buffer((void **)&p->d_gstep, cap, d * sizeof(uint32_t), "gstep")) ||
         (cap = 0, st = ensure_buffer((void **)&p->d_shifts, cap, (size_t)padded_rows(m) * d * sizeof(double),
                                      "shifts")) ||
-        (cap = 0, st = ensure_buffer((void **)&p->d_out, cap, (2 * (size_t)m + 4) * sizeof(double), "out"))) {
+        (cap = 0, st = ensure_buffer((void **)&p->d_out, cap, out_doubles(m) * sizeof(double), "out"))) {
         qmc_plan_destroy(p);
         return st;
     }
-    e = hipHostMalloc((void **)&p->h_out, (2 * (size_t)m + 4) * sizeof(double), hipHostMallocDefault);
+    e = hipHostMalloc((void **)&p->h_out, out_doubles(m) * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         qmc_plan_destroy(p);
         return fail(QMC_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));

@@ -24,7 +24,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const FinalizeArgs a) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double out[4] = {0.0, 0.0, 0.0, 0.0};
+        // results per pair of parts: (mean a, mean b, err a, err b)
+        const uint32_t rs = 4 * ((a.np + 1) / 2);
+        double out[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (uint32_t p = 0; p < a.np; ++p) {
             dd s{0.0, 0.0};
             for (uint32_t k = 0; k < a.m; ++k) dd_accumulate(s.hi, s.lo, qs[k * a.np + p]);
@@ -34,10 +36,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const FinalizeArgs a) {
                 const double t = qs[k * a.np + p] - mean;
                 dd_accumulate(v.hi, v.lo, t * t);
             }
-            out[p] = mean;
-            out[2 + p] = sqrt((v.hi + v.lo) / ((double)a.m * (double)(a.m - 1)));
+            out[4 * (p / 2) + p % 2] = mean;
+            out[4 * (p / 2) + 2 + p % 2] = sqrt((v.hi + v.lo) / ((double)a.m * (double)(a.m - 1)));
         }
-        for (int t = 0; t < 4; ++t) a.res[(size_t)inst * 4 + t] = out[t];
+        for (uint32_t t = 0; t < rs; ++t) a.res[(size_t)inst * rs + t] = out[t];
     }
 }
 
@@ -130,7 +132,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(const FinalizeBatchAr
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double out[4] = {0.0, 0.0, 0.0, 0.0};
+        // results per pair of parts: (mean a, mean b, err a, err b)
+        const uint32_t rs = 4 * ((a.np + 1) / 2);
+        double out[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (uint32_t p = 0; p < a.np; ++p) {
             dd s{0.0, 0.0};
             for (uint32_t k = 0; k < sc.m; ++k) dd_accumulate(s.hi, s.lo, qs[k * a.np + p]);

@@ -542,11 +542,10 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
     Packed pk;
     qmc_status st = pack_params((int)family, p->d, params, pk);
     if (st) return st;
-    if (pk.np != 1) return fail(QMC_EUNSUPPORTED, "control variates are built for real integrands");
     const uint32_t n = p->n, d = p->d, F = R * K, RB = (R + 31) / 32;
     hipError_t e;
     std::string err;
-    hipFunction_t sample = jit_sample_kernel(pk.blob, d, p->tr, p->device, err);
+    hipFunction_t sample = jit_sample_kernel(pk.blob, d, p->tr, pk.np == 2, p->device, err);
     if (!sample) return fail(QMC_EUNSUPPORTED, "training sampler: %s", err.c_str());
     if ((st = plan_upload_params(p, pk))) return st;
 
@@ -605,11 +604,22 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
         (st = s.alloc((size_t)n * 4)) || (st = s.alloc(8)))
         return st;
     hipStream_t stream = p->stream;
-    hipEvent_t t0, t1;
-    (void)hipEventCreate(&t0);
-    (void)hipEventCreate(&t1);
-    (void)hipEventRecord(t0, stream);
+    struct Events {
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        ~Events() {
+            if (t0) (void)hipEventDestroy(t0);
+            if (t1) (void)hipEventDestroy(t1);
+        }
+    } ev;
+    (void)hipEventCreate(&ev.t0);
+    (void)hipEventCreate(&ev.t1);
+    (void)hipEventRecord(ev.t0, stream);
 
+    // one model per component: the real part, then (complex integrands) the
+    // imaginary part
+    uint32_t sweeps_total = 0;
+    double rel_worst = 0.0, scale0 = 0.0;
+    for (uint32_t comp = 0; comp < pk.np; ++comp) {
     CvSampleArgs sa{};
     sa.n = n;
     sa.d = d;
@@ -620,6 +630,7 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
     sa.z = (float *)s.ptr[0];
     sa.sw = (float *)s.ptr[1];
     sa.yw = (float *)s.ptr[2];
+    sa.part = comp;
     if ((e = jit_launch_sample(sample, sa, rblocks, stream)) != hipSuccess) return hip_fail(e, "training sampler");
     hipLaunchKernelGGL(k_cv_absmean, dim3(rblocks), dim3(kBlock), 0, stream, n, (const float *)s.ptr[2],
                        (double *)s.ptr[15]);
@@ -749,17 +760,17 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
         if (prev - rel < o.tol * prev) break;
         prev = rel;
     }
-    (void)hipEventRecord(t1, stream);
+    std::memcpy(w_out + (size_t)comp * R * d * K, w_best.data(), w_best.size() * 8);
+    for (uint32_t r = 0; r < R; ++r) c_out[(size_t)comp * R + r] = scale;
+    sweeps_total += sweeps;
+    rel_worst = std::max(rel_worst, best);
+    if (comp == 0) scale0 = scale;
+    }  // components
+    (void)hipEventRecord(ev.t1, stream);
     (void)hipStreamSynchronize(stream);
-    w64 = w_best;
-    rel = best;
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, t0, t1);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    std::memcpy(w_out, w64.data(), w64.size() * 8);
-    for (uint32_t r = 0; r < R; ++r) c_out[r] = scale;
-    if (rep) *rep = qmc_cv_train_report{sweeps, rel, scale, ms / 1e3};
+    (void)hipEventElapsedTime(&ms, ev.t0, ev.t1);
+    if (rep) *rep = qmc_cv_train_report{sweeps_total, rel_worst, scale0, ms / 1e3};
     return QMC_OK;
 }
 
@@ -784,52 +795,66 @@ qmc_status qmc_integrate_cv(qmc_plan_t p, qmc_family family, const void *params,
     LossFn lf;
     ResidFn ef;
     if (!cv_fns(R, K, rf, lf, ef)) return fail(QMC_EUNSUPPORTED, "(R, K) = (%u, %u) not compiled", R, K);
+    if (p->d > 12) return fail(QMC_EUNSUPPORTED, "d > 12");
     Packed pk;
     qmc_status st = pack_params((int)family, p->d, params, pk);
     if (st) return st;
-    if (pk.np != 1) return fail(QMC_EUNSUPPORTED, "control variates are built for real integrands");
-    const size_t base = pk.blob.size();
-    for (uint32_t r = 0; r < R; ++r)
-        if (!std::isfinite(c[r])) return fail(QMC_EINVAL, "c not finite");
-    for (size_t t = 0; t < (size_t)R * p->d * K; ++t)
+    const uint32_t nm = pk.np, d = p->d;  // one model per component
+    const size_t wsize = (size_t)R * d * K;
+    for (uint32_t t = 0; t < nm * R; ++t)
+        if (!std::isfinite(c[t])) return fail(QMC_EINVAL, "c not finite");
+    for (size_t t = 0; t < nm * wsize; ++t)
         if (!std::isfinite(w[t])) return fail(QMC_EINVAL, "W not finite");
     // weights in the lane order of the FP64 matrix instructions (FamCvResidual):
-    // fragment ((i * RB + rb) * KS + ks), lane l -> W[16 rb + l % 16, i, 4 ks + l / 16]
-    // * sqrt(2k + 1), times c_r in dimension 0, zero outside R x K
+    // per model, fragment ((i * RB + rb) * KS + ks), lane l ->
+    // W[16 rb + l % 16, i, 4 ks + l / 16] * sqrt(2k + 1), times c_r in
+    // dimension 0, zero outside R x K
+    const size_t base = pk.blob.size();
     const uint32_t RB = (R + 15) / 16, KS = (K + 3) / 4;
-    pk.blob.resize(base + (size_t)p->d * RB * KS * kWave, 0.0);
-    for (uint32_t i = 0; i < p->d; ++i)
-        for (uint32_t rb = 0; rb < RB; ++rb)
-            for (uint32_t ks = 0; ks < KS; ++ks)
-                for (uint32_t l = 0; l < kWave; ++l) {
-                    const uint32_t r = 16 * rb + l % 16, k = 4 * ks + l / 16;
-                    if (r >= R || k >= K) continue;
-                    double v = w[((size_t)r * p->d + i) * K + k] * std::sqrt(2.0 * k + 1.0);
-                    if (i == 0) v *= c[r];
-                    pk.blob[base + (((size_t)i * RB + rb) * KS + ks) * kWave + l] = v;
-                }
+    const size_t msize = (size_t)d * RB * KS * kWave;
+    pk.blob.resize(base + nm * msize, 0.0);
+    for (uint32_t mi = 0; mi < nm; ++mi)
+        for (uint32_t i = 0; i < d; ++i)
+            for (uint32_t rb = 0; rb < RB; ++rb)
+                for (uint32_t ks = 0; ks < KS; ++ks)
+                    for (uint32_t l = 0; l < kWave; ++l) {
+                        const uint32_t r = 16 * rb + l % 16, k = 4 * ks + l / 16;
+                        if (r >= R || k >= K) continue;
+                        double v = w[mi * wsize + ((size_t)r * d + i) * K + k] * std::sqrt(2.0 * k + 1.0);
+                        if (i == 0) v *= c[(size_t)mi * R + r];
+                        pk.blob[base + mi * msize + (((size_t)i * RB + rb) * KS + ks) * kWave + l] = v;
+                    }
     std::string err;
-    hipFunction_t fn = jit_cv_kernel(pk.blob, base, p->d, p->tr, R, K, p->device, err);
+    hipFunction_t fn = jit_cv_kernel(pk.blob, base, d, p->tr, R, K, nm == 2, p->device, err);
     if (!fn) return fail(QMC_EUNSUPPORTED, "control-variate kernel: %s", err.c_str());
     Packed cv = pk;
-    cv.np = 2;
+    cv.np = 2 * nm;
     cv.key_family = -1;  // not in the kernel registry
     if ((st = plan_enqueue_fn(p, cv, fn, 1))) return st;
-    qmc_result both;
-    std::vector<double> q(2 * (size_t)p->m);
-    st = plan_collect(p, 2, &both, q.data());
+    qmc_result first;
+    std::vector<double> q((size_t)cv.np * p->m);
+    st = plan_collect(p, cv.np, &first, q.data());
     if (st && st != QMC_ENONFINITE) return st;
-    double ig = 0.0;
-    qmc_cv_integral(R, p->d, K, w, c, &ig);
-    const qmc_result plain{both.mean_re, 0.0, both.err_re, 0.0, 0, 0};
-    const qmc_result cvr{ig + both.mean_im, 0.0, both.err_im, 0.0, 0, 1};
+    // parts: real -> (f, f - g); complex -> (Re f, Im f, Re f - g_0, Im f - g_1)
+    const double *res = p->h_out + out_res_offset(p->m);
+    double ig[2] = {0.0, 0.0};
+    for (uint32_t mi = 0; mi < nm; ++mi) qmc_cv_integral(R, d, K, w + mi * wsize, c + (size_t)mi * R, &ig[mi]);
+    qmc_result plain, cvr;
+    if (nm == 1) {
+        plain = qmc_result{res[0], 0.0, res[2], 0.0, 0, 0};
+        cvr = qmc_result{ig[0] + res[1], 0.0, res[3], 0.0, 0, 1};
+    } else {
+        plain = qmc_result{res[0], res[1], res[2], res[3], 1, 0};
+        cvr = qmc_result{ig[0] + res[4], ig[1] + res[5], res[6], res[7], 1, 1};
+    }
     if (plain_out) *plain_out = plain;
     if (per_shift) std::memcpy(per_shift, q.data(), q.size() * 8);
     if (st == QMC_ENONFINITE) {
-        *out = qmc_result{NAN, NAN, NAN, NAN, 0, 0};
+        *out = qmc_result{NAN, NAN, NAN, NAN, (int32_t)(nm == 2), 0};
         return st;
     }
-    *out = (cvr.err_re < plain.err_re) ? cvr : plain;
+    const double e_cv = std::hypot(cvr.err_re, cvr.err_im), e_plain = std::hypot(plain.err_re, plain.err_im);
+    *out = e_cv < e_plain ? cvr : plain;
     return QMC_OK;
 }
 

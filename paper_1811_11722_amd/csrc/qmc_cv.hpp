@@ -45,8 +45,10 @@ __device__ __forceinline__ double cv_pick4(double a, double b, double c, double 
     return t;
 }
 
-// Residual family: part 0 is the base integrand fhat, part 1 is
-// fhat - J g(z), both without the transform constant (applied to the sums).
+// Residual family.  For a real base integrand the parts are fhat and
+// fhat - J g; for a complex one (Re fhat, Im fhat, Re fhat - J g_0,
+// Im fhat - J g_1) with one model per component.  The transform constant is
+// applied to the sums.
 //
 // g is evaluated for the wave's 64 points at once with FP64 matrix
 // instructions.  For dimension i, H_i[r][pt] = sum_k W'[r,i,k] P_k(z_pt,i) is
@@ -55,36 +57,25 @@ __device__ __forceinline__ double cv_pick4(double a, double b, double c, double 
 // l / 16; B = Legendre values: lane l holds column l % 16, inner index
 // l / 16; output element e of lane l is row 4e + l / 16, column l % 16).
 // The product over dimensions is taken elementwise on the output tiles and
-// the sum over ranks by two cross-lane adds.  Each lane gathers the z of the
-// 4 points its B columns stand for (one per 16-point block).
+// the sum over ranks by two cross-lane adds.  Each lane reads the z of the 4
+// points its B columns stand for (one per 16-point block) from LDS.
 //
-// cv points at the weights in fragment order at word CvOff of the parameter
-// blob: fragment ((i * RB + rb) * KS + ks) holds, for lane l,
+// The weights sit in fragment order at word CvOff of the parameter blob,
+// model after model (D * RB * KS * 64 words each): fragment
+// ((i * RB + rb) * KS + ks) holds, for lane l,
 // W[r = 16 rb + l % 16, i, k = 4 ks + l / 16] * sqrt(2k + 1), times c_r for
 // i = 0, and 0 for r >= R or k >= K.
 template <class Base, int R, int K, int CvOff>
 struct FamCvResidual {
-    static constexpr int NP = 2;
+    static constexpr int NM = Base::NP;  // one model per component
+    static constexpr int NP = 2 * NM;
     static constexpr bool kWaveUniform = true;  // the whole wave runs the matrix instructions
     static constexpr int RB = (R + 15) / 16, KS = (K + 3) / 4;
-    static_assert(Base::NP == 1, "control variate for real integrands");
-    template <class Tr, int D, int T>
-    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D], double (&v)[T][NP]) {
-        static_assert(T == 1, "one shift per thread");
-        double fb[1][1];
-        Base::template eval<Tr, D, 1>(p, x, fb);
-        double z[1][D], jac[1];
-        apply_transform<Tr, D, 1>(x, z, jac);
-        const uint32_t lane = threadIdx.x & (kWave - 1), grp = lane >> 4, col = lane & 15;
-        // the wave's z values go through LDS (each wave uses its own rows;
-        // a wave's LDS accesses complete in order)
-        __shared__ double zs[kBlock * D];
-        double *zw = zs + (size_t)(threadIdx.x - lane) * D;
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int i = 0; i < D; ++i) zw[lane * D + i] = z[0][i];
-        __builtin_amdgcn_wave_barrier();
-        const double *__restrict__ w = p + CvOff + lane;
+
+    // g of the lane's own point for the model whose fragments start at w
+    template <int D>
+    __device__ static double model(const double *__restrict__ w, const double *zw, uint32_t lane) {
+        const uint32_t grp = lane >> 4, col = lane & 15;
         const bool s1 = grp == 1, s2 = grp == 2, s3 = grp == 3;
         cv_d4 prod[RB][4];
 #pragma unroll
@@ -137,7 +128,6 @@ struct FamCvResidual {
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) wa[rb][ks] = wn[rb][ks];
         }
-        __builtin_amdgcn_wave_barrier();
         double s[4];
 #pragma unroll
         for (int pb = 0; pb < 4; ++pb) {
@@ -148,12 +138,33 @@ struct FamCvResidual {
             t += __shfl_xor(t, 32);
             s[pb] = t;
         }
-        double g = s[0];
-        g = grp == 1 ? s[1] : g;
-        g = grp == 2 ? s[2] : g;
-        g = grp == 3 ? s[3] : g;
-        v[0][0] = fb[0][0];
-        v[0][1] = Tr::kJac ? fma_(-jac[0], g, fb[0][0]) : fb[0][0] - g;
+        // the lane's own point is column l % 16 of block l / 16
+        return cv_pick4(s[0], s[1], s[2], s[3], s1, s2, s3);
+    }
+
+    template <class Tr, int D, int T>
+    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D], double (&v)[T][NP]) {
+        static_assert(T == 1, "one shift per thread");
+        double fb[1][NM];
+        Base::template eval<Tr, D, 1>(p, x, fb);
+        double z[1][D], jac[1];
+        apply_transform<Tr, D, 1>(x, z, jac);
+        const uint32_t lane = threadIdx.x & (kWave - 1);
+        // the wave's z values go through LDS (each wave uses its own rows;
+        // a wave's LDS accesses complete in order)
+        __shared__ double zs[kBlock * D];
+        double *zw = zs + (size_t)(threadIdx.x - lane) * D;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < D; ++i) zw[lane * D + i] = z[0][i];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int mi = 0; mi < NM; ++mi) {
+            const double g = model<D>(p + CvOff + (size_t)mi * D * RB * KS * kWave + lane, zw, lane);
+            v[0][mi] = fb[0][mi];
+            v[0][NM + mi] = Tr::kJac ? fma_(-jac[0], g, fb[0][mi]) : fb[0][mi] - g;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 };
 
@@ -165,7 +176,8 @@ struct CvSampleArgs {
     const double *params;
     float *z;             // (n, d) transformed coordinates
     float *sw;            // (n) Jacobian J: square root of the loss weight
-    float *yw;            // (n) fhat = J f(z): the weighted target
+    float *yw;            // (n) fhat = J f(z): the weighted target (component `part`)
+    uint32_t part;        // 0 real part, 1 imaginary part of a complex integrand
 };
 
 // Points of the training lattice {j g / n + shift}, j < n: z(x), J(x) and
@@ -180,13 +192,13 @@ __global__ __launch_bounds__(kBlock) void k_cv_sample(const CvSampleArgs a) {
         const uint32_t idx = mulmod(j, a.g[i], a.n, a.inv_n);
         x[0][i] = fract((double)idx * a.inv_n + a.shift[i]);
     }
-    double v[1][1], z[1][D], jac[1];
+    double v[1][Fam::NP], z[1][D], jac[1];
     Fam::template eval<Tr, D, 1>(a.params, x, v);
     apply_transform<Tr, D, 1>(x, z, jac);
 #pragma unroll
     for (int i = 0; i < D; ++i) a.z[(size_t)j * D + i] = (float)z[0][i];
     a.sw[j] = (float)jac[0];
-    a.yw[j] = (float)v[0][0];
+    a.yw[j] = (float)(Fam::NP == 1 || a.part == 0 ? v[0][0] : v[0][Fam::NP - 1]);
 }
 
 }  // namespace qmc

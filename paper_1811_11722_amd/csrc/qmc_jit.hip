@@ -229,31 +229,32 @@ hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_
 // The lattice kernel with the control-variate residual around the
 // specialised functor (parts: fhat, fhat - J g).
 hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint32_t d, const qmc_transform &tr,
-                            uint32_t R, uint32_t K, int dev, std::string &err) {
+                            uint32_t R, uint32_t K, bool cplx, int dev, std::string &err) {
     std::string structure;
-    const std::string fam = functor_source(blob, d, false, structure);
+    const std::string fam = functor_source(blob, d, cplx, structure);
     std::ostringstream ne, src, key, cvt;
     cvt << "FamCvResidual<FamJit, " << R << ", " << K << ", " << cv_off << ">";
-    // up to R = 32 the kernel fits two waves per SIMD without spills
-    const char *kern = R <= 32 ? "k_lattice_w2" : "k_lattice";
+    // real integrands up to R = 32 fit two waves per SIMD without spills
+    const char *kern = R <= 32 && !cplx ? "k_lattice_w2" : "k_lattice";
     ne << "qmc::" << kern << "<qmc::FamCvResidual<qmc::FamJit, " << R << ", " << K << ", " << cv_off << ">, qmc::"
        << transform_type(tr) << ", " << d << ", 1>";
     src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void " << kern << "<" << cvt.str()
         << ", " << transform_type(tr) << ", " << d << ", 1>(const LatticeArgs);\n}  // namespace qmc\n";
-    key << dev << "#cv#R" << R << "K" << K << "o" << cv_off << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
+    key << dev << "#cv#R" << R << "K" << K << "o" << cv_off << "c" << cplx << "t" << tr.kind << "a" << tr.alpha << "#"
+        << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);
 }
 
 // The training-lattice sampler with the specialised functor.
-hipFunction_t jit_sample_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, int dev,
-                                std::string &err) {
+hipFunction_t jit_sample_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, bool cplx,
+                                int dev, std::string &err) {
     std::string structure;
-    const std::string fam = functor_source(blob, d, false, structure);
+    const std::string fam = functor_source(blob, d, cplx, structure);
     std::ostringstream ne, src, key;
     ne << "qmc::k_cv_sample<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ">";
     src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_cv_sample<FamJit, "
         << transform_type(tr) << ", " << d << ">(const CvSampleArgs);\n}  // namespace qmc\n";
-    key << dev << "#sample#t" << tr.kind << "a" << tr.alpha << "#" << structure;
+    key << dev << "#sample#c" << cplx << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);
 }
 

@@ -270,7 +270,7 @@ struct FinalizeArgs {
     double scale;             // transform constant applied to every Q_k
     double sub;               // subtracted from each sum before scaling (0, or n for P2)
     double *q;                // (inst, m, np): Q_k
-    double *res;              // (inst, 4): mean_re, mean_im, err_re, err_im
+    double *res;              // (inst, 4 ceil(np / 2)): per pair of parts (mean a, mean b, err a, err b)
 };
 
 constexpr uint32_t kMaxRows = 4096;  // m * np per instance

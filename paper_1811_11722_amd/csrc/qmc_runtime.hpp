@@ -14,6 +14,12 @@
 namespace qmc {
 
 constexpr uint32_t kMaxDim = 16;
+// Per-plan result buffer: Q_k for up to kMaxParts parts (m * kMaxParts
+// doubles), then the results of every pair of parts, (mean a, mean b,
+// err a, err b), 4 doubles per pair.
+constexpr uint32_t kMaxParts = 4;
+inline size_t out_res_offset(uint32_t m) { return (size_t)kMaxParts * m; }
+inline size_t out_doubles(uint32_t m) { return (size_t)kMaxParts * m + 2 * kMaxParts; }
 constexpr uint32_t kMaxTile = 8;  // largest shift tile of any kernel
 
 struct qmc_plan_extra;  // batch / graph state, owned by qmc_batch.hip
@@ -82,8 +88,8 @@ hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_
 hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s);
 struct CvSampleArgs;
 hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint32_t d, const qmc_transform &tr,
-                            uint32_t R, uint32_t K, int dev, std::string &err);
-hipFunction_t jit_sample_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, int dev,
+                            uint32_t R, uint32_t K, bool cplx, int dev, std::string &err);
+hipFunction_t jit_sample_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, bool cplx, int dev,
                                 std::string &err);
 hipError_t jit_launch_sample(hipFunction_t fn, const CvSampleArgs &a, uint32_t blocks, hipStream_t s);
 qmc_status plan_enqueue_fn(qmc_plan_s *p, const Packed &pk, hipFunction_t jfn, uint32_t T);

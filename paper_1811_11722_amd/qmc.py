@@ -262,25 +262,40 @@ class Plan:
     def cv_train(self, params: Params, R: int, K: int, max_sweeps: int = 0, ridge: float = 0.0,
                  tol: float = 1e-4, seed: int = 1):
         """Fit the Legendre control variate on this plan's lattice (first shift).
-        Returns (W (R, d, K), c (R,), report)."""
-        W = np.zeros((R, self.d, K))
-        c = np.zeros(R)
+        Returns (W, c, report): W (R, d, K) and c (R,) for a real integrand,
+        W (2, R, d, K) and c (2, R) (real-part model, imaginary-part model)
+        for a complex one."""
+        nm = 2 if params.is_complex else 1
+        W = np.zeros((nm, R, self.d, K))
+        c = np.zeros((nm, R))
         opts = qmc_cv_train_opts(max_sweeps, ridge, tol, seed)
         rep = qmc_cv_train_report()
         check(lib().qmc_cv_train(self.handle, params.family, params.ptr, R, K, C.byref(opts), _p(W),
                                  _p(c), C.byref(rep)), "qmc_cv_train")
+        if nm == 1:
+            return W[0], c[0], rep
         return W, c, rep
 
     def integrate_cv(self, params: Params, W, c):
-        """Returns (result, plain result, per-shift (plain, residual) arrays)."""
+        """Returns (result, plain result, plain per-shift Q_k, residual
+        per-shift Q_k); complex integrands give complex Q_k arrays."""
         W = _arr(W, np.float64)
         c = _arr(c, np.float64)
-        R, d, K = W.shape
+        nm = 2 if params.is_complex else 1
+        if W.ndim == 3:
+            W = W[None]
+            c = c.reshape(1, -1)
+        if W.shape[0] != nm or c.shape != (nm, W.shape[1]):
+            raise ValueError("W must be (R, d, K) for a real integrand and (2, R, d, K) for a complex one")
+        _, R, d, K = W.shape
         out, plain = qmc_result(), qmc_result()
-        per = np.zeros(2 * self.m)
+        per = np.zeros(2 * nm * self.m)
         check(lib().qmc_integrate_cv(self.handle, params.family, params.ptr, R, K, _p(W), _p(c),
                                      C.byref(out), C.byref(plain), _p(per)), "qmc_integrate_cv")
-        return out, plain, per[0::2].copy(), per[1::2].copy()
+        if nm == 1:
+            return out, plain, per[0::2].copy(), per[1::2].copy()
+        per = per.reshape(self.m, 4)
+        return out, plain, per[:, 0] + 1j * per[:, 1], per[:, 2] + 1j * per[:, 3]
 
     def lattice_dump(self, j_lo: int, count: int):
         idx = np.zeros((count, self.d), dtype=np.uint32)

@@ -158,3 +158,81 @@ def test_cv_validation(Q):
     with pytest.raises(Q.QMCError) as e:
         plan.cv_train(Q.Params("sector", d, sector=tab), 7, 4)
     assert e.value.status == Q.QMC_EUNSUPPORTED
+
+
+def _complex_positive_sector(seed, d, n_u, n_f, delta=0.01):
+    """Positive U and F (well conditioned) with F -> F - i delta."""
+    t = synth.sector_tables(seed, d, n_u, n_f)
+    t.delta_im, t.is_complex = delta, True
+    return t
+
+
+def test_cv_complex_residual_matches_oracle(Q):
+    """Two models (real and imaginary part), same FP64 weights on both sides."""
+    d, n, m, R, K = 5, 16381, 6, 16, 8
+    tab = _complex_positive_sector(61, d, 7, 12)
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(61, m, d)
+    rng = np.random.default_rng(7)
+    W = rng.normal(size=(2, R, d, K)) / np.sqrt(K)
+    W[:, :, :, 0] += 1.0
+    c = rng.normal(size=(2, R)) * 1e-3
+    plan = Q.Plan(d, n, g, sh, "baker")
+    _say("cv complex residual")
+    out, plain, qp, qr = plan.integrate_cv(Q.Params("sector", d, sector=tab), W, c)
+    ep = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
+    er = O.estimate(n, g, sh, O.Params("sector", d, sector=tab, cv=(W, c)), "baker", threads=THREADS)
+    ep_q = ep.q_re + 1j * ep.q_im
+    er_q = er.q_re + 1j * er.q_im
+    assert np.all(np.abs(qp - ep_q) <= 1e-12 * np.abs(ep_q))
+    scale = np.maximum(np.abs(ep_q), np.abs(er_q))
+    assert np.all(np.abs(qr - er_q) <= 1e-12 * scale), np.max(np.abs(qr - er_q) / scale)
+    assert plain.is_complex == 1
+
+
+def test_cv_complex_exact_models(Q):
+    """f = U0^-2 (F0 - i delta)^p prod z^nu: exact real and imaginary models
+    make the residual vanish; the estimate is the closed form."""
+    d = 4
+    nu = [1, 2, 0, 1]
+    s = synth.SectorTables(d=d, coef_u=np.array([1.5]), exp_u=np.zeros((1, d), np.uint8),
+                           coef_f=np.array([0.7]), exp_f=np.zeros((1, d), np.uint8),
+                           nu=np.array(nu, np.uint8), delta_im=0.05, is_complex=True)
+    Cc = 1.5 ** -2 * complex(0.7, -0.05) ** -1.3
+    exact = Cc / (2 * 3 * 1 * 2)
+    W = np.zeros((2, 8, d, 4))
+    c = np.zeros((2, 8))
+    for i, v in enumerate(nu):
+        W[0, 0, i] = W[1, 0, i] = _monomial_legendre(v)
+    c[0, 0], c[1, 0] = Cc.real, Cc.imag
+    n = 16381
+    plan = Q.Plan(d, n, O.korobov_vector(n, d, 5029), synth.shifts(4, 8, d), "baker")
+    _say("cv complex exact models")
+    out, plain, qp, qr = plan.integrate_cv(Q.Params("sector", d, sector=s), W, c)
+    assert out.used_cv == 1 and out.is_complex == 1
+    assert math.hypot(out.err_re, out.err_im) <= 1e-14 * abs(exact)
+    assert abs(complex(out.mean_re, out.mean_im) - exact) <= 1e-14 * abs(exact)
+
+
+def test_cv_complex_training(Q):
+    """Training fits both components; the estimate agrees with the plain one
+    and the trained residual matches the oracle's."""
+    d = 4
+    tab = _complex_positive_sector(55, d, 6, 10)  # the table of the real training test
+    nt = 65521
+    train = Q.Plan(d, nt, O.korobov_vector(nt, d, 17364), synth.shifts(8, 2, d, stream=3), "baker")
+    p = Q.Params("sector", d, sector=tab)
+    _say("cv complex training")
+    W, c, rep = train.cv_train(p, 16, 8, max_sweeps=6)
+    assert W.shape == (2, 16, d, 8) and c.shape == (2, 16)
+    assert rep.rel_loss < 0.05, rep.rel_loss
+    n = 16381
+    g = O.korobov_vector(n, d, 5029)
+    sh = synth.shifts(9, 8, d)
+    plan = Q.Plan(d, n, g, sh, "baker")
+    out, plain, qp, qr = plan.integrate_cv(p, W, c)
+    e = math.hypot(math.hypot(out.err_re, out.err_im), math.hypot(plain.err_re, plain.err_im))
+    assert abs(complex(out.mean_re, out.mean_im) - complex(plain.mean_re, plain.mean_im)) <= 6 * e
+    er = O.estimate(n, g, sh, O.Params("sector", d, sector=tab, cv=(W, c)), "baker", threads=THREADS)
+    er_q = er.q_re + 1j * er.q_im
+    assert np.all(np.abs(qr - er_q) <= 1e-12 * np.maximum(np.abs(qp), np.abs(er_q)))

@@ -532,3 +532,43 @@ def test_cv_residual_estimate():
     W[0, :, 0] = 1.0
     res = O.estimate(n, g, sh, O.Params("const", d, c=1.0, cv=(W, np.ones(1))), "baker")
     assert np.all(res.q_re == 0.0)
+
+
+def _monomial_legendre(nu):
+    """Coefficients of z^nu (nu <= 2) in the orthonormal shifted Legendre basis
+    sqrt(2k+1) P_k(2z - 1), k < 4: z = (1 + t)/2 and z^2 = (1 + t)^2/4 with
+    t^2 = (2 P_2 + 1)/3."""
+    return {0: [1.0, 0.0, 0.0, 0.0],
+            1: [0.5, 0.5 / math.sqrt(3.0), 0.0, 0.0],
+            2: [1.0 / 3.0, 0.5 / math.sqrt(3.0), 1.0 / (6.0 * math.sqrt(5.0)), 0.0]}[nu]
+
+
+def test_cv_complex_exact_models():
+    """Complex sector with constant U and F: f = U0^-2 (F0 - i delta)^p prod z^nu
+    is a rank-1 Legendre model in each of its real and imaginary parts.  With
+    those models the residual vanishes in both components and int g_re +
+    i int g_im is the closed form (U0^-2 (F0 - i delta)^p) / prod (nu_i + 1)."""
+    d = 3
+    nu = [2, 0, 1]
+    s = synth.SectorTables(d=d, coef_u=np.array([1.3]), exp_u=np.zeros((1, d), np.uint8),
+                           coef_f=np.array([0.8]), exp_f=np.zeros((1, d), np.uint8),
+                           nu=np.array(nu, np.uint8), delta_im=0.05, is_complex=True)
+    Cc = 1.3 ** -2 * complex(0.8, -0.05) ** -1.3
+    closed = Cc / math.prod(v + 1 for v in nu)
+    W = np.zeros((2, 2, d, 4))
+    c = np.zeros((2, 2))
+    for i, v in enumerate(nu):
+        W[0, 0, i] = W[1, 0, i] = _monomial_legendre(v)
+    c[0, 0], c[1, 0] = Cc.real, Cc.imag
+    ig = complex(O.cv_integral(W[0], c[0]), O.cv_integral(W[1], c[1]))
+    assert abs(ig - closed) <= 1e-15 * abs(closed)
+    n = 1021
+    g = O.korobov_vector(n, d, 76)
+    sh = synth.shifts(5, 4, d)
+    plain = O.estimate(n, g, sh, O.Params("sector", d, sector=s), "baker")
+    res = O.estimate(n, g, sh, O.Params("sector", d, sector=s, cv=(W, c)), "baker")
+    assert np.all(np.abs(res.q_re) <= 1e-14 * abs(Cc))
+    assert np.all(np.abs(res.q_im) <= 1e-14 * abs(Cc))
+    # the real part of the model alone leaves the imaginary part untouched
+    only_re = O.estimate(n, g, sh, O.Params("sector", d, sector=s, cv=(W[0], c[0])), "baker")
+    assert np.array_equal(only_re.q_im, plain.q_im)
