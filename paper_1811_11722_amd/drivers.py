@@ -216,47 +216,73 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
 
 
 def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEED_BASE + 5, m: int = 32,
-                kmin: int = 16, kmax: int = 30, log=None) -> dict:
-    """Convergence table of the plain estimator on the complex sector
-    integrand (F - 0.01 i, mixed-sign F, baker's transform) over the ladder
-    of primes below 2^k: n, mean, error, relative error, wall time and
-    lattice-point evaluations per second for every rung."""
+                kmin: int = 16, kmax: int = 30, cv_kmax: int = 30, R: int = 64, K: int = 12,
+                n_train: int = 1048573, max_sweeps: int = 12, log=None) -> dict:
+    """Convergence table of the complex sector integrand (F - 0.01 i,
+    mixed-sign F, baker's transform) over the ladder of primes below 2^k:
+    n, mean, error, relative error, wall time and lattice-point evaluations
+    per second for every rung, for the plain estimator and (up to 2^cv_kmax)
+    the control variate (one model per component, trained on n_train points
+    of an independent lattice)."""
     w = synth.sector_workload(n=synth.largest_prime_below(1 << kmax), m=m, d=d, n_u=n_u, n_f=n_f,
                               seed=seed, complex_kinematics=True)
     params = qmc.Params("sector", d, sector=w.sector)
     gv = GeneratingVectors(seed, candidates=32)
     say = log or (lambda msg: None)
-    rows = []
-    first = True
-    for n in synth.prime_ladder(kmin, kmax):
-        ts = time.perf_counter()
-        g = gv(n, d)
-        t_search = time.perf_counter() - ts
-        plan = qmc.Plan(d, n, g, w.shifts, "baker")
-        if first:
-            plan.integrate(params)  # compiles the specialised kernel
-            first = False
-        _sync()
-        t = time.perf_counter()
-        res, _ = plan.integrate(params)
-        _sync()
-        t = time.perf_counter() - t
-        plan.close()
+
+    def row(n, res, t, t_search):
         mean = complex(res.mean_re, res.mean_im)
         err = math.hypot(res.err_re, res.err_im)
-        rows.append({"n": n, "mean_re": res.mean_re, "mean_im": res.mean_im, "err_re": res.err_re,
-                     "err_im": res.err_im, "rel_err": err / abs(mean), "seconds": t,
-                     "evals_per_s": n * m / t, "search_seconds": t_search})
-        say(f"  n={n} mean={mean!r} rel_err={err / abs(mean):.3e} {t * 1e3:.2f} ms "
-            f"{n * m / t:.3e} evals/s")
-    return {"d": d, "n_u": n_u, "n_f": n_f, "m": m, "transform": "baker", "complex": True,
-            "name": w.name, "rows": rows}
+        return {"n": n, "mean_re": res.mean_re, "mean_im": res.mean_im, "err_re": res.err_re,
+                "err_im": res.err_im, "rel_err": err / abs(mean), "seconds": t,
+                "evals_per_s": n * m / t, "search_seconds": t_search, "used_cv": res.used_cv}
+
+    def ladder(step, top, label):
+        rows = []
+        for n in synth.prime_ladder(kmin, top):
+            ts = time.perf_counter()
+            g = gv(n, d)
+            t_search = time.perf_counter() - ts
+            plan = qmc.Plan(d, n, g, w.shifts, "baker")
+            if not rows:
+                step(plan)  # compiles the specialised kernel
+            _sync()
+            t = time.perf_counter()
+            res = step(plan)
+            _sync()
+            t = time.perf_counter() - t
+            plan.close()
+            rows.append(row(n, res, t, t_search))
+            r = rows[-1]
+            say(f"  {label} n={n} mean={complex(res.mean_re, res.mean_im)!r} rel_err={r['rel_err']:.3e} "
+                f"used_cv={res.used_cv} {t * 1e3:.2f} ms {n * m / t:.3e} evals/s")
+        return rows
+
+    say("plain")
+    rows_p = ladder(lambda plan: plan.integrate(params)[0], kmax, "plain")
+    out = {"d": d, "n_u": n_u, "n_f": n_f, "m": m, "transform": "baker", "complex": True,
+           "name": w.name, "rows": rows_p}
+    if cv_kmax >= kmin:
+        say("control variate: training")
+        train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), "baker")
+        _sync()
+        t = time.perf_counter()
+        W, c, rep = train.cv_train(params, R, K, max_sweeps=max_sweeps)
+        _sync()
+        t_train = time.perf_counter() - t
+        train.close()
+        say(f"  sweeps={rep.sweeps} rel_loss={rep.rel_loss:.3e} {t_train:.3f} s")
+        out["cv"] = {"R": R, "K": K, "n_train": n_train, "train_seconds": t_train,
+                     "train_sweeps": rep.sweeps, "train_rel_loss": rep.rel_loss,
+                     "rows": ladder(lambda plan: plan.integrate_cv(params, W, c)[0], cv_kmax, "cv")}
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence"])
     ap.add_argument("--kmax", type=int, default=0)
+    ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--count", type=int, default=0)
     ap.add_argument("--tile-points", type=int, default=-1)
     ap.add_argument("--no-compare", action="store_true")
@@ -271,7 +297,9 @@ def main(argv=None):
     elif args.what == "time_to_error":
         out = time_to_error(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     else:
-        out = convergence(kmax=args.kmax or 30, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+        kmax = args.kmax or 30
+        out = convergence(kmax=kmax, cv_kmax=kmax if args.cv_kmax < 0 else args.cv_kmax,
+                          log=lambda msg: print(msg, file=sys.stderr, flush=True))
     print(json.dumps(out))
 
 
