@@ -195,17 +195,27 @@ qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint
 /* Many independent estimates in one launch: plan p of `count` plans is
    evaluated with family and params[p].  All plans must share the transform;
    each plan keeps its own d, n, g, m and shifts.  The work is cut into tiles
-   ordered longest first and run by one persistent kernel per dimension; when
-   every plan has the same d, n and m and tile_points is 0, the plans instead
-   run as instances of one lattice-kernel launch.  When use_graph is
-   set, the launch sequence is captured once into a HIP graph and replayed
-   on later calls with the same plans.  out receives count results.
-   Supported families: QMC_F_SECTOR (real) and the Genz families. */
+   (tile_points lattice points times one shift tile) ordered longest first,
+   one work list per dimension, and run by one kernel launch per dimension:
+   persistent workgroups that loop over the list, or one workgroup per tile
+   taking tiles in list order (schedule).  When every plan has the same d, n
+   and m and tile_points is 0, the plans instead run as instances of one
+   lattice-kernel launch.  When use_graph is set, the launch sequence is
+   captured once into a HIP graph and replayed on later calls with the same
+   plans.  out receives count results.  Supported families: QMC_F_SECTOR
+   (real) and the Genz families. */
+typedef enum {
+    QMC_BATCH_DEFAULT = 0,    /* one workgroup per tile */
+    QMC_BATCH_PERSISTENT = 1, /* CUs x 8 workgroups loop over the work list */
+    QMC_BATCH_PER_TILE = 2    /* one workgroup per tile */
+} qmc_batch_schedule;
+
 typedef struct {
     int32_t use_graph;         /* capture/replay through a HIP graph */
     int32_t per_plan_launches; /* 1 = one launch per plan instead (for comparison) */
     uint32_t tile_points;      /* lattice points per tile (0 = default 8192, or the
                                   instance launch for uniform batches) */
+    int32_t schedule;          /* qmc_batch_schedule */
 } qmc_batch_opts;
 
 qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_family family,

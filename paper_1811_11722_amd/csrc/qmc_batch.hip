@@ -34,6 +34,7 @@ struct BatchCtx {
     std::vector<std::vector<double>> blobs;
     int key_family = 0;
     uint32_t np = 1, T = 4, tile_points = 0;
+    int persistent = 0;  // 1: persistent workgroups, 0: one workgroup per tile
     int device = 0;
     hipStream_t stream = nullptr;
     struct Group {
@@ -317,7 +318,7 @@ hipError_t enqueue_batch(BatchCtx &c) {
         a.ntiles = c.groups[gi].ntiles;
         a.counter = c.args.counter + gi;
         const uint32_t blocks = std::min<uint32_t>(c.blocks, a.ntiles);
-        e = c.groups[gi].fn(a, blocks, c.stream);
+        e = c.groups[gi].fn(a, blocks, c.persistent, c.stream);
     }
     if (e == hipSuccess) e = launch_finalize_batch(c.fargs, (uint32_t)c.plans.size(), c.stream);
     return e;
@@ -344,8 +345,10 @@ qmc_status run_graph(BatchCtx &c, bool use_graph) {
 }
 
 bool same_ctx(const BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk,
-              uint32_t tile_points) {
-    if (c.plans.size() != count || c.tile_points != tile_points || c.key_family != pk[0].key_family) return false;
+              uint32_t tile_points, int persistent) {
+    if (c.plans.size() != count || c.tile_points != tile_points || c.key_family != pk[0].key_family ||
+        c.persistent != persistent)
+        return false;
     for (uint32_t i = 0; i < count; ++i)
         if (c.plans[i] != plans[i] || c.blobs[i] != pk[i].blob) return false;
     return true;
@@ -374,9 +377,12 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
                                const qmc_batch_opts *opts, qmc_result *out) {
     if (count == 0) return fail(QMC_EINVAL, "count must be >= 1");
     if (!plans || !params || !out) return fail(QMC_EINVAL, "null argument");
-    const qmc_batch_opts o = opts ? *opts : qmc_batch_opts{1, 0, 0};
+    const qmc_batch_opts o = opts ? *opts : qmc_batch_opts{1, 0, 0, QMC_BATCH_DEFAULT};
     uint32_t tile_points = o.tile_points ? o.tile_points : 8192;
     if (tile_points % kBlock) return fail(QMC_EINVAL, "tile_points must be a multiple of %d", kBlock);
+    if (o.schedule < QMC_BATCH_DEFAULT || o.schedule > QMC_BATCH_PER_TILE)
+        return fail(QMC_EINVAL, "unknown schedule %d", o.schedule);
+    const int persistent = o.schedule == QMC_BATCH_PERSISTENT;
     std::vector<Packed> pk(count);
     for (uint32_t i = 0; i < count; ++i) {
         if (!plans[i]) return fail(QMC_EINVAL, "plan %u is NULL", i);
@@ -392,7 +398,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
     std::lock_guard<std::mutex> lock(g_batch_mu);
     BatchCtx *c = nullptr;
     for (auto &x : g_batch)
-        if (same_ctx(*x, count, plans, pk, tile_points)) c = x.get();
+        if (same_ctx(*x, count, plans, pk, tile_points, persistent)) c = x.get();
     if (!c) {
         auto fresh = std::make_unique<BatchCtx>();
         bool uniform = o.tile_points == 0 && count * ((plans[0]->m + 7) / 8) <= 65535;
@@ -401,6 +407,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
         qmc_status st = uniform ? build_uniform(*fresh, count, plans, pk)
                                 : build_ctx(*fresh, count, plans, pk, tile_points);
         if (st) return st;
+        fresh->persistent = persistent;
         if (g_batch.size() >= kMaxContexts) g_batch.erase(g_batch.begin());
         g_batch.push_back(std::move(fresh));
         c = g_batch.back().get();

@@ -50,7 +50,9 @@ struct BatchKey {
     }
 };
 
-using BatchLaunch = hipError_t (*)(const BatchArgs &, uint32_t blocks, hipStream_t);
+// persistent = 1: `blocks` workgroups loop over the work list; 0: one
+// workgroup per tile (blocks ignored)
+using BatchLaunch = hipError_t (*)(const BatchArgs &, uint32_t blocks, int persistent, hipStream_t);
 
 std::map<BatchKey, BatchLaunch> &batch_registry();
 
@@ -59,8 +61,11 @@ struct BatchRegistrar {
 };
 
 template <class Fam, class Tr, int D, int T>
-hipError_t launch_batch(const BatchArgs &a, uint32_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_batch<Fam, Tr, D, T>), dim3(blocks), dim3(kBlock), 0, s, a);
+hipError_t launch_batch(const BatchArgs &a, uint32_t blocks, int persistent, hipStream_t s) {
+    if (persistent)
+        hipLaunchKernelGGL((k_batch<Fam, Tr, D, T>), dim3(blocks), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_batch_flat<Fam, Tr, D, T>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

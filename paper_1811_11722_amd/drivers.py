@@ -91,6 +91,8 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
     evals = int(sum(n * m for n in ns))
     res, t_graph = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True,
                                                      tile_points=tile_points), reps)
+    res_ps, t_persist = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True, tile_points=tile_points,
+                                                          schedule="persistent"), reps)
     out = {
         "sectors": count, "m": m, "goal": goal, "tile_points": tile_points,
         "pilot_n": n0, "pilot_seconds": t_pilot,
@@ -98,6 +100,9 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
         "sectors_at_cap": int(sum(1 for v in ns if v == LADDER[-1])),
         "evals": evals, "setup_seconds": t_setup,
         "graph_seconds": t_graph, "graph_evals_per_s": evals / t_graph,
+        "graph_persistent_seconds": t_persist, "graph_persistent_evals_per_s": evals / t_persist,
+        "max_rel_diff_per_tile_vs_persistent": float(max(
+            abs(a.mean_re - b.mean_re) / abs(b.mean_re) for a, b in zip(res, res_ps))),
         "rel_err_max": float(max(abs(r.err_re) / abs(r.mean_re) for r in res)),
         "rel_err_median": float(np.median([abs(r.err_re) / abs(r.mean_re) for r in res])),
     }

@@ -79,7 +79,10 @@ class qmc_launch(C.Structure):
 
 class qmc_batch_opts(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("per_plan_launches", C.c_int32),
-                ("tile_points", C.c_uint32)]
+                ("tile_points", C.c_uint32), ("schedule", C.c_int32)]
+
+
+BATCH_SCHEDULE = {"default": 0, "persistent": 1, "per_tile": 2}
 
 
 # every symbol include/qmc.h declares, with its ctypes signature
@@ -344,11 +347,13 @@ def korobov_search(n: int, d: int, cand):
 
 
 def integrate_batch(plans: Sequence[Plan], params: Sequence[Params], use_graph: bool = True,
-                    per_plan_launches: bool = False, tile_points: int = 0):
+                    per_plan_launches: bool = False, tile_points: int = 0, schedule: str = "default"):
+    """schedule: "default", "persistent" (workgroups loop over the work list)
+    or "per_tile" (one workgroup per tile)."""
     fam = params[0].family
     handles = (C.c_void_p * len(plans))(*[p.handle for p in plans])
     pp = (C.c_void_p * len(params))(*[p.ptr for p in params])
-    opts = qmc_batch_opts(int(use_graph), int(per_plan_launches), tile_points)
+    opts = qmc_batch_opts(int(use_graph), int(per_plan_launches), tile_points, BATCH_SCHEDULE[schedule])
     out = (qmc_result * len(plans))()
     check(lib().qmc_integrate_batch(len(plans), handles, fam, pp, C.byref(opts), out),
           "qmc_integrate_batch")

@@ -45,12 +45,13 @@ def _sector_plans(Q, count, seed, ns, m):
     return plans, params, cases
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_sector_batch_parity(Q, use_graph):
-    """Sectors of d = 2..9 and uneven n in one persistent launch."""
+@pytest.mark.parametrize("use_graph,schedule", [(True, "default"), (False, "default"), (True, "persistent"),
+                                               (False, "persistent"), (True, "per_tile")])
+def test_sector_batch_parity(Q, use_graph, schedule):
+    """Sectors of d = 2..9 and uneven n in one launch per dimension."""
     plans, params, cases = _sector_plans(Q, 24, 77, [1021, 4093, 16381, 257, 65521], 6)
-    _say(f"sector batch graph={use_graph}")
-    res = Q.integrate_batch(plans, params, use_graph=use_graph, tile_points=1024)
+    _say(f"sector batch graph={use_graph} schedule={schedule}")
+    res = Q.integrate_batch(plans, params, use_graph=use_graph, tile_points=1024, schedule=schedule)
     per = Q.batch_per_shift(plans)
     for (d, n, g, sh, tab), q, r in zip(cases, per, res):
         est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
@@ -71,6 +72,10 @@ def test_batch_graph_replay_and_per_plan_mode(Q):
         assert [r.mean_re for r in again] == [r.mean_re for r in first]
     eager = Q.integrate_batch(plans, params, use_graph=False)
     assert [r.mean_re for r in eager] == [r.mean_re for r in first]
+    # the two schedules write the same tile slots and add them in the same
+    # order, so they agree bit for bit
+    persist = Q.integrate_batch(plans, params, use_graph=True, schedule="persistent")
+    assert [r.mean_re for r in persist] == [r.mean_re for r in first]
     _say("per-plan launches")
     pp = Q.integrate_batch(plans, params, per_plan_launches=True)
     for a, b in zip(pp, first):
