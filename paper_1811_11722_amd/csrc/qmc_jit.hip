@@ -165,12 +165,16 @@ static hipFunction_t compile_cached(const std::string &src, const std::string &n
     if (const char *dump = std::getenv("QMC_JIT_DUMP")) {  // write the generated source for inspection
         std::ofstream(std::string(dump) + "/" + std::to_string(std::hash<std::string>()(key)) + ".hip") << src;
     }
-    std::lock_guard<std::mutex> lock(g_jit_mu);
-    auto it = g_jit_cache.find(key);
-    if (it != g_jit_cache.end()) {
-        err = it->second.error;
-        return it->second.fn;
+    {
+        std::lock_guard<std::mutex> lock(g_jit_mu);
+        auto it = g_jit_cache.find(key);
+        if (it != g_jit_cache.end()) {
+            err = it->second.error;
+            return it->second.fn;
+        }
     }
+    // compile without holding the lock, so that several threads can compile
+    // different programs at once; the first result stored for a key wins
     JitEntry e;
     hiprtcProgram prog = nullptr;
     hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "qmc_sector_jit.hip", kJitHeaderCount, kJitHeaderText,
@@ -208,9 +212,11 @@ static hipFunction_t compile_cached(const std::string &src, const std::string &n
         }
     }
     if (prog) hiprtcDestroyProgram(&prog);
-    err = e.error;
-    g_jit_cache[key] = e;
-    return e.fn;
+    std::lock_guard<std::mutex> lock(g_jit_mu);
+    auto ins = g_jit_cache.emplace(key, e);
+    if (!ins.second && e.mod) (void)hipModuleUnload(e.mod);  // another thread stored this key first
+    err = ins.first->second.error;
+    return ins.first->second.fn;
 }
 
 // The lattice kernel with the specialised sector functor.

@@ -9,6 +9,7 @@ and times calls.
     python -m paper_1811_11722_amd.drivers product_peak_batch [--count 512]
     python -m paper_1811_11722_amd.drivers time_to_error
     python -m paper_1811_11722_amd.drivers convergence
+    python -m paper_1811_11722_amd.drivers cv_estimate
 """
 from __future__ import annotations
 
@@ -283,9 +284,34 @@ def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEE
     return out
 
 
+def cv_estimate(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 4, n: int = 4194301,
+                m: int = 32, R: int = 32, K: int = 12, n_train: int = 1048573, max_sweeps: int = 12,
+                reps: int = 3) -> dict:
+    """One control-variate estimate of the d = 8 sector integrand: training on
+    the independent lattice, then plain and residual sums in one pass at n;
+    the timed pass is the median of reps."""
+    tab = synth.sector_tables(seed, d, n_u, n_f)
+    params = qmc.Params("sector", d, sector=tab)
+    gv = GeneratingVectors(seed)
+    train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), "baker")
+    t0 = time.perf_counter()
+    W, c, rep = train.cv_train(params, R, K, max_sweeps=max_sweeps)
+    t_train = time.perf_counter() - t0
+    train.close()
+    plan = qmc.Plan(d, n, gv(n, d), synth.shifts(seed, m, d), "baker")
+    (out, plain, _, _), t_cv = _timed(lambda: plan.integrate_cv(params, W, c), reps)
+    _, t_plain = _timed(lambda: plan.integrate(params), reps)
+    plan.close()
+    return {"d": d, "n": n, "m": m, "R": R, "K": K, "n_train": n_train, "train_seconds": t_train,
+            "train_device_seconds": rep.seconds, "train_sweeps": rep.sweeps, "train_rel_loss": rep.rel_loss,
+            "cv_pass_seconds": t_cv, "plain_seconds": t_plain, "used_cv": out.used_cv,
+            "err_cv": out.err_re, "err_plain": plain.err_re, "mean_cv": out.mean_re, "mean_plain": plain.mean_re}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence"])
+    ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
+                                     "cv_estimate"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--count", type=int, default=0)
@@ -299,6 +325,8 @@ def main(argv=None):
     elif args.what == "product_peak_batch":
         out = product_peak_batch(count=args.count or 512,
                                  tile_points=0 if args.tile_points < 0 else args.tile_points)
+    elif args.what == "cv_estimate":
+        out = cv_estimate()
     elif args.what == "time_to_error":
         out = time_to_error(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     else:
