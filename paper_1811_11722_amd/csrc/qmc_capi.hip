@@ -362,6 +362,10 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
         if (!fn)
             return fail(QMC_EUNSUPPORTED, "no kernel for family %d, transform %d/%d, d = %u", pk.key_family,
                         p->tr.kind, p->tr.alpha, p->d);
+    } else if (bpc == 0) {
+        // the specialised sector kernels hold few enough registers for four
+        // waves per SIMD; 16 workgroups per CU fill whole residency rounds
+        bpc = 16;
     }
     return plan_launch(p, pk, fn, jfn, T, bpc);
 }

@@ -98,6 +98,8 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
         st << c << ",";
     }
     const uint64_t nuc = word(blob, 6);
+    const uint32_t flags = (uint32_t)word(blob, 2);
+    st << "|f" << flags;
     std::vector<int> nuf;
     for (uint32_t i = 0; i < d; ++i)
         for (uint64_t r = 0; r < ((nuc >> (2 * i)) & 3u); ++r) nuf.push_back((int)i);
@@ -113,11 +115,16 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
          " double (&v)[T][NP]) {\n"
       << "        double z[T][D], jac[T];\n"
       << "        apply_transform<Tr, D, T>(x, z, jac);\n"
-      << "        const uint32_t flags = (uint32_t)__double_as_longlong(p[2]);\n"
-      << "        const double pow_u = p[3], pow_f = p[4], delta = p[5];\n"
-      << "        const double *cu = p + kSectorHeader;\n"
-      << "        asm volatile(\"\" : \"+s\"(cu));  // keep coefficient loads in the point loop\n"
-      << "        const double *cf = cu + " << 2 * nu << ";\n"
+      << "        constexpr uint32_t flags = " << flags << "u;\n"
+      // the parameter words are read through a constant-address-space
+      // pointer laundered per point: scalar loads inside the point loop
+      // (SGPR operands of the FMAs) instead of vector loads hoisted into VGPRs
+      << "        const __attribute__((address_space(4))) double *cp =\n"
+      << "            (const __attribute__((address_space(4))) double *)p;\n"
+      << "        asm volatile(\"\" : \"+s\"(cp));\n"
+      << "        const double pow_u = cp[3], pow_f = cp[4], delta = cp[5];\n"
+      << "        const __attribute__((address_space(4))) double *cu = cp + kSectorHeader;\n"
+      << "        const __attribute__((address_space(4))) double *cf = cu + " << 2 * nu << ";\n"
       << "#pragma unroll\n"
       << "        for (int k = 0; k < T; ++k) {\n";
     auto ref = [&](int id) {
