@@ -200,7 +200,8 @@ qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint
    persistent workgroups that loop over the list, or one workgroup per tile
    taking tiles in list order (schedule).  When every plan has the same d, n
    and m and tile_points is 0, the plans instead run as instances of one
-   lattice-kernel launch.  When use_graph is set, the launch sequence is
+   lattice-kernel launch (with the first plan's qmc_plan_set_launch
+   configuration, if any).  When use_graph is set, the launch sequence is
    captured once into a HIP graph and replayed on later calls with the same
    plans.  out receives count results.  Supported families: QMC_F_SECTOR
    (real) and the Genz families. */

@@ -99,8 +99,12 @@ qmc_status build_uniform(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, c
     c.np = pk[0].np;
     c.device = p0->device;
     for (uint32_t i = 0; i < count; ++i) c.blobs.push_back(pk[i].blob);
+    // the first plan's launch configuration (qmc_plan_set_launch) applies to
+    // the whole launch; otherwise shift tile 8 where 4 is the default
     uint32_t T = 0;
-    c.lfn = find_kernel(c.key_family, p0->tr, p0->d, default_tile(c.key_family) == 4 ? 8 : default_tile(c.key_family), T);
+    const uint32_t want_T = p0->launch.shift_tile ? p0->launch.shift_tile
+                                                  : (default_tile(c.key_family) == 4 ? 8 : default_tile(c.key_family));
+    c.lfn = find_kernel(c.key_family, p0->tr, p0->d, want_T, T);
     if (!c.lfn)
         return fail(QMC_EUNSUPPORTED, "no kernel for family %d, transform %d/%d, d = %u", c.key_family, p0->tr.kind,
                     p0->tr.alpha, p0->d);
@@ -108,7 +112,7 @@ qmc_status build_uniform(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, c
     c.T = T;
     c.ltiles = (m + T - 1) / T;
     if ((uint64_t)count * c.ltiles > 65535) return fail(QMC_EUNSUPPORTED, "too many instances for one launch");
-    c.lbx = grid_x(n, count * c.ltiles, c.device, 8);
+    c.lbx = grid_x(n, count * c.ltiles, c.device, p0->launch.blocks_per_cu ? p0->launch.blocks_per_cu : 8);
     size_t pstride = 0;
     for (auto &b : pk) pstride = std::max(pstride, b.blob.size());
     std::vector<uint32_t> g((size_t)count * d), gs((size_t)count * d);

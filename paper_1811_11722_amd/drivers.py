@@ -121,9 +121,11 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
 
 
 def product_peak_batch(count: int = 512, n: int = 131071, m: int = 16, d: int = 4,
-                       seed: int = synth.SEED_BASE + 1, tile_points: int = 0, reps: int = 5) -> dict:
+                       seed: int = synth.SEED_BASE + 1, tile_points: int = 0, reps: int = 5,
+                       shift_tile: int = 0, blocks_per_cu: int = 0) -> dict:
     """Throughput on many Genz product-peak instances (Korobov weight 3):
-    shared generating vector and shifts, own a_i and u_i per instance."""
+    shared generating vector and shifts, own a_i and u_i per instance.
+    shift_tile / blocks_per_cu (0 = default) set the instance launch."""
     w = synth.product_peak_workload(n=n, m=m, d=d, seed=seed)
     a, _, _ = qmc.korobov_search(n, d, w.candidates)
     g = qmc.korobov_vector(n, d, a)
@@ -131,13 +133,15 @@ def product_peak_batch(count: int = 512, n: int = 131071, m: int = 16, d: int = 
     for b in range(count):
         aa, uu = synth.genz_params(seed, d, stream=16 + b)
         plans.append(qmc.Plan(d, n, g, w.shifts, "korobov", 3))
+        if shift_tile or blocks_per_cu:
+            plans[-1].set_launch(shift_tile, blocks_per_cu)
         params.append(qmc.Params("genz_product_peak", d, a=aa, u=uu))
     res, t = _timed(lambda: qmc.integrate_batch(plans, params, tile_points=tile_points), reps)
     evals = count * n * m
     for p in plans:
         p.close()
     return {"instances": count, "n": n, "m": m, "d": d, "evals": evals, "seconds": t,
-            "evals_per_s": evals / t, "generator_a": a}
+            "evals_per_s": evals / t, "generator_a": a, "shift_tile": shift_tile, "blocks_per_cu": blocks_per_cu}
 
 
 def _sync():
@@ -314,6 +318,8 @@ def main(argv=None):
                                      "cv_estimate"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
+    ap.add_argument("--shift-tile", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--count", type=int, default=0)
     ap.add_argument("--tile-points", type=int, default=-1)
     ap.add_argument("--no-compare", action="store_true")
@@ -324,7 +330,8 @@ def main(argv=None):
                            compare=not args.no_compare)
     elif args.what == "product_peak_batch":
         out = product_peak_batch(count=args.count or 512,
-                                 tile_points=0 if args.tile_points < 0 else args.tile_points)
+                                 tile_points=0 if args.tile_points < 0 else args.tile_points,
+                                 shift_tile=args.shift_tile, blocks_per_cu=args.blocks_per_cu)
     elif args.what == "cv_estimate":
         out = cv_estimate()
     elif args.what == "time_to_error":
