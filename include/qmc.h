@@ -94,7 +94,8 @@ typedef struct {
    U(z) = sum_t coef_u[t] prod_i z_i^exp_u[t*d+i]  (row-major (n_u, d)), F alike.
    Exponents and nu are 0..2; a monomial may have total degree <= 12.
    Real form (is_complex = 0) needs U > 0 and F > 0 on the domain; complex form
-   uses the principal branch.  pow_u, pow_f, delta_im are plain doubles. */
+   uses the principal branch.  pow_u, pow_f, delta_im are plain doubles;
+   EUNSUPPORTED for a complex sector with |pow_f| > 1e5. */
 typedef struct {
     uint32_t n_u, n_f;
     const double *coef_u;
@@ -298,9 +299,11 @@ qmc_status qmc_integrate_cv(qmc_plan_t plan, qmc_family family, const void *para
                             const double *w, const double *c, qmc_result *out, qmc_result *plain_out,
                             double *per_shift);
 
-/* The library's device FP64 logarithm (fn = 0, argument > 0) or exponential
-   (fn = 1) on count host values x, results in y; for checking the device
-   math the sector integrand uses against a host reference. */
+/* The library's device FP64 math on count host inputs, for checking the
+   functions the sector integrand uses against a host reference:
+   fn = 0 logarithm (x > 0), 1 exponential: x and y hold count values;
+   fn = 2 atan2: x holds count pairs (y_i, x_i), y count angles;
+   fn = 3 sincos (|x| < 2^19): x count values, y count pairs (sin, cos). */
 qmc_status qmc_math_eval(int32_t fn, uint64_t count, const double *x, double *y);
 
 /* Release a plan and its device memory (NULL is ignored). */

@@ -149,6 +149,9 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
         if (!std::isfinite(p->pow_u) || !std::isfinite(p->pow_f)) return fail(QMC_EINVAL, "power not finite");
         const bool cplx = p->is_complex != 0;
         if (cplx && (!std::isfinite(p->delta_im))) return fail(QMC_EINVAL, "delta_im not finite");
+        // the phase pow_f * arg(F - i delta) must stay inside the exact range
+        // of the device sine and cosine (|x| < 2^19)
+        if (cplx && std::fabs(p->pow_f) > 1.0e5) return fail(QMC_EUNSUPPORTED, "|pow_f| > 1e5 for a complex sector");
         uint64_t nucode = 0;
         for (uint32_t i = 0; i < d; ++i) {
             if (p->nu[i] > 2) return fail(QMC_EINVAL, "nu_%u = %u > 2", i, (unsigned)p->nu[i]);
@@ -570,16 +573,17 @@ qmc_status qmc_integrate(qmc_plan_t p, qmc_family family, const void *params, qm
 }
 
 qmc_status qmc_math_eval(int32_t fn, uint64_t count, const double *x, double *y) {
-    if (fn != 0 && fn != 1) return fail(QMC_EINVAL, "fn must be 0 (log) or 1 (exp)");
+    if (fn < 0 || fn > 3) return fail(QMC_EINVAL, "fn must be 0 (log), 1 (exp), 2 (atan2) or 3 (sincos)");
     if (count && (!x || !y)) return fail(QMC_EINVAL, "null array");
     if (count > (1ull << 28)) return fail(QMC_EINVAL, "count > 2^28");
     if (count == 0) return QMC_OK;
+    const size_t nx = fn == 2 ? 2 * count : count, ny = fn == 3 ? 2 * count : count;
     DeviceScratch s;
     qmc_status st;
-    if ((st = s.alloc(count * 8)) || (st = s.alloc(count * 8))) return st;
-    hipError_t e = hipMemcpy(s.ptr[0], x, count * 8, hipMemcpyHostToDevice);
+    if ((st = s.alloc(nx * 8)) || (st = s.alloc(ny * 8))) return st;
+    hipError_t e = hipMemcpy(s.ptr[0], x, nx * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_math(fn, count, (const double *)s.ptr[0], (double *)s.ptr[1], nullptr);
-    if (e == hipSuccess) e = hipMemcpy(y, s.ptr[1], count * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(y, s.ptr[1], ny * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "math eval");
     return QMC_OK;
 }

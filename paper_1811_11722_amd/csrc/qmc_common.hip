@@ -89,7 +89,11 @@ std::map<KernelKey, LatticeLaunch> &lattice_registry() {
 // device math on an array: fn 0 = qlog, 1 = qexp
 __global__ __launch_bounds__(kBlock) void k_math(int fn, uint64_t count, const double *x, double *y) {
     const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < count) y[i] = fn == 0 ? qlog(x[i]) : qexp(x[i]);
+    if (i >= count) return;
+    if (fn == 0) y[i] = qlog(x[i]);
+    else if (fn == 1) y[i] = qexp(x[i]);
+    else if (fn == 2) y[i] = qatan2(x[2 * i], x[2 * i + 1]);
+    else qsincos(x[i], y[2 * i], y[2 * i + 1]);
 }
 
 hipError_t launch_math(int fn, uint64_t count, const double *x, double *y, hipStream_t s) {

@@ -131,6 +131,77 @@ __device__ __forceinline__ double qlog(double x) {
     return x > 0.0 ? r : __builtin_nan("");
 }
 
+// ------------------------------------------------- FP64 atan2 and sincos
+// For the complex sector integrand (F - i delta)^p = |.|^p e^{i p arg}: the
+// phase needs arg(F - i delta) = atan2(-delta, F) and the sine and cosine of
+// p times it, a bounded argument.  Both are branch-free; their polynomials
+// are Chebyshev fits (near-minimax) made for this library with multiprecision
+// arithmetic, each below 3e-17 in its reduced range.
+
+// atan2(y, x) for finite (x, y) not both zero.  With n = min(|x|, |y|) and
+// d = max(|x|, |y|), t = n / d lies in [0, 1]; above tan(pi/8) it is replaced
+// by (n - d) / (n + d) = tan(atan(t) - pi/4), so one division leaves
+// |t| <= tan(pi/8), where atan(t) = t + t^3 P(t^2) with P of degree 10.  The
+// octant and quadrant are restored with pi/4, pi/2 - a, pi - a and the sign
+// of y.
+__device__ __forceinline__ double qatan2(double y, double x) {
+    constexpr double kTanPi8 = 0x1.a827999fcef32p-2;
+    constexpr double kPi4 = 0x1.921fb54442d18p-1, kPi2 = 0x1.921fb54442d18p+0, kPi = 0x1.921fb54442d18p+1;
+    const double ax = __builtin_fabs(x), ay = __builtin_fabs(y);
+    const double n = __builtin_fmin(ax, ay), d = __builtin_fmax(ax, ay);
+    const bool big = n > kTanPi8 * d;
+    const double t = divide(big ? n - d : n, big ? n + d : d);
+    const double s = t * t;
+    double p = -0x1.3a31b1c0fd3b7p-6;
+    p = fma_(p, s, 0x1.4162c02b1dda3p-5);
+    p = fma_(p, s, -0x1.a0999c632b6edp-5);
+    p = fma_(p, s, 0x1.dfe6497e96323p-5);
+    p = fma_(p, s, -0x1.10fa77b1a6d57p-4);
+    p = fma_(p, s, 0x1.3b1263064f6b9p-4);
+    p = fma_(p, s, -0x1.745d0b28a7e37p-4);
+    p = fma_(p, s, 0x1.c71c71853d7fap-4);
+    p = fma_(p, s, -0x1.2492492436201p-3);
+    p = fma_(p, s, 0x1.999999999934cp-3);
+    p = fma_(p, s, -0x1.5555555555555p-2);
+    double a = fma_(t * s, p, t);
+    a = big ? a + kPi4 : a;
+    a = ay > ax ? kPi2 - a : a;
+    a = x < 0.0 ? kPi - a : a;
+    return __builtin_copysign(a, y);
+}
+
+// sin and cos of x for |x| < 2^19 (the phase is |p| times an angle in
+// [-pi, pi]).  x = k pi/2 + r with k = rint(2x/pi) and pi/2 in three parts
+// (the first two with 33 significant bits, so k times them is exact for
+// |k| < 2^20), |r| <= pi/4; sin r = r + r^3 S(r^2), cos r = 1 - r^2/2 +
+// r^4 C(r^2) with S, C of degree 5; the quadrant k mod 4 swaps and negates.
+__device__ __forceinline__ void qsincos(double x, double &sn, double &cs) {
+    constexpr double k2Pi = 0x1.45f306dc9c883p-1;
+    const double k = __builtin_rint(x * k2Pi);
+    double r = fma_(-k, 0x1.921fb54400000p+0, x);
+    r = fma_(-k, 0x1.0b4611a600000p-34, r);
+    r = fma_(-k, 0x1.3198a2e037073p-69, r);
+    const double r2 = r * r;
+    double ps = 0x1.5e0b19f8b1451p-33;
+    ps = fma_(ps, r2, -0x1.ae600b02b6262p-26);
+    ps = fma_(ps, r2, 0x1.71de37968a100p-19);
+    ps = fma_(ps, r2, -0x1.a01a019e83aaep-13);
+    ps = fma_(ps, r2, 0x1.1111111110bb2p-7);
+    ps = fma_(ps, r2, -0x1.5555555555555p-3);
+    double pc = -0x1.907da367a37cbp-37;
+    pc = fma_(pc, r2, 0x1.1eeb68e93b64cp-29);
+    pc = fma_(pc, r2, -0x1.27e4fa17da09ep-22);
+    pc = fma_(pc, r2, 0x1.a01a019f4eb01p-16);
+    pc = fma_(pc, r2, -0x1.6c16c16c16967p-10);
+    pc = fma_(pc, r2, 0x1.5555555555555p-5);
+    const double sr = fma_(r * r2, ps, r);
+    const double cr = fma_(r2 * r2, pc, fma_(-0.5, r2, 1.0));
+    const int q = (int)k;
+    const double ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+    sn = (q & 2) ? -ss : ss;
+    cs = ((q + 1) & 2) ? -cc : cc;
+}
+
 // Knuth's TwoSum: s + e == a + b exactly.
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
     s = a + b;

@@ -391,9 +391,9 @@ __device__ __forceinline__ void sector_finish(double mono, double U, double F, u
         // log(F - i delta) = ln|F - i delta| + i atan2(-delta, F)
         const double mod2 = fma_(F, F, delta * delta);
         const double e = fma_(0.5 * pow_f, qlog(mod2), lu);
-        const double ph = pow_f * atan2(-delta, F);
+        const double ph = pow_f * qatan2(-delta, F);
         double s, c;
-        sincos(ph, &s, &c);
+        qsincos(ph, s, c);
         const double mag = pre * qexp(e);
         v[0] = mag * c;
         v[1] = mag * s;

@@ -313,11 +313,16 @@ class Plan:
         return best.shift_tile, best.blocks_per_cu
 
 
-def math_eval(fn: str, x) -> np.ndarray:
-    """Device qlog ('log') or qexp ('exp') on an array."""
+def math_eval(fn: str, x, x2=None) -> np.ndarray:
+    """Device math on arrays: 'log', 'exp', 'atan2' (math_eval('atan2', y, x))
+    or 'sincos' (returns an (n, 2) array of sin, cos)."""
+    code = {"log": 0, "exp": 1, "atan2": 2, "sincos": 3}[fn]
     x = _arr(x, np.float64)
-    y = np.zeros_like(x)
-    check(lib().qmc_math_eval({"log": 0, "exp": 1}[fn], x.size, _p(x), _p(y)), "qmc_math_eval")
+    n = x.size
+    if code == 2:
+        x = _arr(np.stack([x, _arr(x2, np.float64)], axis=-1), np.float64)
+    y = np.zeros((n, 2) if code == 3 else n)
+    check(lib().qmc_math_eval(code, n, _p(x), _p(y)), "qmc_math_eval")
     return y
 
 

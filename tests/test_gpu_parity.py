@@ -77,6 +77,36 @@ def test_device_log_exp_ulps(Q):
     assert Q.math_eval("exp", np.array([-800.0]))[0] == 0.0
 
 
+def test_device_atan2_sincos(Q):
+    """qatan2 / qsincos against long-double libm: every quadrant, the sector
+    phase's own arguments (-delta, F) with F of both signs, the octant
+    boundary tan(pi/8), and phases up to |x| = 1e5."""
+    rng = np.random.default_rng(11)
+    mag = 10.0 ** rng.uniform(-6, 6, 100000)
+    ang = rng.uniform(-np.pi, np.pi, 100000)
+    yy = np.concatenate([mag * np.sin(ang), -10.0 ** rng.uniform(-4, 0, 50000),
+                         [0.0, -0.0, 1.0, -1.0, np.tan(np.pi / 8), -1e-300, 2.0]])
+    xx = np.concatenate([mag * np.cos(ang), rng.choice([-1.0, 1.0], 50000) * 10.0 ** rng.uniform(-3, 3, 50000),
+                         [1.0, -1.0, 0.0, -0.0, 1.0, -1.0, 2.0]])
+    _say("device atan2")
+    a = Q.math_eval("atan2", yy, xx)
+    ref = np.arctan2(yy.astype(np.longdouble), xx.astype(np.longdouble))
+    err = np.abs((a - ref).astype(np.float64))
+    assert np.all(err <= 2.5 * np.spacing(np.abs(ref.astype(np.float64))) + 1e-300), err.max()
+    assert np.array_equal(np.signbit(a[-7:-3]), np.signbit(np.arctan2(yy[-7:-3], xx[-7:-3])))
+    t = np.concatenate([rng.uniform(-4.5, 4.5, 200000), rng.uniform(-1e5, 1e5, 100000),
+                        [0.0, np.pi / 4, np.pi / 2, -np.pi, 1e-300]])
+    _say("device sincos")
+    sc = Q.math_eval("sincos", t)
+    tl = t.astype(np.longdouble)
+    for col, ref in ((0, np.sin(tl)), (1, np.cos(tl))):
+        err = np.abs((sc[:, col] - ref).astype(np.float64))
+        # absolute error of a few ulps of 1 (the reduced argument carries
+        # the rounding of |x| for the large arguments)
+        bound = 4.0 * 2.0 ** -53 * np.maximum(1.0, np.abs(t) * 2.0 ** -20)
+        assert np.all(err <= bound), (col, err.max())
+
+
 # ---------------------------------------------------------- lattice indices
 def test_indices_bit_exact_all_points(Q):
     n, d = 131071, 4
