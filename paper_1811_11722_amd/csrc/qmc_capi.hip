@@ -355,7 +355,7 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     hipFunction_t jfn = nullptr;
     const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
     if (sector && p->jit_mode != 0) {
-        T = want_T ? want_T : (pk.np == 2 ? 1u : 2u);
+        T = want_T ? want_T : 2u;  // measured best for real and complex sectors
         std::string err;
         jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.np == 2, p->device, err);
         if (!jfn && p->jit_mode == 2) return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
