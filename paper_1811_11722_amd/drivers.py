@@ -10,6 +10,7 @@ and times calls.
     python -m paper_1811_11722_amd.drivers time_to_error
     python -m paper_1811_11722_amd.drivers convergence
     python -m paper_1811_11722_amd.drivers cv_estimate
+    python -m paper_1811_11722_amd.drivers fig3
 """
 from __future__ import annotations
 
@@ -312,10 +313,33 @@ def cv_estimate(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED
             "err_cv": out.err_re, "err_plain": plain.err_re, "mean_cv": out.mean_re, "mean_plain": plain.mean_re}
 
 
+def fig3(dims=(6, 9, 10), alphas=(3, 6), kmin: int = 10, kmax: int = 26, m: int = 32,
+         seed: int = synth.SEED_BASE + 6, log=None) -> dict:
+    """The error study of Sec. 2 (Fig. 3): the constant 1 integrated with the
+    Korobov transform of weight alpha in d dimensions, for the ladder of
+    primes below 2^k.  The exact value is 1; for every (d, alpha, n) the
+    reported relative error sigma / |mean| and the true error |mean - 1|.
+    (The baker transform integrates a constant exactly for any lattice.)"""
+    say = log or (lambda msg: None)
+    rows = []
+    for d in dims:
+        gv = GeneratingVectors(seed + d)
+        sh = synth.shifts(seed + d, m, d)
+        for alpha in alphas:
+            for n in synth.prime_ladder(kmin, kmax):
+                plan = qmc.Plan(d, n, gv(n, d), sh, "korobov", alpha)
+                res, _ = plan.integrate(qmc.Params("const", d, c=1.0))
+                plan.close()
+                rows.append({"d": d, "alpha": alpha, "n": n, "mean": res.mean_re, "err": res.err_re,
+                             "rel_err": res.err_re / abs(res.mean_re), "true_err": abs(res.mean_re - 1.0)})
+                say(f"  d={d} alpha={alpha} n={n} err={res.err_re:.3e} true={abs(res.mean_re - 1.0):.3e}")
+    return {"m": m, "rows": rows}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
-                                     "cv_estimate"])
+                                     "cv_estimate", "fig3"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--shift-tile", type=int, default=0)
@@ -334,6 +358,8 @@ def main(argv=None):
                                  shift_tile=args.shift_tile, blocks_per_cu=args.blocks_per_cu)
     elif args.what == "cv_estimate":
         out = cv_estimate()
+    elif args.what == "fig3":
+        out = fig3(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "time_to_error":
         out = time_to_error(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     else:

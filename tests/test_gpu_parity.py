@@ -107,6 +107,22 @@ def test_device_atan2_sincos(Q):
         assert np.all(err <= bound), (col, err.max())
 
 
+def test_korobov_constant_error_decay(Q):
+    """Sec. 2, Fig. 3: integrating 1 with the Korobov weight-3 transform in
+    d = 6, the reported error falls far faster than 1/n, and the per-shift
+    sums stay within the oracle's parity bar."""
+    d, m = 6, 16
+    sh = synth.shifts(81, m, d)
+    errs = []
+    for n, a in ((1021, 76), (16381, 5029), (262139, 100135)):
+        g = O.korobov_vector(n, d, a)
+        _say(f"fig3 n={n}")
+        res, q, est = _both(Q, "const", d, n, g, sh, "korobov", 3, c=1.0)
+        assert np.all(np.abs(q - est.q_re) <= 1e-12 * np.abs(est.q_re))
+        errs.append(res.err_re)
+    assert errs[1] < errs[0] / 50 and errs[2] < errs[1] / 50, errs
+
+
 # ---------------------------------------------------------- lattice indices
 def test_indices_bit_exact_all_points(Q):
     n, d = 131071, 4
