@@ -106,6 +106,13 @@ typedef struct {
     double pow_u, pow_f;
     double delta_im;
     int32_t is_complex;
+    /* Expansion in a regulator e (qmc_integrate_orders): with n_orders >= 2
+       the exponents become pow_u + eps_u e and pow_f + eps_f e and the
+       integrand's coefficients of e^0 .. e^(n_orders-1) are integrated in one
+       pass; order k is f L^k / k!, L = eps_u ln U + eps_f ln(F - i delta).
+       n_orders <= 4; 0 or 1 is the plain integrand. */
+    uint32_t n_orders;
+    double eps_u, eps_f;
 } qmc_sector_params;
 
 /* Result of eqs. (2)-(3).  err = sqrt(sigma^2); complex integrands carry
@@ -298,6 +305,19 @@ qmc_status qmc_cv_integral(uint32_t R, uint32_t d, uint32_t K, const double *w, 
 qmc_status qmc_integrate_cv(qmc_plan_t plan, qmc_family family, const void *params, uint32_t R, uint32_t K,
                             const double *w, const double *c, qmc_result *out, qmc_result *plain_out,
                             double *per_shift);
+
+/* The coefficients of e^0 .. e^(n_orders-1) of a sector integrand whose
+   exponents depend on a regulator e (qmc_sector_params.n_orders >= 2), all
+   from one pass over the lattice: the sector functions U, F, their
+   logarithms and the powers are shared between the orders.  Sector
+   integrands are expanded in the dimensional regulator order by order
+   (Sec. 1); the exponents' dependence on it is what the caller passes as
+   eps_u, eps_f.  out: n_orders results (caller-owned); per_shift (nullable):
+   m * parts doubles, per shift the orders in turn, (Re, Im) for complex.
+   Needs the specialised kernel (EUNSUPPORTED with qmc_plan_set_jit(0));
+   qmc_integrate rejects n_orders >= 2 with EINVAL. */
+qmc_status qmc_integrate_orders(qmc_plan_t plan, qmc_family family, const void *params, qmc_result *out,
+                                double *per_shift);
 
 /* The library's device FP64 math on count host inputs, for checking the
    functions the sector integrand uses against a host reference:

@@ -64,6 +64,9 @@ class _Params(C.Structure):
         ("cv_k", C.c_uint32),
         ("cv_w_im", C.c_void_p),
         ("cv_c_im", C.c_void_p),
+        ("eps_u", C.c_double),
+        ("eps_f", C.c_double),
+        ("eps_order", C.c_int32),
         ("point_mode", C.c_int32),
     ]
 
@@ -112,12 +115,16 @@ class Params:
     """Integrand description; keeps the numpy arrays alive for the call."""
 
     def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
-                 sector=None, cv=None, point_mode: int = 0):
+                 sector=None, cv=None, point_mode: int = 0, eps=None):
+        """eps (sector): (eps_u, eps_f, k) selects the coefficient of e^k of the
+        integrand with exponents pow_u + eps_u e, pow_f + eps_f e."""
         self.keep = []
         p = _Params()
         p.family = FAMILIES[family]
         p.c = float(c)
         p.point_mode = int(point_mode)
+        if eps is not None:
+            p.eps_u, p.eps_f, p.eps_order = float(eps[0]), float(eps[1]), int(eps[2])
 
         def arr(x, dt):
             v = np.ascontiguousarray(np.asarray(x, dtype=dt))

@@ -87,6 +87,12 @@ typedef struct {
     uint32_t cv_r, cv_k;
     const double *cv_w_im;
     const double *cv_c_im;
+    /* expansion in a regulator e: with eps_order = k >= 1 the sector
+       integrand is replaced by its coefficient of e^k when the exponents are
+       pow_u + eps_u e and pow_f + eps_f e, namely f L^k / k! with
+       L = eps_u ln U + eps_f ln(F - i delta) (principal branch) */
+    double eps_u, eps_f;
+    int32_t eps_order;
     /* coordinate rounding: 0 -> idx / n (IEEE division), 1 -> idx * (1/n) */
     int32_t point_mode;
 } or_params;
@@ -319,14 +325,19 @@ void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, d
         double U = or_poly(d, p->n_u, p->coef_u, p->exp_u, z);
         double F = or_poly(d, p->n_f, p->coef_f, p->exp_f, z);
         double pre = mono * pow(U, p->pow_u);
+        double complex v, L;
         if (p->is_complex) {
             double complex Fc = F - I * p->delta_im;
-            double complex v = pre * cpow(Fc, p->pow_f);
-            vr = creal(v);
-            vi = cimag(v);
+            v = pre * cpow(Fc, p->pow_f);
+            L = p->eps_u * log(U) + p->eps_f * clog(Fc);
         } else {
-            vr = pre * pow(F, p->pow_f);
+            v = pre * pow(F, p->pow_f);
+            L = p->eps_u * log(U) + p->eps_f * log(F);
         }
+        for (int32_t k = 1; k <= p->eps_order; ++k)
+            v = v * L / (double)k;
+        vr = creal(v);
+        vi = p->is_complex ? cimag(v) : 0.0;
         break;
     }
     default:

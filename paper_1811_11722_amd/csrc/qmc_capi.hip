@@ -176,6 +176,18 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
         if (cplx) {
             pk.np = 2;
             pk.key_family = kFamSectorComplex;
+            pk.cplx = true;
+        }
+        if (p->n_orders >= 2) {
+            if (p->n_orders > kSectorMaxOrders)
+                return fail(QMC_EUNSUPPORTED, "n_orders = %u > %u", p->n_orders, kSectorMaxOrders);
+            if (!std::isfinite(p->eps_u) || !std::isfinite(p->eps_f)) return fail(QMC_EINVAL, "eps not finite");
+            pk.blob[2] = bits(flags | kSectorOrders);
+            pk.blob.push_back(p->eps_u);
+            pk.blob.push_back(p->eps_f);
+            pk.blob.push_back(bits(p->n_orders));
+            pk.orders = p->n_orders;
+            pk.np *= p->n_orders;
         }
         break;
     }
@@ -357,9 +369,11 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     if (sector && p->jit_mode != 0) {
         T = want_T ? want_T : 2u;  // measured best for real and complex sectors
         std::string err;
-        jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.np == 2, p->device, err);
-        if (!jfn && p->jit_mode == 2) return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
+        jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.cplx, p->device, err);
+        if (!jfn && (p->jit_mode == 2 || pk.orders >= 2))
+            return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
     }
+    if (!jfn && pk.orders >= 2) return fail(QMC_EUNSUPPORTED, "expansion orders need the specialised kernel (jit mode 1 or 2)");
     if (!jfn) {
         fn = find_kernel(pk.key_family, p->tr, p->d, want_T ? want_T : default_tile(pk.key_family), T);
         if (!fn)
@@ -562,6 +576,7 @@ qmc_status qmc_integrate(qmc_plan_t p, qmc_family family, const void *params, qm
     Packed pk;
     qmc_status st = pack_params((int)family, p->d, params, pk);
     if (st) return st;
+    if (pk.orders >= 2) return fail(QMC_EINVAL, "n_orders >= 2: use qmc_integrate_orders");
     qmc_launch L = p->launch;
     if (L.shift_tile == 0 && L.blocks_per_cu == 0) {
         const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
@@ -570,6 +585,31 @@ qmc_status qmc_integrate(qmc_plan_t p, qmc_family family, const void *params, qm
     }
     if ((st = plan_enqueue(p, pk, L.shift_tile, L.blocks_per_cu))) return st;
     return plan_collect(p, pk.np, out, per_shift);
+}
+
+qmc_status qmc_integrate_orders(qmc_plan_t p, qmc_family family, const void *params, qmc_result *out,
+                                double *per_shift) {
+    if (!p) return fail(QMC_EINVAL, "plan is NULL");
+    if (!out) return fail(QMC_EINVAL, "out is NULL");
+    if (family != QMC_F_SECTOR) return fail(QMC_EUNSUPPORTED, "expansion orders are built for QMC_F_SECTOR");
+    Packed pk;
+    qmc_status st = pack_params((int)family, p->d, params, pk);
+    if (st) return st;
+    const uint32_t no = pk.orders >= 2 ? pk.orders : 1u;
+    if ((st = plan_enqueue(p, pk, p->launch.shift_tile, p->launch.blocks_per_cu))) return st;
+    qmc_result first;
+    st = plan_collect(p, pk.np, &first, per_shift);
+    const double *res = p->h_out + out_res_offset(p->m);
+    for (uint32_t k = 0; k < no; ++k) {
+        if (pk.cplx) {  // parts (2k, 2k+1) = (Re, Im) of order k form pair k
+            out[k] = qmc_result{res[4 * k], res[4 * k + 1], res[4 * k + 2], res[4 * k + 3], 1, 0};
+        } else {        // part k = order k, pairs of orders share a result block
+            const uint32_t b = 4 * (k / 2), o = k % 2;
+            out[k] = qmc_result{res[b + o], 0.0, res[b + 2 + o], 0.0, 0, 0};
+        }
+        if (st == QMC_ENONFINITE) out[k] = qmc_result{NAN, NAN, NAN, NAN, pk.cplx ? 1 : 0, 0};
+    }
+    return st;
 }
 
 qmc_status qmc_math_eval(int32_t fn, uint64_t count, const double *x, double *y) {

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const FinalizeArgs a) {
     if (threadIdx.x == 0) {
         // results per pair of parts: (mean a, mean b, err a, err b)
         const uint32_t rs = 4 * ((a.np + 1) / 2);
-        double out[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double out[2 * kMaxParts] = {};
         for (uint32_t p = 0; p < a.np; ++p) {
             dd s{0.0, 0.0};
             for (uint32_t k = 0; k < a.m; ++k) dd_accumulate(s.hi, s.lo, qs[k * a.np + p]);
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(const FinalizeBatchAr
     if (threadIdx.x == 0) {
         // results per pair of parts: (mean a, mean b, err a, err b)
         const uint32_t rs = 4 * ((a.np + 1) / 2);
-        double out[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double out[2 * kMaxParts] = {};
         for (uint32_t p = 0; p < a.np; ++p) {
             dd s{0.0, 0.0};
             for (uint32_t k = 0; k < sc.m; ++k) dd_accumulate(s.hi, s.lo, qs[k * a.np + p]);

@@ -369,6 +369,10 @@ __device__ __forceinline__ void nu_eval(uint32_t code, const double (&init)[T], 
 //        coef_u (n_u), code_u (n_u), coef_f (n_f), code_f (n_f)]
 // flags bit 0: complex, bit 1: pow_u == -2 (U^-2 by reciprocal).
 enum : uint32_t { kSectorComplex = 1u, kSectorPowUm2 = 2u };
+// Expansion orders (qmc_integrate_orders, flag 4): three words after the F
+// exponent codes hold eps_u, eps_f and the number of orders.
+enum : uint32_t { kSectorOrders = 4u };
+constexpr uint32_t kSectorMaxOrders = 4;
 constexpr int kSectorHeader = 7;
 
 // fhat from the polynomial values: mono = jac * prod z^nu, then
@@ -397,6 +401,54 @@ __device__ __forceinline__ void sector_finish(double mono, double U, double F, u
         const double mag = pre * qexp(e);
         v[0] = mag * c;
         v[1] = mag * s;
+    }
+}
+
+// Coefficients of the expansion in a regulator e of
+// mono * U^(pow_u + eps_u e) * (F - i delta)^(pow_f + eps_f e):
+// with f the value at e = 0 and L = eps_u ln U + eps_f ln(F - i delta)
+// (principal branch), the coefficient of e^k is f L^k / k!.  Part k (real)
+// or parts (2k, 2k+1) (complex) receive order k, k < NO.
+template <bool Complex, int NO>
+__device__ __forceinline__ void sector_orders(double mono, double U, double F, uint32_t flags, double pow_u,
+                                              double pow_f, double delta, double eps_u, double eps_f,
+                                              double (&v)[(Complex ? 2 : 1) * NO]) {
+    const double lnu = qlog(U);
+    double pre = mono;
+    if (flags & kSectorPowUm2) {
+        const double r = recip(U);
+        pre = pre * (r * r);
+    } else {
+        pre = pre * qexp(pow_u * lnu);
+    }
+    if constexpr (!Complex) {
+        const double lnf = qlog(F);
+        double f = pre * qexp(pow_f * lnf);
+        const double L = fma_(eps_u, lnu, eps_f * lnf);
+        v[0] = f;
+#pragma unroll
+        for (int k = 1; k < NO; ++k) {
+            f = (f * L) * (1.0 / k);
+            v[k] = f;
+        }
+    } else {
+        const double lnm = 0.5 * qlog(fma_(F, F, delta * delta));  // ln|F - i delta|
+        const double th = qatan2(-delta, F);                        // arg(F - i delta)
+        double s, c;
+        qsincos(pow_f * th, s, c);
+        const double mag = pre * qexp(pow_f * lnm);
+        double fr = mag * c, fi = mag * s;
+        const double lr = fma_(eps_u, lnu, eps_f * lnm), li = eps_f * th;
+        v[0] = fr;
+        v[1] = fi;
+#pragma unroll
+        for (int k = 1; k < NO; ++k) {
+            const double nr = fma_(fr, lr, -fi * li), ni = fma_(fr, li, fi * lr);
+            fr = nr * (1.0 / k);
+            fi = ni * (1.0 / k);
+            v[2 * k] = fr;
+            v[2 * k + 1] = fi;
+        }
     }
 }
 

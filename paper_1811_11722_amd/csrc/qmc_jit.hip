@@ -82,6 +82,10 @@ const char *transform_type(const qmc_transform &t) {
 // canonical description of what the code depends on.
 static std::string functor_source(const std::vector<double> &blob, uint32_t d, bool cplx, std::string &structure) {
     const uint32_t nu = (uint32_t)word(blob, 0), nf = (uint32_t)word(blob, 1);
+    // expansion orders (flag 4): three words after the F codes (eps_u,
+    // eps_f, count); other blobs may carry other data there
+    const size_t eps_at = kSectorHeader + 2 * (size_t)nu + 2 * (size_t)nf;
+    const uint32_t orders = (word(blob, 2) & kSectorOrders) ? (uint32_t)word(blob, eps_at + 2) : 0u;
     Trie trie;
     std::vector<int> mu(nu), mf(nf);
     std::ostringstream st;
@@ -99,7 +103,7 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
     }
     const uint64_t nuc = word(blob, 6);
     const uint32_t flags = (uint32_t)word(blob, 2);
-    st << "|f" << flags;
+    st << "|f" << flags << "|o" << orders;
     std::vector<int> nuf;
     for (uint32_t i = 0; i < d; ++i)
         for (uint64_t r = 0; r < ((nuc >> (2 * i)) & 3u); ++r) nuf.push_back((int)i);
@@ -108,8 +112,9 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
     structure = st.str();
 
     std::ostringstream s;
+    const uint32_t np = (cplx ? 2u : 1u) * (orders >= 2 ? orders : 1u);
     s << "struct FamJit {\n"
-      << "    static constexpr int NP = " << (cplx ? 2 : 1) << ";\n"
+      << "    static constexpr int NP = " << np << ";\n"
       << "    template <class Tr, int D, int T>\n"
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"
@@ -151,10 +156,14 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
     poly("U", "cu", mu);
     poly("F", "cf", mf);
     s << "            const double mono = " << (mnu < 0 ? std::string("jac[k]") : "jac[k] * " + ref(mnu))
-      << ";\n"
-      << "            sector_finish<" << (cplx ? "true" : "false")
-      << ">(mono, U, F, flags, pow_u, pow_f, delta, v[k]);\n"
-      << "        }\n    }\n};\n";
+      << ";\n";
+    if (orders >= 2)
+        s << "            sector_orders<" << (cplx ? "true" : "false") << ", " << orders
+          << ">(mono, U, F, flags, pow_u, pow_f, delta, cp[" << eps_at << "], cp[" << eps_at + 1 << "], v[k]);\n";
+    else
+        s << "            sector_finish<" << (cplx ? "true" : "false")
+          << ">(mono, U, F, flags, pow_u, pow_f, delta, v[k]);\n";
+    s << "        }\n    }\n};\n";
     return s.str();
 }
 

@@ -288,6 +288,7 @@ struct FinalizeArgs {
 };
 
 constexpr uint32_t kMaxRows = 4096;  // m * np per instance
+constexpr uint32_t kMaxParts = 8;    // parts per shift (k_finalize, result buffers)
 
 struct DumpArgs {
     uint32_t n, d;

@@ -16,8 +16,7 @@ namespace qmc {
 constexpr uint32_t kMaxDim = 16;
 // Per-plan result buffer: Q_k for up to kMaxParts parts (m * kMaxParts
 // doubles), then the results of every pair of parts, (mean a, mean b,
-// err a, err b), 4 doubles per pair.
-constexpr uint32_t kMaxParts = 4;
+// err a, err b), 4 doubles per pair (kMaxParts in qmc_kernels.hpp).
 inline size_t out_res_offset(uint32_t m) { return (size_t)kMaxParts * m; }
 inline size_t out_doubles(uint32_t m) { return (size_t)kMaxParts * m + 2 * kMaxParts; }
 constexpr uint32_t kMaxTile = 8;  // largest shift tile of any kernel
@@ -62,8 +61,10 @@ namespace qmc {
 
 struct Packed {
     std::vector<double> blob;
-    uint32_t np = 1;
+    uint32_t np = 1;       // parts accumulated per shift
     int key_family = 0;
+    bool cplx = false;     // complex sector
+    uint32_t orders = 0;   // expansion orders (>= 2: qmc_integrate_orders)
 };
 
 qmc_status fail(qmc_status s, const char *fmt, ...);

@@ -55,7 +55,8 @@ class qmc_sector_params(C.Structure):
     _fields_ = [("n_u", C.c_uint32), ("n_f", C.c_uint32), ("coef_u", C.c_void_p),
                 ("exp_u", C.c_void_p), ("coef_f", C.c_void_p), ("exp_f", C.c_void_p),
                 ("nu", C.c_void_p), ("pow_u", C.c_double), ("pow_f", C.c_double),
-                ("delta_im", C.c_double), ("is_complex", C.c_int32)]
+                ("delta_im", C.c_double), ("is_complex", C.c_int32), ("n_orders", C.c_uint32),
+                ("eps_u", C.c_double), ("eps_f", C.c_double)]
 
 
 class qmc_result(C.Structure):
@@ -106,6 +107,7 @@ SIGNATURES = {
     "qmc_cv_train": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp]),
     "qmc_cv_integral": (C.c_int, [_u32, _u32, _u32, _vp, _vp, _vp]),
     "qmc_integrate_cv": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "qmc_integrate_orders": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
     "qmc_last_error": (C.c_char_p, []),
@@ -159,8 +161,10 @@ class Params:
     """Family parameter struct plus the arrays it points into."""
 
     def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
-                 sector=None):
+                 sector=None, orders=None):
+        """orders (sector only): (n_orders, eps_u, eps_f) for qmc_integrate_orders."""
         self.family = FAMILY[family]
+        self.n_orders = 0
         self.keep = []
 
         def keep(x, dt):
@@ -183,7 +187,9 @@ class Params:
                 s.n_u, s.n_f, _p(keep(s.coef_u, np.float64)), _p(keep(s.exp_u, np.uint8)),
                 _p(keep(s.coef_f, np.float64)), _p(keep(s.exp_f, np.uint8)),
                 _p(keep(s.nu, np.uint8)), float(s.pow_u), float(s.pow_f), float(s.delta_im),
-                int(bool(s.is_complex)))
+                int(bool(s.is_complex)), int(orders[0]) if orders else 0,
+                float(orders[1]) if orders else 0.0, float(orders[2]) if orders else 0.0)
+            self.n_orders = int(orders[0]) if orders else 0
         else:
             self.struct = qmc_genz_params(_p(keep(a, np.float64)), _p(keep(u, np.float64)))
 
@@ -299,6 +305,20 @@ class Plan:
             return out, plain, per[0::2].copy(), per[1::2].copy()
         per = per.reshape(self.m, 4)
         return out, plain, per[:, 0] + 1j * per[:, 1], per[:, 2] + 1j * per[:, 3]
+
+    def integrate_orders(self, params: Params):
+        """Expansion coefficients in one pass: (list of n_orders results,
+        per-shift array (m, n_orders), complex for complex sectors)."""
+        no = max(params.n_orders, 1)
+        out = (qmc_result * no)()
+        parts = no * (2 if params.is_complex else 1)
+        per = np.zeros(self.m * parts)
+        check(lib().qmc_integrate_orders(self.handle, params.family, params.ptr, out, _p(per)),
+              "qmc_integrate_orders")
+        per = per.reshape(self.m, parts)
+        if params.is_complex:
+            per = per[:, 0::2] + 1j * per[:, 1::2]
+        return list(out), per
 
     def lattice_dump(self, j_lo: int, count: int):
         idx = np.zeros((count, self.d), dtype=np.uint32)

@@ -368,3 +368,51 @@ def test_sector_full_size_sampled_shifts(Q):
     est = O.estimate(w.n, g, w.shifts[pick], O.Params("sector", w.d, sector=w.sector), "baker",
                      threads=THREADS)
     assert np.all(_rel(q[pick], est.q_re) < TOL), _rel(q[pick], est.q_re).max()
+
+
+# ----------------------------------------------------------- expansion orders
+@pytest.mark.parametrize("cplx", [False, True])
+def test_sector_orders_match_oracle(Q, cplx):
+    """Coefficients of e^0..e^3 of x^nu U^(-2 + 0.7 e) (F - i delta)^(-1.3 - 1.2 e)
+    in one pass, each order's per-shift sums against the oracle's."""
+    d, n, m = 5, 16381, 8
+    tab = synth.sector_tables(91, d, 7, 12)
+    if cplx:
+        tab.delta_im, tab.is_complex = 0.02, True
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(91, m, d)
+    plan = Q.Plan(d, n, g, sh, "baker")
+    _say(f"orders complex={cplx}")
+    res, per = plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(4, 0.7, -1.2)))
+    assert len(res) == 4 and per.shape == (m, 4)
+    for k in range(4):
+        est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab, eps=(0.7, -1.2, k)), "baker", threads=THREADS)
+        ref = est.q_re + 1j * est.q_im if cplx else est.q_re
+        assert np.all(np.abs(per[:, k] - ref) <= 1e-12 * np.abs(ref)), (k, np.max(np.abs(per[:, k] - ref) / np.abs(ref)))
+        mean, err, _ = est.mean_error()
+        got = complex(res[k].mean_re, res[k].mean_im)
+        assert abs(got - mean) <= 1e-12 * abs(mean)
+    # order 0 of the expansion is the plain integrand
+    r0, q0 = plan.integrate(Q.Params("sector", d, sector=tab))
+    assert abs(complex(r0.mean_re, r0.mean_im) - complex(res[0].mean_re, res[0].mean_im)) <= 1e-12 * abs(r0.mean_re)
+
+
+def test_sector_orders_validation(Q):
+    d, n = 3, 1021
+    tab = synth.sector_tables(92, d, 3, 4)
+    plan = Q.Plan(d, n, O.korobov_vector(n, d, 76), synth.shifts(92, 2, d), "baker")
+    with pytest.raises(Q.QMCError) as e:
+        plan.integrate(Q.Params("sector", d, sector=tab, orders=(2, 1.0, 1.0)))
+    assert e.value.status == Q.QMC_EINVAL
+    with pytest.raises(Q.QMCError) as e:
+        plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(5, 1.0, 1.0)))
+    assert e.value.status == Q.QMC_EUNSUPPORTED
+    plan.set_jit(0)
+    with pytest.raises(Q.QMCError) as e:
+        plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(2, 1.0, 1.0)))
+    assert e.value.status == Q.QMC_EUNSUPPORTED
+    # one order is the plain integrand through either entry point
+    plan.set_jit(1)
+    one, _ = plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(1, 1.0, 1.0)))
+    plain, _ = plan.integrate(Q.Params("sector", d, sector=tab))
+    assert one[0].mean_re == plain.mean_re

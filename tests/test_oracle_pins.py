@@ -572,3 +572,36 @@ def test_cv_complex_exact_models():
     # the real part of the model alone leaves the imaginary part untouched
     only_re = O.estimate(n, g, sh, O.Params("sector", d, sector=s, cv=(W[0], c[0])), "baker")
     assert np.array_equal(only_re.q_im, plain.q_im)
+
+
+def test_sector_eps_orders_closed_form():
+    """With U and F constant, int x^nu U^(a + a' e) (F - i delta)^(b + b' e) =
+    U0^a (F0 - i delta)^b exp(e L0) / prod (nu_i + 1), L0 = a' ln U0 +
+    b' ln(F0 - i delta): the coefficient of e^k is the e = 0 value times
+    L0^k / k!.  Real and complex kinematics; every lattice is exact for the
+    baker-transformed monomial up to the rule's error, so compare the mean
+    within its error and the ratios of orders exactly."""
+    d = 3
+    nu = [1, 0, 2]
+    for cplx, delta, F0 in ((False, 0.0, 0.9), (True, 0.04, 0.9), (True, 0.04, -0.6)):
+        s = synth.SectorTables(d=d, coef_u=np.array([1.7]), exp_u=np.zeros((1, d), np.uint8),
+                               coef_f=np.array([F0]), exp_f=np.zeros((1, d), np.uint8),
+                               nu=np.array(nu, np.uint8), delta_im=delta, is_complex=cplx)
+        eu, ef = 0.8, -1.1
+        base = 1.7 ** -2 * complex(F0, -delta) ** -1.3
+        L0 = eu * math.log(1.7) + ef * np.log(complex(F0, -delta))
+        n, m = 4093, 4
+        g = O.korobov_vector(n, d, 1200)
+        sh = synth.shifts(9, m, d)
+        q0 = None
+        for k in range(4):
+            est = O.estimate(n, g, sh, O.Params("sector", d, sector=s, eps=(eu, ef, k)), "baker")
+            q = est.q_re + 1j * est.q_im
+            closed = base * L0 ** k / math.factorial(k) / math.prod(v + 1 for v in nu)
+            mean, err, _ = est.mean_error()
+            assert abs(mean - closed) <= 1e-6 * abs(closed) + 6 * abs(err)
+            if k == 0:
+                q0 = q
+            else:
+                # per shift the order-k sums are the order-0 sums times L0^k / k!
+                assert np.allclose(q, q0 * L0 ** k / math.factorial(k), rtol=1e-13, atol=0)
