@@ -11,6 +11,7 @@ and times calls.
     python -m paper_1811_11722_amd.drivers convergence
     python -m paper_1811_11722_amd.drivers cv_estimate
     python -m paper_1811_11722_amd.drivers fig3
+    python -m paper_1811_11722_amd.drivers allocation_compare [--count 2000]
 """
 from __future__ import annotations
 
@@ -54,6 +55,65 @@ def allocate_n(rel_err0: float, n0: int, goal: float, rate: float = 2.0) -> int:
         if n >= want:
             return n
     return LADDER[-1]
+
+
+def allocate_total(sigma0, cost, n0: int, goal: float, rate=2.0, ladder=None):
+    """Lattice sizes for a sum of sectors with a total error goal.
+
+    With sector s's error sigma_s(n) = sigma0_s (n0 / n)^rate_s (a pilot at
+    n0 and the sector's rate) and its time cost_s * n, minimise
+    sum_s cost_s n_s subject to sum_s sigma_s(n_s)^2 <= goal^2.  The Lagrange
+    condition cost_s = lam * 2 rate_s sigma_s(n_s)^2 / n_s gives
+    n_s(lam) = (2 rate_s lam sigma0_s^2 n0^(2 rate_s) / cost_s)^(1 / (2 rate_s + 1));
+    the total error falls as lam grows, and lam is found by bisection on
+    log lam (closed form when all rates are equal).  Each n_s is then rounded
+    up to the ladder (which only lowers the error) and clamped to its ends.
+    rate: a scalar or one value per sector.
+    Returns (sizes, continuous sizes, predicted total error of the sizes)."""
+    ladder = list(LADDER if ladder is None else ladder)
+    s0 = np.asarray(sigma0, dtype=np.float64)
+    c = np.asarray(cost, dtype=np.float64)
+    r = np.broadcast_to(np.asarray(rate, dtype=np.float64), s0.shape)
+    if np.any(~np.isfinite(s0)) or np.any(c <= 0) or goal <= 0 or np.any(r <= 0):
+        raise ValueError("sigma0 must be finite; cost, goal and rate positive")
+    live = s0 > 0
+    cont = np.full(s0.shape, float(ladder[0]))
+    if np.any(live):
+        sl, cl, rl = s0[live], c[live], r[live]
+        b = 2.0 * rl
+        ln0 = math.log(n0)
+
+        def log_n(loglam):  # log n_s(lam), in logarithms (n0^(2 rate) overflows)
+            return (np.log(b) + loglam + 2.0 * np.log(sl) + b * ln0 - np.log(cl)) / (b + 1.0)
+
+        def log_err2(loglam):  # log of sum_s sigma_s(n_s(lam))^2
+            t = 2.0 * np.log(sl) + b * (ln0 - log_n(loglam))
+            mx = t.max()
+            return mx + math.log(np.sum(np.exp(t - mx)))
+
+        target = 2.0 * math.log(goal)
+        lo, hi = -200.0, 200.0
+        for _ in range(200):  # log err^2 is decreasing in log lam
+            mid = 0.5 * (lo + hi)
+            if log_err2(mid) > target:
+                lo = mid
+            else:
+                hi = mid
+        cont[live] = np.exp(log_n(hi))
+    sizes = np.asarray([next((n for n in ladder if n >= v), ladder[-1]) for v in cont], dtype=np.int64)
+    pred = float(np.sqrt(np.sum((s0 * (n0 / sizes.astype(np.float64)) ** r) ** 2)))
+    return sizes, cont, pred
+
+
+def estimate_rates(sigma_a, sigma_b, n_a: int, n_b: int, lo: float = 0.25, hi: float = 2.5):
+    """Per-sector convergence rates from error estimates at two lattice
+    sizes, sigma ~ n^-rate, clamped to [lo, hi] (the estimates are noisy:
+    lattices of similar size can differ by orders of magnitude, Sec. 2)."""
+    a = np.asarray(sigma_a, dtype=np.float64)
+    b = np.asarray(sigma_b, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rate = np.log(a / b) / math.log(n_b / n_a)
+    return np.clip(np.nan_to_num(rate, nan=lo, posinf=hi, neginf=lo), lo, hi)
 
 
 def _timed(fn, reps: int):
@@ -119,6 +179,56 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
     for p in plans:
         p.close()
     return out
+
+
+def allocation_compare(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int = synth.SEED_BASE + 3,
+                       tile_points: int = 8192, reps: int = 2) -> dict:
+    """The per-sector error-goal rule against the total-error allocation on
+    the same sectors.  Rule 1: each sector to goal relative to its own pilot
+    mean (sizes from its pilot error at the assumed rate 2).  Rule 2: sizes
+    minimising the modelled time sum_s cost_s n_s for the total error rule 1
+    achieves, with each sector's rate estimated from pilots at two sizes and
+    cost_s = 100 + 4 (n_u + n_f) FP64 flops per point.  Both run as
+    graph-replayed batches."""
+    tabs = synth.sector_batch(seed, count)
+    gv = GeneratingVectors(seed)
+    n0, n1 = LADDER[0], LADDER[2]
+    params = [qmc.Params("sector", t.d, sector=t) for t in tabs]
+
+    def pilot(n):
+        plans = [qmc.Plan(t.d, n, gv(n, t.d), synth.shifts(seed, m, t.d, stream=16 + s, sub=3), "baker")
+                 for s, t in enumerate(tabs)]
+        res = qmc.integrate_batch(plans, params, tile_points=tile_points)
+        for p in plans:
+            p.close()
+        return np.array([r.err_re for r in res]), np.array([r.mean_re for r in res])
+
+    s0, q0 = pilot(n0)
+    s1, _ = pilot(n1)
+    rates = estimate_rates(s0, s1, n0, n1)
+    cost = np.array([100.0 + 4.0 * (t.n_u + t.n_f) for t in tabs])
+
+    def run(ns, label):
+        plans = [qmc.Plan(t.d, int(n), gv(int(n), t.d), synth.sector_batch_shifts(seed, s, m, t.d), "baker")
+                 for s, (t, n) in enumerate(zip(tabs, ns))]
+        res, t = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True, tile_points=tile_points), reps)
+        for p in plans:
+            p.close()
+        total = float(np.sqrt(np.sum([r.err_re ** 2 for r in res])))
+        value = float(np.sum([r.mean_re for r in res]))
+        return {"rule": label, "evals": int(sum(int(n) * m for n in ns)), "seconds": t,
+                "modelled_cost": float(np.sum(cost * np.asarray(ns, dtype=np.float64))),
+                "total": value, "total_err": total, "total_rel_err": total / abs(value),
+                "sectors_at_cap": int(sum(1 for n in ns if n == LADDER[-1]))}
+
+    per_sector = [allocate_n(abs(e) / abs(q), n0, goal) for e, q in zip(s0, q0)]
+    r1 = run(per_sector, "per-sector relative goal (rate 2)")
+    sizes, _, pred = allocate_total(s1, cost, n1, r1["total_err"], rates)
+    r2 = run(sizes, "total-error allocation (estimated rates)")
+    r2["predicted_total_err"] = pred
+    return {"sectors": count, "m": m, "pilot_n": [n0, n1], "rate_median": float(np.median(rates)),
+            "rate_quartiles": [float(np.percentile(rates, 25)), float(np.percentile(rates, 75))],
+            "rules": [r1, r2]}
 
 
 def product_peak_batch(count: int = 512, n: int = 131071, m: int = 16, d: int = 4,
@@ -339,7 +449,7 @@ def fig3(dims=(6, 9, 10), alphas=(3, 6), kmin: int = 10, kmax: int = 26, m: int 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
-                                     "cv_estimate", "fig3"])
+                                     "cv_estimate", "fig3", "allocation_compare"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--shift-tile", type=int, default=0)
@@ -358,6 +468,8 @@ def main(argv=None):
                                  shift_tile=args.shift_tile, blocks_per_cu=args.blocks_per_cu)
     elif args.what == "cv_estimate":
         out = cv_estimate()
+    elif args.what == "allocation_compare":
+        out = allocation_compare(count=args.count or 2000)
     elif args.what == "fig3":
         out = fig3(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "time_to_error":
