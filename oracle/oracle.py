@@ -67,6 +67,7 @@ class _Params(C.Structure):
         ("eps_u", C.c_double),
         ("eps_f", C.c_double),
         ("eps_order", C.c_int32),
+        ("deform_lambda", C.c_double),
         ("point_mode", C.c_int32),
     ]
 
@@ -115,7 +116,7 @@ class Params:
     """Integrand description; keeps the numpy arrays alive for the call."""
 
     def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
-                 sector=None, cv=None, point_mode: int = 0, eps=None):
+                 sector=None, cv=None, point_mode: int = 0, eps=None, deform: float = 0.0):
         """eps (sector): (eps_u, eps_f, k) selects the coefficient of e^k of the
         integrand with exponents pow_u + eps_u e, pow_f + eps_f e."""
         self.keep = []
@@ -125,6 +126,7 @@ class Params:
         p.point_mode = int(point_mode)
         if eps is not None:
             p.eps_u, p.eps_f, p.eps_order = float(eps[0]), float(eps[1]), int(eps[2])
+        p.deform_lambda = float(deform)  # contour deformation of a sector (0 = none)
 
         def arr(x, dt):
             v = np.ascontiguousarray(np.asarray(x, dtype=dt))

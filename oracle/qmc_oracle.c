@@ -93,6 +93,10 @@ typedef struct {
        L = eps_u ln U + eps_f ln(F - i delta) (principal branch) */
     double eps_u, eps_f;
     int32_t eps_order;
+    /* contour deformation of the sector variables (lambda != 0):
+       z_k = x_k - i lambda x_k (1 - x_k) dF/dx_k(x), the integrand becomes
+       f(z) det(dz/dx) and is complex */
+    double deform_lambda;
     /* coordinate rounding: 0 -> idx / n (IEEE division), 1 -> idx * (1/n) */
     int32_t point_mode;
 } or_params;
@@ -182,6 +186,74 @@ static double or_ipow(double v, int e)
 }
 
 /* sparse polynomial sum_t coef[t] prod_i z_i^exp[t,i] */
+/* sum_t coef[t] prod_i z_i^(ex[t,i] - dk[i]) * falling factor of the
+   derivative: d/dz_k lowers ex[t,k] by one and multiplies by it; dk counts
+   the derivatives per variable (0, 1 or 2 in total) */
+static double or_poly_deriv(uint32_t d, uint32_t nt, const double *coef, const uint8_t *ex, const double *z,
+                            const int *dk)
+{
+    double s = 0.0;
+    for (uint32_t t = 0; t < nt; ++t) {
+        double mono = coef[t];
+        for (uint32_t i = 0; i < d && mono != 0.0; ++i) {
+            int e = ex[t * d + i];
+            for (int r = 0; r < dk[i]; ++r) {
+                mono *= (double)e;
+                e -= 1;
+            }
+            if (e < 0)
+                mono = 0.0;
+            else
+                mono *= or_ipow(z[i], e);
+        }
+        s += mono;
+    }
+    return s;
+}
+
+static double complex or_cpoly(uint32_t d, uint32_t nt, const double *coef, const uint8_t *ex,
+                               const double complex *z)
+{
+    double complex s = 0.0;
+    for (uint32_t t = 0; t < nt; ++t) {
+        double complex mono = coef[t];
+        for (uint32_t i = 0; i < d; ++i)
+            for (int r = 0; r < ex[t * d + i]; ++r)
+                mono *= z[i];
+        s += mono;
+    }
+    return s;
+}
+
+/* determinant by LU with partial pivoting (a is overwritten, n x n row-major) */
+static double complex or_cdet(int n, double complex *a)
+{
+    double complex det = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (cabs(a[r * n + c]) > cabs(a[piv * n + c]))
+                piv = r;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                double complex t = a[c * n + k];
+                a[c * n + k] = a[piv * n + k];
+                a[piv * n + k] = t;
+            }
+            det = -det;
+        }
+        det *= a[c * n + c];
+        if (a[c * n + c] == 0.0)
+            return 0.0;
+        for (int r = c + 1; r < n; ++r) {
+            double complex f = a[r * n + c] / a[c * n + c];
+            for (int k = c; k < n; ++k)
+                a[r * n + k] -= f * a[c * n + k];
+        }
+    }
+    return det;
+}
+
 double or_poly(uint32_t d, uint32_t nt, const double *coef, const uint8_t *ex, const double *z)
 {
     double s = 0.0;
@@ -319,6 +391,47 @@ void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, d
         break;
     }
     case OR_F_SECTOR: {
+        if (p->deform_lambda != 0.0) {
+            /* contour deformation: z = x - i lambda x (1 - x) grad F(x) */
+            const double lam = p->deform_lambda;
+            double complex zc[64], J[16 * 16];
+            double grad[64];
+            int dk[64];
+            for (uint32_t i = 0; i < d; ++i)
+                dk[i] = 0;
+            for (uint32_t k = 0; k < d; ++k) {
+                dk[k] = 1;
+                grad[k] = or_poly_deriv(d, p->n_f, p->coef_f, p->exp_f, z, dk);
+                dk[k] = 0;
+                zc[k] = z[k] - I * lam * z[k] * (1.0 - z[k]) * grad[k];
+            }
+            for (uint32_t k = 0; k < d; ++k)
+                for (uint32_t l = 0; l < d; ++l) {
+                    dk[k] += 1;
+                    dk[l] += 1;
+                    const double h = or_poly_deriv(d, p->n_f, p->coef_f, p->exp_f, z, dk);
+                    dk[k] = 0;
+                    dk[l] = 0;
+                    double complex e = -I * lam * z[k] * (1.0 - z[k]) * h;
+                    if (k == l)
+                        e += 1.0 - I * lam * (1.0 - 2.0 * z[k]) * grad[k];
+                    J[k * d + l] = e;
+                }
+            const double complex detj = or_cdet((int)d, J);
+            double complex monoc = 1.0;
+            for (uint32_t i = 0; i < d; ++i)
+                for (int r = 0; r < p->nu[i]; ++r)
+                    monoc *= zc[i];
+            const double complex Uc = or_cpoly(d, p->n_u, p->coef_u, p->exp_u, zc);
+            const double complex Fc = or_cpoly(d, p->n_f, p->coef_f, p->exp_f, zc) - I * p->delta_im;
+            double complex v = monoc * cpow(Uc, p->pow_u) * cpow(Fc, p->pow_f) * detj;
+            const double complex L = p->eps_u * clog(Uc) + p->eps_f * clog(Fc);
+            for (int32_t k = 1; k <= p->eps_order; ++k)
+                v = v * L / (double)k;
+            vr = creal(v);
+            vi = cimag(v);
+            break;
+        }
         double mono = 1.0;
         for (uint32_t i = 0; i < d; ++i)
             mono *= or_ipow(z[i], p->nu[i]);

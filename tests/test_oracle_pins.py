@@ -605,3 +605,71 @@ def test_sector_eps_orders_closed_form():
             else:
                 # per shift the order-k sums are the order-0 sums times L0^k / k!
                 assert np.allclose(q, q0 * L0 ** k / math.factorial(k), rtol=1e-13, atol=0)
+
+
+# ------------------------------------------------- contour deformation
+def test_deformation_euclidean_unchanged():
+    """Sec. 3 (contour deformation): with F > 0 on the cube the deformed
+    integrand is holomorphic on the swept region and the deformation fixes the
+    faces of the cube, so by Cauchy's theorem the integral is unchanged and its
+    imaginary part vanishes.  F has cross terms and squares, so a wrong
+    Hessian entry or a wrong sign in det(dz/dx) breaks the equality."""
+    d = 3
+    s = _sector(d, [1.0, 1.0, 1.0], [[0, 0, 0], [1, 0, 0], [0, 1, 1]],
+                [0.3, 1.0, 2.0, 1.0], [[0, 0, 0], [1, 1, 0], [0, 1, 2], [2, 0, 1]], [1, 0, 0],
+                pow_u=-2.0, pow_f=-1.3)
+    n = 65521
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(13, 8, d)
+    plain = O.estimate(n, g, sh, O.Params("sector", d, sector=s), "korobov", 3)
+    m0, e0, _ = plain.mean_error()
+    for lam in (0.2, 0.6):
+        est = O.estimate(n, g, sh, O.Params("sector", d, sector=s, deform=lam), "korobov", 3)
+        m1, er, ei = est.mean_error()
+        assert abs(m1.real - m0.real) < 6 * (er + e0) + 1e-9
+        assert abs(m1.imag) < 6 * ei + 1e-9
+    # point by point the deformation changes the value
+    x = [0.3, 0.6, 0.2]
+    v0 = O.integrand(O.Params("sector", d, sector=s), x)
+    v1 = O.integrand(O.Params("sector", d, sector=s, deform=0.6), x)
+    assert abs(v1.imag) > 1e-3 * abs(v0)
+
+
+def test_deformation_1d_threshold_closed_form():
+    """F = x - a vanishes inside the cube; the deformed contour realises the
+    -i0 prescription, int_0^1 (x - a - i0)^b dx =
+    [(1 - a)^(b+1) - a^(b+1) e^(-i pi (b+1))] / (b + 1), also for b < -1
+    (analytic continuation), with delta = 0."""
+    a = 0.37
+    for b in (-0.6, -1.5):
+        s = _sector(1, [1.0], [[0]], [-a, 1.0], [[0], [1]], [0], pow_u=-2.0, pow_f=b,
+                    delta=0.0, cplx=True)
+        want = ((1 - a) ** (b + 1) - a ** (b + 1) * np.exp(-1j * np.pi * (b + 1))) / (b + 1)
+        n = 65521
+        g = np.array([1], np.uint32)
+        est = O.estimate(n, g, synth.shifts(5, 8, 1), O.Params("sector", 1, sector=s, deform=0.5),
+                         "korobov", 3)
+        mean, er, ei = est.mean_error()
+        assert abs(mean - want) < 1e-9 * abs(want) + 6 * (er + ei)
+        assert abs(mean - want) < 1e-7 * abs(want)
+
+
+def test_deformation_2d_xmy_delta_zero():
+    """eq. (7) at delta -> 0, F = x1 - x2 vanishing on the diagonal:
+    I = [1 + e^(-i pi eps)] / (eps (eps - 1)).  F of the deformed point still
+    vanishes at the corners (0,0) and (1,1); the Korobov weight-3 transform
+    damps that singularity enough for the rule to converge (the baker
+    transform does not)."""
+    d, eps = 2, 0.3
+    s = _sector(d, [1.0], [[0, 0]], [1.0, -1.0], [[1, 0], [0, 1]], [0, 0], pow_u=-2.0,
+                pow_f=-2.0 + eps, delta=0.0, cplx=True)
+    want = (1 + np.exp(-1j * np.pi * eps)) / (eps * (eps - 1))
+    n = 262139
+    a, _, _ = O.korobov_search(n, d, synth.korobov_candidates(8, n, 16))
+    g = O.korobov_vector(n, d, a)
+    est = O.estimate(n, g, synth.shifts(8, 16, d), O.Params("sector", d, sector=s, deform=1.0),
+                     "korobov", 3)
+    mean, er, ei = est.mean_error()
+    assert abs(mean.real - want.real) < 6 * er
+    assert abs(mean.imag - want.imag) < 6 * ei
+    assert abs(mean - want) < 1e-3 * abs(want)
