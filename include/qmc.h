@@ -113,6 +113,16 @@ typedef struct {
        n_orders <= 4; 0 or 1 is the plain integrand. */
     uint32_t n_orders;
     double eps_u, eps_f;
+    /* Contour deformation (Sec. 3), deform_lambda != 0: the integrand is
+       evaluated at z_k = x_k - i lambda x_k (1 - x_k) dF/dx_k (x) (x the
+       transformed point) and multiplied by det(dz/dx); the faces of the cube
+       stay fixed, and F(z) gains a negative imaginary part to first order, so
+       a sector whose F changes sign inside the cube is integrated with the
+       -i0 prescription (delta_im may be 0).  The result is complex whatever
+       is_complex says; delta_im applies when is_complex != 0.  Needs the
+       specialised kernel (jit mode 1 or 2); EUNSUPPORTED in batches and
+       control variates, and for |pow_u| or |pow_f| > 1e5.  0 = none. */
+    double deform_lambda;
 } qmc_sector_params;
 
 /* Result of eqs. (2)-(3).  err = sqrt(sigma^2); complex integrands carry

@@ -95,7 +95,7 @@ typedef struct {
     int32_t eps_order;
     /* contour deformation of the sector variables (lambda != 0):
        z_k = x_k - i lambda x_k (1 - x_k) dF/dx_k(x), the integrand becomes
-       f(z) det(dz/dx) and is complex */
+       f(z) det(dz/dx) and is complex; delta_im applies when is_complex */
     double deform_lambda;
     /* coordinate rounding: 0 -> idx / n (IEEE division), 1 -> idx * (1/n) */
     int32_t point_mode;
@@ -423,7 +423,8 @@ void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, d
                 for (int r = 0; r < p->nu[i]; ++r)
                     monoc *= zc[i];
             const double complex Uc = or_cpoly(d, p->n_u, p->coef_u, p->exp_u, zc);
-            const double complex Fc = or_cpoly(d, p->n_f, p->coef_f, p->exp_f, zc) - I * p->delta_im;
+            const double delta = p->is_complex ? p->delta_im : 0.0;
+            const double complex Fc = or_cpoly(d, p->n_f, p->coef_f, p->exp_f, zc) - I * delta;
             double complex v = monoc * cpow(Uc, p->pow_u) * cpow(Fc, p->pow_f) * detj;
             const double complex L = p->eps_u * clog(Uc) + p->eps_f * clog(Fc);
             for (int32_t k = 1; k <= p->eps_order; ++k)

@@ -182,12 +182,25 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
             if (p->n_orders > kSectorMaxOrders)
                 return fail(QMC_EUNSUPPORTED, "n_orders = %u > %u", p->n_orders, kSectorMaxOrders);
             if (!std::isfinite(p->eps_u) || !std::isfinite(p->eps_f)) return fail(QMC_EINVAL, "eps not finite");
-            pk.blob[2] = bits(flags | kSectorOrders);
+            flags |= kSectorOrders;
+            pk.blob[2] = bits(flags);
             pk.blob.push_back(p->eps_u);
             pk.blob.push_back(p->eps_f);
             pk.blob.push_back(bits(p->n_orders));
             pk.orders = p->n_orders;
             pk.np *= p->n_orders;
+        }
+        if (p->deform_lambda != 0.0) {
+            if (!std::isfinite(p->deform_lambda)) return fail(QMC_EINVAL, "deform_lambda not finite");
+            if (std::fabs(p->pow_f) > 1.0e5 || std::fabs(p->pow_u) > 1.0e5)
+                return fail(QMC_EUNSUPPORTED, "|pow_u| or |pow_f| > 1e5 for a deformed sector");
+            flags |= kSectorComplex | kSectorDeform;
+            pk.blob[2] = bits(flags);
+            pk.blob.push_back(p->deform_lambda);
+            pk.deform = true;
+            pk.cplx = true;
+            pk.key_family = kFamSectorComplex;
+            pk.np = 2 * (p->n_orders >= 2 ? p->n_orders : 1u);
         }
         break;
     }
@@ -367,13 +380,16 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     hipFunction_t jfn = nullptr;
     const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
     if (sector && p->jit_mode != 0) {
-        T = want_T ? want_T : 2u;  // measured best for real and complex sectors
+        // two points per thread measured best for real and complex sectors;
+        // a deformed point carries the Jacobian's triangle, so one
+        T = want_T ? want_T : (pk.deform ? 1u : 2u);
         std::string err;
         jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.cplx, p->device, err);
-        if (!jfn && (p->jit_mode == 2 || pk.orders >= 2))
+        if (!jfn && (p->jit_mode == 2 || pk.orders >= 2 || pk.deform))
             return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
     }
     if (!jfn && pk.orders >= 2) return fail(QMC_EUNSUPPORTED, "expansion orders need the specialised kernel (jit mode 1 or 2)");
+    if (!jfn && pk.deform) return fail(QMC_EUNSUPPORTED, "contour deformation needs the specialised kernel (jit mode 1 or 2)");
     if (!jfn) {
         fn = find_kernel(pk.key_family, p->tr, p->d, want_T ? want_T : default_tile(pk.key_family), T);
         if (!fn)

@@ -546,6 +546,7 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
     hipError_t e;
     std::string err;
     if (pk.orders >= 2) return fail(QMC_EUNSUPPORTED, "control variates take the plain integrand (n_orders < 2)");
+    if (pk.deform) return fail(QMC_EUNSUPPORTED, "control variates take undeformed sectors (deform_lambda = 0)");
     hipFunction_t sample = jit_sample_kernel(pk.blob, d, p->tr, pk.cplx, p->device, err);
     if (!sample) return fail(QMC_EUNSUPPORTED, "training sampler: %s", err.c_str());
     if ((st = plan_upload_params(p, pk))) return st;
@@ -801,6 +802,7 @@ qmc_status qmc_integrate_cv(qmc_plan_t p, qmc_family family, const void *params,
     qmc_status st = pack_params((int)family, p->d, params, pk);
     if (st) return st;
     if (pk.orders >= 2) return fail(QMC_EUNSUPPORTED, "control variates take the plain integrand (n_orders < 2)");
+    if (pk.deform) return fail(QMC_EUNSUPPORTED, "control variates take undeformed sectors (deform_lambda = 0)");
     const uint32_t nm = pk.np, d = p->d;  // one model per component
     const size_t wsize = (size_t)R * d * K;
     for (uint32_t t = 0; t < nm * R; ++t)

@@ -452,6 +452,103 @@ __device__ __forceinline__ void sector_orders(double mono, double U, double F, u
     }
 }
 
+// ------------------------------------------------ contour deformation
+// Sec. 3: a sector whose F changes sign inside the cube is integrated along
+// z_k = x_k - i lam x_k (1 - x_k) dF/dx_k (x), which keeps the faces of the
+// cube fixed and gives F(z) a negative imaginary part to first order (the
+// -i0 prescription).  The integrand gains det(dz/dx).
+enum : uint32_t { kSectorDeform = 8u };
+
+// det(dz/dx) = det(I + i B), B_kl = -lam [s_k H_kl + delta_kl (1 - 2 x_k) g_k],
+// s_k = x_k (1 - x_k), g = grad F, H = Hessian of F.  With r_k = sqrt(s_k),
+// B is similar to the symmetric Bs_kl = -lam [r_k r_l H_kl + delta_kl (1 - 2 x_k) g_k]
+// (a diagonal similarity, so every leading block keeps its determinant;
+// r_k = 0 follows by continuity; each term of det holds r_k r_k, so a
+// rounded s_k slightly below 0 may use r_k = sqrt(|s_k|)).  I + i Bs is complex symmetric with
+// Hermitian part I: each leading block is nonsingular, so the LDL^T
+// factorisation without pivoting exists and det = prod of the pivots.
+// a holds the lower triangle of I + i Bs, row-major packed: (i, j), j <= i, at
+// i (i + 1) / 2 + j; it is overwritten.
+template <int D>
+__device__ __forceinline__ void csym_det(double (&ar)[D * (D + 1) / 2], double (&ai)[D * (D + 1) / 2],
+                                         double &dr, double &di) {
+    double pr = 1.0, pi = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int kk = k * (k + 1) / 2 + k;
+        const double a = ar[kk], b = ai[kk];
+        {
+            const double nr = fma_(pr, a, -pi * b), ni = fma_(pr, b, pi * a);
+            pr = nr;
+            pi = ni;
+        }
+        const double h = recip(fma_(a, a, b * b));
+        const double vr = a * h, vi = -b * h;  // 1 / pivot
+#pragma unroll
+        for (int i = k + 1; i < D; ++i) {
+            const int ik = i * (i + 1) / 2 + k;
+            const double lr = fma_(ar[ik], vr, -ai[ik] * vi), li = fma_(ar[ik], vi, ai[ik] * vr);
+#pragma unroll
+            for (int j = k + 1; j <= i; ++j) {
+                const int ij = i * (i + 1) / 2 + j, jk = j * (j + 1) / 2 + k;
+                ar[ij] = ar[ij] - fma_(lr, ar[jk], -li * ai[jk]);
+                ai[ij] = ai[ij] - fma_(lr, ai[jk], li * ar[jk]);
+            }
+        }
+    }
+    dr = pr;
+    di = pi;
+}
+
+// Value (and expansion orders) of the deformed sector integrand:
+// mono * det * U^pow_u * (F - i delta)^pow_f at complex mono, det, U, F, with
+// the principal branch of each power; order k multiplies by L^k / k!,
+// L = eps_u ln U + eps_f ln(F - i delta).  Parts (2k, 2k+1) hold order k.
+template <int NO>
+__device__ __forceinline__ void sector_deformed(double mr, double mi, double dr, double di, double ur, double ui,
+                                                double fr, double fi, uint32_t flags, double pow_u, double pow_f,
+                                                double delta, double eps_u, double eps_f, double (&v)[2 * NO]) {
+    fi = fi - delta;
+    // pre = mono * det
+    double pr = fma_(mr, dr, -mi * di), pim = fma_(mr, di, mi * dr);
+    const double lmf = 0.5 * qlog(fma_(fr, fr, fi * fi)), thf = qatan2(fi, fr);  // ln(F - i delta)
+    double lmu = 0.0, thu = 0.0;
+    double lm = pow_f * lmf, th = pow_f * thf;
+    if ((flags & kSectorPowUm2) == 0 || NO >= 2) {
+        lmu = 0.5 * qlog(fma_(ur, ur, ui * ui));
+        thu = qatan2(ui, ur);
+    }
+    if (flags & kSectorPowUm2) {
+        // 1 / U^2 = conj(U)^2 / |U|^4
+        const double h = recip(fma_(ur, ur, ui * ui));
+        const double qr = ur * h, qi = -ui * h;
+        const double sr = fma_(qr, qr, -qi * qi), si = 2.0 * qr * qi;
+        const double nr = fma_(pr, sr, -pim * si), ni = fma_(pr, si, pim * sr);
+        pr = nr;
+        pim = ni;
+    } else {
+        lm = fma_(pow_u, lmu, lm);
+        th = fma_(pow_u, thu, th);
+    }
+    double s, c;
+    qsincos(th, s, c);
+    const double mag = qexp(lm);
+    double wr = mag * fma_(pr, c, -pim * s), wi = mag * fma_(pr, s, pim * c);
+    v[0] = wr;
+    v[1] = wi;
+    if constexpr (NO >= 2) {
+        const double lr = fma_(eps_u, lmu, eps_f * lmf), li = fma_(eps_u, thu, eps_f * thf);
+#pragma unroll
+        for (int k = 1; k < NO; ++k) {
+            const double nr = fma_(wr, lr, -wi * li), ni = fma_(wr, li, wi * lr);
+            wr = nr * (1.0 / k);
+            wi = ni * (1.0 / k);
+            v[2 * k] = wr;
+            v[2 * k + 1] = wi;
+        }
+    }
+}
+
 template <bool Complex>
 struct FamSector {
     static constexpr int NP = Complex ? 2 : 1;

@@ -14,6 +14,7 @@
 // compiled from the same headers (embedded into the library at build time).
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -78,6 +79,146 @@ const char *transform_type(const qmc_transform &t) {
 
 }  // namespace
 
+// Source of FamJit for a deformed contour (flag 8): straight-line code for
+// the gradient and Hessian of F at the real point (their monomials share a
+// real product trie), the deformed point z - i lam s grad F, the complex
+// monomials of U, F and z^nu at that point (a complex product trie), the
+// symmetrised Jacobian and its determinant, then sector_deformed.
+static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
+                                   size_t eps_at, size_t lam_at, const std::vector<std::vector<int>> &fu,
+                                   const std::vector<std::vector<int>> &ff, const std::vector<int> &nuf) {
+    Trie rt, ct;  // real (derivative) and complex (deformed point) monomials
+    const uint32_t nu = (uint32_t)fu.size(), nf = (uint32_t)ff.size();
+    struct Term {
+        int coef;   // index into cf
+        int mult;   // integer factor from differentiation
+        int mono;   // real trie node (-1: constant)
+    };
+    std::vector<std::vector<Term>> grad(d);
+    std::vector<std::vector<Term>> hess(d * d);  // (i, j), j <= i, at i * d + j
+    auto drop = [](std::vector<int> f, int v, int &mult) {
+        int cnt = 0;
+        for (int x : f) cnt += x == v;
+        mult *= cnt;
+        if (cnt) f.erase(std::find(f.begin(), f.end(), v));
+        return f;
+    };
+    for (uint32_t t = 0; t < nf; ++t)
+        for (uint32_t i = 0; i < d; ++i) {
+            int mi = 1;
+            const std::vector<int> gi = drop(ff[t], (int)i, mi);
+            if (!mi) continue;
+            grad[i].push_back({(int)t, mi, rt.insert(gi)});
+            for (uint32_t j = 0; j <= i; ++j) {
+                int mj = mi;
+                const std::vector<int> hij = drop(gi, (int)j, mj);
+                if (mj) hess[i * d + j].push_back({(int)t, mj, rt.insert(hij)});
+            }
+        }
+    std::vector<int> cu(nu), cfm(nf);
+    for (uint32_t t = 0; t < nu; ++t) cu[t] = ct.insert(fu[t]);
+    for (uint32_t t = 0; t < nf; ++t) cfm[t] = ct.insert(ff[t]);
+    const int cnu = ct.insert(nuf);
+
+    const uint32_t no = orders >= 2 ? orders : 1u;
+    std::ostringstream s;
+    s << "struct FamJit {\n"
+      << "    static constexpr int NP = " << 2 * no << ";\n"
+      << "    template <class Tr, int D, int T>\n"
+      << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
+         " double (&v)[T][NP]) {\n"
+      << "        double z[T][D], jac[T];\n"
+      << "        apply_transform<Tr, D, T>(x, z, jac);\n"
+      << "        constexpr uint32_t flags = " << flags << "u;\n"
+      << "        const __attribute__((address_space(4))) double *cp =\n"
+      << "            (const __attribute__((address_space(4))) double *)p;\n"
+      << "        asm volatile(\"\" : \"+s\"(cp));\n"
+      << "        const double pow_u = cp[3], pow_f = cp[4], delta = cp[5], lam = cp[" << lam_at << "];\n"
+      << "        const double eps_u = " << (orders >= 2 ? "cp[" + std::to_string(eps_at) + "]" : std::string("0.0"))
+      << ", eps_f = " << (orders >= 2 ? "cp[" + std::to_string(eps_at + 1) + "]" : std::string("0.0")) << ";\n"
+      << "        const __attribute__((address_space(4))) double *cu = cp + kSectorHeader;\n"
+      << "        const __attribute__((address_space(4))) double *cf = cu + " << 2 * nu << ";\n"
+      << "#pragma unroll\n"
+      << "        for (int k = 0; k < T; ++k) {\n";
+    // real monomials of the derivatives
+    for (size_t id = 0; id < rt.node.size(); ++id) {
+        const auto &nd = rt.node[id];
+        s << "            const double r" << id << " = ";
+        if (nd.first < 0) s << "z[k][" << nd.second << "];\n";
+        else s << "r" << nd.first << " * z[k][" << nd.second << "];\n";
+    }
+    auto sum = [&](const std::string &name, const std::vector<Term> &terms) {
+        s << "            double " << name << " = 0.0;\n";
+        for (const Term &t : terms) {
+            std::ostringstream c;
+            if (t.mult == 1) c << "cf[" << t.coef << "]";
+            else c << "(cf[" << t.coef << "] * " << t.mult << ".0)";
+            if (t.mono < 0) s << "            " << name << " = " << name << " + " << c.str() << ";\n";
+            else s << "            " << name << " = fma_(" << c.str() << ", r" << t.mono << ", " << name << ");\n";
+        }
+    };
+    for (uint32_t i = 0; i < d; ++i) sum("g" + std::to_string(i), grad[i]);
+    for (uint32_t i = 0; i < d; ++i)
+        for (uint32_t j = 0; j <= i; ++j) sum("h" + std::to_string(i) + "_" + std::to_string(j), hess[i * d + j]);
+    // the deformed point: real part z, imaginary part y
+    for (uint32_t i = 0; i < d; ++i)
+        s << "            const double s" << i << " = z[k][" << i << "] * (1.0 - z[k][" << i << "]);\n"
+          << "            const double y" << i << " = -lam * (s" << i << " * g" << i << ");\n";
+    // complex monomials at the deformed point
+    for (size_t id = 0; id < ct.node.size(); ++id) {
+        const auto &nd = ct.node[id];
+        const int v = nd.second;
+        if (nd.first < 0) {
+            s << "            const double c" << id << "r = z[k][" << v << "], c" << id << "i = y" << v << ";\n";
+        } else {
+            const int q = nd.first;
+            s << "            const double c" << id << "r = fma_(c" << q << "r, z[k][" << v << "], -(c" << q << "i * y" << v
+              << ")), c" << id << "i = fma_(c" << q << "r, y" << v << ", c" << q << "i * z[k][" << v << "]);\n";
+        }
+    }
+    auto cpoly = [&](const char *name, const char *coef, const std::vector<int> &mono) {
+        s << "            double " << name << "r = 0.0, " << name << "i = 0.0;\n";
+        for (size_t t = 0; t < mono.size(); ++t) {
+            if (mono[t] < 0) {
+                s << "            " << name << "r = " << name << "r + " << coef << "[" << t << "];\n";
+            } else {
+                s << "            " << name << "r = fma_(" << coef << "[" << t << "], c" << mono[t] << "r, " << name
+                  << "r);\n";
+                s << "            " << name << "i = fma_(" << coef << "[" << t << "], c" << mono[t] << "i, " << name
+                  << "i);\n";
+            }
+        }
+    };
+    cpoly("U", "cu", cu);
+    cpoly("F", "cf", cfm);
+    if (cnu < 0) s << "            const double mr = jac[k], mi = 0.0;\n";
+    else s << "            const double mr = jac[k] * c" << cnu << "r, mi = jac[k] * c" << cnu << "i;\n";
+    // I + i Bs, packed lower triangle
+    const uint32_t nt = d * (d + 1) / 2;
+    s << "            double ar[" << nt << "], ai[" << nt << "];\n";
+    // a transformed coordinate may round a few ulp outside [0, 1], making s
+    // slightly negative: every term of det pairs q_k with itself (q_k^2
+    // stands for s_k), so |s_k| changes det by O(|s_k|) only
+    for (uint32_t i = 0; i < d; ++i)
+        s << "            const double q" << i << " = __builtin_sqrt(__builtin_fabs(s" << i << "));\n";
+    for (uint32_t i = 0; i < d; ++i)
+        for (uint32_t j = 0; j <= i; ++j) {
+            const uint32_t ij = i * (i + 1) / 2 + j;
+            s << "            ar[" << ij << "] = " << (i == j ? "1.0" : "0.0") << ";\n";
+            s << "            ai[" << ij << "] = -lam * ";
+            if (i == j)
+                s << "fma_(s" << i << ", h" << i << "_" << i << ", (1.0 - 2.0 * z[k][" << i << "]) * g" << i << ");\n";
+            else
+                s << "((q" << i << " * q" << j << ") * h" << i << "_" << j << ");\n";
+        }
+    s << "            double dr, di;\n"
+      << "            csym_det<D>(ar, ai, dr, di);\n"
+      << "            sector_deformed<" << no
+      << ">(mr, mi, dr, di, Ur, Ui, Fr, Fi, flags, pow_u, pow_f, delta, eps_u, eps_f, v[k]);\n"
+      << "        }\n    }\n};\n";
+    return s.str();
+}
+
 // Source of the specialised functor FamJit; `structure` receives a
 // canonical description of what the code depends on.
 static std::string functor_source(const std::vector<double> &blob, uint32_t d, bool cplx, std::string &structure) {
@@ -110,6 +251,14 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
     const int mnu = trie.insert(nuf);
     st << "|" << nuc;
     structure = st.str();
+    if (flags & kSectorDeform) {
+        // the deformation parameter follows the orders words (if any)
+        const size_t lam_at = eps_at + ((flags & kSectorOrders) ? 3u : 0u);
+        std::vector<std::vector<int>> fu(nu), ff(nf);
+        for (uint32_t t = 0; t < nu; ++t) fu[t] = factors_of(word(blob, kSectorHeader + nu + t));
+        for (uint32_t t = 0; t < nf; ++t) ff[t] = factors_of(word(blob, kSectorHeader + 2 * nu + nf + t));
+        return deformed_source(d, flags, orders, eps_at, lam_at, fu, ff, nuf);
+    }
 
     std::ostringstream s;
     const uint32_t np = (cplx ? 2u : 1u) * (orders >= 2 ? orders : 1u);

@@ -65,6 +65,7 @@ struct Packed {
     int key_family = 0;
     bool cplx = false;     // complex sector
     uint32_t orders = 0;   // expansion orders (>= 2: qmc_integrate_orders)
+    bool deform = false;   // contour deformation (complex result, specialised kernel only)
 };
 
 qmc_status fail(qmc_status s, const char *fmt, ...);

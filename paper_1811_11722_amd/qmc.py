@@ -56,7 +56,7 @@ class qmc_sector_params(C.Structure):
                 ("exp_u", C.c_void_p), ("coef_f", C.c_void_p), ("exp_f", C.c_void_p),
                 ("nu", C.c_void_p), ("pow_u", C.c_double), ("pow_f", C.c_double),
                 ("delta_im", C.c_double), ("is_complex", C.c_int32), ("n_orders", C.c_uint32),
-                ("eps_u", C.c_double), ("eps_f", C.c_double)]
+                ("eps_u", C.c_double), ("eps_f", C.c_double), ("deform_lambda", C.c_double)]
 
 
 class qmc_result(C.Structure):
@@ -161,8 +161,10 @@ class Params:
     """Family parameter struct plus the arrays it points into."""
 
     def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
-                 sector=None, orders=None):
-        """orders (sector only): (n_orders, eps_u, eps_f) for qmc_integrate_orders."""
+                 sector=None, orders=None, deform: float = 0.0):
+        """orders (sector only): (n_orders, eps_u, eps_f) for qmc_integrate_orders.
+        deform (sector only): contour-deformation parameter lambda (0 = none);
+        a deformed sector's result is complex."""
         self.family = FAMILY[family]
         self.n_orders = 0
         self.keep = []
@@ -188,7 +190,8 @@ class Params:
                 _p(keep(s.coef_f, np.float64)), _p(keep(s.exp_f, np.uint8)),
                 _p(keep(s.nu, np.uint8)), float(s.pow_u), float(s.pow_f), float(s.delta_im),
                 int(bool(s.is_complex)), int(orders[0]) if orders else 0,
-                float(orders[1]) if orders else 0.0, float(orders[2]) if orders else 0.0)
+                float(orders[1]) if orders else 0.0, float(orders[2]) if orders else 0.0,
+                float(deform))
             self.n_orders = int(orders[0]) if orders else 0
         else:
             self.struct = qmc_genz_params(_p(keep(a, np.float64)), _p(keep(u, np.float64)))
@@ -199,7 +202,8 @@ class Params:
 
     @property
     def is_complex(self) -> bool:
-        return self.family == QMC_F_SECTOR and bool(self.struct.is_complex)
+        return self.family == QMC_F_SECTOR and (bool(self.struct.is_complex)
+                                                or self.struct.deform_lambda != 0.0)
 
 
 class Plan:

@@ -673,3 +673,40 @@ def test_deformation_2d_xmy_delta_zero():
     assert abs(mean.real - want.real) < 6 * er
     assert abs(mean.imag - want.imag) < 6 * ei
     assert abs(mean - want) < 1e-3 * abs(want)
+
+
+def _circle_closed(p, R):
+    """int over the unit square of ((x-1/2)^2 + (y-1/2)^2 - R^2 - i0)^p, R < 1/2:
+    the inscribed disk in polar coordinates, pi/(p+1) [(1/4 - R^2)^(p+1) -
+    R^(2p+2) e^(-i pi (p+1))], plus the four corners (real, one quadrature in
+    the angle)."""
+    inner = np.pi / (p + 1) * ((0.25 - R * R) ** (p + 1) - R ** (2 * (p + 1)) * np.exp(-1j * np.pi * (p + 1)))
+    f = lambda th: ((0.25 / np.cos(th) ** 2 - R * R) ** (p + 1) - (0.25 - R * R) ** (p + 1)) / (2 * (p + 1))
+    outer, _ = integrate.quad(f, 0, np.pi / 4, epsabs=1e-14, epsrel=1e-13)
+    return inner + 8 * outer
+
+
+def circle_sector(R, p):
+    """U = 1, F = (x1 - 1/2)^2 + (x2 - 1/2)^2 - R^2 (zero set: a circle inside the
+    square, so the deformed integrand is smooth and periodisable)."""
+    return _sector(2, [1.0], [[0, 0]], [0.5 - R * R, -1.0, 1.0, -1.0, 1.0],
+                   [[0, 0], [1, 0], [2, 0], [0, 1], [0, 2]], [0, 0], pow_u=-2.0, pow_f=p,
+                   delta=0.0, cplx=True)
+
+
+def test_deformation_2d_circle_threshold():
+    """F vanishes on a circle inside the square; the deformed integrand is
+    smooth, so the Korobov rule reaches the -i0 value to rounding, also for
+    p = -1.5 (analytic continuation).  grad F and the diagonal Hessian enter
+    at every point."""
+    R = 0.3
+    n = 65521
+    a, _, _ = O.korobov_search(n, 2, synth.korobov_candidates(8, n, 16))
+    g = O.korobov_vector(n, 2, a)
+    for p in (-0.7, -1.5):
+        want = _circle_closed(p, R)
+        for lam in (0.5, 1.0):
+            est = O.estimate(n, g, synth.shifts(3, 8, 2), O.Params("sector", 2, sector=circle_sector(R, p),
+                                                                   deform=lam), "korobov", 3)
+            mean, er, ei = est.mean_error()
+            assert abs(mean - want) < 1e-13 * abs(want), (p, lam, mean, want)
