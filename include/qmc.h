@@ -329,6 +329,27 @@ qmc_status qmc_integrate_cv(qmc_plan_t plan, qmc_family family, const void *para
 qmc_status qmc_integrate_orders(qmc_plan_t plan, qmc_family family, const void *params, qmc_result *out,
                                 double *per_shift);
 
+/* Sign check of a contour deformation (Sec. 3): the fraction of the plan's
+   lattice points (all m shifts, transformed as the plan says, unweighted) at
+   which the deformed F(z) - i delta has a positive imaginary part, i.e. the
+   contour lies on the wrong side of the -i0 prescription there.  params is
+   a sector with deform_lambda != 0 (EINVAL otherwise); orders are ignored.
+   fraction: host double; per_shift (nullable): m doubles, the fraction per
+   shift.  A valid deformation gives 0.  Needs the specialised kernel. */
+qmc_status qmc_deform_check(qmc_plan_t plan, const qmc_sector_params *params, double *fraction,
+                            double *per_shift);
+
+/* Choice of the deformation parameter on a (pilot) plan: for lambda =
+   lam_max * shrink^i, i = 0 .. count-1, the sign check above runs; every
+   lambda that passes it is integrated, and the one with the smallest
+   estimated error sqrt(err_re^2 + err_im^2) is returned in *lam_out with its
+   result in *out (all host memory).  By Cauchy's theorem every valid lambda
+   gives the same integral, so the error is the criterion.  shrink in (0, 1),
+   count 1..64, lam_max > 0 (EINVAL otherwise); n_orders >= 2 is EINVAL
+   (select on the plain integrand); EUNSUPPORTED when no lambda passes. */
+qmc_status qmc_deform_select(qmc_plan_t plan, const qmc_sector_params *params, double lam_max, double shrink,
+                             uint32_t count, double *lam_out, qmc_result *out);
+
 /* The library's device FP64 math on count host inputs, for checking the
    functions the sector integrand uses against a host reference:
    fn = 0 logarithm (x > 0), 1 exponential: x and y hold count values;

@@ -68,6 +68,7 @@ class _Params(C.Structure):
         ("eps_f", C.c_double),
         ("eps_order", C.c_int32),
         ("deform_lambda", C.c_double),
+        ("deform_check", C.c_int32),
         ("point_mode", C.c_int32),
     ]
 
@@ -116,7 +117,8 @@ class Params:
     """Integrand description; keeps the numpy arrays alive for the call."""
 
     def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
-                 sector=None, cv=None, point_mode: int = 0, eps=None, deform: float = 0.0):
+                 sector=None, cv=None, point_mode: int = 0, eps=None, deform: float = 0.0,
+                 deform_check: bool = False):
         """eps (sector): (eps_u, eps_f, k) selects the coefficient of e^k of the
         integrand with exponents pow_u + eps_u e, pow_f + eps_f e."""
         self.keep = []
@@ -127,6 +129,7 @@ class Params:
         if eps is not None:
             p.eps_u, p.eps_f, p.eps_order = float(eps[0]), float(eps[1]), int(eps[2])
         p.deform_lambda = float(deform)  # contour deformation of a sector (0 = none)
+        p.deform_check = int(bool(deform_check))  # 1 where Im(F(z) - i delta) > 0, unweighted
 
         def arr(x, dt):
             v = np.ascontiguousarray(np.asarray(x, dtype=dt))

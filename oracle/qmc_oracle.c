@@ -97,6 +97,10 @@ typedef struct {
        z_k = x_k - i lambda x_k (1 - x_k) dF/dx_k(x), the integrand becomes
        f(z) det(dz/dx) and is complex; delta_im applies when is_complex */
     double deform_lambda;
+    /* with deform_check != 0 a deformed sector returns 1 where the deformed
+       F - i delta has a positive imaginary part (the contour crosses to the
+       wrong side of the -i0 prescription) and 0 elsewhere, unweighted */
+    int32_t deform_check;
     /* coordinate rounding: 0 -> idx / n (IEEE division), 1 -> idx * (1/n) */
     int32_t point_mode;
 } or_params;
@@ -425,6 +429,11 @@ void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, d
             const double complex Uc = or_cpoly(d, p->n_u, p->coef_u, p->exp_u, zc);
             const double delta = p->is_complex ? p->delta_im : 0.0;
             const double complex Fc = or_cpoly(d, p->n_f, p->coef_f, p->exp_f, zc) - I * delta;
+            if (p->deform_check) {
+                vr = cimag(Fc) > 0.0 ? 1.0 : 0.0;
+                vi = 0.0;
+                break;
+            }
             double complex v = monoc * cpow(Uc, p->pow_u) * cpow(Fc, p->pow_f) * detj;
             const double complex L = p->eps_u * clog(Uc) + p->eps_f * clog(Fc);
             for (int32_t k = 1; k <= p->eps_order; ++k)
@@ -478,6 +487,8 @@ void or_fhat(const or_params *p, uint32_t d, int32_t tkind, int32_t alpha, const
     }
     double vr, vi;
     or_integrand(p, d, z, &vr, &vi);
+    if (p->family == OR_F_SECTOR && p->deform_lambda != 0.0 && p->deform_check)
+        wprod = 1.0; /* the sign check counts points */
     *re = vr * wprod;
     *im = vi * wprod;
 }

@@ -628,6 +628,66 @@ qmc_status qmc_integrate_orders(qmc_plan_t p, qmc_family family, const void *par
     return st;
 }
 
+qmc_status qmc_deform_check(qmc_plan_t p, const qmc_sector_params *params, double *fraction, double *per_shift) {
+    if (!p) return fail(QMC_EINVAL, "plan is NULL");
+    if (!fraction || !params) return fail(QMC_EINVAL, "null argument");
+    if (params->deform_lambda == 0.0) return fail(QMC_EINVAL, "deform_lambda is 0");
+    Packed pk;
+    qmc_status st = pack_params(QMC_F_SECTOR, p->d, params, pk);
+    if (st) return st;
+    // the check functor: one real part, 1 where Im(F(z) - i delta) > 0
+    uint64_t flags;
+    std::memcpy(&flags, &pk.blob[2], sizeof flags);
+    pk.blob[2] = bits(flags | kSectorDeformCheck);
+    pk.np = 1;
+    pk.cplx = false;
+    pk.orders = 0;
+    if ((st = plan_enqueue(p, pk, p->launch.shift_tile, p->launch.blocks_per_cu))) return st;
+    qmc_result r;
+    st = plan_collect(p, 1, &r, per_shift);
+    if (st) return st;
+    // finalize multiplies every sum by the transform's constant
+    const double scale = transform_scale(p->tr, p->d);
+    *fraction = r.mean_re / scale;
+    if (per_shift)
+        for (uint32_t k = 0; k < p->m; ++k) per_shift[k] /= scale;
+    return QMC_OK;
+}
+
+qmc_status qmc_deform_select(qmc_plan_t p, const qmc_sector_params *params, double lam_max, double shrink,
+                             uint32_t count, double *lam_out, qmc_result *out) {
+    if (!p) return fail(QMC_EINVAL, "plan is NULL");
+    if (!params || !lam_out || !out) return fail(QMC_EINVAL, "null argument");
+    if (!(lam_max > 0.0) || !std::isfinite(lam_max)) return fail(QMC_EINVAL, "lam_max must be positive and finite");
+    if (!(shrink > 0.0 && shrink < 1.0)) return fail(QMC_EINVAL, "shrink must lie in (0, 1)");
+    if (count == 0 || count > 64) return fail(QMC_EINVAL, "count must be 1..64");
+    if (params->n_orders >= 2) return fail(QMC_EINVAL, "select lambda on the plain integrand (n_orders < 2)");
+    qmc_sector_params q = *params;
+    bool found = false;
+    double best_err = 0.0;
+    double lam = lam_max;
+    for (uint32_t i = 0; i < count; ++i, lam *= shrink) {
+        q.deform_lambda = lam;
+        double frac;
+        qmc_status st = qmc_deform_check(p, &q, &frac, nullptr);
+        if (st) return st;
+        if (frac > 0.0) continue;
+        qmc_result r;
+        st = qmc_integrate(p, QMC_F_SECTOR, &q, &r, nullptr);
+        if (st == QMC_ENONFINITE) continue;
+        if (st) return st;
+        const double err = std::hypot(r.err_re, r.err_im);
+        if (!found || err < best_err) {
+            found = true;
+            best_err = err;
+            *lam_out = lam;
+            *out = r;
+        }
+    }
+    if (!found) return fail(QMC_EUNSUPPORTED, "every lambda of the ladder crosses the -i0 side or is not finite");
+    return QMC_OK;
+}
+
 qmc_status qmc_math_eval(int32_t fn, uint64_t count, const double *x, double *y) {
     if (fn < 0 || fn > 3) return fail(QMC_EINVAL, "fn must be 0 (log), 1 (exp), 2 (atan2) or 3 (sincos)");
     if (count && (!x || !y)) return fail(QMC_EINVAL, "null array");

@@ -44,14 +44,23 @@ struct TrKorobov {
     static_assert(A >= 1 && A <= 6, "Korobov weight 1..6");
     static constexpr bool kJac = true;
     static constexpr double kC = cfact(2 * A + 1) / (cfact(A) * cfact(A));
-    static constexpr double coef(int j) {
-        return kC * cbinom(A, j) * cpow4(j - A) * ((j & 1) ? -1.0 : 1.0) / (2 * j + 1);
+    // the c_j as a table evaluated by the compiler: calling the recursive
+    // helpers from device code would leave them as run-time calls
+    struct Coefs {
+        double c[A + 1];
+    };
+    static constexpr Coefs make_coefs() {
+        Coefs r{};
+        for (int j = 0; j <= A; ++j)
+            r.c[j] = kC * cbinom(A, j) * cpow4(j - A) * ((j & 1) ? -1.0 : 1.0) / (2 * j + 1);
+        return r;
     }
+    static constexpr Coefs kCoef = make_coefs();
     // h(t^2) = sum_j c_j t^(2j), Horner from the top coefficient
     __device__ static double h(double t2) {
-        double r = coef(A);
+        double r = kCoef.c[A];
 #pragma unroll
-        for (int j = A - 1; j >= 0; --j) r = fma_(r, t2, coef(j));
+        for (int j = A - 1; j >= 0; --j) r = fma_(r, t2, kCoef.c[j]);
         return r;
     }
     // z and u = x (1 - x) = 1/4 - t^2
@@ -458,6 +467,9 @@ __device__ __forceinline__ void sector_orders(double mono, double U, double F, u
 // cube fixed and gives F(z) a negative imaginary part to first order (the
 // -i0 prescription).  The integrand gains det(dz/dx).
 enum : uint32_t { kSectorDeform = 8u };
+// Sign check of a deformation (with flag 8): the functor returns 1 where the
+// deformed F - i delta has a positive imaginary part, else 0, unweighted.
+enum : uint32_t { kSectorDeformCheck = 16u };
 
 // det(dz/dx) = det(I + i B), B_kl = -lam [s_k H_kl + delta_kl (1 - 2 x_k) g_k],
 // s_k = x_k (1 - x_k), g = grad F, H = Hessian of F.  With r_k = sqrt(s_k),

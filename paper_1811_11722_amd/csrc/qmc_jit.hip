@@ -121,9 +121,10 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
     const int cnu = ct.insert(nuf);
 
     const uint32_t no = orders >= 2 ? orders : 1u;
+    const bool check = (flags & kSectorDeformCheck) != 0;
     std::ostringstream s;
     s << "struct FamJit {\n"
-      << "    static constexpr int NP = " << 2 * no << ";\n"
+      << "    static constexpr int NP = " << (check ? 1u : 2 * no) << ";\n"
       << "    template <class Tr, int D, int T>\n"
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"
@@ -158,8 +159,9 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
         }
     };
     for (uint32_t i = 0; i < d; ++i) sum("g" + std::to_string(i), grad[i]);
-    for (uint32_t i = 0; i < d; ++i)
-        for (uint32_t j = 0; j <= i; ++j) sum("h" + std::to_string(i) + "_" + std::to_string(j), hess[i * d + j]);
+    if (!check)
+        for (uint32_t i = 0; i < d; ++i)
+            for (uint32_t j = 0; j <= i; ++j) sum("h" + std::to_string(i) + "_" + std::to_string(j), hess[i * d + j]);
     // the deformed point: real part z, imaginary part y
     for (uint32_t i = 0; i < d; ++i)
         s << "            const double s" << i << " = z[k][" << i << "] * (1.0 - z[k][" << i << "]);\n"
@@ -189,6 +191,12 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
             }
         }
     };
+    if (check) {
+        cpoly("F", "cf", cfm);
+        s << "            v[k][0] = Fi - delta > 0.0 ? 1.0 : 0.0;\n"
+          << "        }\n    }\n};\n";
+        return s.str();
+    }
     cpoly("U", "cu", cu);
     cpoly("F", "cf", cfm);
     if (cnu < 0) s << "            const double mr = jac[k], mi = 0.0;\n";

@@ -53,7 +53,8 @@ void load_locked() {
 std::string tune_key(const qmc_plan_s *p, const Packed &pk, bool jit) {
     std::ostringstream s;
     s << arch_name(p->device) << "|f" << pk.key_family << "|t" << p->tr.kind << "|a" << p->tr.alpha << "|d" << p->d
-      << "|m" << p->m << "|n" << (int)std::floor(std::log2((double)p->n)) << "|j" << (jit ? 1 : 0);
+      << "|m" << p->m << "|n" << (int)std::floor(std::log2((double)p->n)) << "|j" << (jit ? 1 : 0)
+      << (pk.deform ? "|def" : "") << (pk.orders >= 2 ? "|o" + std::to_string(pk.orders) : std::string());
     return s.str();
 }
 

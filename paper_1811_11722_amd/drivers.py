@@ -16,6 +16,7 @@ and times calls.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import sys
@@ -446,10 +447,66 @@ def fig3(dims=(6, 9, 10), alphas=(3, 6), kmin: int = 10, kmax: int = 26, m: int 
     return {"m": m, "rows": rows}
 
 
+def deform(d: int = 6, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 7, n: int = 16777213,
+           m: int = 32, n_pilot: int = 65521, lam_max: float = 0.8, shrink: float = 0.5, count: int = 8,
+           reps: int = 5, log=None) -> dict:
+    """Contour deformation (Sec. 3) of a mixed-sign sector (F vanishes inside
+    the cube) at delta = 0: lambda chosen on a pilot lattice by the sign check
+    and the smallest error, then the full lattice.  For comparison the same
+    sector regulated by a constant -i delta (delta = 1e-2, 1e-3) instead.
+    Kernel times from HIP events on the plan's stream (median of reps)."""
+    say = log or (lambda msg: None)
+    tab = synth.sector_tables(seed, d, n_u, n_f, complex_kinematics=True)
+    tab0 = dataclasses.replace(tab, delta_im=0.0, is_complex=True)
+    gv = GeneratingVectors(seed)
+    sh = synth.shifts(seed, m, d)
+    pilot = qmc.Plan(d, n_pilot, gv(n_pilot, d), sh[:8], "korobov", 3)
+    t0 = time.perf_counter()
+    lam, pres = pilot.deform_select(qmc.Params("sector", d, sector=tab0), lam_max, shrink, count)
+    t_select = time.perf_counter() - t0
+    ladder = []
+    for i in range(count):
+        L = lam_max * shrink ** i
+        frac, _ = pilot.deform_check(qmc.Params("sector", d, sector=tab0, deform=L))
+        ladder.append({"lambda": L, "violations": frac})
+    pilot.close()
+    say(f"  selected lambda={lam} pilot mean={complex(pres.mean_re, pres.mean_im)!r} ({t_select:.2f} s)")
+
+    def run(params, label):
+        plan = qmc.Plan(d, n, gv(n, d), sh, "korobov", 3)
+        plan.integrate(params)  # compiles the specialised kernel
+        plan.set_timing(True)
+        ks, ws = [], []
+        for _ in range(reps):
+            plan.kernel_time(reset=True)
+            _sync()
+            t = time.perf_counter()
+            res, _ = plan.integrate(params)
+            ws.append(time.perf_counter() - t)
+            ks.append(plan.kernel_time()[0])
+        launch = plan.last_launch()
+        plan.close()
+        k_ms, w_s = float(np.median(ks)), float(np.median(ws))
+        mean = complex(res.mean_re, res.mean_im)
+        row = {"label": label, "kernel_ms": k_ms, "wall_s": w_s, "evals_per_s": n * m / (k_ms * 1e-3),
+               "mean_re": res.mean_re, "mean_im": res.mean_im, "err_re": res.err_re, "err_im": res.err_im,
+               "rel_err": math.hypot(res.err_re, res.err_im) / abs(mean), "launch": list(launch)}
+        say(f"  {label}: {k_ms:.3f} ms kernel, {row['evals_per_s']:.3e} evals/s, mean={mean!r} "
+            f"rel_err={row['rel_err']:.3e}")
+        return row
+
+    rows = [run(qmc.Params("sector", d, sector=tab0, deform=lam), f"deformed lambda={lam}")]
+    for delta in (1e-2, 1e-3):
+        rows.append(run(qmc.Params("sector", d, sector=dataclasses.replace(tab, delta_im=delta, is_complex=True)),
+                        f"-i delta, delta={delta}"))
+    return {"d": d, "n_u": n_u, "n_f": n_f, "n": n, "m": m, "transform": "korobov3", "lambda": lam,
+            "select_seconds": t_select, "ladder": ladder, "rows": rows}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
-                                     "cv_estimate", "fig3", "allocation_compare"])
+                                     "cv_estimate", "fig3", "allocation_compare", "deform"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--shift-tile", type=int, default=0)
@@ -470,6 +527,8 @@ def main(argv=None):
         out = cv_estimate()
     elif args.what == "allocation_compare":
         out = allocation_compare(count=args.count or 2000)
+    elif args.what == "deform":
+        out = deform(log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "fig3":
         out = fig3(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "time_to_error":

@@ -108,6 +108,8 @@ SIGNATURES = {
     "qmc_cv_integral": (C.c_int, [_u32, _u32, _u32, _vp, _vp, _vp]),
     "qmc_integrate_cv": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
     "qmc_integrate_orders": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "qmc_deform_check": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "qmc_deform_select": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_uint32, _vp, _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
     "qmc_last_error": (C.c_char_p, []),
@@ -323,6 +325,23 @@ class Plan:
         if params.is_complex:
             per = per[:, 0::2] + 1j * per[:, 1::2]
         return list(out), per
+
+    def deform_check(self, params: Params):
+        """Fraction of lattice points where the deformed F - i delta has a
+        positive imaginary part: (overall, per-shift array (m,))."""
+        frac = C.c_double()
+        per = np.zeros(self.m)
+        check(lib().qmc_deform_check(self.handle, params.ptr, C.byref(frac), _p(per)), "qmc_deform_check")
+        return frac.value, per
+
+    def deform_select(self, params: Params, lam_max: float = 1.0, shrink: float = 0.5, count: int = 10):
+        """(lambda, result): the ladder lam_max * shrink^i lambda with no sign
+        violation and the smallest estimated error on this plan."""
+        lam = C.c_double()
+        res = qmc_result()
+        check(lib().qmc_deform_select(self.handle, params.ptr, float(lam_max), float(shrink), int(count),
+                                      C.byref(lam), C.byref(res)), "qmc_deform_select")
+        return lam.value, res
 
     def lattice_dump(self, j_lo: int, count: int):
         idx = np.zeros((count, self.d), dtype=np.uint32)

@@ -255,3 +255,74 @@ def test_deform_full_size_sampled(Q):
     fl = _floor(16381, O.korobov_vector(16381, w.d, 1234), w.shifts[pick], tab, 0.5, "korobov", 3)
     ok, worst = _ok(q2[pick], est, fl)
     assert ok, (worst, fl)
+
+
+@pytest.mark.parametrize("lam", [3.0, 6.0, 20.0])
+def test_deform_check_quartic_counts(Q, lam):
+    """Sign check of F = x1^2 x2^2 - 0.05 (violated on a region for large
+    lambda, none at 3): per-shift violation counts equal the oracle's."""
+    n, d = 65521, 2
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(21, 4, d)
+    tab = synth.SectorTables(d=d, coef_u=np.array([1.0]), exp_u=np.zeros((1, d), np.uint8),
+                             coef_f=np.array([-0.05, 1.0]), exp_f=np.array([[0, 0], [2, 2]], np.uint8),
+                             nu=np.zeros(d, np.uint8), pow_u=-2.0, pow_f=-1.5, delta_im=0.0, is_complex=True)
+    plan = Q.Plan(d, n, g, sh, "none")
+    _say(f"deform check quartic lam={lam}")
+    frac, per = plan.deform_check(Q.Params("sector", d, sector=tab, deform=lam))
+    plan.close()
+    est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab, deform=lam, deform_check=True), threads=THREADS)
+    assert np.array_equal(np.rint(per * n), np.rint(est.q_re * n)), (per * n, est.q_re * n)
+    assert (frac == 0.0) == (lam == 3.0)
+    assert abs(frac - est.q_re.mean()) <= 1e-15
+
+
+@pytest.mark.parametrize("lam", [0.05, 0.1, 0.2, 0.5])
+def test_deform_check_sector_counts(Q, lam):
+    """Sign check of a mixed-sign d = 6 sector under the Korobov transform:
+    per-shift counts equal the oracle's."""
+    d, n, m = 6, 65521, 4
+    tab = synth.sector_tables(406, d, 12, 30, complex_kinematics=True)
+    tab = dataclasses.replace(tab, delta_im=0.0, is_complex=True)
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(406, m, d)
+    plan = Q.Plan(d, n, g, sh, "korobov", 3)
+    _say(f"deform check sector lam={lam}")
+    frac, per = plan.deform_check(Q.Params("sector", d, sector=tab, deform=lam))
+    plan.close()
+    est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab, deform=lam, deform_check=True), "korobov", 3,
+                     threads=THREADS)
+    assert np.array_equal(np.rint(per * n), np.rint(est.q_re * n)), (per * n, est.q_re * n)
+
+
+def test_deform_select_rule(Q):
+    """The selection returns the ladder lambda with no violation and the
+    smallest error, and its result is qmc_integrate's at that lambda."""
+    d, n, m = 6, 65521, 8
+    tab = synth.sector_tables(406, d, 12, 30, complex_kinematics=True)
+    tab = dataclasses.replace(tab, delta_im=0.0, is_complex=True)
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(406, m, d)
+    plan = Q.Plan(d, n, g, sh, "korobov", 3)
+    _say("deform select")
+    lam, res = plan.deform_select(Q.Params("sector", d, sector=tab), lam_max=0.8, shrink=0.5, count=7)
+    ladder = [0.8 * 0.5 ** i for i in range(7)]
+    assert lam in ladder
+    errs = {}
+    for L in ladder:
+        p = Q.Params("sector", d, sector=tab, deform=L)
+        frac, _ = plan.deform_check(p)
+        if frac == 0.0:
+            st, r, _ = plan.integrate_status(p)
+            if st == Q.QMC_OK:
+                errs[L] = math.hypot(r.err_re, r.err_im)
+    assert errs and lam == min(errs, key=errs.get)
+    r, _ = plan.integrate(Q.Params("sector", d, sector=tab, deform=lam))
+    assert (r.mean_re, r.mean_im, r.err_re, r.err_im) == (res.mean_re, res.mean_im, res.err_re, res.err_im)
+    with pytest.raises(Q.QMCError) as e:
+        plan.deform_select(Q.Params("sector", d, sector=tab), lam_max=0.8, shrink=1.5, count=7)
+    assert e.value.status == Q.QMC_EINVAL
+    with pytest.raises(Q.QMCError) as e:
+        plan.deform_check(Q.Params("sector", d, sector=tab))
+    assert e.value.status == Q.QMC_EINVAL
+    plan.close()

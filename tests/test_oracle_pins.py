@@ -710,3 +710,28 @@ def test_deformation_2d_circle_threshold():
                                                                    deform=lam), "korobov", 3)
             mean, er, ei = est.mean_error()
             assert abs(mean - want) < 1e-13 * abs(want), (p, lam, mean, want)
+
+
+def test_deformation_sign_check_closed_form():
+    """F = x^3 - c in one dimension: with y = 3 lam x^3 (1 - x) the deformed
+    F(x - i y) has imaginary part y (y^2 - 3 x^2), positive exactly where
+    x^2 (1 - x) > 1 / (sqrt(3) lam).  The check counts lattice points (no
+    transform weight), so the fraction is that interval's length within 1/n.
+    A linear F is never violated (Im F(z) = -lam x (1 - x) F'^2)."""
+    n = 100003
+    g = np.array([1], np.uint32)
+    sh = synth.shifts(21, 4, 1)
+    for lam in (3.0, 6.0, 20.0):
+        s = _sector(1, [1.0], [[0]], [-0.2, 1.0], [[0], [3]], [0], pow_u=-2.0, pow_f=-1.5, delta=0.0, cplx=True)
+        est = O.estimate(n, g, sh, O.Params("sector", 1, sector=s, deform=lam, deform_check=True))
+        t = 1.0 / (math.sqrt(3.0) * lam)
+        r = np.roots([-1.0, 1.0, 0.0, -t])  # x^2 (1 - x) - t = 0
+        r = np.sort(r[(np.abs(r.imag) < 1e-12) & (r.real > 0) & (r.real < 1)].real)
+        length = r[1] - r[0] if r.size == 2 else 0.0
+        if lam == 3.0:
+            assert length == 0.0  # 4/27 < 1/(3 sqrt 3)
+        assert np.all(np.abs(est.q_re - length) <= 1.0 / n + 1e-15), (lam, est.q_re, length)
+        assert np.all(est.q_im == 0.0)
+    s = _sector(1, [1.0], [[0]], [-0.37, 1.0], [[0], [1]], [0], pow_u=-2.0, pow_f=-1.5, delta=0.0, cplx=True)
+    est = O.estimate(n, g, sh, O.Params("sector", 1, sector=s, deform=50.0, deform_check=True))
+    assert np.all(est.q_re == 0.0)
