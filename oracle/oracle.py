@@ -23,7 +23,7 @@ FAMILIES = {
     "const": 0, "trig": 1, "p2kernel": 2, "genz_product_peak": 3, "genz_oscillatory": 4,
     "genz_gaussian": 5, "genz_continuous": 6, "genz_corner_peak": 7, "sector": 8,
 }
-TRANSFORMS = {"none": 0, "korobov": 1, "baker": 2}
+TRANSFORMS = {"none": 0, "korobov": 1, "baker": 2, "sidi": 3}
 
 
 def build(force: bool = True) -> str:

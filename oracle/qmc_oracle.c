@@ -13,6 +13,8 @@
  *   eq. (3):  sigma^2 = sum_k (Q_k - Qbar)^2 / (m (m - 1))
  *   eq. (4):  Korobov transform z(x) = int_0^x w, w(u) = u^a (1-u)^a / B
  *   eq. (5):  baker's transform z(x) = 1 - |2x - 1|
+ *   Sidi's sin^m transform, z(x) = int_0^x sin^m(pi u) du / int_0^1 sin^m
+ *             (one of the other periodising substitutions Sec. 2 refers to)
  *   fhat(x) = f(z(x)) * prod_i z_i'(x_i)   (substitution x -> z(x), Sec. 2)
  *
  * Readings taken where the paper is silent (each also listed in the design
@@ -54,7 +56,7 @@ enum {
 };
 
 /* transform codes used by this oracle */
-enum { OR_T_NONE = 0, OR_T_KOROBOV = 1, OR_T_BAKER = 2 };
+enum { OR_T_NONE = 0, OR_T_KOROBOV = 1, OR_T_BAKER = 2, OR_T_SIDI = 3 };
 
 typedef struct {
     int32_t family;
@@ -172,6 +174,39 @@ void or_transform(int32_t kind, int32_t alpha, double x, double *z, double *w)
     } else if (kind == OR_T_BAKER) {
         *z = 1.0 - fabs(2.0 * x - 1.0);
         *w = 1.0;
+    } else if (kind == OR_T_SIDI) {
+        /* Sidi's sin^m transform (one of the periodising substitutions the
+           paper refers to in Sec. 2): w(u) = sin^m(pi u) / T_m, T_m the
+           integral of sin^m over [0, 1], z(x) = int_0^x w.  Antiderivatives:
+           m = 2p:   int_0^x sin^2p(pi t) dt = binom(2p, p) x / 4^p
+                     + sum_{k=1..p} (-1)^k binom(2p, p-k) sin(2 k pi x) / (4^p k pi)
+           m = 2p+1: substitute u = cos(pi t): (1/pi) [P(1) - P(cos pi x)],
+                     P(u) = sum_{k=0..p} binom(p, k) (-1)^k u^(2k+1) / (2k+1). */
+        const int m = alpha;
+        const long double pi = 3.141592653589793238462643383279502884L;
+        const long double xl = x;
+        long double theta, total;
+        if (m % 2 == 0) {
+            const int p = m / 2;
+            long double four_p = powl(4.0L, p);
+            theta = or_binom(2 * p, p) * xl / four_p;
+            for (int k = 1; k <= p; ++k)
+                theta += ((k % 2) ? -1.0L : 1.0L) * or_binom(2 * p, p - k) * sinl(2.0L * k * pi * xl) /
+                         (four_p * k * pi);
+            total = or_binom(2 * p, p) / four_p;
+        } else {
+            const int p = (m - 1) / 2;
+            long double P1 = 0.0L, Pc = 0.0L, c = cosl(pi * xl);
+            for (int k = 0; k <= p; ++k) {
+                const long double t = or_binom(p, k) * ((k % 2) ? -1.0L : 1.0L) / (2 * k + 1);
+                P1 += t;
+                Pc += t * powl(c, 2 * k + 1);
+            }
+            theta = (P1 - Pc) / pi;
+            total = 2.0L * P1 / pi;
+        }
+        *z = (double)(theta / total);
+        *w = (double)(powl(sinl(pi * xl), m) / total);
     } else {
         *z = x;
         *w = 1.0;

@@ -735,3 +735,46 @@ def test_deformation_sign_check_closed_form():
     s = _sector(1, [1.0], [[0]], [-0.37, 1.0], [[0], [1]], [0], pow_u=-2.0, pow_f=-1.5, delta=0.0, cplx=True)
     est = O.estimate(n, g, sh, O.Params("sector", 1, sector=s, deform=50.0, deform_check=True))
     assert np.all(est.q_re == 0.0)
+
+
+# ---------------------------------------------------- Sidi's transform
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+def test_sidi_transform_against_quadrature(m):
+    """Sidi's sin^m substitution: z against quadrature of sin^m(pi t), the
+    weight against sin^m(pi x) pi / B((m+1)/2, 1/2) (the integral of sin^m over
+    [0, 1] through the Beta function), the symmetry z(1-x) = 1 - z(x), and the
+    ends."""
+    total = special.beta((m + 1) / 2, 0.5) / np.pi
+    for x in (0.0, 0.013, 0.2, 0.37, 0.5, 0.71, 0.999, 1.0):
+        z, w = O.transform("sidi", m, x)
+        q, _ = integrate.quad(lambda t: np.sin(np.pi * t) ** m, 0, x, epsabs=1e-14, epsrel=1e-13)
+        assert abs(z - q / total) < 1e-14, (m, x, z, q / total)
+        assert abs(w - np.sin(np.pi * x) ** m / total) <= 1e-14 * max(1.0, w)
+        z2, _ = O.transform("sidi", m, 1.0 - x)
+        assert abs(z + z2 - 1.0) < 4e-16
+    assert O.transform("sidi", m, 0.5)[0] == pytest.approx(0.5, abs=1e-16)
+
+
+def test_sidi_constant_exact_and_decay():
+    """An even-m Sidi weight is a trigonometric polynomial (frequencies up to
+    m/2 per coordinate), so a lattice without a short dual vector integrates
+    the constant exactly.  On the Genz product peak (closed form) the error
+    falls by orders of magnitude from n = 1021 to n = 65521."""
+    d = 3
+    n = 1021
+    a, _, _ = O.korobov_search(n, d, synth.korobov_candidates(3, n, 16))
+    g = O.korobov_vector(n, d, a)
+    est = O.estimate(n, g, synth.shifts(3, 8, d), O.Params("const", d, c=1.0), "sidi", 4)
+    mean, err, _ = est.mean_error()
+    assert abs(mean.real - 1.0) < 1e-14 and err < 1e-14
+    av, uv = np.array([2.0, 3.0, 1.5]), np.array([0.3, 0.6, 0.45])
+    want = np.prod(av * (np.arctan(av * (1 - uv)) + np.arctan(av * uv)))
+    errs = []
+    for n in (1021, 65521):
+        a, _, _ = O.korobov_search(n, d, synth.korobov_candidates(3, n, 16))
+        g = O.korobov_vector(n, d, a)
+        est = O.estimate(n, g, synth.shifts(3, 8, d), O.Params("genz_product_peak", d, a=av, u=uv), "sidi", 3)
+        mean, err, _ = est.mean_error()
+        assert abs(mean.real - want) < 6 * err + 1e-13 * want
+        errs.append(abs(mean.real - want))
+    assert errs[1] < 1e-4 * errs[0], errs
