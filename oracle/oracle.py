@@ -105,6 +105,8 @@ def lib() -> C.CDLL:
         L.or_p2.argtypes = [u32, u64, vp, i32]
         L.or_korobov_search.restype = C.c_int
         L.or_korobov_search.argtypes = [u64, u32, vp, u32, i32, vp, vp, vp]
+        L.or_cbc.restype = C.c_int
+        L.or_cbc.argtypes = [u64, u32, vp, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -309,3 +311,17 @@ def korobov_search(n: int, d: int, cand, threads: int = 0):
     if st != 0:
         raise ValueError("bad korobov search arguments")
     return int(a.value), float(pb.value), allp
+
+
+def cbc(n: int, d: int, gamma=None, threads: int = 0):
+    """Component-by-component generating vector: (z (d,), e2 (d,)), e2[s] the
+    squared worst-case error after component s."""
+    gamma = np.ones(d) if gamma is None else np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    z = np.zeros(d, dtype=np.uint64)
+    e2 = np.zeros(d)
+    if lib().or_cbc(n, d, _ptr(gamma), threads, _ptr(z), _ptr(e2)) != 0:
+        raise ValueError("bad cbc arguments")
+    return z, e2
+

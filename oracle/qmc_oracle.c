@@ -779,3 +779,122 @@ int or_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint32_t nca
     *p2_best = best;
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Component-by-component construction of a generating vector          */
+/* ------------------------------------------------------------------ */
+/* Sec. 2 uses rank-1 lattices and leaves the generating vector open; the
+   standard construction of the lattice literature (Sloan, Kuo, Joe;
+   Nuyens, Cools) fixes z_1 = 1 and, for s = 2..d, takes z_s from
+   {1 <= c <= n/2, gcd(c, n) = 1} minimising the squared worst-case error of
+   the weighted Korobov space of smoothness 2,
+     e_s^2(c) = -1 + (1/n) sum_{j=0}^{n-1} prod_{i<s} (1 + gamma_i w({j z_i / n}))
+                                        * (1 + gamma_s w({j c / n})),
+   w(x) = 2 pi^2 B_2(x), B_2(x) = x^2 - x + 1/6.  Ties go to the smaller c.
+   e2[s-1] receives e_s^2(z_s) (e2[0] for z_1 = 1). */
+typedef struct {
+    uint64_t n;
+    double gamma;
+    const long double *prod; /* [n] product over the chosen components */
+    const uint64_t *cand;
+    uint64_t ncand;
+    long double *val;        /* [ncand] sums */
+    uint64_t next;
+    pthread_mutex_t lock;
+} or_cbcjob;
+
+static void *or_cbc_worker(void *arg)
+{
+    const long double PI = 3.141592653589793238462643383279502884L;
+    or_cbcjob *jb = (or_cbcjob *)arg;
+    for (;;) {
+        pthread_mutex_lock(&jb->lock);
+        uint64_t c0 = jb->next;
+        jb->next += 64;
+        pthread_mutex_unlock(&jb->lock);
+        if (c0 >= jb->ncand)
+            break;
+        uint64_t c1 = c0 + 64 < jb->ncand ? c0 + 64 : jb->ncand;
+        for (uint64_t t = c0; t < c1; ++t) {
+            or_acc a = {0, 0};
+            for (uint64_t j = 0; j < jb->n; ++j) {
+                long double x = (long double)or_lattice_index(j, jb->cand[t], jb->n) / (long double)jb->n;
+                long double b2 = x * x - x + 1.0L / 6.0L;
+                or_acc_add(&a, jb->prod[j] * (1.0L + jb->gamma * 2.0L * PI * PI * b2));
+            }
+            jb->val[t] = a.s + a.c;
+        }
+    }
+    return NULL;
+}
+
+static uint64_t or_gcd(uint64_t a, uint64_t b)
+{
+    while (b) {
+        uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+int or_cbc(uint64_t n, uint32_t d, const double *gamma, int32_t nthreads, uint64_t *z, double *e2)
+{
+    const long double PI = 3.141592653589793238462643383279502884L;
+    if (n < 2 || d == 0 || d > 64)
+        return 1;
+    long double *prod = (long double *)malloc(n * sizeof(long double));
+    uint64_t *cand = (uint64_t *)malloc((n / 2 + 1) * sizeof(uint64_t));
+    long double *val = (long double *)malloc((n / 2 + 1) * sizeof(long double));
+    uint64_t ncand = 0;
+    for (uint64_t c = 1; c <= n / 2; ++c)
+        if (or_gcd(c, n) == 1)
+            cand[ncand++] = c;
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    for (uint64_t j = 0; j < n; ++j)
+        prod[j] = 1.0L;
+    for (uint32_t s = 0; s < d; ++s) {
+        uint64_t best_c = 1;
+        long double best = 0.0L;
+        if (s == 0) {
+            /* z_1 = 1: in one dimension every admissible c gives the same
+               point set */
+            or_cbcjob one = {n, gamma[0], prod, cand, 1, val, 0};
+            pthread_mutex_init(&one.lock, NULL);
+            or_cbc_worker(&one);
+            pthread_mutex_destroy(&one.lock);
+            best = val[0];
+        } else {
+            or_cbcjob jb = {n, gamma[s], prod, cand, ncand, val, 0};
+            pthread_mutex_init(&jb.lock, NULL);
+            pthread_t th[256];
+            for (int t = 1; t < nthreads; ++t)
+                pthread_create(&th[t], NULL, or_cbc_worker, &jb);
+            or_cbc_worker(&jb);
+            for (int t = 1; t < nthreads; ++t)
+                pthread_join(th[t], NULL);
+            pthread_mutex_destroy(&jb.lock);
+            best = val[0];
+            best_c = cand[0];
+            for (uint64_t t = 1; t < ncand; ++t)
+                if (val[t] < best) {
+                    best = val[t];
+                    best_c = cand[t];
+                }
+        }
+        z[s] = best_c;
+        e2[s] = (double)(-1.0L + best / (long double)n);
+        for (uint64_t j = 0; j < n; ++j) {
+            long double x = (long double)or_lattice_index(j, best_c, n) / (long double)n;
+            prod[j] *= 1.0L + gamma[s] * 2.0L * PI * PI * (x * x - x + 1.0L / 6.0L);
+        }
+    }
+    free(prod);
+    free(cand);
+    free(val);
+    return 0;
+}
+

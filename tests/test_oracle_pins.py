@@ -778,3 +778,47 @@ def test_sidi_constant_exact_and_decay():
         assert abs(mean.real - want) < 6 * err + 1e-13 * want
         errs.append(abs(mean.real - want))
     assert errs[1] < 1e-4 * errs[0], errs
+
+
+# ------------------------------------------ component-by-component vectors
+def test_cbc_unit_weights_match_p2_and_greedy_optimum():
+    """With unit weights the CBC error after component s is P2 of the prefix
+    (P2 pinned separately against the dual-lattice sum), and each component
+    minimises P2 over every admissible candidate given the earlier ones
+    (brute force through P2)."""
+    n, d = 251, 4
+    z, e2 = O.cbc(n, d)
+    assert z[0] == 1
+    # e^2 = -1 + (mean of products near 1): compare on the scale of 1 + e^2
+    for s in range(d):
+        assert abs(e2[s] - O.p2(n, z[: s + 1])) <= 1e-14 * (1 + e2[s])
+    for s in range(1, d):
+        vals = np.array([O.p2(n, np.concatenate([z[:s], [c]])) for c in range(1, n // 2 + 1)])
+        assert vals[int(z[s]) - 1] - vals.min() <= 1e-14 * (1 + vals.min())
+
+
+def test_cbc_weighted_first_component_closed_form():
+    """One dimension: (1/n) sum_j B2(j/n) = 1/(6 n^2), so e_1^2 = gamma_1 pi^2 / (3 n^2)
+    for any weight; a zero weight beyond the first component makes every
+    candidate tie, and ties go to c = 1."""
+    n = 1021
+    for g1 in (1.0, 0.3, 2.5):
+        z, e2 = O.cbc(n, 3, gamma=[g1, 0.0, 0.0])
+        assert abs(e2[0] - g1 * np.pi ** 2 / (3 * n * n)) <= 1e-12 * e2[0]
+        assert list(z) == [1, 1, 1]
+        assert abs(e2[2] - e2[0]) <= 1e-15
+
+
+def test_cbc_weights_change_the_choice():
+    """Decaying product weights: the weighted error is below the unit-weight
+    one, both are positive and grow with s, and the prefix property holds
+    (the first s components of a d-dimensional CBC vector are the
+    s-dimensional CBC vector)."""
+    n, d = 1021, 6
+    gam = 1.0 / np.arange(1, d + 1) ** 2
+    z, e2 = O.cbc(n, d, gamma=gam)
+    z1, e21 = O.cbc(n, d)
+    assert np.all(np.diff(e2) > 0) and np.all(e2 > 0)
+    assert e2[0] == e21[0] and np.all(e2[1:] < e21[1:])
+    z3, e23 = O.cbc(n, 3, gamma=gam[:3])
+    assert list(z3) == list(z[:3]) and np.array_equal(e23, e2[:3])
