@@ -50,12 +50,17 @@ typedef enum {
     QMC_T_NONE = 0,
     QMC_T_KOROBOV = 1,  /* weight alpha in 1..6 */
     QMC_T_BAKER = 2,
-    QMC_T_TENT = 2
+    QMC_T_TENT = 2,
+    /* Sidi's sin^m transform, m = alpha in 1..6: w(x) = sin^m(pi x) / T_m,
+       T_m the integral of sin^m over [0, 1]; one of the other periodising
+       substitutions Sec. 2 refers to.  Compiled for QMC_F_CONST,
+       QMC_F_GENZ_PRODUCT_PEAK and the specialised sector kernels. */
+    QMC_T_SIDI = 3
 } qmc_transform_kind;
 
 typedef struct {
     int32_t kind;   /* qmc_transform_kind */
-    int32_t alpha;  /* Korobov weight; ignored otherwise */
+    int32_t alpha;  /* Korobov weight or Sidi order; ignored otherwise */
 } qmc_transform;
 
 /* Integrand families f(z), z in [0,1]^d. */

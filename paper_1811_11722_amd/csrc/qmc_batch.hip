@@ -187,7 +187,7 @@ qmc_status build_ctx(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const
     c.device = p0->device;
     c.tile_points = tile_points;
     for (uint32_t i = 0; i < count; ++i) c.blobs.push_back(pk[i].blob);
-    const int alpha = p0->tr.kind == QMC_T_KOROBOV ? p0->tr.alpha : 0;
+    const int alpha = (p0->tr.kind == QMC_T_KOROBOV || p0->tr.kind == QMC_T_SIDI) ? p0->tr.alpha : 0;
     auto &reg = batch_registry();
     // one shift tile for the whole batch: the largest compiled for plan 0's d
     c.T = 0;

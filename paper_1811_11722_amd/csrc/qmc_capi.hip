@@ -211,6 +211,23 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
 }
 
 double transform_scale(const qmc_transform &t, uint32_t d) {
+    if (t.kind == QMC_T_SIDI) {
+        // 1 / T_m per dimension, T_m = int_0^1 sin^m(pi x) dx
+        const int m = t.alpha, p = m / 2;
+        double tm;
+        if (m % 2 == 0) {
+            tm = 1.0;  // binom(2p, p) / 4^p
+            for (int k = 1; k <= p; ++k) tm *= (double)(p + k) / (4.0 * k);
+        } else {
+            double p1 = 0.0, b = 1.0;  // sum_k binom(p, k) (-1)^k / (2k + 1)
+            for (int k = 0; k <= p; ++k) {
+                p1 += ((k & 1) ? -b : b) / (2 * k + 1);
+                b = b * (p - k) / (k + 1);
+            }
+            tm = 2.0 * p1 / 3.141592653589793;
+        }
+        return std::pow(1.0 / tm, (double)d);
+    }
     if (t.kind != QMC_T_KOROBOV) return 1.0;
     double c = 1.0;  // (2a+1)! / (a!)^2
     for (int k = t.alpha + 1; k <= 2 * t.alpha + 1; ++k) c *= k;
@@ -224,7 +241,7 @@ static const int kTChoices[] = {8, 4, 2, 1};
 LatticeLaunch find_kernel(int key_family, const qmc_transform &t, uint32_t d, uint32_t want_T,
                           uint32_t &T_out) {
     auto &reg = lattice_registry();
-    const int alpha = t.kind == QMC_T_KOROBOV ? t.alpha : 0;
+    const int alpha = (t.kind == QMC_T_KOROBOV || t.kind == QMC_T_SIDI) ? t.alpha : 0;
     if (want_T) {
         auto it = reg.find(KernelKey{key_family, t.kind, alpha, (int)d, (int)want_T});
         if (it != reg.end()) {
@@ -470,11 +487,13 @@ qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m
     if (!shifts) return fail(QMC_EINVAL, "shifts is NULL");
     for (size_t i = 0; i < (size_t)m * d; ++i)
         if (!(shifts[i] >= 0.0 && shifts[i] < 1.0)) return fail(QMC_EINVAL, "shift %zu outside [0,1)", i);
-    if (t.kind != QMC_T_NONE && t.kind != QMC_T_KOROBOV && t.kind != QMC_T_BAKER)
+    if (t.kind != QMC_T_NONE && t.kind != QMC_T_KOROBOV && t.kind != QMC_T_BAKER && t.kind != QMC_T_SIDI)
         return fail(QMC_EINVAL, "unknown transform %d", t.kind);
     if (t.kind == QMC_T_KOROBOV && t.alpha < 1) return fail(QMC_EINVAL, "Korobov weight must be >= 1");
     if (t.kind == QMC_T_KOROBOV && t.alpha > 6) return fail(QMC_EUNSUPPORTED, "Korobov weight > 6");
-    if (t.kind != QMC_T_KOROBOV) t.alpha = 0;
+    if (t.kind == QMC_T_SIDI && t.alpha < 1) return fail(QMC_EINVAL, "Sidi order must be >= 1");
+    if (t.kind == QMC_T_SIDI && t.alpha > 6) return fail(QMC_EUNSUPPORTED, "Sidi order > 6");
+    if (t.kind != QMC_T_KOROBOV && t.kind != QMC_T_SIDI) t.alpha = 0;
 
     auto *p = new (std::nothrow) qmc_plan_s();
     if (!p) return fail(QMC_ENOMEM, "host allocation");

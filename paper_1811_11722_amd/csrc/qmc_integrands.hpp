@@ -86,6 +86,85 @@ struct TrKorobov {
     }
 };
 
+// Sidi's sin^M transform: w(x) = sin^M(pi x) / T_M with T_M the integral of
+// sin^M over [0, 1], z = int_0^x w.  With c = cos(pi x):
+//   M = 2p+1: z = 1/2 - c sum_k d_k c^(2k), d_k = binom(p, k) (-1)^k /
+//             ((2k + 1) 2 P1), P1 = sum_k binom(p, k) (-1)^k / (2k + 1)
+//             (substituting u = cos(pi t) in the integral of sin^M);
+//   M = 2p:   z = x + sin(2 pi x) sum_{k=1..p} e_k U_{k-1}(cos 2 pi x),
+//             e_k = (-1)^k binom(2p, p-k) / (pi k binom(2p, p)), U the
+//             Chebyshev polynomials of the second kind (sin(2k t) =
+//             sin(2t) U_{k-1}(cos 2t)).
+// u = sin(pi x); the Jacobian is (prod u)^M and 1/T_M^d is applied to the
+// final sums.
+template <int M>
+struct TrSidi {
+    static_assert(M >= 1 && M <= 6, "Sidi order 1..6");
+    static constexpr bool kJac = true;
+    static constexpr int P = M / 2;
+    static constexpr double kPiD = 3.141592653589793;
+    struct Coefs {
+        double c[P + 1];
+    };
+    static constexpr Coefs make_coefs() {
+        Coefs r{};
+        if (M % 2) {
+            double p1 = 0.0;
+            for (int k = 0; k <= P; ++k) p1 += cbinom(P, k) * ((k & 1) ? -1.0 : 1.0) / (2 * k + 1);
+            for (int k = 0; k <= P; ++k) r.c[k] = cbinom(P, k) * ((k & 1) ? -1.0 : 1.0) / ((2 * k + 1) * 2.0 * p1);
+        } else {
+            r.c[0] = 0.0;
+            for (int k = 1; k <= P; ++k)
+                r.c[k] = ((k & 1) ? -1.0 : 1.0) * cbinom(2 * P, P - k) / (kPiD * k * cbinom(2 * P, P));
+        }
+        return r;
+    }
+    static constexpr Coefs kCoef = make_coefs();
+    // z = base + q r with (q, r) from the sine and cosine: odd M base 1/2,
+    // q = -cos, even M base x, q = sin 2 pi x
+    __device__ static void parts(double x, double &u, double &q, double &r) {
+        double sn, cs;
+        qsincos(kPiD * x, sn, cs);
+        u = sn;
+        if constexpr (M % 2) {
+            const double c2 = cs * cs;
+            r = kCoef.c[P];
+#pragma unroll
+            for (int k = P - 1; k >= 0; --k) r = fma_(r, c2, kCoef.c[k]);
+            q = -cs;
+        } else {
+            const double C = fma_(-2.0 * sn, sn, 1.0);  // cos 2 pi x
+            double um2 = 0.0, um1 = 1.0;                 // U_{-1}, U_0
+            r = kCoef.c[1];
+#pragma unroll
+            for (int k = 2; k <= P; ++k) {
+                const double uk = fma_(2.0 * C, um1, -um2);
+                um2 = um1;
+                um1 = uk;
+                r = fma_(kCoef.c[k], uk, r);
+            }
+            q = 2.0 * sn * cs;
+        }
+    }
+    __device__ static double z(double x, double &u) {
+        double q, r;
+        parts(x, u, q, r);
+        return fma_(q, r, (M % 2) ? 0.5 : x);
+    }
+    // z - b given hmb = 1/2 - b, and u
+    __device__ static double z_minus(double x, double hmb, double &u) {
+        double q, r;
+        parts(x, u, q, r);
+        return fma_(q, r, (M % 2) ? hmb : (x - 0.5) + hmb);
+    }
+    __device__ static double jac(double pu) {
+        double r = pu;
+#pragma unroll
+        for (int a = 1; a < M; ++a) r *= pu;
+        return r;
+    }
+};
+
 // z for all D coordinates of T shifts, and the Jacobian (without C_A^d)
 template <class Tr, int D, int T>
 __device__ __forceinline__ void apply_transform(const double (&x)[T][D], double (&z)[T][D],

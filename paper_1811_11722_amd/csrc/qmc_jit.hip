@@ -73,7 +73,9 @@ struct Trie {
 const char *transform_type(const qmc_transform &t) {
     static const char *kor[] = {"", "TrKorobov<1>", "TrKorobov<2>", "TrKorobov<3>",
                                 "TrKorobov<4>", "TrKorobov<5>", "TrKorobov<6>"};
+    static const char *sidi[] = {"", "TrSidi<1>", "TrSidi<2>", "TrSidi<3>", "TrSidi<4>", "TrSidi<5>", "TrSidi<6>"};
     if (t.kind == QMC_T_KOROBOV) return kor[t.alpha];
+    if (t.kind == QMC_T_SIDI) return sidi[t.alpha];
     return t.kind == QMC_T_BAKER ? "TrBaker" : "TrNone";
 }
 

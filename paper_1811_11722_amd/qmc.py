@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libqmc.so")
 # status codes
 QMC_OK, QMC_EINVAL, QMC_EUNSUPPORTED, QMC_ENOMEM, QMC_EDEVICE, QMC_ENONFINITE = range(6)
 # transforms
-QMC_T_NONE, QMC_T_KOROBOV, QMC_T_BAKER = 0, 1, 2
+QMC_T_NONE, QMC_T_KOROBOV, QMC_T_BAKER, QMC_T_SIDI = 0, 1, 2, 3
 QMC_T_TENT = QMC_T_BAKER
 # families
 (QMC_F_CONST, QMC_F_TRIG, QMC_F_P2KERNEL, QMC_F_GENZ_PRODUCT_PEAK, QMC_F_GENZ_OSCILLATORY,
@@ -31,7 +31,7 @@ FAMILY = {
     "genz_corner_peak": QMC_F_GENZ_CORNER_PEAK, "sector": QMC_F_SECTOR,
 }
 TRANSFORM = {"none": QMC_T_NONE, "korobov": QMC_T_KOROBOV, "baker": QMC_T_BAKER,
-             "tent": QMC_T_TENT}
+             "tent": QMC_T_TENT, "sidi": QMC_T_SIDI}
 
 
 class qmc_transform(C.Structure):

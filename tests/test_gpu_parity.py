@@ -416,3 +416,33 @@ def test_sector_orders_validation(Q):
     one, _ = plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(1, 1.0, 1.0)))
     plain, _ = plan.integrate(Q.Params("sector", d, sector=tab))
     assert one[0].mean_re == plain.mean_re
+
+
+# ------------------------------------------------------------ Sidi transform
+@pytest.mark.parametrize("family", ["genz_product_peak", "const"])
+@pytest.mark.parametrize("m_", [1, 2, 3, 4, 5, 6])
+def test_sidi_transform_families(Q, family, m_):
+    """Sidi's sin^m transform compiled ahead of time, against the oracle."""
+    d, n, m = 3, 4093, 5
+    a, u = synth.genz_params(17, d)
+    g = O.korobov_vector(n, d, 76)
+    sh = synth.shifts(17, m, d)
+    kw = dict(a=a / 3.0, u=u) if family.startswith("genz") else {"c": 1.7}
+    _say(f"{family} sidi{m_}")
+    res, q, est = _both(Q, family, d, n, g, sh, "sidi", m_, **kw)
+    assert np.all(_rel(q, est.q_re) < TOL), (_rel(q, est.q_re).max())
+
+
+@pytest.mark.parametrize("m_", [1, 2, 3, 6])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_sidi_transform_sectors(Q, m_, cplx):
+    """Sectors with Sidi's transform through the specialised kernel."""
+    d, n, m = 6, 16381, 5
+    tab = synth.sector_tables(231, d, 12, 30)
+    if cplx:
+        tab.delta_im, tab.is_complex = 0.02, True
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(231, m, d)
+    _say(f"sector sidi{m_} complex={cplx}")
+    res, q, est = _both(Q, "sector", d, n, g, sh, "sidi", m_, sector=tab)
+    assert np.all(_rel(q, est.q) < TOL), (_rel(q, est.q).max())
