@@ -355,6 +355,45 @@ qmc_status qmc_deform_check(qmc_plan_t plan, const qmc_sector_params *params, do
 qmc_status qmc_deform_select(qmc_plan_t plan, const qmc_sector_params *params, double lam_max, double shrink,
                              uint32_t count, double *lam_out, qmc_result *out);
 
+/* Component-by-component construction of a generating vector (rank-1
+   lattices, Sec. 2; the construction is the standard one of the lattice
+   literature): z_1 = 1 and, for s = 2..d, z_s is the candidate c minimising
+     e_s^2(c) = -1 + (1/n) sum_{j<n} prod_{i<s} (1 + gamma_i 2 pi^2 B2({j z_i/n}))
+                                     * (1 + gamma_s 2 pi^2 B2({j c/n})),
+   B2(x) = x^2 - x + 1/6, the squared worst-case error of the weighted
+   Korobov space of smoothness 2 (with unit weights, the P2 of
+   qmc_korobov_search).  gamma: d non-negative product weights (NULL: all 1).
+   cand: ncand candidates, each a unit mod n (NULL: every unit in [1, n/2]);
+   values within 1e-13 (1 + e^2) of the minimum are ties (lattice symmetries
+   make exact ties common: c and c^-1 in two dimensions), and ties go to the
+   smaller c.  z_out: d values; e2_out: d values, e_s^2(z_s)
+   after each component (host memory, caller-owned).  n in [2, 2^31],
+   d <= 16; EUNSUPPORTED when candidates x n exceeds 2^44 (pass a subset).
+   Runs on the current device, synchronously. */
+qmc_status qmc_cbc_search(uint64_t n, uint32_t d, const double *gamma, const uint64_t *cand, uint32_t ncand,
+                          uint64_t *z_out, double *e2_out);
+
+/* Embedded (extensible) lattices in base 2 (rank-1 lattices of Sec. 2 whose
+   point sets nest): with n = 2^k and g = (1, a, a^2, ...) mod 2^kmax, the
+   2n-point lattice is the n-point lattice plus the same lattice with every
+   shift moved by (g mod 2n) / (2n), so a ladder of sizes evaluates every
+   point once.  This search scores each odd candidate a by the mean over
+   k = kmin..kmax of ln P2(2^k, korobov_vector(2^k, d, a)) (qmc_korobov_search
+   per rung) and returns the best (ties: smaller a).  cand: ncand odd values
+   (EINVAL otherwise), ncand <= 4096; 1 <= kmin <= kmax <= 31.  score: the
+   best mean log P2; p2_levels (nullable): kmax - kmin + 1 values, the best
+   candidate's P2 per rung.  Host memory. */
+qmc_status qmc_korobov_search_extensible(uint32_t kmin, uint32_t kmax, uint32_t d, const uint64_t *cand,
+                                         uint32_t ncand, uint64_t *a_best, double *score, double *p2_levels);
+
+/* Merge of two half-lattice estimates into the estimate of their union
+   (eqs. (2)-(3)): q_out = (q_a + q_b) / 2 per shift and part, then the mean
+   and the error over the m shifts.  q_a, q_b, q_out: m * np doubles laid out
+   as qmc_integrate's per_shift (np = 1 real, 2 complex); out: host result.
+   ENONFINITE when a merged sum is not finite. */
+qmc_status qmc_lattice_merge(uint32_t m, uint32_t np, const double *q_a, const double *q_b, double *q_out,
+                             qmc_result *out);
+
 /* The library's device FP64 math on count host inputs, for checking the
    functions the sector integrand uses against a host reference:
    fn = 0 logarithm (x > 0), 1 exponential: x and y hold count values;

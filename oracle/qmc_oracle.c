@@ -790,7 +790,8 @@ int or_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint32_t nca
    the weighted Korobov space of smoothness 2,
      e_s^2(c) = -1 + (1/n) sum_{j=0}^{n-1} prod_{i<s} (1 + gamma_i w({j z_i / n}))
                                         * (1 + gamma_s w({j c / n})),
-   w(x) = 2 pi^2 B_2(x), B_2(x) = x^2 - x + 1/6.  Ties go to the smaller c.
+   w(x) = 2 pi^2 B_2(x), B_2(x) = x^2 - x + 1/6.  Ties, taken as values
+   within 1e-13 (1 + e^2) of the minimum, go to the smallest c.
    e2[s-1] receives e_s^2(z_s) (e2[0] for z_1 = 1). */
 typedef struct {
     uint64_t n;
@@ -877,12 +878,20 @@ int or_cbc(uint64_t n, uint32_t d, const double *gamma, int32_t nthreads, uint64
             for (int t = 1; t < nthreads; ++t)
                 pthread_join(th[t], NULL);
             pthread_mutex_destroy(&jb.lock);
-            best = val[0];
-            best_c = cand[0];
+            /* lattice symmetries make exact ties common (in two dimensions
+               c and c^-1 mod n give the same error), and rounding would pick
+               among them: values within 1e-13 (1 + e^2) of the minimum count
+               as ties, and ties go to the smallest c */
+            long double vmin = val[0];
             for (uint64_t t = 1; t < ncand; ++t)
-                if (val[t] < best) {
+                if (val[t] < vmin)
+                    vmin = val[t];
+            const long double tau = 1e-13L * (long double)n * (1.0L + fabsl(vmin / (long double)n - 1.0L));
+            for (uint64_t t = 0; t < ncand; ++t)
+                if (val[t] <= vmin + tau) {
                     best = val[t];
                     best_c = cand[t];
+                    break;
                 }
         }
         z[s] = best_c;

@@ -161,18 +161,18 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
         uint32_t flags = (cplx ? 1u : 0u) | (p->pow_u == -2.0 ? 2u : 0u);
         pk.blob = {bits(p->n_u), bits(p->n_f), bits(flags), p->pow_u, p->pow_f, cplx ? p->delta_im : 0.0,
                    bits(nucode)};
-        for (uint32_t t = 0; t < p->n_u; ++t) pk.blob.push_back(p->coef_u[t]);
-        for (uint32_t t = 0; t < p->n_u; ++t) {
-            uint64_t c;
-            if ((st = monomial_code(p->exp_u + (size_t)t * d, d, c))) return st;
-            pk.blob.push_back(bits(c));
-        }
-        for (uint32_t t = 0; t < p->n_f; ++t) pk.blob.push_back(p->coef_f[t]);
-        for (uint32_t t = 0; t < p->n_f; ++t) {
-            uint64_t c;
-            if ((st = monomial_code(p->exp_f + (size_t)t * d, d, c))) return st;
-            pk.blob.push_back(bits(c));
-        }
+        // terms are stored in the order the specialised code reads them (the
+        // polynomial is the same sum in any order)
+        std::vector<uint64_t> cu(p->n_u), cf(p->n_f);
+        for (uint32_t t = 0; t < p->n_u; ++t)
+            if ((st = monomial_code(p->exp_u + (size_t)t * d, d, cu[t]))) return st;
+        for (uint32_t t = 0; t < p->n_f; ++t)
+            if ((st = monomial_code(p->exp_f + (size_t)t * d, d, cf[t]))) return st;
+        const std::vector<uint32_t> ou = horner_term_order(cu, d), of = horner_term_order(cf, d);
+        for (uint32_t t : ou) pk.blob.push_back(p->coef_u[t]);
+        for (uint32_t t : ou) pk.blob.push_back(bits(cu[t]));
+        for (uint32_t t : of) pk.blob.push_back(p->coef_f[t]);
+        for (uint32_t t : of) pk.blob.push_back(bits(cf[t]));
         if (cplx) {
             pk.np = 2;
             pk.key_family = kFamSectorComplex;

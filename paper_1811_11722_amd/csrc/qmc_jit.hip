@@ -229,6 +229,85 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
     return s.str();
 }
 
+// Multivariate Horner form of sum_t coef[t] prod_i z_i^e[t][i]: split off
+// the variable v that occurs in most non-constant terms, P = P0 + z_v P1,
+// and recurse on P1 (exponents of v lowered) and P0.  Each split costs one
+// FMA (one multiply when P0 is empty), so a polynomial of T terms takes
+// about T operations instead of one multiply per product-trie edge plus one
+// FMA per term.  Emits the temporaries into s and returns the expression of
+// the value.
+using HornerTerms = std::vector<std::pair<int, std::vector<int>>>;
+static std::string horner(const char *coef, HornerTerms terms, std::ostringstream &s, int &tmp) {
+    HornerTerms consts;
+    for (const auto &t : terms)
+        if (std::all_of(t.second.begin(), t.second.end(), [](int e) { return e == 0; })) consts.push_back(t);
+    if (consts.size() == terms.size()) {
+        std::ostringstream e;
+        for (size_t c = 0; c < consts.size(); ++c) e << (c ? " + " : "") << coef << "[" << consts[c].first << "]";
+        return consts.size() == 1 ? e.str() : "(" + e.str() + ")";
+    }
+    const size_t nv = terms[0].second.size();
+    size_t v = 0;
+    int best = -1;
+    for (size_t i = 0; i < nv; ++i) {
+        int c = 0;
+        for (const auto &t : terms) c += t.second[i] > 0;
+        if (c > best) {
+            best = c;
+            v = i;
+        }
+    }
+    HornerTerms p1, p0;
+    for (auto t : terms) {
+        if (t.second[v] > 0) {
+            t.second[v] -= 1;
+            p1.push_back(t);
+        } else {
+            p0.push_back(t);
+        }
+    }
+    const std::string a = horner(coef, p1, s, tmp);
+    const std::string b = p0.empty() ? std::string() : horner(coef, p0, s, tmp);
+    const std::string name = "h" + std::to_string(tmp++);
+    s << "            const double " << name << " = ";
+    if (b.empty()) s << a << " * z[k][" << v << "];\n";
+    else s << "fma_(" << a << ", z[k][" << v << "], " << b << ");\n";
+    return name;
+}
+
+// The order in which the Horner form above first reads each coefficient.
+// The host packer stores the terms in this order, so the generated code
+// reads the coefficients in ascending address order and the compiler can
+// fetch them with few scalar loads and few live scalar registers.
+std::vector<uint32_t> horner_term_order(const std::vector<uint64_t> &codes, uint32_t d) {
+    HornerTerms terms;
+    for (size_t t = 0; t < codes.size(); ++t) {
+        std::vector<int> e(d, 0);
+        for (int v : factors_of(codes[t])) e[v] += 1;
+        terms.push_back({(int)t, e});
+    }
+    std::ostringstream s;
+    int tmp = 0;
+    const std::string top = horner("c", terms, s, tmp);
+    s << top;
+    const std::string text = s.str();
+    std::vector<uint32_t> order;
+    std::vector<bool> seen(codes.size(), false);
+    for (size_t i = 0; i + 1 < text.size(); ++i) {
+        if (text[i] != 'c' || text[i + 1] != '[') continue;
+        size_t j = i + 2;
+        uint32_t v = 0;
+        while (j < text.size() && text[j] >= '0' && text[j] <= '9') v = 10 * v + (uint32_t)(text[j++] - '0');
+        if (v < codes.size() && !seen[v]) {
+            seen[v] = true;
+            order.push_back(v);
+        }
+    }
+    for (uint32_t t = 0; t < codes.size(); ++t)
+        if (!seen[t]) order.push_back(t);
+    return order;
+}
+
 // Source of the specialised functor FamJit; `structure` receives a
 // canonical description of what the code depends on.
 static std::string functor_source(const std::vector<double> &blob, uint32_t d, bool cplx, std::string &structure) {
@@ -237,19 +316,24 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
     // eps_f, count); other blobs may carry other data there
     const size_t eps_at = kSectorHeader + 2 * (size_t)nu + 2 * (size_t)nf;
     const uint32_t orders = (word(blob, 2) & kSectorOrders) ? (uint32_t)word(blob, eps_at + 2) : 0u;
-    Trie trie;
-    std::vector<int> mu(nu), mf(nf);
+    Trie trie;  // the z^nu product
+    HornerTerms hu, hf;
+    auto exps = [d](uint64_t code) {
+        std::vector<int> e(d, 0);
+        for (int v : factors_of(code)) e[v] += 1;
+        return e;
+    };
     std::ostringstream st;
     st << "d" << d << "c" << cplx << "|";
     for (uint32_t t = 0; t < nu; ++t) {
         const uint64_t c = word(blob, kSectorHeader + nu + t);
-        mu[t] = trie.insert(factors_of(c));
+        hu.push_back({(int)t, exps(c)});
         st << c << ",";
     }
     st << "|";
     for (uint32_t t = 0; t < nf; ++t) {
         const uint64_t c = word(blob, kSectorHeader + 2 * nu + nf + t);
-        mf[t] = trie.insert(factors_of(c));
+        hf.push_back({(int)t, exps(c)});
         st << c << ",";
     }
     const uint64_t nuc = word(blob, 6);
@@ -302,18 +386,11 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
         if (nd.first < 0) continue;
         s << "            const double m" << id << " = " << ref(nd.first) << " * z[k][" << nd.second << "];\n";
     }
-    auto poly = [&](const char *name, const char *coef, const std::vector<int> &mono) {
-        for (size_t t = 0; t < mono.size(); ++t) {
-            s << "            ";
-            if (t == 0) s << "double " << name << " = ";
-            else s << name << " = ";
-            if (mono[t] < 0) s << (t == 0 ? "" : std::string(name) + " + ") << coef << "[" << t << "];\n";
-            else if (t == 0) s << coef << "[" << t << "] * " << ref(mono[t]) << ";\n";
-            else s << "fma_(" << coef << "[" << t << "], " << ref(mono[t]) << ", " << name << ");\n";
-        }
-    };
-    poly("U", "cu", mu);
-    poly("F", "cf", mf);
+    int tmp = 0;
+    const std::string ue = horner("cu", hu, s, tmp);
+    s << "            const double U = " << ue << ";\n";
+    const std::string fe = horner("cf", hf, s, tmp);
+    s << "            const double F = " << fe << ";\n";
     s << "            const double mono = " << (mnu < 0 ? std::string("jac[k]") : "jac[k] * " + ref(mnu))
       << ";\n";
     if (orders >= 2)

@@ -447,6 +447,88 @@ def fig3(dims=(6, 9, 10), alphas=(3, 6), kmin: int = 10, kmax: int = 26, m: int 
     return {"m": m, "rows": rows}
 
 
+TRANSFORM_CHOICES = [("baker", 0)] + [("korobov", a) for a in range(1, 7)] + [("sidi", m_) for m_ in range(1, 7)]
+
+
+def choose_transform(params, d: int, n: int, m: int = 16, seed: int = synth.SEED_BASE + 8,
+                     choices=None, gv=None) -> dict:
+    """Automatic transform choice (the paper's Fig. 3 observation that the
+    best periodisation depends on d and n): integrate the same lattice and
+    shifts under every candidate transform and keep the smallest estimated
+    error sqrt(err_re^2 + err_im^2); kernel times are reported beside it."""
+    choices = TRANSFORM_CHOICES if choices is None else choices
+    gv = gv or GeneratingVectors(seed)
+    g = gv(n, d)
+    sh = synth.shifts(seed, m, d)
+    rows = []
+    for tk, alpha in choices:
+        plan = qmc.Plan(d, n, g, sh, tk, alpha)
+        plan.integrate(params)  # compile / warm up
+        plan.set_timing(True)
+        plan.kernel_time(reset=True)
+        res, _ = plan.integrate(params)
+        ms = plan.kernel_time()[0]
+        plan.close()
+        err = math.hypot(res.err_re, res.err_im)
+        rows.append({"transform": tk, "alpha": alpha, "mean_re": res.mean_re, "mean_im": res.mean_im,
+                     "err": err, "rel_err": err / max(abs(complex(res.mean_re, res.mean_im)), 1e-300),
+                     "kernel_ms": ms})
+    best = min(range(len(rows)), key=lambda i: (rows[i]["err"], i))
+    return {"d": d, "n": n, "m": m, "best": rows[best], "rows": rows}
+
+
+def transform_study(n_list=(65521, 1048573), log=None) -> dict:
+    """choose_transform on the real d = 6 sector (configuration 2's shape) and
+    the complex d = 10 sector (configuration 5's shape) at two lattice sizes."""
+    say = log or (lambda msg: None)
+    out = []
+    for label, d, n_u, n_f, cplx, seed in (("sector_real_d6", 6, 12, 30, False, synth.SEED_BASE + 2),
+                                           ("sector_complex_d10", 10, 20, 60, True, synth.SEED_BASE + 5)):
+        w = synth.sector_workload(n=n_list[0], m=16, d=d, n_u=n_u, n_f=n_f, seed=seed, complex_kinematics=cplx)
+        params = qmc.Params("sector", d, sector=w.sector)
+        for n in n_list:
+            r = choose_transform(params, d, n, m=16, seed=seed)
+            r["workload"] = label
+            say(f"  {label} n={n}: best {r['best']['transform']}{r['best']['alpha']} rel_err={r['best']['rel_err']:.3e}")
+            out.append(r)
+    return {"studies": out}
+
+
+def lattice_study(n: int = 1048573, d: int = 10, m: int = 32, seed: int = synth.SEED_BASE + 5, log=None) -> dict:
+    """Generating vectors for the complex d = 10 sector (configuration 5's
+    shape) at one n: the Korobov P2 search over 64 candidates against
+    component-by-component vectors with unit and with decaying (1/s^2)
+    weights.  For each: construction time, P2, and the relative error of the
+    sector (baker) and of the constant under Korobov weight 3 (Fig. 3's test)."""
+    say = log or (lambda msg: None)
+    w = synth.sector_workload(n=n, m=m, d=d, n_u=20, n_f=60, seed=seed, complex_kinematics=True)
+    params = qmc.Params("sector", d, sector=w.sector)
+    vecs = []
+    t = time.perf_counter()
+    a, p2k, _ = qmc.korobov_search(n, d, synth.korobov_candidates(seed, n, 64))
+    vecs.append(("korobov_p2_64", qmc.korobov_vector(n, d, a), time.perf_counter() - t, p2k))
+    for label, gam in (("cbc_unit", None), ("cbc_decay2", 1.0 / np.arange(1, d + 1) ** 2)):
+        _sync()
+        t = time.perf_counter()
+        z, e2 = qmc.cbc_search(n, d, gamma=gam)
+        vecs.append((label, z, time.perf_counter() - t, float(e2[-1])))
+    rows = []
+    for label, g, t_build, crit in vecs:
+        plan = qmc.Plan(d, n, g, w.shifts, "baker")
+        res, _ = plan.integrate(params)
+        plan.close()
+        plan = qmc.Plan(d, n, g, w.shifts, "korobov", 3)
+        one, _ = plan.integrate(qmc.Params("const", d, c=1.0))
+        plan.close()
+        row = {"vector": label, "g": [int(v) for v in g], "build_seconds": t_build, "criterion": crit,
+               "sector_rel_err": math.hypot(res.err_re, res.err_im) / abs(complex(res.mean_re, res.mean_im)),
+               "const_kor3_rel_err": one.err_re / abs(one.mean_re), "const_kor3_true_err": abs(one.mean_re - 1.0)}
+        rows.append(row)
+        say(f"  {label}: build {t_build:.3f} s, sector rel_err {row['sector_rel_err']:.3e}, "
+            f"constant (Korobov 3) rel_err {row['const_kor3_rel_err']:.3e}")
+    return {"n": n, "d": d, "m": m, "korobov_p2": p2k, "rows": rows}
+
+
 def deform(d: int = 6, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 7, n: int = 16777213,
            m: int = 32, n_pilot: int = 65521, lam_max: float = 0.8, shrink: float = 0.5, count: int = 8,
            reps: int = 5, log=None) -> dict:
@@ -506,7 +588,8 @@ def deform(d: int = 6, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
-                                     "cv_estimate", "fig3", "allocation_compare", "deform"])
+                                     "cv_estimate", "fig3", "allocation_compare", "deform", "transforms",
+                                     "lattices"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--shift-tile", type=int, default=0)
@@ -527,6 +610,10 @@ def main(argv=None):
         out = cv_estimate()
     elif args.what == "allocation_compare":
         out = allocation_compare(count=args.count or 2000)
+    elif args.what == "lattices":
+        out = lattice_study(log=lambda msg: print(msg, file=sys.stderr, flush=True))
+    elif args.what == "transforms":
+        out = transform_study(log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "deform":
         out = deform(log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "fig3":

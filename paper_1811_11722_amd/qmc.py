@@ -109,6 +109,10 @@ SIGNATURES = {
     "qmc_integrate_cv": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
     "qmc_integrate_orders": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "qmc_deform_check": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "qmc_cbc_search": (C.c_int, [C.c_uint64, C.c_uint32, _vp, _vp, C.c_uint32, _vp, _vp]),
+    "qmc_korobov_search_extensible": (C.c_int, [C.c_uint32, C.c_uint32, C.c_uint32, _vp, C.c_uint32, _vp, _vp,
+                                                _vp]),
+    "qmc_lattice_merge": (C.c_int, [C.c_uint32, C.c_uint32, _vp, _vp, _vp, _vp]),
     "qmc_deform_select": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_uint32, _vp, _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
@@ -417,3 +421,80 @@ def batch_per_shift(plans: Sequence[Plan], complex_parts: bool = False):
     if complex_parts:
         return [b[0::2] + 1j * b[1::2] for b in bufs]
     return bufs
+
+
+def cbc_search(n: int, d: int, gamma=None, cand=None):
+    """Component-by-component generating vector on the GPU: (z (d,) uint64,
+    e2 (d,) squared worst-case error after each component)."""
+    g = None if gamma is None else _arr(gamma, np.float64)
+    c = None if cand is None else _arr(cand, np.uint64)
+    z = np.zeros(d, dtype=np.uint64)
+    e2 = np.zeros(d)
+    check(lib().qmc_cbc_search(int(n), int(d), None if g is None else _p(g), None if c is None else _p(c),
+                               0 if c is None else c.size, _p(z), _p(e2)), "qmc_cbc_search")
+    return z, e2
+
+
+def korobov_search_extensible(kmin: int, kmax: int, d: int, cand):
+    """(a, mean log P2 over the rungs, P2 per rung) for odd candidates a."""
+    cand = _arr(cand, np.uint64)
+    a = C.c_uint64()
+    score = C.c_double()
+    p2 = np.zeros(kmax - kmin + 1)
+    check(lib().qmc_korobov_search_extensible(kmin, kmax, d, _p(cand), cand.size, C.byref(a), C.byref(score),
+                                              _p(p2)), "qmc_korobov_search_extensible")
+    return int(a.value), float(score.value), p2
+
+
+class ExtensibleLattice:
+    """Embedded rank-1 lattices of 2^k points, g = (1, a, a^2, ...) mod 2^kmax,
+    with fixed shifts.  ladder() integrates the rungs 2^kmin .. 2^kmax and
+    evaluates each lattice point once: rung k + 1 adds the 2^k-point lattice
+    with the shifts moved by (g mod 2^(k+1)) / 2^(k+1) and merges."""
+
+    def __init__(self, d: int, a: int, kmax: int, shifts, transform: str = "baker", alpha: int = 0):
+        if a % 2 == 0:
+            raise ValueError("a must be odd")
+        self.d, self.a, self.kmax = d, int(a), int(kmax)
+        self.shifts = _arr(shifts, np.float64).reshape(-1, d)
+        self.m = self.shifts.shape[0]
+        self.transform, self.alpha = transform, alpha
+        self.g = korobov_vector(1 << self.kmax, d, self.a)
+
+    def generator(self, k: int) -> np.ndarray:
+        return self.g % np.uint64(1 << k)
+
+    def moved_shifts(self, k: int) -> np.ndarray:
+        """Shifts that turn the 2^k-point lattice into the odd points of 2^(k+1)."""
+        n2 = 1 << (k + 1)
+        return np.mod(self.shifts + (self.g % np.uint64(n2)).astype(np.float64) / n2, 1.0)
+
+    def ladder(self, params: "Params", kmin: int, kmax: int = None, setup=None):
+        """[(n, result, per-shift)] for n = 2^kmin .. 2^kmax; setup(plan) may
+        set launch options on every plan."""
+        kmax = self.kmax if kmax is None else kmax
+        if not (1 <= kmin <= kmax <= self.kmax):
+            raise ValueError("need 1 <= kmin <= kmax <= kmax of the lattice")
+        np_ = 2 if params.is_complex else 1
+
+        def run(k, shifts):
+            plan = Plan(self.d, 1 << k, self.generator(k), shifts, self.transform, self.alpha)
+            if setup:
+                setup(plan)
+            res, q = plan.integrate(params)
+            plan.close()
+            flat = np.column_stack([q.real, q.imag]).ravel() if np_ == 2 else np.asarray(q, np.float64)
+            return res, np.ascontiguousarray(flat)
+
+        res, flat = run(kmin, self.shifts)
+        out = [(1 << kmin, res, flat)]
+        for k in range(kmin, kmax):
+            _, extra = run(k, self.moved_shifts(k))
+            merged = np.zeros_like(flat)
+            res = qmc_result()
+            check(lib().qmc_lattice_merge(self.m, np_, _p(flat), _p(extra), _p(merged), C.byref(res)),
+                  "qmc_lattice_merge")
+            flat = merged
+            out.append((1 << (k + 1), res, flat))
+        return [(n, r, (f[0::2] + 1j * f[1::2]) if np_ == 2 else f) for n, r, f in out]
+
