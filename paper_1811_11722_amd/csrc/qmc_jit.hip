@@ -15,6 +15,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -234,8 +235,8 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
 // and recurse on P1 (exponents of v lowered) and P0.  Each split costs one
 // FMA (one multiply when P0 is empty), so a polynomial of T terms takes
 // about T operations instead of one multiply per product-trie edge plus one
-// FMA per term.  Emits the temporaries into s and returns the expression of
-// the value.
+// FMA per term.  Emits the temporaries (arrays over the thread's shifts k)
+// into s and returns the expression of the value for shift k.
 using HornerTerms = std::vector<std::pair<int, std::vector<int>>>;
 static std::string horner(const char *coef, HornerTerms terms, std::ostringstream &s, int &tmp) {
     HornerTerms consts;
@@ -268,11 +269,57 @@ static std::string horner(const char *coef, HornerTerms terms, std::ostringstrea
     }
     const std::string a = horner(coef, p1, s, tmp);
     const std::string b = p0.empty() ? std::string() : horner(coef, p0, s, tmp);
+    // one statement per line over the T shifts of the thread, so that a
+    // coefficient is loaded once for all of them
     const std::string name = "h" + std::to_string(tmp++);
-    s << "            const double " << name << " = ";
+    s << "        double " << name << "[T]; _Pragma(\"unroll\") for (int k = 0; k < T; ++k) " << name << "[k] = ";
     if (b.empty()) s << a << " * z[k][" << v << "];\n";
     else s << "fma_(" << a << ", z[k][" << v << "], " << b << ");\n";
-    return name;
+    return name + "[k]";
+}
+
+// Each coefficient of the Horner code is read once, in ascending order (the
+// host stores the terms that way).  Left alone, the compiler issues all the
+// scalar loads up front and spills the values it cannot keep in scalar
+// registers (a large polynomial needs more than the 106 available).  A fresh
+// laundered copy of the table pointer every kChunk coefficients, placed just
+// before the first line that reads the chunk, keeps each chunk's loads after
+// that point (volatile asm statements keep their order), so only a few
+// chunks are live at a time.
+static std::string launder_chunks(const std::string &text) {
+    constexpr uint32_t kChunk = 8;
+    std::istringstream in(text);
+    std::ostringstream out;
+    std::string line;
+    int next[2] = {0, 0};  // next chunk start for cu, cf
+    int ptr = 0;
+    while (std::getline(in, line)) {
+        std::string fixed;
+        std::string pre;
+        for (size_t i = 0; i < line.size();) {
+            const bool is_u = line.compare(i, 3, "cu[") == 0, is_f = line.compare(i, 3, "cf[") == 0;
+            if ((!is_u && !is_f) || (i > 0 && (std::isalnum((unsigned char)line[i - 1]) || line[i - 1] == '_'))) {
+                fixed += line[i++];
+                continue;
+            }
+            size_t j = i + 3;
+            int v = 0;
+            while (j < line.size() && std::isdigit((unsigned char)line[j])) v = 10 * v + (line[j++] - '0');
+            const int w = is_u ? 0 : 1;
+            const char *base = is_u ? "cu" : "cf";
+            if (v >= next[w]) {
+                ++ptr;
+                pre += std::string("            const __attribute__((address_space(4))) double *q") +
+                       std::to_string(ptr) + " = " + base + ";\n            asm volatile(\"\" : \"+s\"(q" +
+                       std::to_string(ptr) + "));\n";
+                next[w] = (v / kChunk + 1) * kChunk;
+            }
+            fixed += "q" + std::to_string(ptr) + "[" + std::to_string(v) + "]";
+            i = j + 1;  // skip ']'
+        }
+        out << pre << fixed << "\n";
+    }
+    return out.str();
 }
 
 // The order in which the Horner form above first reads each coefficient.
@@ -372,33 +419,39 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
       << "        asm volatile(\"\" : \"+s\"(cp));\n"
       << "        const double pow_u = cp[3], pow_f = cp[4], delta = cp[5];\n"
       << "        const __attribute__((address_space(4))) double *cu = cp + kSectorHeader;\n"
-      << "        const __attribute__((address_space(4))) double *cf = cu + " << 2 * nu << ";\n"
-      << "#pragma unroll\n"
-      << "        for (int k = 0; k < T; ++k) {\n";
+      << "        const __attribute__((address_space(4))) double *cf = cu + " << 2 * nu << ";\n";
     auto ref = [&](int id) {
         std::ostringstream r;
         if (trie.node[id].first < 0) r << "z[k][" << trie.node[id].second << "]";
-        else r << "m" << id;
+        else r << "m" << id << "[k]";
         return r.str();
     };
     for (size_t id = 0; id < trie.node.size(); ++id) {
         const auto &nd = trie.node[id];
         if (nd.first < 0) continue;
-        s << "            const double m" << id << " = " << ref(nd.first) << " * z[k][" << nd.second << "];\n";
+        s << "        double m" << id << "[T]; _Pragma(\"unroll\") for (int k = 0; k < T; ++k) m" << id
+          << "[k] = " << ref(nd.first) << " * z[k][" << nd.second << "];\n";
     }
     int tmp = 0;
-    const std::string ue = horner("cu", hu, s, tmp);
-    s << "            const double U = " << ue << ";\n";
-    const std::string fe = horner("cf", hf, s, tmp);
-    s << "            const double F = " << fe << ";\n";
-    s << "            const double mono = " << (mnu < 0 ? std::string("jac[k]") : "jac[k] * " + ref(mnu))
+    {
+        std::ostringstream hs;
+        const std::string ue = horner("cu", hu, hs, tmp);
+        hs << "        double U[T]; _Pragma(\"unroll\") for (int k = 0; k < T; ++k) U[k] = " << ue << ";\n";
+        const std::string fe = horner("cf", hf, hs, tmp);
+        hs << "        double F[T]; _Pragma(\"unroll\") for (int k = 0; k < T; ++k) F[k] = " << fe << ";\n";
+        s << launder_chunks(hs.str());
+    }
+    s << "#pragma unroll\n"
+      << "        for (int k = 0; k < T; ++k) {\n"
+      << "            const double mono = " << (mnu < 0 ? std::string("jac[k]") : "jac[k] * " + ref(mnu))
       << ";\n";
     if (orders >= 2)
         s << "            sector_orders<" << (cplx ? "true" : "false") << ", " << orders
-          << ">(mono, U, F, flags, pow_u, pow_f, delta, cp[" << eps_at << "], cp[" << eps_at + 1 << "], v[k]);\n";
+          << ">(mono, U[k], F[k], flags, pow_u, pow_f, delta, cp[" << eps_at << "], cp[" << eps_at + 1
+          << "], v[k]);\n";
     else
         s << "            sector_finish<" << (cplx ? "true" : "false")
-          << ">(mono, U, F, flags, pow_u, pow_f, delta, v[k]);\n";
+          << ">(mono, U[k], F[k], flags, pow_u, pow_f, delta, v[k]);\n";
     s << "        }\n    }\n};\n";
     return s.str();
 }
