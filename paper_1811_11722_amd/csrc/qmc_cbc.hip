@@ -130,6 +130,10 @@ extern "C" qmc_status qmc_cbc_search(uint64_t n, uint32_t d, const double *gamma
         std::sort(cs.begin(), cs.end());
         cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
     } else {
+        // every unit up to n/2: bound the work before enumerating them
+        if ((double)(n / 2) * (double)n > 17592186044416.0)
+            return fail(QMC_EUNSUPPORTED, "n/2 candidates x n = %.3g > 2^44: pass a candidate subset",
+                        (double)(n / 2) * (double)n);
         for (uint64_t c = 1; c <= n / 2; ++c)
             if (gcd_u64(c, n) == 1) cs.push_back((uint32_t)c);
         if (cs.empty()) cs.push_back(1u);

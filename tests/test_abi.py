@@ -103,3 +103,38 @@ def test_null_plan_and_status_strings(Q):
     for s in range(6):
         assert L.qmc_status_string(s)
     assert L.qmc_status_string(99) == b"unknown status"
+
+
+def test_construction_and_merge_validation(Q):
+    """The lattice-construction entry points reject bad arguments before any
+    device work."""
+    L = Q.lib()
+    z = np.zeros(4, dtype=np.uint64)
+    e2 = np.zeros(4)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    assert L.qmc_cbc_search(1021, 0, None, None, 0, p(z), p(e2)) == Q.QMC_EINVAL        # d = 0
+    assert L.qmc_cbc_search(1021, 17, None, None, 0, p(z), p(e2)) == Q.QMC_EUNSUPPORTED  # d > 16
+    assert L.qmc_cbc_search(1, 2, None, None, 0, p(z), p(e2)) == Q.QMC_EINVAL           # n < 2
+    assert L.qmc_cbc_search(2 ** 31 + 1, 2, None, None, 0, p(z), p(e2)) == Q.QMC_EUNSUPPORTED
+    bad_g = np.array([1.0, -1.0])
+    assert L.qmc_cbc_search(1021, 2, p(bad_g), None, 0, p(z), p(e2)) == Q.QMC_EINVAL    # gamma < 0
+    cand = np.array([4, 8], dtype=np.uint64)
+    assert L.qmc_cbc_search(1024, 2, None, p(cand), 2, p(z), p(e2)) == Q.QMC_EINVAL     # not units
+    assert L.qmc_cbc_search(1021, 2, None, None, 0, None, p(e2)) == Q.QMC_EINVAL        # null output
+    assert L.qmc_cbc_search(2 ** 31 - 1, 2, None, None, 0, p(z), p(e2)) == Q.QMC_EUNSUPPORTED  # too much work
+    a, sc = C.c_uint64(), C.c_double()
+    odd = np.array([3, 5], dtype=np.uint64)
+    assert L.qmc_korobov_search_extensible(0, 4, 2, p(odd), 2, C.byref(a), C.byref(sc), None) == Q.QMC_EINVAL
+    assert L.qmc_korobov_search_extensible(5, 4, 2, p(odd), 2, C.byref(a), C.byref(sc), None) == Q.QMC_EINVAL
+    assert L.qmc_korobov_search_extensible(4, 32, 2, p(odd), 2, C.byref(a), C.byref(sc), None) == Q.QMC_EUNSUPPORTED
+    assert L.qmc_korobov_search_extensible(4, 8, 2, p(cand), 2, C.byref(a), C.byref(sc), None) == Q.QMC_EINVAL
+    q = np.zeros(4)
+    res = Q.qmc_result()
+    assert L.qmc_lattice_merge(2, 3, p(q), p(q), p(q), C.byref(res)) == Q.QMC_EINVAL
+    assert L.qmc_lattice_merge(2, 1, None, p(q), p(q), C.byref(res)) == Q.QMC_EINVAL
+    nanq = np.array([np.nan, 1.0])
+    assert L.qmc_lattice_merge(2, 1, p(nanq), p(nanq), p(q[:2].copy()), C.byref(res)) == Q.QMC_ENONFINITE
+    lam, r = C.c_double(), Q.qmc_result()
+    assert L.qmc_deform_select(None, None, 1.0, 0.5, 4, C.byref(lam), C.byref(r)) == Q.QMC_EINVAL
+    frac = C.c_double()
+    assert L.qmc_deform_check(None, None, C.byref(frac), None) == Q.QMC_EINVAL
