@@ -104,12 +104,12 @@ def test_deform_euclidean_matches_oracle_and_cauchy(Q, lam, tk, alpha):
     assert abs(res.mean_im) < 6 * res.err_im
 
 
-@pytest.mark.parametrize("d,n_u,n_f", [(3, 5, 9), (6, 12, 30), (10, 20, 60)])
+@pytest.mark.parametrize("d,n_u,n_f", [(3, 5, 9), (6, 12, 30), (10, 20, 60), (16, 16, 40)])
 @pytest.mark.parametrize("launch", [None, (2, 0)])
 def test_deform_mixed_sign_kinematics(Q, d, n_u, n_f, launch):
     """Mixed-sign F (it vanishes inside the cube) at delta = 0: only the
     deformation makes the integrand finite."""
-    n, m, lam = 16381, 6, 0.5
+    n, m, lam = (16381, 6, 0.5) if d <= 10 else (4093, 4, 0.5)
     tab = synth.sector_tables(400 + d, d, n_u, n_f, complex_kinematics=True)
     tab = dataclasses.replace(tab, delta_im=0.0, is_complex=True)
     ab, _, _ = O.korobov_search(n, d, synth.korobov_candidates(400 + d, n, 8), threads=THREADS)
