@@ -15,6 +15,14 @@
  *   eq. (5):  baker's transform z(x) = 1 - |2x - 1|
  *   Sidi's sin^m transform, z(x) = int_0^x sin^m(pi u) du / int_0^1 sin^m
  *             (one of the other periodising substitutions Sec. 2 refers to)
+ *   Sec. 3:   contour deformation of a sector, z = x - i lambda x (1 - x) grad F,
+ *             integrand f(z) det(dz/dx) (determinant by LU with partial
+ *             pivoting), and the sign-check indicator of Im(F(z) - i delta) > 0
+ *   generating vectors: P2 of a rank-1 lattice, the Korobov search and the
+ *             component-by-component construction for product weights
+ *
+ * Pins (tests/test_oracle_pins.py) tie every function to closed forms,
+ * quadrature, brute force or identities; none is unpinned.
  *   fhat(x) = f(z(x)) * prod_i z_i'(x_i)   (substitution x -> z(x), Sec. 2)
  *
  * Readings taken where the paper is silent (each also listed in the design
