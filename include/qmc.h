@@ -231,7 +231,15 @@ qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint
 typedef enum {
     QMC_BATCH_DEFAULT = 0,    /* one workgroup per tile */
     QMC_BATCH_PERSISTENT = 1, /* CUs x 8 workgroups loop over the work list */
-    QMC_BATCH_PER_TILE = 2    /* one workgroup per tile */
+    QMC_BATCH_PER_TILE = 2,   /* one workgroup per tile */
+    /* sectors only: one launch per plan of the run-time specialised sector
+       kernel, on one stream, without a graph.  Each distinct exponent
+       structure is compiled once per process (hipRTC, about 0.1-0.2 s) and
+       reused for every later call and coefficient set with that structure, so
+       this pays when the same sectors are integrated repeatedly (new
+       kinematics, new shifts); EUNSUPPORTED when a specialised kernel cannot
+       be built. */
+    QMC_BATCH_SPECIALISED = 3
 } qmc_batch_schedule;
 
 typedef struct {

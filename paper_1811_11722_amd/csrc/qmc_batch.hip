@@ -371,6 +371,30 @@ void plan_release_extra(qmc_plan_s *p) {
     p->extra = nullptr;
 }
 
+// One launch per plan of its run-time specialised sector kernel (each plan's
+// own stream and buffers), then one synchronisation per plan's stream.
+static qmc_status batch_specialised(uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk,
+                                    qmc_result *out) {
+    qmc_status first_bad = QMC_OK;
+    for (uint32_t i = 0; i < count; ++i) {
+        qmc_plan_s *p = plans[i];
+        const int32_t jit = p->jit_mode;
+        p->jit_mode = 2;  // specialised kernel or an error
+        qmc_status st = plan_enqueue(p, pk[i], p->launch.shift_tile, p->launch.blocks_per_cu);
+        p->jit_mode = jit;
+        if (st) return st;
+    }
+    for (uint32_t i = 0; i < count; ++i) {
+        qmc_status st = plan_collect(plans[i], pk[i].np, &out[i], nullptr);
+        if (st == QMC_ENONFINITE) {
+            if (!first_bad) first_bad = st;
+        } else if (st) {
+            return st;
+        }
+    }
+    return first_bad;
+}
+
 }  // namespace qmc
 
 using namespace qmc;
@@ -384,8 +408,11 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
     const qmc_batch_opts o = opts ? *opts : qmc_batch_opts{1, 0, 0, QMC_BATCH_DEFAULT};
     uint32_t tile_points = o.tile_points ? o.tile_points : 8192;
     if (tile_points % kBlock) return fail(QMC_EINVAL, "tile_points must be a multiple of %d", kBlock);
-    if (o.schedule < QMC_BATCH_DEFAULT || o.schedule > QMC_BATCH_PER_TILE)
+    if (o.schedule < QMC_BATCH_DEFAULT || o.schedule > QMC_BATCH_SPECIALISED)
         return fail(QMC_EINVAL, "unknown schedule %d", o.schedule);
+    const bool specialised = o.schedule == QMC_BATCH_SPECIALISED;
+    if (specialised && family != QMC_F_SECTOR)
+        return fail(QMC_EUNSUPPORTED, "the specialised schedule is built for QMC_F_SECTOR");
     const int persistent = o.schedule == QMC_BATCH_PERSISTENT;
     std::vector<Packed> pk(count);
     for (uint32_t i = 0; i < count; ++i) {
@@ -400,6 +427,8 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
         if (pk[i].deform) return fail(QMC_EUNSUPPORTED, "batches take undeformed sectors (deform_lambda = 0)");
         if (plans[i]->m * pk[i].np > kMaxRows) return fail(QMC_EUNSUPPORTED, "m * parts > %u", kMaxRows);
     }
+
+    if (specialised) return batch_specialised(count, plans, pk, out);
 
     std::lock_guard<std::mutex> lock(g_batch_mu);
     BatchCtx *c = nullptr;

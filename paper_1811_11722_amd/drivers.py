@@ -182,6 +182,47 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
     return out
 
 
+def sector_batch_specialised(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int = synth.SEED_BASE + 3,
+                             tile_points: int = 8192, reps: int = 3, log=None) -> dict:
+    """Configuration 3 with the run-time specialised sector kernels: the same
+    pilots, lattice sizes and shifts as sector_batch; every distinct exponent
+    structure is compiled once (timed separately, with progress lines), then
+    the batch runs as one launch per sector of its specialised kernel, against
+    the graph-replayed table-driven batch."""
+    say = log or (lambda msg: None)
+    tabs = synth.sector_batch(seed, count)
+    gv = GeneratingVectors(seed)
+    n0 = LADDER[0]
+    params = [qmc.Params("sector", t.d, sector=t) for t in tabs]
+    pilots = [qmc.Plan(t.d, n0, gv(n0, t.d), synth.shifts(seed, m, t.d, stream=16 + s, sub=3),
+                       "baker") for s, t in enumerate(tabs)]
+    pres = qmc.integrate_batch(pilots, params, tile_points=tile_points)
+    ns = [allocate_n(abs(r.err_re) / abs(r.mean_re), n0, goal) for r in pres]
+    # compile every structure on the small pilot lattices, reporting progress
+    t0 = time.perf_counter()
+    for i, (pl, pa) in enumerate(zip(pilots, params)):
+        pl.integrate(pa)
+        if (i + 1) % 100 == 0:
+            say(f"  compiled {i + 1}/{count} sector kernels, {time.perf_counter() - t0:.1f} s")
+    t_compile = time.perf_counter() - t0
+    for p in pilots:
+        p.close()
+    plans = [qmc.Plan(t.d, n, gv(n, t.d), synth.sector_batch_shifts(seed, s, m, t.d), "baker")
+             for s, (t, n) in enumerate(zip(tabs, ns))]
+    evals = int(sum(n * m for n in ns))
+    res_sp, t_sp = _timed(lambda: qmc.integrate_batch(plans, params, schedule="specialised"), reps)
+    say(f"  specialised batch {t_sp:.3f} s")
+    res_g, t_g = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True, tile_points=tile_points), reps)
+    say(f"  table-driven graph batch {t_g:.3f} s")
+    for p in plans:
+        p.close()
+    return {"sectors": count, "m": m, "goal": goal, "evals": evals, "compile_seconds": t_compile,
+            "specialised_seconds": t_sp, "specialised_evals_per_s": evals / t_sp,
+            "graph_seconds": t_g, "graph_evals_per_s": evals / t_g,
+            "max_rel_diff_specialised_vs_graph": float(max(
+                abs(a.mean_re - b.mean_re) / abs(b.mean_re) for a, b in zip(res_sp, res_g)))}
+
+
 def allocation_compare(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int = synth.SEED_BASE + 3,
                        tile_points: int = 8192, reps: int = 2) -> dict:
     """The per-sector error-goal rule against the total-error allocation on
@@ -589,7 +630,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
                                      "cv_estimate", "fig3", "allocation_compare", "deform", "transforms",
-                                     "lattices"])
+                                     "lattices", "sector_batch_specialised"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--shift-tile", type=int, default=0)
@@ -610,6 +651,9 @@ def main(argv=None):
         out = cv_estimate()
     elif args.what == "allocation_compare":
         out = allocation_compare(count=args.count or 2000)
+    elif args.what == "sector_batch_specialised":
+        out = sector_batch_specialised(count=args.count or 2000,
+                                       log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "lattices":
         out = lattice_study(log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "transforms":

@@ -83,7 +83,7 @@ class qmc_batch_opts(C.Structure):
                 ("tile_points", C.c_uint32), ("schedule", C.c_int32)]
 
 
-BATCH_SCHEDULE = {"default": 0, "persistent": 1, "per_tile": 2}
+BATCH_SCHEDULE = {"default": 0, "persistent": 1, "per_tile": 2, "specialised": 3}
 
 
 # every symbol include/qmc.h declares, with its ctypes signature
@@ -400,8 +400,10 @@ def korobov_search(n: int, d: int, cand):
 
 def integrate_batch(plans: Sequence[Plan], params: Sequence[Params], use_graph: bool = True,
                     per_plan_launches: bool = False, tile_points: int = 0, schedule: str = "default"):
-    """schedule: "default", "persistent" (workgroups loop over the work list)
-    or "per_tile" (one workgroup per tile)."""
+    """schedule: "default", "persistent" (workgroups loop over the work list),
+    "per_tile" (one workgroup per tile) or "specialised" (sectors: one launch
+    per plan of its run-time specialised kernel, compiled once per exponent
+    structure)."""
     fam = params[0].family
     handles = (C.c_void_p * len(plans))(*[p.handle for p in plans])
     pp = (C.c_void_p * len(params))(*[p.ptr for p in params])

@@ -179,3 +179,35 @@ def test_autotune(Q, tmp_path, monkeypatch):
     est2 = O.estimate(ws.n, gs, ws.shifts, O.Params("sector", ws.d, sector=ws.sector), "baker",
                       threads=THREADS)
     assert np.all(_rel(q2, est2.q_re) < TOL)
+
+
+def test_batch_specialised_schedule_matches_default(Q):
+    """The specialised schedule (one launch per sector of its run-time
+    specialised kernel) against the table-driven batch and the oracle."""
+    from oracle import oracle as O
+    from paper_1811_11722_amd import synth
+    tabs = synth.sector_batch(synth.SEED_BASE + 3, 12)
+    plans, params, lat = [], [], []
+    for s, t in enumerate(tabs):
+        n = 4093 if s % 2 else 16381
+        g = O.korobov_vector(n, t.d, 17364 % n)
+        sh = synth.sector_batch_shifts(synth.SEED_BASE + 3, s, 4, t.d)
+        plans.append(Q.Plan(t.d, n, g, sh, "baker"))
+        params.append(Q.Params("sector", t.d, sector=t))
+        lat.append((n, g, sh))
+    print("[gpu-case] batch specialised", flush=True)
+    sp = Q.integrate_batch(plans, params, schedule="specialised")
+    df = Q.integrate_batch(plans, params, use_graph=False, tile_points=8192)
+    for a, b in zip(sp, df):
+        assert abs(a.mean_re - b.mean_re) <= 1e-12 * abs(b.mean_re)
+        assert abs(a.err_re - b.err_re) <= 1e-9 * abs(b.err_re) + 1e-18
+    t, (n, g, sh) = tabs[3], lat[3]
+    est = O.estimate(n, g, sh, O.Params("sector", t.d, sector=t), "baker")
+    mean, _, _ = est.mean_error()
+    assert abs(sp[3].mean_re - mean.real) <= 1e-12 * abs(mean.real)
+    with pytest.raises(Q.QMCError) as e:
+        Q.integrate_batch(plans[:1], [Q.Params("genz_gaussian", plans[0].d, a=np.ones(plans[0].d),
+                                               u=np.full(plans[0].d, 0.5))], schedule="specialised")
+    assert e.value.status == Q.QMC_EUNSUPPORTED
+    for p in plans:
+        p.close()
