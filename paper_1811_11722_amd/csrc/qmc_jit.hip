@@ -15,12 +15,17 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cctype>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <iterator>
 #include <mutex>
 #include <sstream>
+
+#include <unistd.h>
 
 #include "qmc_jit_headers.inc"
 #include "qmc_runtime.hpp"
@@ -465,6 +470,63 @@ static std::string device_arch(int dev) {
 
 // Compile (or fetch from the process cache) `src`, returning the function
 // named by name_expr; nullptr and `err` on failure.
+// Optional on-disk store of compiled code objects (directory in QMC_JIT_CACHE):
+// one file per (architecture, kernel name expression, source), holding the
+// lowered kernel name and the code object, so that other processes (or a
+// later run) load the kernel instead of compiling it again.
+static uint64_t fnv1a(const std::string &s) {
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static std::string disk_path(const std::string &arch, const std::string &name_expr, const std::string &src) {
+    const char *dir = std::getenv("QMC_JIT_CACHE");
+    if (!dir || !*dir) return std::string();
+    // the embedded headers are part of what the code depends on
+    static const uint64_t headers = [] {
+        std::string all;
+        for (int i = 0; i < kJitHeaderCount; ++i) all += kJitHeaderText[i];
+        return fnv1a(all);
+    }();
+    char buf[48];
+    std::snprintf(buf, sizeof buf, "%016llx_%016llx", (unsigned long long)headers,
+                  (unsigned long long)fnv1a(arch + "\n" + name_expr + "\n" + src));
+    return std::string(dir) + "/qmc_" + buf + ".co";
+}
+
+// file: u32 length of the lowered name, the name, then the code object
+static bool disk_load(const std::string &path, std::string &lowered, std::vector<char> &code) {
+    if (path.empty()) return false;
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return false;
+    uint32_t len = 0;
+    if (!f.read(reinterpret_cast<char *>(&len), 4) || len == 0 || len > 4096) return false;
+    lowered.resize(len);
+    if (!f.read(&lowered[0], len)) return false;
+    code.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+    return !code.empty();
+}
+
+static void disk_store(const std::string &path, const std::string &lowered, const std::vector<char> &code) {
+    if (path.empty()) return;
+    static std::atomic<unsigned> counter{0};
+    const std::string tmp = path + ".tmp." + std::to_string((long)getpid()) + "." + std::to_string(counter++);
+    {
+        std::ofstream f(tmp, std::ios::binary);
+        if (!f) return;
+        const uint32_t len = (uint32_t)lowered.size();
+        f.write(reinterpret_cast<const char *>(&len), 4);
+        f.write(lowered.data(), len);
+        f.write(code.data(), (std::streamsize)code.size());
+        if (!f) return;
+    }
+    std::rename(tmp.c_str(), path.c_str());  // atomic within one file system
+}
+
 static hipFunction_t compile_cached(const std::string &src, const std::string &name_expr, const std::string &key,
                                     int dev, std::string &err) {
     if (const char *dump = std::getenv("QMC_JIT_DUMP")) {  // write the generated source for inspection
@@ -481,11 +543,29 @@ static hipFunction_t compile_cached(const std::string &src, const std::string &n
     // compile without holding the lock, so that several threads can compile
     // different programs at once; the first result stored for a key wins
     JitEntry e;
+    const std::string arch = "--offload-arch=" + device_arch(dev);
+    const std::string path = disk_path(arch, name_expr, src);
+    {
+        std::string low;
+        std::vector<char> code;
+        if (disk_load(path, low, code)) {
+            hipError_t he = hipModuleLoadData(&e.mod, code.data());
+            if (he == hipSuccess) he = hipModuleGetFunction(&e.fn, e.mod, low.c_str());
+            if (he == hipSuccess) {
+                std::lock_guard<std::mutex> lock(g_jit_mu);
+                auto ins = g_jit_cache.emplace(key, e);
+                if (!ins.second) (void)hipModuleUnload(e.mod);
+                err = ins.first->second.error;
+                return ins.first->second.fn;
+            }
+            if (e.mod) (void)hipModuleUnload(e.mod);  // unreadable entry: compile instead
+            e = JitEntry{};
+        }
+    }
     hiprtcProgram prog = nullptr;
     hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "qmc_sector_jit.hip", kJitHeaderCount, kJitHeaderText,
                                          kJitHeaderName);
     if (r == HIPRTC_SUCCESS) r = hiprtcAddNameExpression(prog, name_expr.c_str());
-    const std::string arch = "--offload-arch=" + device_arch(dev);
     const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
                           "-Xclang", "-packed-fp32-ops"};
     if (r == HIPRTC_SUCCESS) r = hiprtcCompileProgram(prog, 8, opts);
@@ -513,6 +593,8 @@ static hipFunction_t compile_cached(const std::string &src, const std::string &n
             if (he != hipSuccess) {
                 e.error = std::string("module load: ") + hipGetErrorString(he);
                 e.fn = nullptr;
+            } else {
+                disk_store(path, low, code);
             }
         }
     }

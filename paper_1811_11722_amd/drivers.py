@@ -19,6 +19,7 @@ import argparse
 import dataclasses
 import json
 import math
+import os
 import sys
 import time
 from typing import Dict, List, Tuple
@@ -182,14 +183,49 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
     return out
 
 
+def _precompile_worker(args):
+    """Compile the specialised kernels of a slice of sectors by integrating
+    each once on a tiny lattice (the compiled code objects land in the
+    on-disk code-object cache of the ROCm compiler, shared with the parent)."""
+    seed, count, first, step, transform = args
+    tabs = synth.sector_batch(seed, count)
+    for s in range(first, count, step):
+        t = tabs[s]
+        plan = qmc.Plan(t.d, 1021, qmc.korobov_vector(1021, t.d, 76), np.full((2, t.d), 0.5), transform)
+        plan.integrate(qmc.Params("sector", t.d, sector=t))
+        plan.close()
+    return (count - first + step - 1) // step
+
+
+def precompile(seed: int, count: int, workers: int = 8, transform: str = "baker", log=None) -> float:
+    """Compile the 2000 sectors' specialised kernels in `workers` processes
+    (hipRTC serialises compiles inside one process); returns the wall time."""
+    import multiprocessing as mp
+    say = log or (lambda msg: None)
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        done = 0
+        for k in pool.imap_unordered(_precompile_worker, [(seed, count, w, workers, transform)
+                                                          for w in range(workers)]):
+            done += k
+            say(f"  precompiled {done}/{count} sector kernels, {time.perf_counter() - t0:.1f} s")
+    return time.perf_counter() - t0
+
+
 def sector_batch_specialised(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int = synth.SEED_BASE + 3,
-                             tile_points: int = 8192, reps: int = 3, log=None) -> dict:
+                             tile_points: int = 8192, reps: int = 3, workers: int = 0, log=None) -> dict:
     """Configuration 3 with the run-time specialised sector kernels: the same
     pilots, lattice sizes and shifts as sector_batch; every distinct exponent
     structure is compiled once (timed separately, with progress lines), then
     the batch runs as one launch per sector of its specialised kernel, against
     the graph-replayed table-driven batch."""
     say = log or (lambda msg: None)
+    if workers > 1 and not os.environ.get("QMC_JIT_CACHE"):
+        import tempfile
+        # compiled code objects shared between the compile processes and this one
+        os.environ["QMC_JIT_CACHE"] = tempfile.mkdtemp(prefix="qmc_jit_")
+    t_pre = precompile(seed, count, workers, log=log) if workers > 1 else 0.0
     tabs = synth.sector_batch(seed, count)
     gv = GeneratingVectors(seed)
     n0 = LADDER[0]
@@ -216,7 +252,8 @@ def sector_batch_specialised(count: int = 2000, m: int = 16, goal: float = 1e-8,
     say(f"  table-driven graph batch {t_g:.3f} s")
     for p in plans:
         p.close()
-    return {"sectors": count, "m": m, "goal": goal, "evals": evals, "compile_seconds": t_compile,
+    return {"sectors": count, "m": m, "goal": goal, "evals": evals, "precompile_workers": workers,
+            "precompile_seconds": t_pre, "compile_seconds": t_compile,
             "specialised_seconds": t_sp, "specialised_evals_per_s": evals / t_sp,
             "graph_seconds": t_g, "graph_evals_per_s": evals / t_g,
             "max_rel_diff_specialised_vs_graph": float(max(
@@ -638,6 +675,7 @@ def main(argv=None):
     ap.add_argument("--count", type=int, default=0)
     ap.add_argument("--tile-points", type=int, default=-1)
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--workers", type=int, default=0, help="compile processes (sector_batch_specialised)")
     args = ap.parse_args(argv)
     if args.what == "sector_batch":
         out = sector_batch(count=args.count or 2000,
@@ -652,7 +690,7 @@ def main(argv=None):
     elif args.what == "allocation_compare":
         out = allocation_compare(count=args.count or 2000)
     elif args.what == "sector_batch_specialised":
-        out = sector_batch_specialised(count=args.count or 2000,
+        out = sector_batch_specialised(count=args.count or 2000, workers=args.workers,
                                        log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "lattices":
         out = lattice_study(log=lambda msg: print(msg, file=sys.stderr, flush=True))

@@ -211,3 +211,40 @@ def test_batch_specialised_schedule_matches_default(Q):
     assert e.value.status == Q.QMC_EUNSUPPORTED
     for p in plans:
         p.close()
+
+
+def test_jit_code_object_store(Q, tmp_path):
+    """With QMC_JIT_CACHE set, a compiled sector kernel is written to disk and
+    a second process loads it: same per-shift sums, bit for bit."""
+    import json
+    import subprocess
+    from paper_1811_11722_amd import synth
+    os.environ["QMC_JIT_CACHE"] = str(tmp_path)
+    try:
+        tab = synth.sector_tables(4242, 5, 9, 17)
+        g = O.korobov_vector(4093, 5, 1234)
+        sh = synth.shifts(4242, 4, 5)
+        plan = Q.Plan(5, 4093, g, sh, "korobov", 2)
+        print("[gpu-case] jit store parent", flush=True)
+        _, q = plan.integrate(Q.Params("sector", 5, sector=tab))
+        plan.close()
+        files = [f for f in os.listdir(tmp_path) if f.endswith(".co")]
+        assert files, "no code object written"
+        code = (
+            "import json, numpy as np\n"
+            "from oracle import oracle as O\n"
+            "from paper_1811_11722_amd import qmc, synth\n"
+            "tab = synth.sector_tables(4242, 5, 9, 17)\n"
+            "plan = qmc.Plan(5, 4093, O.korobov_vector(4093, 5, 1234), synth.shifts(4242, 4, 5), 'korobov', 2)\n"
+            "_, q = plan.integrate(qmc.Params('sector', 5, sector=tab))\n"
+            "print(json.dumps([float(v) for v in q]))\n")
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        print("[gpu-case] jit store child", flush=True)
+        out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120,
+                             env=dict(os.environ))
+        assert out.returncode == 0, out.stderr[-2000:]
+        q2 = np.array(json.loads(out.stdout.strip().splitlines()[-1]))
+        assert np.array_equal(q2, q)
+        assert sorted(files) == sorted(f for f in os.listdir(tmp_path) if f.endswith(".co"))
+    finally:
+        del os.environ["QMC_JIT_CACHE"]
