@@ -168,10 +168,13 @@ qmc_status qmc_plan_set_launch(qmc_plan_t plan, const qmc_launch *cfg);
 
 /* How sector integrands are evaluated: 0 = interpret the sparse polynomial
    tables in the kernel; 1 (default) = compile a kernel specialised to the
-   exponent structure on first use (hipRTC; about a second, cached per
-   structure for the process) and fall back to the tables if compilation
-   fails; 2 = always specialise and return EUNSUPPORTED if that fails.
-   Results agree to rounding either way. */
+   exponent structure on first use (hipRTC; 0.1-1 s, cached per structure
+   for the process) and fall back to the tables if compilation fails; 2 =
+   always specialise and return EUNSUPPORTED if that fails.  Results agree
+   to rounding either way.  With the environment variable QMC_JIT_CACHE
+   naming a directory, compiled kernels are also stored there (one file per
+   library build, architecture and source) and loaded by later processes
+   instead of being compiled again. */
 qmc_status qmc_plan_set_jit(qmc_plan_t plan, int32_t mode);
 
 /* Launch shape of the plan's last estimate: shift_tile = tile used,
