@@ -125,8 +125,9 @@ typedef struct {
        a sector whose F changes sign inside the cube is integrated with the
        -i0 prescription (delta_im may be 0).  The result is complex whatever
        is_complex says; delta_im applies when is_complex != 0.  Needs the
-       specialised kernel (jit mode 1 or 2); EUNSUPPORTED in batches and
-       control variates, and for |pow_u| or |pow_f| > 1e5.  0 = none. */
+       specialised kernel (jit mode 1 or 2); EUNSUPPORTED in control
+       variates, in batches other than QMC_BATCH_SPECIALISED, and for
+       |pow_u| or |pow_f| > 1e5.  0 = none. */
     double deform_lambda;
 } qmc_sector_params;
 
@@ -241,7 +242,7 @@ typedef enum {
        reused for every later call and coefficient set with that structure, so
        this pays when the same sectors are integrated repeatedly (new
        kinematics, new shifts); EUNSUPPORTED when a specialised kernel cannot
-       be built. */
+       be built.  The only schedule that takes contour-deformed sectors. */
     QMC_BATCH_SPECIALISED = 3
 } qmc_batch_schedule;
 

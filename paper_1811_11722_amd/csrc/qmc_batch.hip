@@ -424,7 +424,8 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
         if (st) return st;
         if (pk[i].key_family != pk[0].key_family) return fail(QMC_EINVAL, "mixed real and complex sectors");
         if (pk[i].orders >= 2) return fail(QMC_EUNSUPPORTED, "batches take the plain integrand (n_orders < 2)");
-        if (pk[i].deform) return fail(QMC_EUNSUPPORTED, "batches take undeformed sectors (deform_lambda = 0)");
+        if (pk[i].deform && !specialised)
+            return fail(QMC_EUNSUPPORTED, "deformed sectors need the specialised schedule");
         if (plans[i]->m * pk[i].np > kMaxRows) return fail(QMC_EUNSUPPORTED, "m * parts > %u", kMaxRows);
     }
 

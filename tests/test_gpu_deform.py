@@ -234,6 +234,24 @@ def test_deform_validation(Q):
     plan.close()
 
 
+def test_deform_in_specialised_batch(Q):
+    """Deformed sectors batched with the specialised schedule equal their
+    single-plan estimates."""
+    d, n = 5, 4093
+    tabs = [dataclasses.replace(synth.sector_tables(500 + s, d, 7, 12, complex_kinematics=True),
+                                delta_im=0.0, is_complex=True) for s in range(4)]
+    g = O.korobov_vector(n, d, 1234)
+    plans = [Q.Plan(d, n, g, synth.shifts(500 + s, 4, d), "korobov", 3) for s in range(4)]
+    params = [Q.Params("sector", d, sector=t, deform=0.05) for t in tabs]
+    _say("deform specialised batch")
+    out = Q.integrate_batch(plans, params, schedule="specialised")
+    for p, pa, r in zip(plans, params, out):
+        single, _ = p.integrate(pa)
+        assert (r.mean_re, r.mean_im, r.err_re, r.err_im) == (single.mean_re, single.mean_im, single.err_re,
+                                                              single.err_im)
+        p.close()
+
+
 def test_deform_full_size_sampled(Q):
     """The benchmark's sector shape (d = 6, n_U = 12, n_F = 30, m = 32) with
     mixed-sign F and the deformation at n = 2^24 - 3 in the default launch;
