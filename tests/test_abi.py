@@ -138,3 +138,21 @@ def test_construction_and_merge_validation(Q):
     assert L.qmc_deform_select(None, None, 1.0, 0.5, 4, C.byref(lam), C.byref(r)) == Q.QMC_EINVAL
     frac = C.c_double()
     assert L.qmc_deform_check(None, None, C.byref(frac), None) == Q.QMC_EINVAL
+
+
+def test_device_log_table():
+    """The logarithm table compiled into the device code: entry j holds
+    1/(1/2 + j/512) rounded to double and -ln of that value rounded to
+    double (checked in 40-digit arithmetic)."""
+    import mpmath
+    text = open(os.path.join(ROOT, "paper_1811_11722_amd", "csrc", "qmc_device.hpp")).read()
+    body = text[text.index("kQlogTab[256] = {"):]
+    body = body[: body.index("};")]
+    pairs = re.findall(r"\{(-?0x[0-9a-fp.+-]+), (-?0x[0-9a-fp.+-]+)\}", body)
+    assert len(pairs) == 256
+    mpmath.mp.dps = 40
+    for j, (a, b) in enumerate(pairs):
+        ic, nl = float.fromhex(a), float.fromhex(b)
+        assert ic == 1.0 / (0.5 + j / 512.0)
+        exact = -mpmath.log(mpmath.mpf(ic))
+        assert abs(mpmath.mpf(nl) - exact) <= mpmath.mpf(np.spacing(abs(nl))) / 2
