@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--workload", default="sector", choices=["sector", "product_peak"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-to-error", action="store_true",
+                    help="skip the time-to-error comparison of the plain estimator and the control variate")
+    ap.add_argument("--tte-goal", type=float, default=1e-4, help="relative error goal of the time-to-error leg")
     ap.add_argument("--tile", type=int, default=0, help="shift tile override (0 = tuned/default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -165,6 +168,19 @@ def main():
                      "flops_per_eval": fpe},
         "result": {"mean": res.mean_re, "err": res.err_re},
     }
+    if not args.no_time_to_error and args.workload == "sector":
+        # the metric's second part: wall time to a relative error goal, plain
+        # estimator against the learned control variate (training included),
+        # on the d = 8 sector workload, each up the ladder of primes below 2^k
+        from paper_1811_11722_amd import drivers
+        print("[bench] time-to-error ladders", file=sys.stderr, flush=True)
+        tte = drivers.time_to_error(goal=args.tte_goal, kmax=26)
+        out["time_to_error"] = {
+            "goal_rel_err": args.tte_goal, "workload": f"sector_real_d{tte['d']}_nu{tte['n_u']}_nf{tte['n_f']}_baker",
+            "m": tte["m"],
+            "plain": {k: tte["plain"][k] for k in ("goal_met", "n", "rel_err", "seconds_at_n", "ladder_seconds")},
+            "cv": {k: tte["cv"][k] for k in ("goal_met", "n", "rel_err", "seconds_at_n", "ladder_seconds",
+                                             "train_seconds", "R", "K")}}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, tk, alpha, g, args.cpu_seconds)
