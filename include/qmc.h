@@ -346,6 +346,18 @@ qmc_status qmc_integrate_cv(qmc_plan_t plan, qmc_family family, const void *para
 qmc_status qmc_integrate_orders(qmc_plan_t plan, qmc_family family, const void *params, qmc_result *out,
                                 double *per_shift);
 
+/* The sum of `count` sector integrals of the plan's dimension in one pass
+   (Sec. 1: an integral is the sum of its sectors' contributions): every
+   lattice point is evaluated once for all sectors, whose values are added
+   before the per-shift sums, so eqs. (2)-(3) estimate the sum directly and
+   its error accounts for the correlation between the sectors.  params:
+   count sector parameter sets (all real or all complex; n_orders < 2,
+   deform_lambda = 0, else EUNSUPPORTED); count <= 32.  One kernel is
+   compiled per combination of exponent structures (specialised kernel
+   only).  out: host result; per_shift (nullable) as qmc_integrate's. */
+qmc_status qmc_integrate_sum(qmc_plan_t plan, uint32_t count, const qmc_sector_params *const *params,
+                             qmc_result *out, double *per_shift);
+
 /* Sign check of a contour deformation (Sec. 3): the fraction of the plan's
    lattice points (all m shifts, transformed as the plan says, unweighted) at
    which the deformed F(z) - i delta has a positive imaginary part, i.e. the

@@ -647,6 +647,40 @@ qmc_status qmc_integrate_orders(qmc_plan_t p, qmc_family family, const void *par
     return st;
 }
 
+qmc_status qmc_integrate_sum(qmc_plan_t p, uint32_t count, const qmc_sector_params *const *params, qmc_result *out,
+                             double *per_shift) {
+    if (!p) return fail(QMC_EINVAL, "plan is NULL");
+    if (!params || !out) return fail(QMC_EINVAL, "null argument");
+    if (count == 0) return fail(QMC_EINVAL, "count must be >= 1");
+    if (count > kMaxSumSectors) return fail(QMC_EUNSUPPORTED, "more than %u sectors in one sum", kMaxSumSectors);
+    Packed sum;
+    std::vector<size_t> offs;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!params[i]) return fail(QMC_EINVAL, "params[%u] is NULL", i);
+        Packed pk;
+        qmc_status st = pack_params(QMC_F_SECTOR, p->d, params[i], pk);
+        if (st) return st;
+        if (pk.orders >= 2 || pk.deform)
+            return fail(QMC_EUNSUPPORTED, "sums take plain sectors (n_orders < 2, deform_lambda = 0)");
+        if (i == 0) {
+            sum.np = pk.np;
+            sum.cplx = pk.cplx;
+            sum.key_family = pk.key_family;
+        } else if (pk.cplx != sum.cplx) {
+            return fail(QMC_EINVAL, "mixed real and complex sectors");
+        }
+        offs.push_back(sum.blob.size());
+        sum.blob.insert(sum.blob.end(), pk.blob.begin(), pk.blob.end());
+    }
+    const uint32_t T = p->launch.shift_tile ? p->launch.shift_tile : 2u;
+    std::string err;
+    hipFunction_t jfn = jit_sum_kernel(sum.blob, offs, p->d, p->tr, T, sum.cplx, p->device, err);
+    if (!jfn) return fail(QMC_EUNSUPPORTED, "specialised sum kernel: %s", err.c_str());
+    qmc_status st = plan_launch(p, sum, nullptr, jfn, T, p->launch.blocks_per_cu ? p->launch.blocks_per_cu : 16);
+    if (st) return st;
+    return plan_collect(p, sum.np, out, per_shift);
+}
+
 qmc_status qmc_deform_check(qmc_plan_t p, const qmc_sector_params *params, double *fraction, double *per_shift) {
     if (!p) return fail(QMC_EINVAL, "plan is NULL");
     if (!fraction || !params) return fail(QMC_EINVAL, "null argument");

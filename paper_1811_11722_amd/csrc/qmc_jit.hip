@@ -461,6 +461,97 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
     return s.str();
 }
 
+// FamJit for a sum of sectors of one dimension evaluated at the same points:
+// the blob is the sectors' blobs one after another (offsets offs), each
+// sector's code is the Horner form above in a scope of its own, and the
+// values are accumulated before the kernel's per-shift sums.
+static std::string sum_source(const std::vector<double> &blob, const std::vector<size_t> &offs, uint32_t d,
+                              bool cplx, std::string &structure) {
+    const uint32_t np = cplx ? 2u : 1u;
+    std::ostringstream st, s;
+    st << "sum|d" << d << "c" << cplx;
+    s << "struct FamJit {\n"
+      << "    static constexpr int NP = " << np << ";\n"
+      << "    template <class Tr, int D, int T>\n"
+      << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
+         " double (&v)[T][NP]) {\n"
+      << "        double z[T][D], jac[T];\n"
+      << "        apply_transform<Tr, D, T>(x, z, jac);\n"
+      << "        double acc[T][NP];\n"
+      << "        _Pragma(\"unroll\") for (int k = 0; k < T; ++k) _Pragma(\"unroll\") for (int q = 0; q < NP; ++q)"
+         " acc[k][q] = 0.0;\n";
+    auto exps = [d](uint64_t code) {
+        std::vector<int> e(d, 0);
+        for (int v : factors_of(code)) e[v] += 1;
+        return e;
+    };
+    int tmp = 0;
+    for (size_t o : offs) {
+        const uint32_t nu = (uint32_t)word(blob, o), nf = (uint32_t)word(blob, o + 1);
+        const uint32_t flags = (uint32_t)word(blob, o + 2);
+        const uint64_t nuc = word(blob, o + 6);
+        HornerTerms hu, hf;
+        st << "|o" << o << "f" << flags << "n" << nuc << ":";
+        for (uint32_t t = 0; t < nu; ++t) {
+            const uint64_t c = word(blob, o + kSectorHeader + nu + t);
+            hu.push_back({(int)t, exps(c)});
+            st << c << ",";
+        }
+        st << ";";
+        for (uint32_t t = 0; t < nf; ++t) {
+            const uint64_t c = word(blob, o + kSectorHeader + 2 * nu + nf + t);
+            hf.push_back({(int)t, exps(c)});
+            st << c << ",";
+        }
+        Trie trie;
+        std::vector<int> nuf;
+        for (uint32_t i = 0; i < d; ++i)
+            for (uint64_t r = 0; r < ((nuc >> (2 * i)) & 3u); ++r) nuf.push_back((int)i);
+        const int mnu = trie.insert(nuf);
+        s << "        {\n"
+          << "        constexpr uint32_t flags = " << flags << "u;\n"
+          << "        const __attribute__((address_space(4))) double *cp =\n"
+          << "            (const __attribute__((address_space(4))) double *)(p + " << o << ");\n"
+          << "        asm volatile(\"\" : \"+s\"(cp));\n"
+          << "        const double pow_u = cp[3], pow_f = cp[4], delta = cp[5];\n"
+          << "        const __attribute__((address_space(4))) double *cu = cp + kSectorHeader;\n"
+          << "        const __attribute__((address_space(4))) double *cf = cu + " << 2 * nu << ";\n";
+        auto ref = [&](int id) {
+            std::ostringstream r;
+            if (trie.node[id].first < 0) r << "z[k][" << trie.node[id].second << "]";
+            else r << "m" << id << "[k]";
+            return r.str();
+        };
+        for (size_t id = 0; id < trie.node.size(); ++id) {
+            const auto &nd = trie.node[id];
+            if (nd.first < 0) continue;
+            s << "        double m" << id << "[T]; _Pragma(\"unroll\") for (int k = 0; k < T; ++k) m" << id
+              << "[k] = " << ref(nd.first) << " * z[k][" << nd.second << "];\n";
+        }
+        std::ostringstream hs;
+        const std::string ue = horner("cu", hu, hs, tmp);
+        hs << "        double U[T]; _Pragma(\"unroll\") for (int k = 0; k < T; ++k) U[k] = " << ue << ";\n";
+        const std::string fe = horner("cf", hf, hs, tmp);
+        hs << "        double F[T]; _Pragma(\"unroll\") for (int k = 0; k < T; ++k) F[k] = " << fe << ";\n";
+        s << launder_chunks(hs.str());
+        s << "#pragma unroll\n"
+          << "        for (int k = 0; k < T; ++k) {\n"
+          << "            const double mono = " << (mnu < 0 ? std::string("jac[k]") : "jac[k] * " + ref(mnu))
+          << ";\n"
+          << "            double w[NP];\n"
+          << "            sector_finish<" << (cplx ? "true" : "false")
+          << ">(mono, U[k], F[k], flags, pow_u, pow_f, delta, w);\n"
+          << "            _Pragma(\"unroll\") for (int q = 0; q < NP; ++q) acc[k][q] += w[q];\n"
+          << "        }\n"
+          << "        }\n";
+    }
+    s << "        _Pragma(\"unroll\") for (int k = 0; k < T; ++k) _Pragma(\"unroll\") for (int q = 0; q < NP; ++q)"
+         " v[k][q] = acc[k][q];\n"
+      << "    }\n};\n";
+    structure = st.str();
+    return s.str();
+}
+
 static std::string device_arch(int dev) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "gfx950";
@@ -616,6 +707,19 @@ hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_
     src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_lattice<FamJit, "
         << transform_type(tr) << ", " << d << ", " << T << ">(const LatticeArgs);\n}  // namespace qmc\n";
     key << dev << "#lattice#T" << T << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
+    return compile_cached(src.str(), ne.str(), key.str(), dev, err);
+}
+
+// The lattice kernel with the functor of a sum of sectors.
+hipFunction_t jit_sum_kernel(const std::vector<double> &blob, const std::vector<size_t> &offs, uint32_t d,
+                             const qmc_transform &tr, uint32_t T, bool cplx, int dev, std::string &err) {
+    std::string structure;
+    const std::string fam = sum_source(blob, offs, d, cplx, structure);
+    std::ostringstream ne, src, key;
+    ne << "qmc::k_lattice<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ", " << T << ">";
+    src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_lattice<FamJit, "
+        << transform_type(tr) << ", " << d << ", " << T << ">(const LatticeArgs);\n}  // namespace qmc\n";
+    key << dev << "#sum#T" << T << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);
 }
 

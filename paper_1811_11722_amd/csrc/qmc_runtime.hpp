@@ -14,6 +14,7 @@
 namespace qmc {
 
 constexpr uint32_t kMaxDim = 16;
+constexpr uint32_t kMaxSumSectors = 32;  // sectors in one summed kernel (qmc_integrate_sum)
 // Per-plan result buffer: Q_k for up to kMaxParts parts (m * kMaxParts
 // doubles), then the results of every pair of parts, (mean a, mean b,
 // err a, err b), 4 doubles per pair (kMaxParts in qmc_kernels.hpp).
@@ -89,6 +90,8 @@ uint32_t padded_rows(uint32_t m);
 std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows);
 hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
                          bool cplx, int dev, std::string &err);
+hipFunction_t jit_sum_kernel(const std::vector<double> &blob, const std::vector<size_t> &offs, uint32_t d,
+                             const qmc_transform &tr, uint32_t T, bool cplx, int dev, std::string &err);
 hipError_t jit_launch(hipFunction_t fn, const LatticeArgs &a, dim3 grid, hipStream_t s);
 struct CvSampleArgs;
 hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint32_t d, const qmc_transform &tr,

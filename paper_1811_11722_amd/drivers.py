@@ -607,6 +607,40 @@ def lattice_study(n: int = 1048573, d: int = 10, m: int = 32, seed: int = synth.
     return {"n": n, "d": d, "m": m, "korobov_p2": p2k, "rows": rows}
 
 
+def sector_sum(count: int = 8, d: int = 6, n: int = 16777213, m: int = 32, seed: int = synth.SEED_BASE + 9,
+               reps: int = 5, log=None) -> dict:
+    """The sum of `count` d = 6 sectors (configuration 2's shape, own tables
+    each) in one pass against one pass per sector; kernel times from HIP
+    events, median of reps."""
+    say = log or (lambda msg: None)
+    tabs = [synth.sector_tables(seed + 97 * s, d, 12, 30) for s in range(count)]
+    params = [qmc.Params("sector", d, sector=t) for t in tabs]
+    gv = GeneratingVectors(seed)
+    plan = qmc.Plan(d, n, gv(n, d), synth.shifts(seed, m, d), "baker")
+    plan.integrate_sum(params)
+    for pa in params:
+        plan.integrate(pa)
+    plan.set_timing(True)
+
+    def kernel_ms(fn):
+        ts = []
+        for _ in range(reps):
+            plan.kernel_time(reset=True)
+            out = fn()
+            ts.append(plan.kernel_time()[0])
+        return out, float(np.median(ts))
+
+    (res, _), t_sum = kernel_ms(lambda: plan.integrate_sum(params))
+    singles, t_sep = kernel_ms(lambda: [plan.integrate(pa)[0] for pa in params])
+    plan.close()
+    total = sum(r.mean_re for r in singles)
+    say(f"  sum of {count}: {t_sum:.3f} ms in one pass, {t_sep:.3f} ms in {count} passes")
+    return {"count": count, "d": d, "n": n, "m": m, "sum_pass_ms": t_sum, "separate_passes_ms": t_sep,
+            "sector_evals_per_s": count * n * m / (t_sum * 1e-3), "mean_sum": res.mean_re, "err_sum": res.err_re,
+            "mean_of_separate": total,
+            "err_of_separate_quadrature": float(np.sqrt(sum(r.err_re ** 2 for r in singles)))}
+
+
 def deform(d: int = 6, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 7, n: int = 16777213,
            m: int = 32, n_pilot: int = 65521, lam_max: float = 0.8, shrink: float = 0.5, count: int = 8,
            reps: int = 5, log=None) -> dict:
@@ -667,7 +701,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
                                      "cv_estimate", "fig3", "allocation_compare", "deform", "transforms",
-                                     "lattices", "sector_batch_specialised"])
+                                     "lattices", "sector_batch_specialised", "sector_sum"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--shift-tile", type=int, default=0)
@@ -689,6 +723,8 @@ def main(argv=None):
         out = cv_estimate()
     elif args.what == "allocation_compare":
         out = allocation_compare(count=args.count or 2000)
+    elif args.what == "sector_sum":
+        out = sector_sum(log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "sector_batch_specialised":
         out = sector_batch_specialised(count=args.count or 2000, workers=args.workers,
                                        log=lambda msg: print(msg, file=sys.stderr, flush=True))

@@ -109,6 +109,7 @@ SIGNATURES = {
     "qmc_integrate_cv": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
     "qmc_integrate_orders": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "qmc_deform_check": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "qmc_integrate_sum": (C.c_int, [_vp, C.c_uint32, _vp, _vp, _vp]),
     "qmc_cbc_search": (C.c_int, [C.c_uint64, C.c_uint32, _vp, _vp, C.c_uint32, _vp, _vp]),
     "qmc_korobov_search_extensible": (C.c_int, [C.c_uint32, C.c_uint32, C.c_uint32, _vp, C.c_uint32, _vp, _vp,
                                                 _vp]),
@@ -329,6 +330,17 @@ class Plan:
         if params.is_complex:
             per = per[:, 0::2] + 1j * per[:, 1::2]
         return list(out), per
+
+    def integrate_sum(self, params: Sequence[Params]):
+        """The sum of several sector integrals in one pass: (result, per-shift
+        array (m,), complex for complex sectors)."""
+        ptrs = (C.c_void_p * len(params))(*[pa.ptr for pa in params])
+        res = qmc_result()
+        per = np.zeros(2 * self.m)
+        check(lib().qmc_integrate_sum(self.handle, len(params), ptrs, C.byref(res), _p(per)), "qmc_integrate_sum")
+        if res.is_complex:
+            return res, per[0::2] + 1j * per[1::2]
+        return res, per[: self.m].copy()
 
     def deform_check(self, params: Params):
         """Fraction of lattice points where the deformed F - i delta has a
