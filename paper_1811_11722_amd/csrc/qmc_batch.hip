@@ -120,7 +120,7 @@ qmc_status build_uniform(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, c
     for (uint32_t i = 0; i < count; ++i) {
         std::copy(plans[i]->g.begin(), plans[i]->g.end(), g.begin() + (size_t)i * d);
         gstep_for(plans[i]->g.data(), d, n, (uint64_t)c.lbx * kBlock, &gs[(size_t)i * d]);
-        const std::vector<double> ps = padded_shifts(plans[i]->shifts, m, d, rows);
+        const std::vector<double> ps = padded_shifts(plans[i]->shifts, m, d, rows, plans[i]->tr);
         std::copy(ps.begin(), ps.end(), sh.begin() + (size_t)i * rows * d);
         std::copy(pk[i].blob.begin(), pk[i].blob.end(), prm.begin() + (size_t)i * pstride);
         BatchSector s{};
@@ -237,7 +237,7 @@ qmc_status build_ctx(BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const
         gstep_for(p->g.data(), p->d, p->n, kBlock, step.data());
         g.insert(g.end(), p->g.begin(), p->g.end());
         gs.insert(gs.end(), step.begin(), step.end());
-        const std::vector<double> psh = padded_shifts(p->shifts, p->m, p->d, (p->m + T - 1) / T * T);
+        const std::vector<double> psh = padded_shifts(p->shifts, p->m, p->d, (p->m + T - 1) / T * T, p->tr);
         sh.insert(sh.end(), psh.begin(), psh.end());
         prm.insert(prm.end(), pk[i].blob.begin(), pk[i].blob.end());
         const uint32_t ktiles = (p->m + T - 1) / T;

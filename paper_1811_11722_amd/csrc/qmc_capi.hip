@@ -286,10 +286,17 @@ void gstep_for(const uint32_t *g, uint32_t d, uint32_t n, uint64_t S, uint32_t *
 // past m repeat the last shift (their sums are never read)
 uint32_t padded_rows(uint32_t m) { return (m + kMaxTile - 1) / kMaxTile * kMaxTile; }
 
-std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows) {
+// The baker's transform reads its points moved by 1/2 (TrBaker): the device
+// table holds {Delta + 1/2} for it, so the move costs nothing per point.
+std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows,
+                                  const qmc_transform &tr) {
+    const bool half = tr.kind == QMC_T_BAKER;
     std::vector<double> out((size_t)rows * d);
     for (uint32_t r = 0; r < rows; ++r)
-        for (uint32_t i = 0; i < d; ++i) out[(size_t)r * d + i] = sh[(size_t)std::min(r, m - 1) * d + i];
+        for (uint32_t i = 0; i < d; ++i) {
+            const double v = sh[(size_t)std::min(r, m - 1) * d + i];
+            out[(size_t)r * d + i] = !half ? v : (v < 0.5 ? v + 0.5 : v - 0.5);
+        }
     return out;
 }
 
@@ -526,7 +533,7 @@ qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m
         return fail(QMC_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     }
     if ((e = hipMemcpy(p->d_g, p->g.data(), d * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->d_shifts, padded_shifts(p->shifts, m, d, padded_rows(m)).data(),
+        (e = hipMemcpy(p->d_shifts, padded_shifts(p->shifts, m, d, padded_rows(m), p->tr).data(),
                        (size_t)padded_rows(m) * d * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipEventCreate(&p->ev0)) != hipSuccess || (e = hipEventCreate(&p->ev1)) != hipSuccess) {
         qmc_plan_destroy(p);

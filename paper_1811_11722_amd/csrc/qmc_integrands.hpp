@@ -19,10 +19,13 @@ struct TrNone {
 };
 
 // Baker's transform, eq. (5): z = 1 - |2x - 1|.  The map is 2-to-1 with
-// |z'| = 2 on each half, so the integrand weight is 1.
+// |z'| = 2 on each half, so the integrand weight is 1.  The kernels receive
+// x' = {x + 1/2} (the shift tables of baker plans hold {Delta + 1/2}), and
+// 1 - |2x - 1| = |2x' - 1|: one FMA, the absolute value a free operand
+// modifier of its uses.
 struct TrBaker {
     static constexpr bool kJac = false;
-    __device__ static double z(double x) { return 1.0 - __builtin_fabs(fma_(2.0, x, -1.0)); }
+    __device__ static double z(double xh) { return __builtin_fabs(fma_(2.0, xh, -1.0)); }
 };
 
 constexpr double cfact(int k) { return k <= 1 ? 1.0 : k * cfact(k - 1); }

@@ -87,7 +87,8 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
 qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift);
 void plan_release_extra(qmc_plan_s *p);
 uint32_t padded_rows(uint32_t m);
-std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows);
+std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows,
+                                  const qmc_transform &tr);
 hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
                          bool cplx, int dev, std::string &err);
 hipFunction_t jit_sum_kernel(const std::vector<double> &blob, const std::vector<size_t> &offs, uint32_t d,

@@ -82,11 +82,14 @@ def _gpu(Q, d, n, g, sh, tab, lam, tk, alpha, launch=None):
     return res, np.asarray(q)
 
 
-@pytest.mark.parametrize("lam", [0.25, 1.0])
+@pytest.mark.parametrize("lam", [0.005, 0.02])
 @pytest.mark.parametrize("tk,alpha", [("baker", 0), ("korobov", 3)])
 def test_deform_euclidean_matches_oracle_and_cauchy(Q, lam, tk, alpha):
     """A Euclidean sector (F > 0): per-shift sums against the oracle, and the
-    mean against the undeformed integral (unchanged by Cauchy's theorem)."""
+    mean against the undeformed integral (unchanged by Cauchy's theorem).
+    |grad F| reaches ~240 on this sector, so lambda up to 0.02 keeps the
+    contour on the -i0 side everywhere (sign check 0); larger lambda leaves
+    the first-order regime."""
     d, n, m = 6, 65521, 8
     tab = synth.sector_tables(301, d, 12, 30)
     g = O.korobov_vector(n, d, 17364)
@@ -99,7 +102,9 @@ def test_deform_euclidean_matches_oracle_and_cauchy(Q, lam, tk, alpha):
     assert ok, worst
     plan = Q.Plan(d, n, g, sh, tk, alpha)
     plain, _ = plan.integrate(Q.Params("sector", d, sector=tab))
+    frac, _ = plan.deform_check(Q.Params("sector", d, sector=tab, deform=lam))
     plan.close()
+    assert frac == 0.0
     assert abs(res.mean_re - plain.mean_re) < 6 * (res.err_re + plain.err_re)
     assert abs(res.mean_im) < 6 * res.err_im
 
