@@ -140,19 +140,43 @@ def test_construction_and_merge_validation(Q):
     assert L.qmc_deform_check(None, None, C.byref(frac), None) == Q.QMC_EINVAL
 
 
-def test_device_log_table():
-    """The logarithm table compiled into the device code: entry j holds
-    1/(1/2 + j/512) rounded to double and -ln of that value rounded to
-    double (checked in 40-digit arithmetic)."""
-    import mpmath
+def _math_table():
     text = open(os.path.join(ROOT, "paper_1811_11722_amd", "csrc", "qmc_device.hpp")).read()
-    body = text[text.index("kQlogTab[256] = {"):]
-    body = body[: body.index("};")]
-    pairs = re.findall(r"\{(-?0x[0-9a-fp.+-]+), (-?0x[0-9a-fp.+-]+)\}", body)
-    assert len(pairs) == 256
+    body = text[text.index("kMathTab[1024]"):]
+    body = body[body.index("{") + 1: body.index("};")]
+    body = "\n".join(line.split("//")[0] for line in body.split("\n"))
+    vals = [float.fromhex(v) for v in re.findall(r"(-?0x[0-9a-fp.+-]+),", body)]
+    assert len(vals) == 1024
+    return vals
+
+
+def test_device_log_table():
+    """The logarithm half of the table compiled into the device code: entry
+    2j holds 1/(1/2 + (j + 1/2)/512) rounded to double and entry 2j + 1 -ln
+    of that value rounded to double (checked in 40-digit arithmetic)."""
+    import mpmath
+    vals = _math_table()
     mpmath.mp.dps = 40
-    for j, (a, b) in enumerate(pairs):
-        ic, nl = float.fromhex(a), float.fromhex(b)
-        assert ic == 1.0 / (0.5 + j / 512.0)
+    for j in range(256):
+        ic, nl = vals[2 * j], vals[2 * j + 1]
+        assert ic == 1.0 / (0.5 + (j + 0.5) / 512.0)
         exact = -mpmath.log(mpmath.mpf(ic))
         assert abs(mpmath.mpf(nl) - exact) <= mpmath.mpf(np.spacing(abs(nl))) / 2
+
+
+def test_device_exp_table():
+    """The exponential half of the table: entry 512 + j holds 2^(j/512)
+    rounded to double (checked in 40-digit arithmetic); and the split of
+    ln 2 / 512 used in the reduction: the high part times any |k| < 2^21 is
+    exact and high + low equals ln 2 / 512 to 1e-27."""
+    import mpmath
+    vals = _math_table()
+    mpmath.mp.dps = 40
+    for j in range(512):
+        t = vals[512 + j]
+        exact = mpmath.power(2, mpmath.mpf(j) / 512)
+        assert abs(mpmath.mpf(t) - exact) <= mpmath.mpf(np.spacing(t)) / 2
+    hi, lo = 6.93147180369123816490e-01 / 512.0, 1.90821492927058770002e-10 / 512.0
+    assert float.fromhex("0x1.62e42feep-1") / 512.0 == hi
+    assert int(float.hex(hi).split("p")[0].split(".")[1], 16) % (1 << 20) == 0  # 32 significant bits
+    assert abs(mpmath.mpf(hi) + mpmath.mpf(lo) - mpmath.log(2) / 512) < mpmath.mpf(1e-27)
