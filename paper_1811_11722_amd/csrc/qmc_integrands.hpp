@@ -16,16 +16,24 @@ namespace qmc {
 struct TrNone {
     static constexpr bool kJac = false;
     __device__ static double z(double x) { return x; }
+    __device__ static double z_operand(double x) { return x; }
 };
 
 // Baker's transform, eq. (5): z = 1 - |2x - 1|.  The map is 2-to-1 with
 // |z'| = 2 on each half, so the integrand weight is 1.  The kernels receive
 // x' = {x + 1/2} (the shift tables of baker plans hold {Delta + 1/2}), and
-// 1 - |2x - 1| = |2x' - 1|: one FMA, the absolute value a free operand
-// modifier of its uses.
+// 1 - |2x - 1| = |2x' - 1|.  z() materialises it (one FMA and a v_max with
+// an absolute-value operand, as many instructions as 1 - |2x - 1|);
+// z_operand() is the FMA alone, the absolute value left as a free modifier
+// of each use.  That form suits functors whose uses of z are all FMAs and
+// multiplies (the run-time specialised ones: one instruction less per
+// coordinate); in the table-driven functors the compiler then keeps both
+// the value and its absolute value live (48 more VGPRs at d = 6 with four
+// shifts, a third of the occupancy lost).
 struct TrBaker {
     static constexpr bool kJac = false;
-    __device__ static double z(double xh) { return __builtin_fabs(fma_(2.0, xh, -1.0)); }
+    __device__ static double z(double xh) { return __builtin_fmax(__builtin_fabs(fma_(2.0, xh, -1.0)), 0.0); }
+    __device__ static double z_operand(double xh) { return __builtin_fabs(fma_(2.0, xh, -1.0)); }
 };
 
 constexpr double cfact(int k) { return k <= 1 ? 1.0 : k * cfact(k - 1); }
@@ -168,8 +176,9 @@ struct TrSidi {
     }
 };
 
-// z for all D coordinates of T shifts, and the Jacobian (without C_A^d)
-template <class Tr, int D, int T>
+// z for all D coordinates of T shifts, and the Jacobian (without C_A^d);
+// Operand selects z_operand() of the transforms without a Jacobian
+template <class Tr, int D, int T, bool Operand = false>
 __device__ __forceinline__ void apply_transform(const double (&x)[T][D], double (&z)[T][D],
                                                 double (&jac)[T]) {
 #pragma unroll
@@ -185,7 +194,7 @@ __device__ __forceinline__ void apply_transform(const double (&x)[T][D], double 
             jac[k] = Tr::jac(pu);
         } else {
 #pragma unroll
-            for (int i = 0; i < D; ++i) z[k][i] = Tr::z(x[k][i]);
+            for (int i = 0; i < D; ++i) z[k][i] = Operand ? Tr::z_operand(x[k][i]) : Tr::z(x[k][i]);
             jac[k] = 1.0;
         }
     }

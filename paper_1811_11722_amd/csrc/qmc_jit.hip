@@ -137,7 +137,7 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"
       << "        double z[T][D], jac[T];\n"
-      << "        apply_transform<Tr, D, T>(x, z, jac);\n"
+      << "        apply_transform<Tr, D, T, true>(x, z, jac);\n"
       << "        constexpr uint32_t flags = " << flags << "u;\n"
       << "        const __attribute__((address_space(4))) double *cp =\n"
       << "            (const __attribute__((address_space(4))) double *)p;\n"
@@ -414,7 +414,7 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"
       << "        double z[T][D], jac[T];\n"
-      << "        apply_transform<Tr, D, T>(x, z, jac);\n"
+      << "        apply_transform<Tr, D, T, true>(x, z, jac);\n"
       << "        constexpr uint32_t flags = " << flags << "u;\n"
       // the parameter words are read through a constant-address-space
       // pointer laundered per point: scalar loads inside the point loop
@@ -476,7 +476,7 @@ static std::string sum_source(const std::vector<double> &blob, const std::vector
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"
       << "        double z[T][D], jac[T];\n"
-      << "        apply_transform<Tr, D, T>(x, z, jac);\n"
+      << "        apply_transform<Tr, D, T, true>(x, z, jac);\n"
       << "        double acc[T][NP];\n"
       << "        _Pragma(\"unroll\") for (int k = 0; k < T; ++k) _Pragma(\"unroll\") for (int q = 0; q < NP; ++q)"
          " acc[k][q] = 0.0;\n";
