@@ -24,6 +24,7 @@
 #include <iterator>
 #include <mutex>
 #include <sstream>
+#include <unordered_map>
 
 #include <unistd.h>
 
@@ -331,7 +332,7 @@ static std::string launder_chunks(const std::string &text) {
 // The host packer stores the terms in this order, so the generated code
 // reads the coefficients in ascending address order and the compiler can
 // fetch them with few scalar loads and few live scalar registers.
-std::vector<uint32_t> horner_term_order(const std::vector<uint64_t> &codes, uint32_t d) {
+static std::vector<uint32_t> horner_term_order_uncached(const std::vector<uint64_t> &codes, uint32_t d) {
     HornerTerms terms;
     for (size_t t = 0; t < codes.size(); ++t) {
         std::vector<int> e(d, 0);
@@ -360,6 +361,44 @@ std::vector<uint32_t> horner_term_order(const std::vector<uint64_t> &codes, uint
     return order;
 }
 
+// Remembered per (d, codes): a plan re-packs its integrand at every estimate.
+std::vector<uint32_t> horner_term_order(const std::vector<uint64_t> &codes, uint32_t d) {
+    static std::mutex mu;
+    static std::unordered_map<std::string, std::vector<uint32_t>> memo;
+    std::string key(sizeof(uint32_t) + codes.size() * sizeof(uint64_t), '\0');
+    std::memcpy(&key[0], &d, sizeof(uint32_t));
+    if (!codes.empty()) std::memcpy(&key[sizeof(uint32_t)], codes.data(), codes.size() * sizeof(uint64_t));
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+    }
+    std::vector<uint32_t> order = horner_term_order_uncached(codes, d);
+    std::lock_guard<std::mutex> lock(mu);
+    if (memo.size() >= 65536) memo.clear();  // bounded: structures of one run rarely exceed it
+    memo.emplace(key, order);
+    return order;
+}
+
+
+// A canonical description of everything the specialised functor of one
+// sector blob depends on (dimension, complex flag, monomial codes, flags,
+// expansion orders, nu): the key of its compiled code.  It is built without
+// generating the source, so that a cached kernel is found cheaply.
+static std::string sector_structure(const std::vector<double> &blob, uint32_t d, bool cplx) {
+    const uint32_t nu = (uint32_t)word(blob, 0), nf = (uint32_t)word(blob, 1);
+    const uint32_t flags = (uint32_t)word(blob, 2);
+    const size_t eps_at = kSectorHeader + 2 * (size_t)nu + 2 * (size_t)nf;
+    const uint32_t orders = (flags & kSectorOrders) ? (uint32_t)word(blob, eps_at + 2) : 0u;
+    std::string st = "d" + std::to_string(d) + "c" + (cplx ? "1" : "0") + "|";
+    st.reserve(st.size() + 21 * (size_t)(nu + nf) + 48);
+    for (uint32_t t = 0; t < nu; ++t) (st += std::to_string(word(blob, kSectorHeader + nu + t))) += ',';
+    st += '|';
+    for (uint32_t t = 0; t < nf; ++t) (st += std::to_string(word(blob, kSectorHeader + 2 * nu + nf + t))) += ',';
+    st += "|f" + std::to_string(flags) + "|o" + std::to_string(orders) + "|" + std::to_string(word(blob, 6));
+    return st;
+}
+
 // Source of the specialised functor FamJit; `structure` receives a
 // canonical description of what the code depends on.
 static std::string functor_source(const std::vector<double> &blob, uint32_t d, bool cplx, std::string &structure) {
@@ -375,28 +414,21 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
         for (int v : factors_of(code)) e[v] += 1;
         return e;
     };
-    std::ostringstream st;
-    st << "d" << d << "c" << cplx << "|";
     for (uint32_t t = 0; t < nu; ++t) {
         const uint64_t c = word(blob, kSectorHeader + nu + t);
         hu.push_back({(int)t, exps(c)});
-        st << c << ",";
     }
-    st << "|";
     for (uint32_t t = 0; t < nf; ++t) {
         const uint64_t c = word(blob, kSectorHeader + 2 * nu + nf + t);
         hf.push_back({(int)t, exps(c)});
-        st << c << ",";
     }
     const uint64_t nuc = word(blob, 6);
     const uint32_t flags = (uint32_t)word(blob, 2);
-    st << "|f" << flags << "|o" << orders;
     std::vector<int> nuf;
     for (uint32_t i = 0; i < d; ++i)
         for (uint64_t r = 0; r < ((nuc >> (2 * i)) & 3u); ++r) nuf.push_back((int)i);
     const int mnu = trie.insert(nuf);
-    st << "|" << nuc;
-    structure = st.str();
+    structure = sector_structure(blob, d, cplx);
     if (flags & kSectorDeform) {
         // the deformation parameter follows the orders words (if any)
         const size_t lam_at = eps_at + ((flags & kSectorOrders) ? 3u : 0u);
@@ -465,11 +497,27 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
 // the blob is the sectors' blobs one after another (offsets offs), each
 // sector's code is the Horner form above in a scope of its own, and the
 // values are accumulated before the kernel's per-shift sums.
+// The key of a sum's functor: each sector's offset, flags, nu and monomial
+// codes.
+static std::string sum_structure(const std::vector<double> &blob, const std::vector<size_t> &offs, uint32_t d,
+                                 bool cplx) {
+    std::string st = "sum|d" + std::to_string(d) + "c" + (cplx ? "1" : "0");
+    for (size_t o : offs) {
+        const uint32_t nu = (uint32_t)word(blob, o), nf = (uint32_t)word(blob, o + 1);
+        st += "|o" + std::to_string(o) + "f" + std::to_string((uint32_t)word(blob, o + 2)) + "n" +
+              std::to_string(word(blob, o + 6)) + ":";
+        for (uint32_t t = 0; t < nu; ++t) (st += std::to_string(word(blob, o + kSectorHeader + nu + t))) += ',';
+        st += ';';
+        for (uint32_t t = 0; t < nf; ++t)
+            (st += std::to_string(word(blob, o + kSectorHeader + 2 * nu + nf + t))) += ',';
+    }
+    return st;
+}
+
 static std::string sum_source(const std::vector<double> &blob, const std::vector<size_t> &offs, uint32_t d,
                               bool cplx, std::string &structure) {
     const uint32_t np = cplx ? 2u : 1u;
-    std::ostringstream st, s;
-    st << "sum|d" << d << "c" << cplx;
+    std::ostringstream s;
     s << "struct FamJit {\n"
       << "    static constexpr int NP = " << np << ";\n"
       << "    template <class Tr, int D, int T>\n"
@@ -491,17 +539,13 @@ static std::string sum_source(const std::vector<double> &blob, const std::vector
         const uint32_t flags = (uint32_t)word(blob, o + 2);
         const uint64_t nuc = word(blob, o + 6);
         HornerTerms hu, hf;
-        st << "|o" << o << "f" << flags << "n" << nuc << ":";
         for (uint32_t t = 0; t < nu; ++t) {
             const uint64_t c = word(blob, o + kSectorHeader + nu + t);
             hu.push_back({(int)t, exps(c)});
-            st << c << ",";
         }
-        st << ";";
         for (uint32_t t = 0; t < nf; ++t) {
             const uint64_t c = word(blob, o + kSectorHeader + 2 * nu + nf + t);
             hf.push_back({(int)t, exps(c)});
-            st << c << ",";
         }
         Trie trie;
         std::vector<int> nuf;
@@ -548,7 +592,7 @@ static std::string sum_source(const std::vector<double> &blob, const std::vector
     s << "        _Pragma(\"unroll\") for (int k = 0; k < T; ++k) _Pragma(\"unroll\") for (int q = 0; q < NP; ++q)"
          " v[k][q] = acc[k][q];\n"
       << "    }\n};\n";
-    structure = st.str();
+    structure = sum_structure(blob, offs, d, cplx);
     return s.str();
 }
 
@@ -697,29 +741,49 @@ static hipFunction_t compile_cached(const std::string &src, const std::string &n
     return ins.first->second.fn;
 }
 
+// The kernel stored under key (or the error its compile gave), if any.
+static bool jit_lookup(const std::string &key, hipFunction_t &fn, std::string &err) {
+    std::lock_guard<std::mutex> lock(g_jit_mu);
+    auto it = g_jit_cache.find(key);
+    if (it == g_jit_cache.end()) return false;
+    fn = it->second.fn;
+    err = it->second.error;
+    return true;
+}
+
+// The getters below build the key from the blob's structure first and
+// generate the source only when no kernel is stored under it: the
+// repeated estimates of one integrand pay a key, not a code generation.
+
 // The lattice kernel with the specialised sector functor.
 hipFunction_t jit_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, uint32_t T,
                          bool cplx, int dev, std::string &err) {
+    std::ostringstream key;
+    key << dev << "#lattice#T" << T << "t" << tr.kind << "a" << tr.alpha << "#" << sector_structure(blob, d, cplx);
+    hipFunction_t fn = nullptr;
+    if (jit_lookup(key.str(), fn, err)) return fn;
     std::string structure;
     const std::string fam = functor_source(blob, d, cplx, structure);
-    std::ostringstream ne, src, key;
+    std::ostringstream ne, src;
     ne << "qmc::k_lattice<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ", " << T << ">";
     src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_lattice<FamJit, "
         << transform_type(tr) << ", " << d << ", " << T << ">(const LatticeArgs);\n}  // namespace qmc\n";
-    key << dev << "#lattice#T" << T << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);
 }
 
 // The lattice kernel with the functor of a sum of sectors.
 hipFunction_t jit_sum_kernel(const std::vector<double> &blob, const std::vector<size_t> &offs, uint32_t d,
                              const qmc_transform &tr, uint32_t T, bool cplx, int dev, std::string &err) {
+    std::ostringstream key;
+    key << dev << "#sum#T" << T << "t" << tr.kind << "a" << tr.alpha << "#" << sum_structure(blob, offs, d, cplx);
+    hipFunction_t fn = nullptr;
+    if (jit_lookup(key.str(), fn, err)) return fn;
     std::string structure;
     const std::string fam = sum_source(blob, offs, d, cplx, structure);
-    std::ostringstream ne, src, key;
+    std::ostringstream ne, src;
     ne << "qmc::k_lattice<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ", " << T << ">";
     src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_lattice<FamJit, "
         << transform_type(tr) << ", " << d << ", " << T << ">(const LatticeArgs);\n}  // namespace qmc\n";
-    key << dev << "#sum#T" << T << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);
 }
 
@@ -727,9 +791,14 @@ hipFunction_t jit_sum_kernel(const std::vector<double> &blob, const std::vector<
 // specialised functor (parts: fhat, fhat - J g).
 hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint32_t d, const qmc_transform &tr,
                             uint32_t R, uint32_t K, bool cplx, int dev, std::string &err) {
+    std::ostringstream key;
+    key << dev << "#cv#R" << R << "K" << K << "o" << cv_off << "c" << cplx << "t" << tr.kind << "a" << tr.alpha << "#"
+        << sector_structure(blob, d, cplx);
+    hipFunction_t fn = nullptr;
+    if (jit_lookup(key.str(), fn, err)) return fn;
     std::string structure;
     const std::string fam = functor_source(blob, d, cplx, structure);
-    std::ostringstream ne, src, key, cvt;
+    std::ostringstream ne, src, cvt;
     cvt << "FamCvResidual<FamJit, " << R << ", " << K << ", " << cv_off << ">";
     // real integrands up to R = 32 fit two waves per SIMD without spills
     const char *kern = R <= 32 && !cplx ? "k_lattice_w2" : "k_lattice";
@@ -737,21 +806,22 @@ hipFunction_t jit_cv_kernel(const std::vector<double> &blob, size_t cv_off, uint
        << transform_type(tr) << ", " << d << ", 1>";
     src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void " << kern << "<" << cvt.str()
         << ", " << transform_type(tr) << ", " << d << ", 1>(const LatticeArgs);\n}  // namespace qmc\n";
-    key << dev << "#cv#R" << R << "K" << K << "o" << cv_off << "c" << cplx << "t" << tr.kind << "a" << tr.alpha << "#"
-        << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);
 }
 
 // The training-lattice sampler with the specialised functor.
 hipFunction_t jit_sample_kernel(const std::vector<double> &blob, uint32_t d, const qmc_transform &tr, bool cplx,
                                 int dev, std::string &err) {
+    std::ostringstream key;
+    key << dev << "#sample#c" << cplx << "t" << tr.kind << "a" << tr.alpha << "#" << sector_structure(blob, d, cplx);
+    hipFunction_t fn = nullptr;
+    if (jit_lookup(key.str(), fn, err)) return fn;
     std::string structure;
     const std::string fam = functor_source(blob, d, cplx, structure);
-    std::ostringstream ne, src, key;
+    std::ostringstream ne, src;
     ne << "qmc::k_cv_sample<qmc::FamJit, qmc::" << transform_type(tr) << ", " << d << ">";
     src << "#include \"qmc_cv.hpp\"\nnamespace qmc {\n" << fam << "template __global__ void k_cv_sample<FamJit, "
         << transform_type(tr) << ", " << d << ">(const CvSampleArgs);\n}  // namespace qmc\n";
-    key << dev << "#sample#c" << cplx << "t" << tr.kind << "a" << tr.alpha << "#" << structure;
     return compile_cached(src.str(), ne.str(), key.str(), dev, err);
 }
 
