@@ -175,7 +175,8 @@ qmc_status qmc_plan_set_launch(qmc_plan_t plan, const qmc_launch *cfg);
    to rounding either way.  With the environment variable QMC_JIT_CACHE
    naming a directory, compiled kernels are also stored there (one file per
    library build, architecture and source) and loaded by later processes
-   instead of being compiled again. */
+   instead of being compiled again.  With QMC_JIT_DUMP naming a directory,
+   the source of every kernel compiled is written there for inspection. */
 qmc_status qmc_plan_set_jit(qmc_plan_t plan, int32_t mode);
 
 /* Launch shape of the plan's last estimate: shift_tile = tile used,
