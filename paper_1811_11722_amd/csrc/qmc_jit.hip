@@ -442,6 +442,7 @@ static std::string functor_source(const std::vector<double> &blob, uint32_t d, b
     const uint32_t np = (cplx ? 2u : 1u) * (orders >= 2 ? orders : 1u);
     s << "struct FamJit {\n"
       << "    static constexpr int NP = " << np << ";\n"
+      << "    static constexpr bool kShiftsInVgprs = true;\n"
       << "    template <class Tr, int D, int T>\n"
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"
@@ -520,6 +521,7 @@ static std::string sum_source(const std::vector<double> &blob, const std::vector
     std::ostringstream s;
     s << "struct FamJit {\n"
       << "    static constexpr int NP = " << np << ";\n"
+      << "    static constexpr bool kShiftsInVgprs = true;\n"
       << "    template <class Tr, int D, int T>\n"
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"

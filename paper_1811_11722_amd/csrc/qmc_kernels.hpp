@@ -56,6 +56,20 @@ template <class F>
 __device__ constexpr bool wave_uniform_walk(long) {
     return false;
 }
+// A family that sets kShiftsInVgprs = true has the T x D shift values of
+// its tile copied into vector registers before the point loop.  Held as
+// scalars they compete with the integrand's coefficients for the 106 scalar
+// registers, and the compiler spills them into vector lanes, paying a
+// v_readlane per value and point; the run-time specialised sector functors
+// have vector registers to spare and ask for this.
+template <class F>
+__device__ constexpr auto shifts_in_vgprs(int) -> decltype(F::kShiftsInVgprs, bool()) {
+    return F::kShiftsInVgprs;
+}
+template <class F>
+__device__ constexpr bool shifts_in_vgprs(long) {
+    return false;
+}
 
 template <class Fam, class Tr, int D, int T, bool Reload = false>
 __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S, uint32_t n, double inv_n,
@@ -77,6 +91,15 @@ __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S,
         idx[i] = mulmod(j, g[i], n, inv_n);
         step[i] = gs[i];
         nms[i] = n - gs[i];
+    }
+    constexpr bool kVgprShifts = !Reload && shifts_in_vgprs<Fam>(0);
+    double dlv[T * D];
+    if constexpr (kVgprShifts) {
+#pragma unroll
+        for (int q = 0; q < T * D; ++q) {
+            dlv[q] = dls[q];
+            asm volatile("" : "+v"(dlv[q]));  // a vector register from here on
+        }
     }
 #pragma unroll 1
     while (more()) {
@@ -102,7 +125,7 @@ __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S,
 #pragma unroll
             for (int k = 0; k < T; ++k)
 #pragma unroll
-                for (int i = 0; i < D; ++i) x[k][i] = fract(y[i] + dl[k * D + i]);
+                for (int i = 0; i < D; ++i) x[k][i] = fract(y[i] + (kVgprShifts ? dlv[k * D + i] : dl[k * D + i]));
             double v[T][NP];
             Fam::template eval<Tr, D, T>(prm, x, v);
             const bool ok = !kUniform || j < j1;
