@@ -61,7 +61,8 @@ __device__ constexpr bool wave_uniform_walk(long) {
 // scalars they compete with the integrand's coefficients for the 106 scalar
 // registers, and the compiler spills them into vector lanes, paying a
 // v_readlane per value and point; the run-time specialised sector functors
-// have vector registers to spare and ask for this.
+// have vector registers to spare and ask for this (for tiles of up to 24
+// values).
 template <class F>
 __device__ constexpr auto shifts_in_vgprs(int) -> decltype(F::kShiftsInVgprs, bool()) {
     return F::kShiftsInVgprs;
@@ -92,7 +93,8 @@ __device__ __forceinline__ void walk_points(uint32_t j, uint32_t j1, uint32_t S,
         step[i] = gs[i];
         nms[i] = n - gs[i];
     }
-    constexpr bool kVgprShifts = !Reload && shifts_in_vgprs<Fam>(0);
+    // (bounded: 24 doubles are 48 VGPRs; larger tiles keep the scalar copies)
+    constexpr bool kVgprShifts = !Reload && shifts_in_vgprs<Fam>(0) && T * D <= 24;
     double dlv[T * D];
     if constexpr (kVgprShifts) {
 #pragma unroll

@@ -276,7 +276,7 @@ def test_sector_real(Q, launch, jit):
 
 
 @pytest.mark.parametrize("jit", [0, 2])
-@pytest.mark.parametrize("d,n_u,n_f", [(2, 4, 5), (3, 17, 31), (8, 12, 30), (9, 40, 40)])
+@pytest.mark.parametrize("d,n_u,n_f", [(2, 4, 5), (3, 17, 31), (8, 12, 30), (9, 40, 40), (14, 12, 30)])
 def test_sector_real_shapes(Q, d, n_u, n_f, jit):
     res, q, est = _sector_case(Q, d, 16381, 5, n_u, n_f, 200 + d, jit=jit)
     assert np.all(_rel(q, est.q_re) < TOL)
