@@ -35,7 +35,7 @@ def flops_per_eval(workload: str) -> float:
 # HBM bytes per lattice-kernel launch from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy of known size); recorded for
 # the kernel as profiled (profiles/k_lattice_sector_jit_d6_n16777213_m32.md).
-TRAFFIC_BYTES = {"sector": 481280}
+TRAFFIC_BYTES = {"sector": 803840}
 
 
 def make_workload(name: str):
