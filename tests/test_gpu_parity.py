@@ -314,6 +314,29 @@ def test_sector_same_structure_new_values(Q):
     plan.close()
 
 
+@pytest.mark.parametrize("d,cplx,want", [(6, False, 4), (3, False, 4), (7, False, 2), (6, True, 2)])
+def test_specialised_default_tile(Q, d, cplx, want):
+    """The default shift tile of the specialised kernel: four shifts per
+    thread for real sectors up to d = 6, two for wider or complex ones; the
+    estimate matches the oracle's either way (m = 6 leaves a ragged last
+    tile at T = 4)."""
+    n, m = 16381, 6
+    tab = synth.sector_tables(300 + d, d, 12, 30, complex_kinematics=cplx)
+    g = O.korobov_vector(n, d, 5029)
+    sh = synth.shifts(300 + d, m, d)
+    plan = Q.Plan(d, n, g, sh, "baker")
+    _say(f"default tile d={d} complex={cplx}")
+    res, q = plan.integrate(Q.Params("sector", d, sector=tab))
+    T, _, used = plan.last_launch()
+    assert used and T == want
+    est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
+    ref = est.q if cplx else est.q_re
+    # a mixed-sign complex F: the bar is the oracle's own reordering floor
+    tol = max(TOL, 4 * _reorder_floor(tab, n, g, sh)) if cplx else TOL
+    assert np.all(_rel(q, ref) < tol), (_rel(q, ref).max(), tol)
+    plan.close()
+
+
 def _reorder_floor(tab, n, g, sh):
     """FP64 evaluation floor of a mixed-sign complex sector: the largest
     relative change of the oracle's Q_k when F's monomials are summed in
