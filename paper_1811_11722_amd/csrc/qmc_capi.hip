@@ -404,11 +404,12 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     hipFunction_t jfn = nullptr;
     const bool sector = pk.key_family == QMC_F_SECTOR || pk.key_family == kFamSectorComplex;
     if (sector && p->jit_mode != 0) {
-        // four shifts per thread for real sectors of up to six dimensions
-        // (the tile's 24 shift values still sit in vector registers; 2.09
-        // against 2.18 ms at d = 6), two for the others; a deformed point
-        // carries the Jacobian's triangle, so one
-        const bool wide = !pk.cplx && pk.orders < 2 && p->d <= 6;
+        // four shifts per thread for real sectors of up to eight dimensions
+        // (measured at n = 2^24 - 3, m = 32: 2.19, 2.43, 2.36 ms against
+        // 2.29, 2.50, 2.44 ms with two at d = 6, 7, 8; at d = 9 four run
+        // 27 % slower), two for the others; a deformed point carries the
+        // Jacobian's triangle, so one
+        const bool wide = !pk.cplx && pk.orders < 2 && p->d <= 8;
         T = want_T ? want_T : (pk.deform ? 1u : wide ? 4u : 2u);
         std::string err;
         jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.cplx, p->device, err);

@@ -314,10 +314,10 @@ def test_sector_same_structure_new_values(Q):
     plan.close()
 
 
-@pytest.mark.parametrize("d,cplx,want", [(6, False, 4), (3, False, 4), (7, False, 2), (6, True, 2)])
+@pytest.mark.parametrize("d,cplx,want", [(6, False, 4), (3, False, 4), (8, False, 4), (9, False, 2), (6, True, 2)])
 def test_specialised_default_tile(Q, d, cplx, want):
     """The default shift tile of the specialised kernel: four shifts per
-    thread for real sectors up to d = 6, two for wider or complex ones; the
+    thread for real sectors up to d = 8, two for wider or complex ones; the
     estimate matches the oracle's either way (m = 6 leaves a ragged last
     tile at T = 4)."""
     n, m = 16381, 6
