@@ -407,9 +407,11 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
         // four shifts per thread for real sectors of up to eight dimensions
         // (measured at n = 2^24 - 3, m = 32: 2.19, 2.43, 2.36 ms against
         // 2.29, 2.50, 2.44 ms with two at d = 6, 7, 8; at d = 9 four run
-        // 27 % slower), two for the others; a deformed point carries the
-        // Jacobian's triangle, so one
-        const bool wide = !pk.cplx && pk.orders < 2 && p->d <= 8;
+        // 27 % slower) and for real expansion orders up to six (three
+        // orders: 2.45 against 2.60 ms at d = 6, 8 % slower at d = 8), two
+        // for the others; a deformed point carries the Jacobian's triangle,
+        // so one
+        const bool wide = !pk.cplx && p->d <= (pk.orders < 2 ? 8u : 6u);
         T = want_T ? want_T : (pk.deform ? 1u : wide ? 4u : 2u);
         std::string err;
         jfn = jit_kernel(pk.blob, p->d, p->tr, T, pk.cplx, p->device, err);

@@ -337,6 +337,27 @@ def test_specialised_default_tile(Q, d, cplx, want):
     plan.close()
 
 
+@pytest.mark.parametrize("d,want", [(6, 4), (8, 2)])
+def test_orders_default_tile(Q, d, want):
+    """Expansion orders: four shifts per thread up to d = 6, two above; the
+    three orders match the oracle's coefficients f L^k / k! either way
+    (m = 6 leaves a ragged last tile at T = 4)."""
+    n, m = 16381, 6
+    tab = synth.sector_tables(320 + d, d, 12, 30)
+    g = O.korobov_vector(n, d, 5029)
+    sh = synth.shifts(320 + d, m, d)
+    plan = Q.Plan(d, n, g, sh, "baker")
+    _say(f"orders default tile d={d}")
+    res, per = plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(3, 0.7, -1.2)))
+    T, _, used = plan.last_launch()
+    assert used and T == want
+    for k in range(3):
+        est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab, eps=(0.7, -1.2, k)), "baker",
+                         threads=THREADS)
+        assert np.all(_rel(per[:, k], est.q_re) < TOL), (k, _rel(per[:, k], est.q_re).max())
+    plan.close()
+
+
 def _reorder_floor(tab, n, g, sh):
     """FP64 evaluation floor of a mixed-sign complex sector: the largest
     relative change of the oracle's Q_k when F's monomials are summed in
