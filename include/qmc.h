@@ -285,6 +285,7 @@ typedef struct {
     double ridge;         /* ridge relative to the mean diagonal (0 = 1e-5) */
     double tol;           /* stop when the relative loss improves less than this */
     uint64_t seed;        /* initial-factor seed */
+    uint32_t refine;      /* refinements per step against the FP64 residual (0 = 4, at most 8) */
 } qmc_cv_train_opts;
 
 typedef struct {
@@ -299,8 +300,9 @@ typedef struct {
    minimising sum_j (fhat_j - J_j g(z_j))^2 + lam |W[., i, .]|^2 with
    alternating least squares over the dimensions i.  Each step assembles its
    normal equations with BF16 MFMA (each feature rounded once, FP32
-   accumulation), factorises them in FP64 and refines the solution twice
-   against the FP32 residual; a sweep ends by balancing each rank's factor
+   accumulation), factorises them in FP64 and refines the solution (4 times
+   by default) against the FP64 residual, whose right-hand side comes from
+   the FP64 design matrix; a sweep ends by balancing each rank's factor
    norms.  lam = ridge times the mean diagonal; it must stay above the
    rounding of the assembled normal matrix for the refinement to converge.
    Training stops when a sweep improves the loss by less than tol (relative)
@@ -319,6 +321,63 @@ typedef struct {
    the real part's target scale, total device time. */
 qmc_status qmc_cv_train(qmc_plan_t train_plan, qmc_family family, const void *params, uint32_t R, uint32_t K,
                         const qmc_cv_train_opts *opts, double *w_out, double *c_out, qmc_cv_train_report *rep);
+
+/* The steps of one training update, callable on their own (same kernels as
+   qmc_cv_train).  Training samples are n points z (n, d) in [0,1]^d with
+   the transform's Jacobian sw (n) and the weighted targets yw = fhat (n),
+   all single precision, row-major.  For the dimension i being solved the
+   model is linear in W[., i, .] (c = 1):
+     sw_j g(z_j) = sum_{r,k} rho_j[r] phi_j[k] W[r,i,k],
+     rho_j[r] = sw_j prod_{i' != i} sum_k W[r,i',k] P~_k(z_{j,i'}),  phi_j[k] = P~_k(z_{j,i}),
+   so the step solves the ridge normal equations of the design matrix
+   A_j[u] = rho_j[r] phi_j[k], columns u = r K + k, F = R K.  The limits are
+   those of qmc_cv_train (d <= 12, the compiled (R, K) pairs, else
+   EUNSUPPORTED) and n <= 2^26.  All pointers are host memory, borrowed
+   for the call; the library allocates and frees its own device memory and
+   runs on the current device's null stream.  Not part of the paper (the
+   control variate is an addition to its estimator). */
+
+/* Training samples of the plan's lattice with its first shift: z_out
+   (n, d), sw_out (n), yw_out (n) = component `part` (0 real, 1 imaginary)
+   of fhat = J f(z), each rounded from FP64 to single precision. */
+qmc_status qmc_cv_samples(qmc_plan_t train_plan, qmc_family family, const void *params, uint32_t part,
+                          float *z_out, float *sw_out, float *yw_out);
+
+/* Design-matrix factors of dimension i in FP64: rho_out (n, R), phi_out
+   (n, K).  w: (R, d, K) orthonormal-basis factors. */
+qmc_status qmc_cv_features(uint32_t n, uint32_t d, uint32_t R, uint32_t K, uint32_t i, const float *z,
+                           const float *sw, const double *w, double *rho_out, double *phi_out);
+
+/* Normal equations of given factors rho (n, R), phi (n, K) and target y (n),
+   all FP64:
+     gram_out (F, F) = sum_j a~_j a~_j^T,  a~_j[u] = bf16(fl32(rho_j[r]) fl32(phi_j[k])),
+   BF16 matrix-core products with FP32 accumulation over at most
+   acc_len_out[0] points, then FP64 over those partial sums;
+     rhs_out (F) = sum_j (rho_j[r] phi_j[k]) y_j,
+   FP64 accumulation over at most acc_len_out[1] points, then FP64 over the
+   partial sums.  acc_len_out (nullable): 2 values. */
+qmc_status qmc_cv_normal(uint32_t n, uint32_t R, uint32_t K, const double *rho, const double *phi, const double *y,
+                         double *gram_out, double *rhs_out, uint32_t *acc_len_out);
+
+/* (G + lam I) x = b in FP64 by a blocked Cholesky factorisation on the
+   device.  gram: (F, F) symmetric (the lower triangle is read), rhs: F.
+   lam = ridge * trace(G) / F, multiplied by 100 at each non-positive pivot,
+   at most three times; lam_out (nullable) the value used, escalations
+   (nullable) how often it was raised.  x_out: F.  EINVAL on non-finite
+   input or ridge <= 0, ENONFINITE when G + lam I stays indefinite. */
+qmc_status qmc_cv_solve(uint32_t R, uint32_t K, const double *gram, const double *rhs, double ridge,
+                        double *lam_out, double *x_out, int32_t *escalations);
+
+/* One alternating-least-squares step for dimension i as qmc_cv_train runs
+   it: FP64 features, BF16 normal matrix, FP64 solve with lam = ridge times
+   the mean diagonal, then `refine` (<= 8) refinements against the FP64
+   residual y - A w with y = yw / scale (the right-hand side of each from the
+   FP64 design matrix, so the BF16 matrix only preconditions).  w_in: (R, d, K); w_out (R, d, K) the
+   same factors with W[., i, .] replaced; lam_out (nullable) the ridge
+   used. */
+qmc_status qmc_cv_als_step(uint32_t n, uint32_t d, uint32_t R, uint32_t K, uint32_t i, const float *z,
+                           const float *sw, const float *yw, double scale, const double *w_in, double ridge,
+                           uint32_t refine, double *w_out, double *lam_out);
 
 /* int g over [0,1]^d in closed form. */
 qmc_status qmc_cv_integral(uint32_t R, uint32_t d, uint32_t K, const double *w, const double *c, double *out);

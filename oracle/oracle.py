@@ -17,6 +17,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "qmc_oracle.c")
+SRC_CV = os.path.join(HERE, "qmc_oracle_cvtrain.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 FAMILIES = {
@@ -30,7 +31,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with plain gcc (no fast-math, no FP contraction)."""
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", SRC, "-o", LIB + ".tmp", "-lm", "-lpthread"]
+               "-shared", SRC, SRC_CV, "-o", LIB + ".tmp", "-lm", "-lpthread"]
         subprocess.check_call(cmd)
         os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -107,6 +108,22 @@ def lib() -> C.CDLL:
         L.or_korobov_search.argtypes = [u64, u32, vp, u32, i32, vp, vp, vp]
         L.or_cbc.restype = C.c_int
         L.or_cbc.argtypes = [u64, u32, vp, i32, vp, vp]
+        L.or_cv_samples.restype = C.c_int
+        L.or_cv_samples.argtypes = [u32, u64, vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.or_bf16.restype = C.c_float
+        L.or_bf16.argtypes = [C.c_float]
+        L.or_cv_features.restype = C.c_int
+        L.or_cv_features.argtypes = [u32, u32, u32, u32, u32, vp, vp, vp, vp, vp, vp]
+        L.or_cv_normal.restype = C.c_int
+        L.or_cv_normal.argtypes = [u32, u32, u32, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.or_cv_normal_at.restype = C.c_int
+        L.or_cv_normal_at.argtypes = [u32, u32, u32, vp, vp, vp, u32, vp, vp, vp, vp, vp, vp]
+        L.or_cv_solve.restype = C.c_int
+        L.or_cv_solve.argtypes = [u32, vp, vp, dbl, vp, vp]
+        L.or_cv_step.restype = C.c_int
+        L.or_cv_step.argtypes = [u32, u32, u32, u32, u32, vp, vp, vp, vp, dbl, i32, vp, vp]
+        L.or_cv_objective.restype = C.c_int
+        L.or_cv_objective.argtypes = [u32, u32, u32, u32, u32, vp, vp, vp, vp, dbl, vp, vp]
         _lib = L
     return _lib
 
@@ -325,3 +342,114 @@ def cbc(n: int, d: int, gamma=None, threads: int = 0):
         raise ValueError("bad cbc arguments")
     return z, e2
 
+
+
+# --------------------------------------------------------------- control-variate training
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def cv_samples(n: int, g, shift, params: Params, tkind: str = "none", alpha: int = 0):
+    """(z (n, d), J (n,), fhat (n,) complex) at the points {j g / n + shift}."""
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.uint64))
+    sh = _f64(shift)
+    d = g.size
+    z, jac, fr, fi = np.zeros((n, d)), np.zeros(n), np.zeros(n), np.zeros(n)
+    if lib().or_cv_samples(d, n, _ptr(g), _ptr(sh), TRANSFORMS[tkind], alpha, params.ref, _ptr(z), _ptr(jac),
+                           _ptr(fr), _ptr(fi)):
+        raise ValueError("bad cv_samples arguments")
+    return z, jac, fr + 1j * fi
+
+
+def bf16(x: float) -> float:
+    """x rounded to bfloat16 (nearest, ties to even), as a float."""
+    return float(lib().or_bf16(float(x)))
+
+
+def cv_features(z, sw, W, i: int):
+    """(rho (n, R), phi (n, K), env (n, R)) of the least-squares step for
+    dimension i, in double; z (n, d) and sw (n,) single precision."""
+    z, sw, W = _f32(z), _f32(sw), _f64(W)
+    n, d = z.shape
+    R, _, K = W.shape
+    rho, phi, env = np.zeros((n, R)), np.zeros((n, K)), np.zeros((n, R))
+    if lib().or_cv_features(n, d, R, K, i, _ptr(z), _ptr(sw), _ptr(W), _ptr(rho), _ptr(phi), _ptr(env)):
+        raise ValueError("bad cv_features arguments")
+    return rho, phi, env
+
+
+def cv_normal(rho, phi, y, threads: int = 0):
+    """Normal equations as the GPU assembles them from double rho, phi, y
+    (bfloat16 matrix of the single-precision factors, double right-hand
+    side), summed in long double: (G, b, |G|, |b|), rows and columns
+    u = r K + k."""
+    rho, phi, y = _f64(rho), _f64(phi), _f64(y)
+    n, R = rho.shape
+    K = phi.shape[1]
+    F = R * K
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    G, Ga, b, ba = np.zeros((F, F)), np.zeros((F, F)), np.zeros(F), np.zeros(F)
+    if lib().or_cv_normal(n, R, K, _ptr(rho), _ptr(phi), _ptr(y), threads, _ptr(G), _ptr(b), _ptr(Ga),
+                          _ptr(ba)):
+        raise ValueError("bad cv_normal arguments")
+    return G, b, Ga, ba
+
+
+def cv_normal_at(rho, phi, y, us, vs):
+    """Entries G[us, vs] and b[us] with their envelopes (sampled form)."""
+    rho, phi, y = _f64(rho), _f64(phi), _f64(y)
+    us = np.ascontiguousarray(np.asarray(us, dtype=np.uint32))
+    vs = np.ascontiguousarray(np.asarray(vs, dtype=np.uint32))
+    n, R = rho.shape
+    K = phi.shape[1]
+    c = us.size
+    G, Ga, b, ba = np.zeros(c), np.zeros(c), np.zeros(c), np.zeros(c)
+    if lib().or_cv_normal_at(n, R, K, _ptr(rho), _ptr(phi), _ptr(y), c, _ptr(us), _ptr(vs), _ptr(G), _ptr(Ga),
+                             _ptr(b), _ptr(ba)):
+        raise ValueError("bad cv_normal_at arguments")
+    return G, Ga, b, ba
+
+
+def cv_solve(G, b, ridge: float):
+    """(x, lam, escalations) of (G + lam I) x = b, lam = ridge trace(G) / F
+    (escalated 100x per non-positive pivot); escalations = -1 if it fails."""
+    G, b = _f64(G), _f64(b)
+    F = b.size
+    x = np.zeros(F)
+    lam = C.c_double()
+    esc = lib().or_cv_solve(F, _ptr(G), _ptr(b), float(ridge), C.byref(lam), _ptr(x))
+    return x, lam.value, int(esc)
+
+
+def cv_step(z, sw, y, W, i: int, ridge: float, threads: int = 0):
+    """One exact ridge least-squares step for dimension i: (W_new, lam);
+    y (n,) the double target."""
+    z, sw, y, W = _f32(z), _f32(sw), _f64(y), _f64(W)
+    n, d = z.shape
+    R, _, K = W.shape
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    out = np.zeros_like(W)
+    lam = C.c_double()
+    st = lib().or_cv_step(n, d, R, K, i, _ptr(z), _ptr(sw), _ptr(y), _ptr(W), float(ridge), threads, _ptr(out),
+                          C.byref(lam))
+    if st:
+        raise ValueError(f"cv_step failed ({st})")
+    return out, lam.value
+
+
+def cv_objective(z, sw, y, W, i: int, lam: float):
+    """(J, sum y^2): J = sum_j (y_j - sw_j g(z_j))^2 + lam |W[., i, .]|^2, c = 1."""
+    z, sw, y, W = _f32(z), _f32(sw), _f64(y), _f64(W)
+    n, d = z.shape
+    R, _, K = W.shape
+    J, sy = C.c_double(), C.c_double()
+    if lib().or_cv_objective(n, d, R, K, i, _ptr(z), _ptr(sw), _ptr(y), _ptr(W), float(lam), C.byref(J),
+                             C.byref(sy)):
+        raise ValueError("bad cv_objective arguments")
+    return J.value, sy.value

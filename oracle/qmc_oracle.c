@@ -338,6 +338,8 @@ void or_legendre(uint32_t K, double x, double *out)
 double or_cv_g(uint32_t d, uint32_t R, uint32_t K, const double *W, const double *c, const double *z)
 {
     double leg[64 * 32];
+    if (d > 64 || K > 32)
+        return NAN; /* beyond the sizes this routine holds */
     for (uint32_t i = 0; i < d; ++i)
         or_legendre(K, z[i], leg + i * K);
     double g = 0.0;
@@ -442,6 +444,10 @@ void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, d
             /* contour deformation: z = x - i lambda x (1 - x) grad F(x) */
             const double lam = p->deform_lambda;
             double complex zc[64], J[16 * 16];
+            if (d > 16) { /* the Jacobian array holds d <= 16 */
+                vr = vi = NAN;
+                break;
+            }
             double grad[64];
             int dk[64];
             for (uint32_t i = 0; i < d; ++i)
@@ -536,6 +542,30 @@ void or_fhat(const or_params *p, uint32_t d, int32_t tkind, int32_t alpha, const
     *im = vi * wprod;
 }
 
+/* Samples of the lattice {j g / n + shift}, j = 0..n-1, for fitting a
+   control variate: the transformed point z (n, d), the Jacobian
+   J = prod_i z_i'(x_i) (n) and fhat = J f(z) (n, re and im). */
+int or_cv_samples(uint32_t d, uint64_t n, const uint64_t *g, const double *shift, int32_t tkind,
+                  int32_t alpha, const or_params *p, double *z, double *jac, double *f_re,
+                  double *f_im)
+{
+    if (d == 0 || d > 64)
+        return 1;
+    double x[64];
+    for (uint64_t j = 0; j < n; ++j) {
+        or_point(d, n, g, j, shift, p->point_mode, x);
+        double wprod = 1.0;
+        for (uint32_t i = 0; i < d; ++i) {
+            double w;
+            or_transform(tkind, alpha, x[i], &z[j * d + i], &w);
+            wprod *= w;
+        }
+        jac[j] = wprod;
+        or_fhat(p, d, tkind, alpha, x, &f_re[j], &f_im[j]);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Compensated long-double accumulation                                 */
 /* ------------------------------------------------------------------ */
@@ -612,6 +642,12 @@ int or_estimate(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const dou
                 double *q_im, double *q_abs)
 {
     if (d == 0 || d > 64 || n < 1 || m < 1)
+        return 1;
+    /* the deformed sector holds its d x d Jacobian in a 16 x 16 array, the
+       control-variate model at most 32 Legendre degrees */
+    if (p->family == OR_F_SECTOR && p->deform_lambda != 0.0 && d > 16)
+        return 1;
+    if ((p->cv_w != NULL || p->cv_w_im != NULL) && p->cv_k > 32)
         return 1;
     or_job jb;
     jb.d = d;

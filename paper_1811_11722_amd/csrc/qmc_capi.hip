@@ -464,6 +464,33 @@ qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per
     return QMC_OK;
 }
 
+// The conditions of a rule (eq. (2)) every entry point that takes one
+// checks before any device call; t.alpha is cleared for transforms
+// without a parameter.
+qmc_status validate_rule(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
+                         qmc_transform &t) {
+    if (d == 0) return fail(QMC_EINVAL, "d must be >= 1");
+    if (d > kMaxDim) return fail(QMC_EUNSUPPORTED, "d = %u > %u", d, kMaxDim);
+    if (n < 2) return fail(QMC_EINVAL, "n must be >= 2");
+    if (n > (1ull << 31)) return fail(QMC_EUNSUPPORTED, "n > 2^31");
+    if (!g) return fail(QMC_EINVAL, "g is NULL");
+    for (uint32_t i = 0; i < d; ++i)
+        if (g[i] % n == 0) return fail(QMC_EINVAL, "g_%u mod n == 0", i);
+    if (m < 2) return fail(QMC_EINVAL, "m must be >= 2 (eq. (3) divides by m - 1)");
+    if (m > kMaxRows) return fail(QMC_EUNSUPPORTED, "m > %u", kMaxRows);
+    if (!shifts) return fail(QMC_EINVAL, "shifts is NULL");
+    for (size_t i = 0; i < (size_t)m * d; ++i)
+        if (!(shifts[i] >= 0.0 && shifts[i] < 1.0)) return fail(QMC_EINVAL, "shift %zu outside [0,1)", i);
+    if (t.kind != QMC_T_NONE && t.kind != QMC_T_KOROBOV && t.kind != QMC_T_BAKER && t.kind != QMC_T_SIDI)
+        return fail(QMC_EINVAL, "unknown transform %d", t.kind);
+    if (t.kind == QMC_T_KOROBOV && t.alpha < 1) return fail(QMC_EINVAL, "Korobov weight must be >= 1");
+    if (t.kind == QMC_T_KOROBOV && t.alpha > 6) return fail(QMC_EUNSUPPORTED, "Korobov weight > 6");
+    if (t.kind == QMC_T_SIDI && t.alpha < 1) return fail(QMC_EINVAL, "Sidi order must be >= 1");
+    if (t.kind == QMC_T_SIDI && t.alpha > 6) return fail(QMC_EUNSUPPORTED, "Sidi order > 6");
+    if (t.kind != QMC_T_KOROBOV && t.kind != QMC_T_SIDI) t.alpha = 0;
+    return QMC_OK;
+}
+
 }  // namespace qmc
 
 using namespace qmc;
@@ -488,25 +515,8 @@ const char *qmc_last_error(void) { return g_last_error.c_str(); }
 qmc_status qmc_plan_create(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
                            qmc_transform t, qmc_plan_t *out) {
     if (!out) return fail(QMC_EINVAL, "out is NULL");
-    if (d == 0) return fail(QMC_EINVAL, "d must be >= 1");
-    if (d > kMaxDim) return fail(QMC_EUNSUPPORTED, "d = %u > %u", d, kMaxDim);
-    if (n < 2) return fail(QMC_EINVAL, "n must be >= 2");
-    if (n > (1ull << 31)) return fail(QMC_EUNSUPPORTED, "n > 2^31");
-    if (!g) return fail(QMC_EINVAL, "g is NULL");
-    for (uint32_t i = 0; i < d; ++i)
-        if (g[i] % n == 0) return fail(QMC_EINVAL, "g_%u mod n == 0", i);
-    if (m < 2) return fail(QMC_EINVAL, "m must be >= 2 (eq. (3) divides by m - 1)");
-    if (m > kMaxRows) return fail(QMC_EUNSUPPORTED, "m > %u", kMaxRows);
-    if (!shifts) return fail(QMC_EINVAL, "shifts is NULL");
-    for (size_t i = 0; i < (size_t)m * d; ++i)
-        if (!(shifts[i] >= 0.0 && shifts[i] < 1.0)) return fail(QMC_EINVAL, "shift %zu outside [0,1)", i);
-    if (t.kind != QMC_T_NONE && t.kind != QMC_T_KOROBOV && t.kind != QMC_T_BAKER && t.kind != QMC_T_SIDI)
-        return fail(QMC_EINVAL, "unknown transform %d", t.kind);
-    if (t.kind == QMC_T_KOROBOV && t.alpha < 1) return fail(QMC_EINVAL, "Korobov weight must be >= 1");
-    if (t.kind == QMC_T_KOROBOV && t.alpha > 6) return fail(QMC_EUNSUPPORTED, "Korobov weight > 6");
-    if (t.kind == QMC_T_SIDI && t.alpha < 1) return fail(QMC_EINVAL, "Sidi order must be >= 1");
-    if (t.kind == QMC_T_SIDI && t.alpha > 6) return fail(QMC_EUNSUPPORTED, "Sidi order > 6");
-    if (t.kind != QMC_T_KOROBOV && t.kind != QMC_T_SIDI) t.alpha = 0;
+    qmc_status vs = validate_rule(d, n, g, m, shifts, t);
+    if (vs) return vs;
 
     auto *p = new (std::nothrow) qmc_plan_s();
     if (!p) return fail(QMC_ENOMEM, "host allocation");

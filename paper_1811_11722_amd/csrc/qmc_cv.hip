@@ -17,6 +17,7 @@
 // training; the trained model is evaluated in FP64 inside the estimator.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "qmc_cv.hpp"
 #include "qmc_runtime.hpp"
@@ -27,36 +28,38 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------- kernels
+// Design-matrix factors of dimension i in FP64:
+//   rho_j[r] = sw_j prod_{i' != i} h_{r,i'}(z_{j,i'}),  phi_j[k] = P~_k(z_{j,i}).
 struct CvRhoArgs {
     uint32_t n, d, i;       // points, dimension, the dimension being solved
     const float *z, *sw;    // (n, d), (n)
-    const float *ws;        // W * sqrt(2k+1), (R, d, K)
-    float *rho;             // (n, R): sw prod_{i' != i} h_{r,i'}
-    float *phi;             // (n, K): P~_k(z_i) (normalised)
+    const double *ws;       // W * sqrt(2k+1), (R, d, K)
+    double *rho;            // (n, R)
+    double *phi;            // (n, K) (normalised)
 };
 
 template <int R, int K>
 __global__ __launch_bounds__(kBlock) void k_cv_rho(const CvRhoArgs a) {
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= a.n) return;
-    float prod[R];
-    const float s = a.sw[j];
+    double prod[R];
+    const double s = a.sw[j];
 #pragma unroll
     for (int r = 0; r < R; ++r) prod[r] = s;
     for (uint32_t i = 0; i < a.d; ++i) {
-        float p[K];
-        legendre_raw<K, float>(a.z[(size_t)j * a.d + i], p);
+        double p[K];
+        legendre_raw<K, double>((double)a.z[(size_t)j * a.d + i], p);
         if (i == a.i) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) a.phi[(size_t)j * K + k] = p[k] * sqrtf((float)(2 * k + 1));
+            for (int k = 0; k < K; ++k) a.phi[(size_t)j * K + k] = p[k] * sqrt((double)(2 * k + 1));
             continue;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float *w = a.ws + ((size_t)r * a.d + i) * K;
-            float h = w[K - 1] * p[K - 1];
+            const double *w = a.ws + ((size_t)r * a.d + i) * K;
+            double h = w[K - 1] * p[K - 1];
 #pragma unroll
-            for (int k = K - 2; k >= 0; --k) h = __builtin_fmaf(w[k], p[k], h);
+            for (int k = K - 2; k >= 0; --k) h = fma(w[k], p[k], h);
             prod[r] *= h;
         }
     }
@@ -64,158 +67,354 @@ __global__ __launch_bounds__(kBlock) void k_cv_rho(const CvRhoArgs a) {
     for (int r = 0; r < R; ++r) a.rho[(size_t)j * R + r] = prod[r];
 }
 
-// One wave job: `count` Gram blocks (k, k0 + q) for row block rb and column
-// block cb of rho (type 0), or the right-hand side block rb (type 1).
-struct CvJob {
-    uint32_t type, k, k0, count, rb, cb, slot0, pad;
+// ----------------------------------------------------------- Gram (SYRK)
+// A~^T A~ for the BF16 design matrix a~_j[u'] = bf16(fl32(rho_j[r]) fl32(phi_j[k]))
+// with the columns in the order u' = k R + r (a block of 32 consecutive
+// columns is one k when R >= 32).  The lower triangle of the NB x NB grid of
+// 32 x 32 tiles (NB = R K / 32) is split into tasks (grid.y).  A task gives
+// each of its 4 waves one region of tiles: rows [r0, r0 + NR) x columns
+// [c0, c0 + NC) of the block grid, the lower part only for a diagonal region
+// (then the rows lie inside the columns).  The region shapes are fixed per
+// task type at compile time (at most 11 tiles, 176 accumulator registers per
+// lane, so two workgroups fit on a CU); the bases come with the task.  A
+// workgroup runs one task over one contiguous range of points (grid.x), 64
+// points per round:
+//   1. the round's rho, phi go to LDS as FP32 (the next round's are loaded
+//      into registers meanwhile),
+//   2. wave w builds the BF16 fragments of points 16 w .. 16 w + 15 for the
+//      task's blocks [blo, bhi) into LDS (v_mfma_f32_32x32x16_bf16 operand
+//      layout: lane l holds column 32 b + l % 32 of points 8 (l / 32) .. +7;
+//      the same fragment serves as A or B),
+//   3. every wave accumulates its tiles over the 4 steps of 16 points.
+// The tiles' FP32 sums go to partial[split][slot], slot = bu (bu + 1) / 2 + bv
+// for the tile (bu >= bv).
+struct CvSyrkTask {
+    uint32_t type, blo, bhi;
+    uint32_t r0[4], c0[4];
 };
-constexpr int kMaxJobCount = 4;
 
-struct CvGramArgs {
-    uint32_t n, R, K;
-    uint32_t job0, njobs, nslots, splits;  // jobs job0 .. njobs-1 run
-    float inv_scale;        // 1 / target scale
-    const float *rho, *phi, *yw;
-    const CvJob *jobs;
-    float *partial;         // (splits, nslots, 32, 32)
+struct CvSyrkArgs {
+    uint32_t n, splits, nslots;
+    const double *rho, *phi;
+    const CvSyrkTask *tasks;
+    float *partial;  // (splits, nslots, 32, 32)
 };
 
-__global__ __launch_bounds__(kBlock) void k_cv_gram(const CvGramArgs a) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t jid = a.job0 + blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (jid >= a.njobs) return;  // whole wave leaves together
-    const CvJob job = a.jobs[jid];
-    const uint32_t half = lane >> 5, col = lane & 31;
-    const uint32_t ra = job.rb * 32 + col;  // rho column held as an A row
-    const uint32_t rbcol = job.cb * 32 + col;
-    const uint32_t j_begin = (uint32_t)((uint64_t)a.n * blockIdx.y / a.splits);
-    const uint32_t j_end = (uint32_t)((uint64_t)a.n * (blockIdx.y + 1) / a.splits);
-    f32x16 acc[kMaxJobCount];
-#pragma unroll
-    for (int q = 0; q < kMaxJobCount; ++q)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
+constexpr int kSyrkPts = 64;  // points per round (4 steps of 16)
+constexpr int kSyrkMaxTiles = 11;
 
-    // Every feature a_j[(r, k)] = rho_j[r] phi_j[k] is rounded to BF16 once,
-    // the same way in both operands, so the assembled matrix is exactly
-    // sum_j a~_j a~_j^T (positive semi-definite up to FP32 accumulation).
-    for (uint32_t base = j_begin; base < j_end; base += 16) {
-        float rv[8], s[8];
-        bf16x8 b, av;
+// region shapes (NR rows, NC columns, lower part only) of the 4 waves
+template <int NR0, int NC0, bool D0, int NR1, int NC1, bool D1, int NR2, int NC2, bool D2, int NR3, int NC3, bool D3>
+struct SyrkShapes {
+    static constexpr int NR[4] = {NR0, NR1, NR2, NR3}, NC[4] = {NC0, NC1, NC2, NC3};
+    static constexpr bool DG[4] = {D0, D1, D2, D3};
+};
+// triangles of 1, 2, 4, 6, 8 blocks in one task
+using ShapeTri1 = SyrkShapes<1, 1, true, 0, 0, false, 0, 0, false, 0, 0, false>;
+using ShapeTri2 = SyrkShapes<1, 1, true, 1, 1, true, 1, 1, false, 0, 0, false>;
+using ShapeTri4 = SyrkShapes<2, 2, true, 2, 2, true, 1, 2, false, 1, 2, false>;
+using ShapeTri6 = SyrkShapes<3, 3, true, 3, 3, true, 2, 3, false, 1, 3, false>;
+using ShapeTri8 = SyrkShapes<4, 4, true, 4, 4, true, 2, 4, false, 2, 4, false>;
+// half of a triangle of 12 blocks (two tasks cover it)
+using ShapeHalf12 = SyrkShapes<4, 4, true, 2, 6, true, 3, 3, false, 3, 3, false>;
+// rectangles: 8 x 4 and 6 x 6 blocks
+using ShapeRect8x4 = SyrkShapes<2, 4, false, 2, 4, false, 2, 4, false, 2, 4, false>;
+using ShapeRect6x6 = SyrkShapes<3, 3, false, 3, 3, false, 3, 3, false, 3, 3, false>;
+
+template <class S, int W>
+constexpr int syrk_tiles() {
+    int t = 0;
+    for (int i = 0; i < S::NR[W]; ++i)
+        for (int j = 0; j < S::NC[W]; ++j)
+            if (!S::DG[W] || j <= i + (S::NC[W] - S::NR[W])) ++t;
+    return t;
+}
+
+// One step of 16 points for wave W: load the region's column fragments
+// (rows of a diagonal region are among them), accumulate its tiles.  In a
+// diagonal region, row i is block r0 + i = c0 + (NC - NR) + i.
+template <class S, int W>
+__device__ __forceinline__ void syrk_step(const bf16x8 *fr, uint32_t lane, uint32_t r0, uint32_t c0,
+                                          f32x16 (&acc)[kSyrkMaxTiles]) {
+    constexpr int NR = S::NR[W], NC = S::NC[W];
+    static_assert(syrk_tiles<S, W>() <= kSyrkMaxTiles, "too many tiles for one wave");
+    if constexpr (NR > 0) {
+        bf16x8 fb[NC];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const uint32_t j = base + 8 * half + e;
-            const bool ok = j < j_end;
-            rv[e] = (ok && ra < a.R) ? a.rho[(size_t)j * a.R + ra] : 0.0f;
-            if (job.type == 0) {
-                s[e] = (ok && rbcol < a.R) ? a.rho[(size_t)j * a.R + rbcol] : 0.0f;
-                const float pk = ok ? a.phi[(size_t)j * a.K + job.k] : 0.0f;
-                av[e] = (__bf16)(rv[e] * pk);
-            } else {
-                const float ph = (ok && col < a.K) ? a.phi[(size_t)j * a.K + col] : 0.0f;
-                b[e] = (__bf16)ph;
-                s[e] = ok ? a.yw[j] * a.inv_scale : 0.0f;
-            }
-        }
-        if (job.type == 0) {
+        for (int j = 0; j < NC; ++j) fb[j] = fr[(c0 + j) * (4 * kWave) + lane];
+        int t = 0;
+        if constexpr (S::DG[W]) {
 #pragma unroll
-            for (int q = 0; q < kMaxJobCount; ++q) {
-                if ((uint32_t)q < job.count) {
+            for (int i = 0; i < NR; ++i)
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const uint32_t j = base + 8 * half + e;
-                        const float pk2 = j < j_end ? a.phi[(size_t)j * a.K + job.k0 + q] : 0.0f;
-                        b[e] = (__bf16)(s[e] * pk2);
-                    }
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b, acc[q], 0, 0, 0);
-                }
-            }
+                for (int j = 0; j <= i + (NC - NR); ++j, ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fb[i + (NC - NR)], fb[j], acc[t], 0, 0, 0);
         } else {
+            bf16x8 fa[NR];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = (__bf16)(rv[e] * s[e]);
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b, acc[0], 0, 0, 0);
-        }
-    }
-    // accumulator layout of the 32x32 tile: register e of lane l holds
-    // row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
-    const uint32_t nq = job.type == 0 ? job.count : 1;
-    for (uint32_t q = 0; q < nq; ++q) {
-        float *out = a.partial + (((size_t)blockIdx.y * a.nslots + job.slot0 + q) << 10);
+            for (int i = 0; i < NR; ++i) fa[i] = fr[(r0 + i) * (4 * kWave) + lane];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint32_t row = 8 * (e / 4) + 4 * half + (e % 4);
-            out[row * 32 + col] = acc[q][e];
+            for (int i = 0; i < NR; ++i)
+#pragma unroll
+                for (int j = 0; j < NC; ++j, ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[t], 0, 0, 0);
         }
     }
 }
 
-// sum the per-split tiles of slots first .. nslots-1 in split order, in FP64
-__global__ __launch_bounds__(kBlock) void k_cv_reduce(const float *partial, uint32_t splits, uint32_t nslots,
-                                                     uint32_t first, double *out) {
-    const uint32_t t = (first << 10) + blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t total = nslots << 10;
-    if (t >= total) return;
+template <class S, int W>
+__device__ __forceinline__ void syrk_store(uint32_t lane, uint32_t r0, uint32_t c0,
+                                           const f32x16 (&acc)[kSyrkMaxTiles], float *out) {
+    constexpr int NR = S::NR[W], NC = S::NC[W];
+    const uint32_t half = lane >> 5, col = lane & 31;
+    int t = 0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            if (S::DG[W] && j > i + (NC - NR)) continue;
+            const uint32_t bu = S::DG[W] ? c0 + (NC - NR) + i : r0 + i, bv = c0 + j;
+            float *o = out + (((size_t)bu * (bu + 1) / 2 + bv) << 10);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) o[(8 * (e / 4) + 4 * half + (e % 4)) * 32 + col] = acc[t][e];
+            ++t;
+        }
+}
+
+template <int R, int K, class S>
+__device__ __forceinline__ void syrk_task(const CvSyrkArgs &a, const CvSyrkTask &task, float *srho, float *sphi,
+                                          bf16x8 *frag) {
+    constexpr int NV = (kSyrkPts * (R + K) + kBlock - 1) / kBlock;  // staged values per thread
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t j_begin = (uint32_t)((uint64_t)a.n * blockIdx.x / a.splits);
+    const uint32_t j_end = (uint32_t)((uint64_t)a.n * (blockIdx.x + 1) / a.splits);
+    // the wave's bases straight from memory (indexing a private copy by the
+    // wave number would put it in scratch)
+    const uint32_t r0 = a.tasks[blockIdx.y].r0[wave], c0 = a.tasks[blockIdx.y].c0[wave];
+
+    f32x16 acc[kSyrkMaxTiles];
+#pragma unroll
+    for (int t = 0; t < kSyrkMaxTiles; ++t)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+
+    // value v of a round: v < 64 R -> rho[p][r], else phi[p][k]
+    double nxt[NV];
+    auto load_round = [&](uint32_t base) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const uint32_t v = tid + q * kBlock;
+            double x = 0.0;
+            if (v < (uint32_t)(kSyrkPts * R)) {
+                if (base + v / R < j_end) x = a.rho[(size_t)base * R + v];
+            } else if (v < (uint32_t)(kSyrkPts * (R + K))) {
+                const uint32_t w = v - kSyrkPts * R;
+                if (base + w / K < j_end) x = a.phi[(size_t)base * K + w];
+            }
+            nxt[q] = x;
+        }
+    };
+    if (j_begin < j_end) load_round(j_begin);
+    for (uint32_t base = j_begin; base < j_end; base += kSyrkPts) {
+        __syncthreads();  // the previous round's fragments are consumed
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const uint32_t v = tid + q * kBlock;
+            if (v < (uint32_t)(kSyrkPts * R)) srho[v] = (float)nxt[q];
+            else if (v < (uint32_t)(kSyrkPts * (R + K))) sphi[v - kSyrkPts * R] = (float)nxt[q];
+        }
+        if (base + kSyrkPts < j_end) load_round(base + kSyrkPts);
+        __syncthreads();
+        {
+            const uint32_t half = lane >> 5, c = lane & 31;
+            for (uint32_t b = task.blo; b < task.bhi; ++b) {
+                const uint32_t u = 32 * b + c, k = u / R, r = u - k * R;
+                bf16x8 f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t p = 16 * wave + 8 * half + e;
+                    f[e] = (__bf16)(srho[p * R + r] * sphi[p * K + k]);
+                }
+                frag[(b * 4 + wave) * kWave + lane] = f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bf16x8 *fr = frag + s * kWave;
+            switch (wave) {
+            case 0: syrk_step<S, 0>(fr, lane, r0, c0, acc); break;
+            case 1: syrk_step<S, 1>(fr, lane, r0, c0, acc); break;
+            case 2: syrk_step<S, 2>(fr, lane, r0, c0, acc); break;
+            default: syrk_step<S, 3>(fr, lane, r0, c0, acc); break;
+            }
+        }
+    }
+    float *out = a.partial + (size_t)blockIdx.x * a.nslots * 1024;
+    switch (wave) {
+    case 0: syrk_store<S, 0>(lane, r0, c0, acc, out); break;
+    case 1: syrk_store<S, 1>(lane, r0, c0, acc, out); break;
+    case 2: syrk_store<S, 2>(lane, r0, c0, acc, out); break;
+    default: syrk_store<S, 3>(lane, r0, c0, acc, out); break;
+    }
+}
+
+// S0: shapes of task type 0, S1 of type 1 (void: none); NB blocks of fragments in LDS
+template <int R, int K, class S0, class S1>
+__global__ __launch_bounds__(kBlock, 2) void k_cv_syrk(const CvSyrkArgs a) {
+    constexpr int NB = R * K / 32;
+    __shared__ float srho[kSyrkPts * R], sphi[kSyrkPts * K];
+    __shared__ bf16x8 frag[NB * 4 * kWave];
+    const CvSyrkTask task = a.tasks[blockIdx.y];
+    if (task.type == 0) {
+        syrk_task<R, K, S0>(a, task, srho, sphi, frag);
+    } else if constexpr (!std::is_same<S1, void>::value) {
+        syrk_task<R, K, S1>(a, task, srho, sphi, frag);
+    }
+}
+
+// Sum the per-split tiles in split order, in FP64, into the lower triangle
+// of the normal matrix A0 (F x F row-major, rows and columns u = r K + k):
+// row u = blockIdx.y, column v = blockIdx.x * kBlock + thread.  Column u of
+// A0 is column u' = k R + r of the tiles.
+__global__ __launch_bounds__(kBlock) void k_cv_gather(const float *partial, uint32_t splits, uint32_t nslots,
+                                                     uint32_t R, uint32_t K, double *A0) {
+    // one wave per entry (u, v), v <= u: lanes take splits lane, lane + 64,
+    // ... in order, then a fixed butterfly over the lanes
+    const uint32_t F = R * K, lane = threadIdx.x & (kWave - 1);
+    const uint64_t e = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (e >= (uint64_t)F * (F + 1) / 2) return;
+    uint32_t u = (uint32_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+    while ((uint64_t)u * (u + 1) / 2 > e) --u;
+    while ((uint64_t)(u + 1) * (u + 2) / 2 <= e) ++u;
+    const uint32_t v = (uint32_t)(e - (uint64_t)u * (u + 1) / 2);
+    const uint32_t r = u / K, k = u - r * K, rp = v / K, kp = v - rp * K;
+    uint32_t a = k * R + r, b = kp * R + rp;
+    if (a < b) {
+        const uint32_t t = a;
+        a = b;
+        b = t;
+    }
+    const uint32_t ba = a / 32, bb = b / 32;
+    const size_t o = (((size_t)ba * (ba + 1) / 2 + bb) << 10) + (a % 32) * 32 + b % 32;
     double s = 0.0;
-    for (uint32_t sp = 0; sp < splits; ++sp) s += (double)partial[(size_t)sp * total + t];
-    out[t] = s;
+    for (uint32_t sp = lane; sp < splits; sp += kWave) s += (double)partial[(size_t)sp * nslots * 1024 + o];
+#pragma unroll
+    for (int w = kWave / 2; w > 0; w >>= 1) s += __shfl_xor(s, w);
+    if (lane == 0) A0[(size_t)u * F + v] = s;
 }
 
-// residual of the current fit of dimension i in FP32 arithmetic:
+// Right-hand side partial sums of the FP64 design matrix:
+//   part[split][u] = sum_{j in split} (rho_j[r] phi_j[k]) y_j,  u = r K + k,
+// y_j = yd_j, or yf_j * y_scale when yd is null; FP64, points in order (one
+// thread per column; a block of 32 points is staged in LDS).
+// R <= 64, K <= 16, R K <= 3 kBlock.
+constexpr uint32_t kRhsStage = 32;
+__global__ __launch_bounds__(kBlock) void k_cv_rhs(uint32_t n, uint32_t R, uint32_t K, uint32_t splits,
+                                                  const double *rho, const double *phi, const float *yf,
+                                                  double y_scale, const double *yd, double *part) {
+    const uint32_t F = R * K, tid = threadIdx.x;
+    const uint32_t j0 = (uint32_t)((uint64_t)n * blockIdx.x / splits);
+    const uint32_t j1 = (uint32_t)((uint64_t)n * (blockIdx.x + 1) / splits);
+    __shared__ double srho[kRhsStage * 64], sphi[kRhsStage * 16], sy[kRhsStage];
+    double acc[3] = {0.0, 0.0, 0.0};
+    uint32_t ru[3], ku[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const uint32_t u = tid + q * kBlock;
+        ru[q] = u < F ? u / K : 0;
+        ku[q] = u < F ? u % K : 0;
+    }
+    for (uint32_t base = j0; base < j1; base += kRhsStage) {
+        const uint32_t cnt = min(kRhsStage, j1 - base);
+        __syncthreads();
+        for (uint32_t t = tid; t < cnt * R; t += kBlock) srho[t] = rho[(size_t)base * R + t];
+        for (uint32_t t = tid; t < cnt * K; t += kBlock) sphi[t] = phi[(size_t)base * K + t];
+        if (tid < cnt) sy[tid] = yd ? yd[base + tid] : (double)yf[base + tid] * y_scale;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (tid + q * kBlock < F) {
+                double s = acc[q];
+                for (uint32_t p = 0; p < cnt; ++p) s = fma(srho[p * R + ru[q]] * sphi[p * K + ku[q]], sy[p], s);
+                acc[q] = s;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (tid + q * kBlock < F) part[(size_t)blockIdx.x * F + tid + q * kBlock] = acc[q];
+}
+
+// b[u] = sum over splits of the right-hand side partials: one wave per
+// column, lanes take splits lane, lane + 64, ... in order, then a fixed
+// butterfly over the lanes
+__global__ __launch_bounds__(kBlock) void k_cv_rhs_reduce(const double *part, uint32_t splits, uint32_t F, double *b) {
+    const uint32_t u = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    if (u >= F) return;
+    double s = 0.0;
+    for (uint32_t sp = lane; sp < splits; sp += kWave) s += part[(size_t)sp * F + u];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) b[u] = s;
+}
+
+// residual of the current fit of dimension i in FP64:
 //   e_j = yw_j / scale - sum_{r,k} rho_j[r] phi_j[k] W[r,i,k]
 // (the right-hand side of a refinement step is A^T e)
 template <int R, int K>
-__global__ __launch_bounds__(kBlock) void k_cv_resid(uint32_t n, uint32_t d, uint32_t i, const float *rho,
-                                                    const float *phi, const float *yw, float inv_scale,
-                                                    const double *w64, float *e) {
+__global__ __launch_bounds__(kBlock) void k_cv_resid(uint32_t n, uint32_t d, uint32_t i, const double *rho,
+                                                    const double *phi, const float *yw, double inv_scale,
+                                                    const double *w64, double *e) {
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
-    float ph[K];
+    double ph[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) ph[k] = phi[(size_t)j * K + k];
-    float g = 0.0f;
+    double g = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const double *w = w64 + ((size_t)r * d + i) * K;
-        float h = 0.0f;
+        double h = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) h = __builtin_fmaf((float)w[k], ph[k], h);
-        g = __builtin_fmaf(rho[(size_t)j * R + r], h, g);
+        for (int k = 0; k < K; ++k) h = fma(w[k], ph[k], h);
+        g = fma(rho[(size_t)j * R + r], h, g);
     }
-    e[j] = yw[j] * inv_scale - g;
+    e[j] = (double)yw[j] * inv_scale - g;
 }
 
 struct CvSolveArgs {
-    uint32_t R, K, d, i, nslots_pair_base, rhs_slot0, RB;
+    uint32_t R, K, d, i;
     double ridge;           // relative to the mean diagonal
     int refine;             // 1: reuse the factor in A and add the solution to W[., i, .]
     double *lam;            // absolute ridge of the current factorisation
-    const double *tiles;    // (nslots, 32, 32)
-    const uint32_t *pair_slot;  // (K, K): slot of the first (rb, cb) tile of pair (min, max)
-    double *A;              // (F, F) scratch, F = R K
+    const double *A0;       // (F, F) assembled normal matrix, lower triangle
+    const double *b;        // (F) right-hand side
+    double *A;              // (F, F) factor, F = R K
     double *w64;            // (R, d, K) model, normalised basis
-    float *ws32;            // (R, d, K) model times sqrt(2k+1)
-    int *status;            // 0 ok, 1 not positive definite
+    double *ws;             // (R, d, K) model times sqrt(2k+1)
+    int *status;            // number of ridge escalations, or -1: not positive definite
 };
 
 // One workgroup solves the normal equations of dimension i.
 //
-// Assembly: the lower triangle of A (F x F, F = R K, row-major in HBM) is
-// gathered from the Gram tiles, plus the ridge lam = ridge * trace / F.
-// Factorisation: blocked right-looking Cholesky, A = L L^T in place.  Each
-// panel of kPanel columns is loaded into LDS and factorised there; the
-// trailing lower triangle is then updated by A -= P P^T, each thread owning
-// 4 x 4 blocks.  A non-positive pivot restarts the factorisation with a 100x
-// larger ridge (at most three times).  Solves: blocked forward and backward
-// substitution in LDS.  A refinement call (refine = 1) reuses the factor
-// left in A, solves (A + lam I) delta = A^T e - lam w and adds delta to
-// W[., i, .].
+// Assembly: the lower triangle of A0 is copied to A plus the ridge
+// lam = ridge * trace / F.  Factorisation: blocked right-looking Cholesky,
+// A = L L^T in place.  Each panel of kPanel columns is loaded into LDS and
+// factorised there; the trailing lower triangle is then updated by
+// A -= P P^T, each thread owning 4 x 4 blocks.  A non-positive pivot
+// restarts the factorisation with a 100x larger ridge (at most three
+// times).  Solves: blocked forward and backward substitution in LDS.  A
+// refinement call (refine = 1) reuses the factor left in A, solves
+// (A + lam I) delta = b - lam w (b = A^T e of the current residual e) and
+// adds delta to W[., i, .].
 constexpr uint32_t kPanel = 8;
 constexpr uint32_t kMaxF = 768;  // largest R K compiled: (64, 12)
 
 __device__ void cv_load_rhs(const CvSolveArgs &a, uint32_t F, double *y, double lam) {
     for (uint32_t u = threadIdx.x; u < F; u += blockDim.x) {
         const uint32_t r = u / a.K, k = u - r * a.K;
-        double v = a.tiles[((size_t)(a.rhs_slot0 + r / 32) << 10) + (r % 32) * 32 + k];
+        double v = a.b[u];
         if (a.refine) v -= lam * a.w64[((size_t)r * a.d + a.i) * a.K + k];
         y[u] = v;
     }
@@ -231,23 +430,11 @@ __global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
 
     if (!a.refine) {
         double ridge = a.ridge;
-        for (int attempt = 0; attempt < 4; ++attempt, ridge *= 100.0) {
+        int attempt = 0;
+        for (; attempt < 4; ++attempt, ridge *= 100.0) {
             // lower triangle of the normal matrix
-            for (uint32_t u = tid / 32; u < F; u += nt / 32) {
-                const uint32_t r = u / a.K, k = u - r * a.K;
-                for (uint32_t v = tid % 32; v <= u; v += 32) {
-                    const uint32_t rp = v / a.K, kp = v - rp * a.K;
-                    double g;
-                    if (k <= kp) {
-                        const uint32_t slot = a.pair_slot[k * a.K + kp] + (r / 32) * a.RB + (rp / 32);
-                        g = a.tiles[((size_t)slot << 10) + (r % 32) * 32 + (rp % 32)];
-                    } else {
-                        const uint32_t slot = a.pair_slot[kp * a.K + k] + (rp / 32) * a.RB + (r / 32);
-                        g = a.tiles[((size_t)slot << 10) + (rp % 32) * 32 + (r % 32)];
-                    }
-                    A[(size_t)u * F + v] = g;
-                }
-            }
+            for (uint32_t u = tid / 32; u < F; u += nt / 32)
+                for (uint32_t v = tid % 32; v <= u; v += 32) A[(size_t)u * F + v] = a.A0[(size_t)u * F + v];
             __syncthreads();
             if (tid == 0) {
                 double tr = 0.0;
@@ -266,23 +453,33 @@ __global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
                     P[t] = (q < nb && q <= r) ? A[(size_t)(c0 + r) * F + c0 + q] : 0.0;
                 }
                 __syncthreads();
-                for (uint32_t q = 0; q < nb; ++q) {
-                    if (tid == 0) {
+                // the panel is factorised by wave 0 alone (its lanes take
+                // rows lane, lane + 64, ...), ordered by wave-level fences
+                // instead of workgroup barriers
+                if (tid < kWave) {
+                    for (uint32_t q = 0; q < nb; ++q) {
                         const double piv = P[q * kPanel + q];
-                        if (!(piv > 0.0)) s_bad = 1;
-                        P[q * kPanel + q] = piv > 0.0 ? sqrt(piv) : 1.0;
+                        const double dq = piv > 0.0 ? sqrt(piv) : 1.0;
+                        if (tid == 0) {
+                            if (!(piv > 0.0)) s_bad = 1;
+                            P[q * kPanel + q] = dq;
+                        }
+                        const double inv = 1.0 / dq;
+                        for (uint32_t r = q + 1 + tid; r < rows; r += kWave) P[r * kPanel + q] *= inv;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        for (uint32_t r = q + 1 + tid; r < rows; r += kWave) {
+                            const double l = P[r * kPanel + q];
+                            for (uint32_t q2 = q + 1; q2 < nb && q2 <= r; ++q2)
+                                P[r * kPanel + q2] -= l * P[q2 * kPanel + q];
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     }
-                    __syncthreads();
-                    const double inv = 1.0 / P[q * kPanel + q];
-                    for (uint32_t r = q + 1 + tid; r < rows; r += nt) P[r * kPanel + q] *= inv;
-                    __syncthreads();
-                    for (uint32_t r = q + 1 + tid; r < rows; r += nt) {
-                        const double l = P[r * kPanel + q];
-                        for (uint32_t q2 = q + 1; q2 < nb && q2 <= r; ++q2)
-                            P[r * kPanel + q2] -= l * P[q2 * kPanel + q];
-                    }
-                    __syncthreads();
                 }
+                __syncthreads();
                 for (uint32_t t = tid; t < rows * kPanel; t += nt) {
                     const uint32_t r = t / kPanel, q = t % kPanel;
                     if (q < nb && q <= r) A[(size_t)(c0 + r) * F + c0 + q] = P[t];
@@ -325,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
             if (!bad) break;
         }
         if (tid == 0) {
-            *a.status = s_bad;
+            *a.status = s_bad ? -1 : attempt;
             *a.lam = s_ridge;
         }
         cv_load_rhs(a, F, y, 0.0);
@@ -334,14 +531,19 @@ __global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
     }
     __syncthreads();
 
-    // forward substitution L z = y, one panel at a time
+    // forward substitution L z = y, one panel at a time: the panel's
+    // diagonal block goes to LDS, one thread solves it, then every thread
+    // updates its rows below
+    __shared__ double D[kPanel * kPanel];
     for (uint32_t c0 = 0; c0 < F; c0 += kPanel) {
         const uint32_t nb = min(kPanel, F - c0);
+        if (tid < nb * nb) D[tid] = A[(size_t)(c0 + tid / nb) * F + c0 + tid % nb];
+        __syncthreads();
         if (tid == 0) {
             for (uint32_t q = 0; q < nb; ++q) {
                 double v = y[c0 + q];
-                for (uint32_t q2 = 0; q2 < q; ++q2) v -= A[(size_t)(c0 + q) * F + c0 + q2] * y[c0 + q2];
-                y[c0 + q] = v / A[(size_t)(c0 + q) * F + c0 + q];
+                for (uint32_t q2 = 0; q2 < q; ++q2) v -= D[q * nb + q2] * y[c0 + q2];
+                y[c0 + q] = v / D[q * nb + q];
             }
         }
         __syncthreads();
@@ -352,26 +554,25 @@ __global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
         }
         __syncthreads();
     }
-    // backward substitution L^T w = z, panels from the last; P holds the
-    // per-column partial dot products (kPanel groups of nt / kPanel threads)
-    const uint32_t per = nt / kPanel, grp = tid / per, lane = tid % per;
+    // backward substitution L^T w = z by columns of L^T, panels from the
+    // last: solve the panel's diagonal block, then every thread removes the
+    // panel's unknowns from its rows above, z[r] -= sum_q L[c0 + q][r] w[c0 + q]
     for (uint32_t c0 = ((F - 1) / kPanel) * kPanel;; c0 -= kPanel) {
-        const uint32_t nb = min(kPanel, F - c0), c1 = c0 + nb;
-        double s = 0.0;
-        if (grp < nb)
-            for (uint32_t v = c1 + lane; v < F; v += per) s += A[(size_t)v * F + c0 + grp] * y[v];
-        P[tid] = s;
+        const uint32_t nb = min(kPanel, F - c0);
+        if (tid < nb * nb) D[tid] = A[(size_t)(c0 + tid / nb) * F + c0 + tid % nb];
         __syncthreads();
-        for (uint32_t h = per / 2; h > 0; h >>= 1) {
-            if (lane < h) P[tid] += P[tid + h];
-            __syncthreads();
-        }
         if (tid == 0) {
             for (uint32_t q = nb; q-- > 0;) {
-                double v = y[c0 + q] - P[q * per];
-                for (uint32_t q2 = q + 1; q2 < nb; ++q2) v -= A[(size_t)(c0 + q2) * F + c0 + q] * y[c0 + q2];
-                y[c0 + q] = v / A[(size_t)(c0 + q) * F + c0 + q];
+                double v = y[c0 + q];
+                for (uint32_t q2 = q + 1; q2 < nb; ++q2) v -= D[q2 * nb + q] * y[c0 + q2];
+                y[c0 + q] = v / D[q * nb + q];
             }
+        }
+        __syncthreads();
+        for (uint32_t r = tid; r < c0; r += nt) {
+            double v = y[r];
+            for (uint32_t q = 0; q < nb; ++q) v -= A[(size_t)(c0 + q) * F + r] * y[c0 + q];
+            y[r] = v;
         }
         __syncthreads();
         if (c0 == 0) break;
@@ -381,13 +582,13 @@ __global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
         const size_t o = ((size_t)r * a.d + a.i) * a.K + k;
         const double w = a.refine ? a.w64[o] + y[u] : y[u];
         a.w64[o] = w;
-        a.ws32[o] = (float)(w * sqrt(2.0 * k + 1.0));
+        a.ws[o] = w * sqrt(2.0 * k + 1.0);
     }
 }
 
 // Rescales the factors of each rank to equal norms across dimensions (the
 // product, hence the model, is unchanged): keeps ALS well conditioned.
-__global__ void k_cv_balance(uint32_t R, uint32_t d, uint32_t K, double *w64, float *ws32) {
+__global__ void k_cv_balance(uint32_t R, uint32_t d, uint32_t K, double *w64, double *ws) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     double lg = 0.0;
@@ -405,36 +606,36 @@ __global__ void k_cv_balance(uint32_t R, uint32_t d, uint32_t K, double *w64, fl
         for (uint32_t k = 0; k < K; ++k) {
             const size_t o = ((size_t)r * d + i) * K + k;
             w64[o] *= f;
-            ws32[o] = (float)(w64[o] * sqrt(2.0 * k + 1.0));
+            ws[o] = w64[o] * sqrt(2.0 * k + 1.0);
         }
     }
 }
 
-// training loss sum_j (yw_j / scale - sw_j g32(z_j))^2 and sum_j (yw_j / scale)^2,
-// one pair of partial sums per block
+// training loss sum_j (yw_j / scale - sw_j g(z_j))^2 and sum_j (yw_j / scale)^2
+// (FP64), one pair of partial sums per block
 template <int R, int K>
 __global__ __launch_bounds__(kBlock) void k_cv_loss(uint32_t n, uint32_t d, const float *z, const float *sw,
-                                                   const float *yw, float inv_scale, const float *ws,
+                                                   const float *yw, double inv_scale, const double *ws,
                                                    double *partial) {
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     double e2 = 0.0, y2 = 0.0;
     if (j < n) {
-        float prod[R];
+        double prod[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) prod[r] = 1.0f;
+        for (int r = 0; r < R; ++r) prod[r] = 1.0;
         for (uint32_t i = 0; i < d; ++i) {
-            float p[K];
-            legendre_raw<K, float>(z[(size_t)j * d + i], p);
+            double p[K];
+            legendre_raw<K, double>((double)z[(size_t)j * d + i], p);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float *w = ws + ((size_t)r * d + i) * K;
-                float h = w[K - 1] * p[K - 1];
+                const double *w = ws + ((size_t)r * d + i) * K;
+                double h = w[K - 1] * p[K - 1];
 #pragma unroll
-                for (int k = K - 2; k >= 0; --k) h = __builtin_fmaf(w[k], p[k], h);
+                for (int k = K - 2; k >= 0; --k) h = fma(w[k], p[k], h);
                 prod[r] *= h;
             }
         }
-        float g = 0.0f;
+        double g = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) g += prod[r];
         const double y = (double)yw[j] * inv_scale;
@@ -476,39 +677,97 @@ __global__ __launch_bounds__(kBlock) void k_cv_absmean(uint32_t n, const float *
 namespace {
 
 using RhoFn = void (*)(const CvRhoArgs &, uint32_t, hipStream_t);
-using LossFn = void (*)(uint32_t, uint32_t, const float *, const float *, const float *, float, const float *,
+using LossFn = void (*)(uint32_t, uint32_t, const float *, const float *, const float *, double, const double *,
                         double *, uint32_t, hipStream_t);
-using ResidFn = void (*)(uint32_t, uint32_t, uint32_t, const float *, const float *, const float *, float,
-                         const double *, float *, uint32_t, hipStream_t);
+using ResidFn = void (*)(uint32_t, uint32_t, uint32_t, const double *, const double *, const float *, double,
+                         const double *, double *, uint32_t, hipStream_t);
+using SyrkFn = void (*)(const CvSyrkArgs &, dim3, hipStream_t);
 
 template <int R, int K>
 void launch_rho(const CvRhoArgs &a, uint32_t blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_cv_rho<R, K>), dim3(blocks), dim3(kBlock), 0, s, a);
 }
 template <int R, int K>
-void launch_loss(uint32_t n, uint32_t d, const float *z, const float *sw, const float *yw, float is, const float *ws,
+void launch_loss(uint32_t n, uint32_t d, const float *z, const float *sw, const float *yw, double is, const double *ws,
                  double *part, uint32_t blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_cv_loss<R, K>), dim3(blocks), dim3(kBlock), 0, s, n, d, z, sw, yw, is, ws, part);
 }
-
 template <int R, int K>
-void launch_resid(uint32_t n, uint32_t d, uint32_t i, const float *rho, const float *phi, const float *yw, float is,
-                  const double *w64, float *e, uint32_t blocks, hipStream_t s) {
+void launch_resid(uint32_t n, uint32_t d, uint32_t i, const double *rho, const double *phi, const float *yw,
+                  double is, const double *w64, double *e, uint32_t blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_cv_resid<R, K>), dim3(blocks), dim3(kBlock), 0, s, n, d, i, rho, phi, yw, is, w64, e);
 }
+template <int R, int K, class S0, class S1>
+void launch_syrk(const CvSyrkArgs &a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_cv_syrk<R, K, S0, S1>), grid, dim3(kBlock), 0, s, a);
+}
 
-bool cv_fns(uint32_t R, uint32_t K, RhoFn &rho, LossFn &loss, ResidFn &resid) {
-#define QMC_CV_CASE(RR, KK)                  \
-    if (R == RR && K == KK) {                \
-        rho = &launch_rho<RR, KK>;           \
-        loss = &launch_loss<RR, KK>;         \
-        resid = &launch_resid<RR, KK>;       \
-        return true;                         \
+struct CvFns {
+    RhoFn rho;
+    LossFn loss;
+    ResidFn resid;
+    SyrkFn syrk;
+};
+
+// (R, K) pairs compiled, with the Gram kernel's task shapes (see
+// syrk_tasks for how they cover the triangle)
+bool cv_fns(uint32_t R, uint32_t K, CvFns &f) {
+#define QMC_CV_CASE(RR, KK, S0, S1)              \
+    if (R == RR && K == KK) {                    \
+        f.rho = &launch_rho<RR, KK>;             \
+        f.loss = &launch_loss<RR, KK>;           \
+        f.resid = &launch_resid<RR, KK>;         \
+        f.syrk = &launch_syrk<RR, KK, S0, S1>;   \
+        return true;                             \
     }
-    QMC_CV_CASE(8, 4) QMC_CV_CASE(8, 8) QMC_CV_CASE(16, 8) QMC_CV_CASE(16, 12) QMC_CV_CASE(32, 8)
-    QMC_CV_CASE(32, 12) QMC_CV_CASE(32, 16) QMC_CV_CASE(64, 12)
+    QMC_CV_CASE(8, 4, ShapeTri1, void) QMC_CV_CASE(8, 8, ShapeTri2, void) QMC_CV_CASE(16, 8, ShapeTri4, void)
+    QMC_CV_CASE(16, 12, ShapeTri6, void) QMC_CV_CASE(32, 8, ShapeTri8, void)
+    QMC_CV_CASE(32, 12, ShapeHalf12, void) QMC_CV_CASE(32, 16, ShapeTri8, ShapeRect8x4)
+    QMC_CV_CASE(64, 12, ShapeHalf12, ShapeRect6x6)
 #undef QMC_CV_CASE
     return false;
+}
+
+// Tasks covering the lower triangle of NB x NB tiles once, with the shapes
+// cv_fns names: NB <= 8 one triangle; NB = 12 two halves; NB = 16 two
+// triangles of 8 and the 8 x 8 block below them as two 8 x 4 rectangles;
+// NB = 24 two 12-triangles (two halves each) and the 12 x 12 block below as
+// four 6 x 6 rectangles.  Fragments are built for blocks [blo, bhi).
+std::vector<CvSyrkTask> syrk_tasks(uint32_t NB) {
+    std::vector<CvSyrkTask> out;
+    auto tri = [&](uint32_t o, const uint32_t (&r)[4], const uint32_t (&c)[4], uint32_t n) {
+        CvSyrkTask t{0, o, o + n, {o + r[0], o + r[1], o + r[2], o + r[3]}, {o + c[0], o + c[1], o + c[2], o + c[3]}};
+        out.push_back(t);
+    };
+    switch (NB) {
+    case 1: tri(0, {0, 0, 0, 0}, {0, 0, 0, 0}, 1); break;
+    case 2: tri(0, {0, 1, 1, 0}, {0, 1, 0, 0}, 2); break;
+    case 4: tri(0, {0, 2, 2, 3}, {0, 2, 0, 0}, 4); break;
+    case 6: tri(0, {0, 3, 3, 5}, {0, 3, 0, 0}, 6); break;
+    case 8: tri(0, {0, 4, 4, 6}, {0, 4, 0, 0}, 8); break;
+    case 16:
+        for (uint32_t o : {0u, 8u}) tri(o, {0, 4, 4, 6}, {0, 4, 0, 0}, 8);
+        for (uint32_t c : {0u, 4u}) out.push_back(CvSyrkTask{1, 0, 16, {8, 10, 12, 14}, {c, c, c, c}});
+        break;
+    case 12:
+    case 24:
+        for (uint32_t o = 0; o < NB; o += 12) {
+            // half A: rows 0..5 (lower), rows 6..8 x columns 0..5; half B:
+            // rows 6..11 (lower), rows 9..11 x columns 0..5 (diagonal
+            // regions name their first column block)
+            tri(o, {0, 0, 6, 6}, {0, 0, 0, 3}, 9);
+            tri(o, {6, 6, 9, 9}, {6, 6, 0, 3}, 12);
+        }
+        if (NB == 24)
+            for (uint32_t a = 0; a < 2; ++a)
+                for (uint32_t b = 0; b < 2; ++b) {
+                    const uint32_t r = 12 + 6 * a, c = 6 * b;
+                    out.push_back(CvSyrkTask{1, c, r + 6, {r, r, r + 3, r + 3}, {c, c + 3, c, c + 3}});
+                }
+        break;
+    default: break;
+    }
+    return out;
 }
 
 // simple seeded generator for the initial factors (SplitMix64)
@@ -518,6 +777,148 @@ double splitmix_uniform(uint64_t &s) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     return (double)(z >> 11) * 0x1.0p-53;
+}
+
+uint32_t rhs_splits(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>(1024, (n + 255) / 256)); }
+
+// Device buffers of one training problem (n samples, d dimensions, rank R,
+// K Legendre degrees) and the launches of one alternating-least-squares
+// step.  Everything is freed with the object.
+struct CvTrainer {
+    uint32_t n = 0, d = 0, R = 0, K = 0, F = 0, NB = 0;
+    uint32_t splits = 1, rsplits = 1, rblocks = 1, nslots = 0, ntasks = 0;
+    CvFns fn{};
+    DeviceScratch s;
+    float *z = nullptr, *sw = nullptr, *yw = nullptr, *partial = nullptr;
+    double *rho = nullptr, *phi = nullptr, *rpart = nullptr, *resid = nullptr, *ws = nullptr;
+    double *w64 = nullptr, *A0 = nullptr, *A = nullptr, *b = nullptr, *lam = nullptr;
+    double *loss_part = nullptr, *abs_part = nullptr;
+    int *status = nullptr;
+    CvSyrkTask *tasks = nullptr;
+
+    // samples: allocate z, sw, yw too; features: rho, phi and the Gram's
+    // and right-hand side's partial sums
+    qmc_status init(uint32_t n_, uint32_t d_, uint32_t R_, uint32_t K_, bool samples, bool features) {
+        n = n_;
+        d = d_;
+        R = R_;
+        K = K_;
+        F = R * K;
+        NB = F / 32;
+        if (!cv_fns(R, K, fn))
+            return fail(QMC_EUNSUPPORTED, "(R, K) = (%u, %u) not compiled; use (32,12), (64,12), (16,8), ...", R, K);
+        const std::vector<CvSyrkTask> tk = syrk_tasks(NB);
+        if (tk.empty()) return fail(QMC_EUNSUPPORTED, "no Gram task layout for %u blocks", NB);
+        ntasks = (uint32_t)tk.size();
+        nslots = NB * (NB + 1) / 2;
+        // two workgroups per CU in flight: about 512 workgroups in all, each
+        // with at least one round of points
+        splits = std::max<uint32_t>(1, std::min<uint32_t>(512 / ntasks, (n + kSyrkPts - 1) / kSyrkPts));
+        rsplits = rhs_splits(n);
+        rblocks = (n + kBlock - 1) / kBlock;
+        qmc_status st;
+        auto take = [&](size_t bytes, auto *&ptr) -> qmc_status {
+            qmc_status r = s.alloc(bytes);
+            if (!r) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(s.ptr.back());
+            return r;
+        };
+        if ((samples && ((st = take((size_t)n * d * 4, z)) || (st = take((size_t)n * 4, sw)) ||
+                         (st = take((size_t)n * 4, yw)))) ||
+            (features && ((st = take((size_t)n * R * 8, rho)) || (st = take((size_t)n * K * 8, phi)) ||
+                          (st = take((size_t)splits * nslots * 4096, partial)) ||
+                          (st = take((size_t)rsplits * F * 8, rpart)) || (st = take((size_t)n * 8, resid)))) ||
+            (st = take((size_t)R * d * K * 8, ws)) || (st = take((size_t)R * d * K * 8, w64)) ||
+            (st = take(tk.size() * sizeof(CvSyrkTask), tasks)) || (st = take((size_t)F * F * 8, A0)) ||
+            (st = take((size_t)F * F * 8, A)) || (st = take((size_t)F * 8, b)) || (st = take(8, lam)) ||
+            (st = take(8, status)) || (st = take((size_t)rblocks * 16, loss_part)) ||
+            (st = take((size_t)rblocks * 8, abs_part)))
+            return st;
+        hipError_t e = hipMemcpy(tasks, tk.data(), tk.size() * sizeof(CvSyrkTask), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "training setup");
+        return QMC_OK;
+    }
+
+    // factors in the orthonormal basis (R, d, K), and a copy with the
+    // sqrt(2k+1) normalisation folded in
+    qmc_status set_weights(const double *w) {
+        std::vector<double> wsh((size_t)R * d * K);
+        for (size_t t = 0; t < wsh.size(); ++t) wsh[t] = w[t] * std::sqrt(2.0 * (t % K) + 1.0);
+        hipError_t e;
+        if ((e = hipMemcpy(w64, w, wsh.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(ws, wsh.data(), wsh.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "training weights");
+        return QMC_OK;
+    }
+
+    void features(uint32_t i, hipStream_t st) {
+        const CvRhoArgs ra{n, d, i, z, sw, ws, rho, phi};
+        fn.rho(ra, rblocks, st);
+    }
+
+    // A0 = sum_j a~_j a~_j^T (BF16 MFMA, FP32 accumulation per split, FP64 over splits)
+    void gram(hipStream_t st) {
+        const CvSyrkArgs ga{n, splits, nslots, rho, phi, tasks, partial};
+        fn.syrk(ga, dim3(splits, ntasks), st);
+        const uint64_t entries = (uint64_t)F * (F + 1) / 2, per = kBlock / kWave;
+        hipLaunchKernelGGL(k_cv_gather, dim3((uint32_t)((entries + per - 1) / per)), dim3(kBlock), 0, st,
+                           (const float *)partial, splits, nslots, R, K, A0);
+    }
+
+    // b = sum_j rho_j phi_j^T y_j, y = yd, or yf * y_scale when yd is null
+    void rhs(const float *yf, double y_scale, const double *yd, hipStream_t st) {
+        hipLaunchKernelGGL(k_cv_rhs, dim3(rsplits), dim3(kBlock), 0, st, n, R, K, rsplits, (const double *)rho,
+                           (const double *)phi, yf, y_scale, yd, rpart);
+        hipLaunchKernelGGL(k_cv_rhs_reduce, dim3((F + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0, st,
+                           (const double *)rpart, rsplits, F, b);
+    }
+
+    void solve(uint32_t dd, uint32_t i, double ridge, int refine, hipStream_t st) {
+        CvSolveArgs so{};
+        so.R = R;
+        so.K = K;
+        so.d = dd;
+        so.i = i;
+        so.ridge = ridge;
+        so.refine = refine;
+        so.lam = lam;
+        so.A0 = A0;
+        so.b = b;
+        so.A = A;
+        so.w64 = w64;
+        so.ws = ws;
+        so.status = status;
+        hipLaunchKernelGGL(k_cv_solve, dim3(1), dim3(1024), 0, st, so);
+    }
+
+    // One alternating-least-squares step for dimension i: FP64 features,
+    // the BF16 normal matrix, the FP64 solve, then `refine` refinements
+    // against the FP64 residual e = y - A w, whose right-hand side
+    // A^T e - lam w comes from the FP64 design matrix: the BF16 matrix only
+    // preconditions, so the fixed point is the FP64 least-squares solution.
+    void step(uint32_t i, double inv_scale, double ridge, uint32_t refine, hipStream_t st) {
+        features(i, st);
+        gram(st);
+        rhs(yw, inv_scale, nullptr, st);
+        solve(d, i, ridge, 0, st);
+        for (uint32_t it = 0; it < refine; ++it) {
+            fn.resid(n, d, i, rho, phi, yw, inv_scale, w64, resid, rblocks, st);
+            rhs(nullptr, 1.0, resid, st);
+            solve(d, i, ridge, 1, st);
+        }
+    }
+};
+
+constexpr uint32_t kRefineSteps = 4;
+
+qmc_status check_step_sizes(uint32_t n, uint32_t d, uint32_t R, uint32_t K, uint32_t i) {
+    if (n == 0) return fail(QMC_EINVAL, "n must be >= 1");
+    if (n > (1u << 26)) return fail(QMC_EUNSUPPORTED, "n > 2^26 training samples");
+    if (d == 0) return fail(QMC_EINVAL, "d must be >= 1");
+    if (d > 12) return fail(QMC_EUNSUPPORTED, "d > 12");
+    if (i >= d) return fail(QMC_EINVAL, "dimension %u >= d = %u", i, d);
+    CvFns f;
+    if (!cv_fns(R, K, f)) return fail(QMC_EUNSUPPORTED, "(R, K) = (%u, %u) not compiled", R, K);
+    return QMC_OK;
 }
 
 }  // namespace
@@ -532,17 +933,17 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
                         const qmc_cv_train_opts *opts, double *w_out, double *c_out, qmc_cv_train_report *rep) {
     if (!p || !w_out || !c_out) return fail(QMC_EINVAL, "null argument");
     if (family != QMC_F_SECTOR) return fail(QMC_EUNSUPPORTED, "control variates are built for QMC_F_SECTOR");
-    RhoFn rho_fn;
-    LossFn loss_fn;
-    ResidFn resid_fn;
-    if (!cv_fns(R, K, rho_fn, loss_fn, resid_fn))
+    CvFns fns;
+    if (!cv_fns(R, K, fns))
         return fail(QMC_EUNSUPPORTED, "(R, K) = (%u, %u) not compiled; use (32,12), (64,12), (16,8), ...", R, K);
     if (p->d > 12) return fail(QMC_EUNSUPPORTED, "d > 12");
-    const qmc_cv_train_opts o = opts ? *opts : qmc_cv_train_opts{12, 1e-5, 1e-4, 1};
+    const qmc_cv_train_opts o = opts ? *opts : qmc_cv_train_opts{12, 1e-5, 1e-4, 1, 0};
+    if (o.refine > 8) return fail(QMC_EINVAL, "refine > 8");
+    const uint32_t refine = o.refine ? o.refine : kRefineSteps;
     Packed pk;
     qmc_status st = pack_params((int)family, p->d, params, pk);
     if (st) return st;
-    const uint32_t n = p->n, d = p->d, F = R * K, RB = (R + 31) / 32;
+    const uint32_t n = p->n, d = p->d;
     hipError_t e;
     std::string err;
     if (pk.orders >= 2) return fail(QMC_EUNSUPPORTED, "control variates take the plain integrand (n_orders < 2)");
@@ -551,60 +952,8 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
     if (!sample) return fail(QMC_EUNSUPPORTED, "training sampler: %s", err.c_str());
     if ((st = plan_upload_params(p, pk))) return st;
 
-    // jobs: Gram blocks (k, k0..k0+count) x (rb, cb), then the RHS blocks
-    std::vector<CvJob> jobs;
-    std::vector<uint32_t> pair_slot((size_t)K * K, 0);
-    uint32_t slot = 0;
-    for (uint32_t k = 0; k < K; ++k)
-        for (uint32_t k0 = k; k0 < K; k0 += kMaxJobCount) {
-            const uint32_t cnt = std::min<uint32_t>(kMaxJobCount, K - k0);
-            for (uint32_t rb = 0; rb < RB; ++rb)
-                for (uint32_t cb = 0; cb < RB; ++cb)
-                    jobs.push_back(CvJob{0, k, k0, cnt, rb, cb, 0, 0});
-        }
-    // slots: pair (k, kp) occupies RB*RB consecutive slots (rb-major)
-    for (uint32_t k = 0; k < K; ++k)
-        for (uint32_t kp = k; kp < K; ++kp) {
-            pair_slot[k * K + kp] = slot;
-            slot += RB * RB;
-        }
-    for (CvJob &jb : jobs) jb.slot0 = pair_slot[jb.k * K + jb.k0] + jb.rb * RB + jb.cb;
-    // a job's q-th pair (k, k0+q) must sit RB*RB slots after the previous one:
-    // re-express slot0 + q as pair_slot[k, k0+q] by using stride RB*RB.
-    const uint32_t rhs_slot0 = slot;
-    for (uint32_t rb = 0; rb < RB; ++rb) jobs.push_back(CvJob{1, 0, 0, 1, rb, 0, rhs_slot0 + rb, 0});
-    const uint32_t nslots = rhs_slot0 + RB;
-    // the kernel writes job.slot0 + q; make q-steps land on the right pair by
-    // splitting jobs so that each covers pairs at unit slot stride (RB == 1),
-    // or one pair per job otherwise
-    if (RB > 1) {
-        std::vector<CvJob> split;
-        for (const CvJob &jb : jobs) {
-            if (jb.type != 0) {
-                split.push_back(jb);
-                continue;
-            }
-            for (uint32_t q = 0; q < jb.count; ++q)
-                split.push_back(CvJob{0, jb.k, jb.k0 + q, 1, jb.rb, jb.cb,
-                                      pair_slot[jb.k * K + jb.k0 + q] + jb.rb * RB + jb.cb, 0});
-        }
-        jobs.swap(split);
-    }
-    const uint32_t splits = std::max<uint32_t>(1, std::min<uint32_t>(256, n / 4096));
-    const uint32_t rblocks = (n + kBlock - 1) / kBlock;
-
-    DeviceScratch s;
-    // 0 z, 1 sw, 2 yw, 3 rho, 4 phi, 5 ws32, 6 w64, 7 jobs, 8 partial, 9 tiles, 10 pair_slot, 11 A, 12 b,
-    // 13 status, 14 loss partials, 15 absmean partials, 16 residual, 17 ridge
-    if ((st = s.alloc((size_t)n * d * 4)) || (st = s.alloc((size_t)n * 4)) || (st = s.alloc((size_t)n * 4)) ||
-        (st = s.alloc((size_t)n * R * 4)) || (st = s.alloc((size_t)n * K * 4)) ||
-        (st = s.alloc((size_t)R * d * K * 4)) || (st = s.alloc((size_t)R * d * K * 8)) ||
-        (st = s.alloc(jobs.size() * sizeof(CvJob))) || (st = s.alloc((size_t)splits * nslots * 4096)) ||
-        (st = s.alloc((size_t)nslots * 8192)) || (st = s.alloc(pair_slot.size() * 4)) ||
-        (st = s.alloc((size_t)F * F * 8)) || (st = s.alloc((size_t)F * 8)) || (st = s.alloc(8)) ||
-        (st = s.alloc((size_t)rblocks * 16)) || (st = s.alloc((size_t)rblocks * 8)) ||
-        (st = s.alloc((size_t)n * 4)) || (st = s.alloc(8)))
-        return st;
+    CvTrainer t;
+    if ((st = t.init(n, d, R, K, true, true))) return st;
     hipStream_t stream = p->stream;
     struct Events {
         hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -621,158 +970,240 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
     // imaginary part
     uint32_t sweeps_total = 0;
     double rel_worst = 0.0, scale0 = 0.0;
+    std::vector<double> part(2 * (size_t)t.rblocks);
     for (uint32_t comp = 0; comp < pk.np; ++comp) {
-    CvSampleArgs sa{};
-    sa.n = n;
-    sa.d = d;
-    sa.inv_n = p->inv_n;
-    sa.g = p->d_g;
-    sa.shift = p->d_shifts;  // the plan's first shift
-    sa.params = p->d_params;
-    sa.z = (float *)s.ptr[0];
-    sa.sw = (float *)s.ptr[1];
-    sa.yw = (float *)s.ptr[2];
-    sa.part = comp;
-    if ((e = jit_launch_sample(sample, sa, rblocks, stream)) != hipSuccess) return hip_fail(e, "training sampler");
-    hipLaunchKernelGGL(k_cv_absmean, dim3(rblocks), dim3(kBlock), 0, stream, n, (const float *)s.ptr[2],
-                       (double *)s.ptr[15]);
-    std::vector<double> part(2 * (size_t)rblocks);
-    if ((e = hipMemcpyAsync(part.data(), s.ptr[15], rblocks * 8, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(stream)) != hipSuccess)
-        return hip_fail(e, "training samples");
-    double scale = 0.0;
-    for (uint32_t b = 0; b < rblocks; ++b) scale += part[b];
-    scale /= n;
-    if (!(scale > 0.0) || !std::isfinite(scale)) return fail(QMC_ENONFINITE, "training targets are zero or not finite");
-
-    // initial factors: near-constant with seeded perturbations (breaks the
-    // symmetry between ranks)
-    std::vector<double> w64((size_t)R * d * K, 0.0);
-    std::vector<float> ws32(w64.size());
-    uint64_t seed = o.seed ? o.seed : 1;
-    const double base = std::pow(1.0 / R, 1.0 / d);
-    for (uint32_t r = 0; r < R; ++r)
-        for (uint32_t i = 0; i < d; ++i)
-            for (uint32_t k = 0; k < K; ++k) {
-                const double u = splitmix_uniform(seed) - 0.5;
-                const double v = k == 0 ? base * (1.0 + 0.5 * u) : 0.1 * base * u / (k + 1);
-                w64[((size_t)r * d + i) * K + k] = v;
-            }
-    for (size_t t = 0; t < w64.size(); ++t) ws32[t] = (float)(w64[t] * std::sqrt(2.0 * (t % K) + 1.0));
-    if ((e = hipMemcpy(s.ptr[5], ws32.data(), ws32.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(s.ptr[6], w64.data(), w64.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(s.ptr[7], jobs.data(), jobs.size() * sizeof(CvJob), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(s.ptr[10], pair_slot.data(), pair_slot.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "training upload");
-
-    CvRhoArgs ra{n, d, 0, (const float *)s.ptr[0], (const float *)s.ptr[1], (const float *)s.ptr[5],
-                 (float *)s.ptr[3], (float *)s.ptr[4]};
-    CvGramArgs ga{};
-    ga.n = n;
-    ga.R = R;
-    ga.K = K;
-    ga.job0 = 0;
-    ga.njobs = (uint32_t)jobs.size();
-    ga.nslots = nslots;
-    ga.splits = splits;
-    ga.inv_scale = (float)(1.0 / scale);
-    ga.rho = ra.rho;
-    ga.phi = ra.phi;
-    ga.yw = (const float *)s.ptr[2];
-    ga.jobs = (const CvJob *)s.ptr[7];
-    ga.partial = (float *)s.ptr[8];
-    CvSolveArgs so{};
-    so.R = R;
-    so.K = K;
-    so.d = d;
-    so.rhs_slot0 = rhs_slot0;
-    so.RB = RB;
-    so.ridge = o.ridge > 0 ? o.ridge : 1e-5;
-    so.tiles = (const double *)s.ptr[9];
-    so.pair_slot = (const uint32_t *)s.ptr[10];
-    so.A = (double *)s.ptr[11];
-    so.w64 = (double *)s.ptr[6];
-    so.ws32 = (float *)s.ptr[5];
-    so.status = (int *)s.ptr[13];
-    so.lam = (double *)s.ptr[17];
-
-    const uint32_t max_sweeps = o.max_sweeps ? o.max_sweeps : 12;
-    double prev = INFINITY, rel = INFINITY, best = INFINITY;
-    std::vector<double> w_best(w64.size());
-    uint32_t sweeps = 0;
-    const uint32_t gblocks = (ga.njobs + 3) / 4;
-    const float inv_scale = (float)(1.0 / scale);
-    uint32_t rhs_job0 = 0;
-    while (jobs[rhs_job0].type == 0) ++rhs_job0;
-    constexpr uint32_t kRefineSteps = 2;
-    for (; sweeps < max_sweeps;) {
-        for (uint32_t i = 0; i < d; ++i) {
-            ra.i = i;
-            rho_fn(ra, rblocks, stream);
-            ga.job0 = 0;
-            ga.yw = (const float *)s.ptr[2];
-            ga.inv_scale = inv_scale;
-            hipLaunchKernelGGL(k_cv_gram, dim3(gblocks, splits), dim3(kBlock), 0, stream, ga);
-            hipLaunchKernelGGL(k_cv_reduce, dim3((nslots * 1024 + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
-                               (const float *)ga.partial, splits, nslots, 0u, (double *)s.ptr[9]);
-            so.i = i;
-            so.refine = 0;
-            hipLaunchKernelGGL(k_cv_solve, dim3(1), dim3(1024), 0, stream, so);
-            // iterative refinement: the BF16 normal matrix only preconditions;
-            // the right-hand side A^T e comes from the FP32 residual, so the
-            // fixed point is the least-squares solution at FP32 accuracy
-            ga.job0 = rhs_job0;
-            ga.yw = (const float *)s.ptr[16];
-            ga.inv_scale = 1.0f;
-            so.refine = 1;
-            for (uint32_t it = 0; it < kRefineSteps; ++it) {
-                resid_fn(n, d, i, ra.rho, ra.phi, (const float *)s.ptr[2], inv_scale, so.w64, (float *)s.ptr[16],
-                         rblocks, stream);
-                hipLaunchKernelGGL(k_cv_gram, dim3((RB + 3) / 4, splits), dim3(kBlock), 0, stream, ga);
-                hipLaunchKernelGGL(k_cv_reduce, dim3((RB * 1024 + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
-                                   (const float *)ga.partial, splits, nslots, rhs_slot0, (double *)s.ptr[9]);
-                hipLaunchKernelGGL(k_cv_solve, dim3(1), dim3(1024), 0, stream, so);
-            }
-        }
-        ++sweeps;
-        hipLaunchKernelGGL(k_cv_balance, dim3((R + 63) / 64), dim3(64), 0, stream, R, d, K, so.w64, so.ws32);
-        loss_fn(n, d, ra.z, ra.sw, (const float *)s.ptr[2], inv_scale, so.ws32, (double *)s.ptr[14], rblocks,
-                stream);
-        int bad = 0;
-        if ((e = hipMemcpyAsync(part.data(), s.ptr[14], (size_t)rblocks * 16, hipMemcpyDeviceToHost, stream)) !=
+        CvSampleArgs sa{};
+        sa.n = n;
+        sa.d = d;
+        sa.inv_n = p->inv_n;
+        sa.g = p->d_g;
+        sa.shift = p->d_shifts;  // the plan's first shift
+        sa.params = p->d_params;
+        sa.z = t.z;
+        sa.sw = t.sw;
+        sa.yw = t.yw;
+        sa.part = comp;
+        sa.tscale = transform_scale(p->tr, d);
+        if ((e = jit_launch_sample(sample, sa, t.rblocks, stream)) != hipSuccess)
+            return hip_fail(e, "training sampler");
+        hipLaunchKernelGGL(k_cv_absmean, dim3(t.rblocks), dim3(kBlock), 0, stream, n, (const float *)t.yw,
+                           t.abs_part);
+        if ((e = hipMemcpyAsync(part.data(), t.abs_part, t.rblocks * 8, hipMemcpyDeviceToHost, stream)) !=
                 hipSuccess ||
-            (e = hipMemcpyAsync(&bad, s.ptr[13], 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
             (e = hipStreamSynchronize(stream)) != hipSuccess)
-            return hip_fail(e, "training loop");
-        double se = 0.0, sy = 0.0;
-        for (uint32_t b = 0; b < rblocks; ++b) {
-            se += part[2 * b];
-            sy += part[2 * b + 1];
+            return hip_fail(e, "training samples");
+        double scale = 0.0;
+        for (uint32_t b = 0; b < t.rblocks; ++b) scale += part[b];
+        scale /= n;
+        if (!(scale > 0.0) || !std::isfinite(scale))
+            return fail(QMC_ENONFINITE, "training targets are zero or not finite");
+
+        // initial factors: near-constant with seeded perturbations (breaks the
+        // symmetry between ranks)
+        std::vector<double> w64((size_t)R * d * K, 0.0);
+        uint64_t seed = o.seed ? o.seed : 1;
+        const double base = std::pow(1.0 / R, 1.0 / d);
+        for (uint32_t r = 0; r < R; ++r)
+            for (uint32_t i = 0; i < d; ++i)
+                for (uint32_t k = 0; k < K; ++k) {
+                    const double u = splitmix_uniform(seed) - 0.5;
+                    const double v = k == 0 ? base * (1.0 + 0.5 * u) : 0.1 * base * u / (k + 1);
+                    w64[((size_t)r * d + i) * K + k] = v;
+                }
+        if ((st = t.set_weights(w64.data()))) return st;
+
+        const uint32_t max_sweeps = o.max_sweeps ? o.max_sweeps : 12;
+        const double ridge = o.ridge > 0 ? o.ridge : 1e-5;
+        double prev = INFINITY, rel = INFINITY, best = INFINITY;
+        std::vector<double> w_best(w64.size());
+        uint32_t sweeps = 0;
+        const double inv_scale = 1.0 / scale;
+        for (; sweeps < max_sweeps;) {
+            for (uint32_t i = 0; i < d; ++i) t.step(i, inv_scale, ridge, refine, stream);
+            ++sweeps;
+            hipLaunchKernelGGL(k_cv_balance, dim3((R + 63) / 64), dim3(64), 0, stream, R, d, K, t.w64, t.ws);
+            t.fn.loss(n, d, t.z, t.sw, t.yw, inv_scale, t.ws, t.loss_part, t.rblocks, stream);
+            if ((e = hipMemcpyAsync(part.data(), t.loss_part, (size_t)t.rblocks * 16, hipMemcpyDeviceToHost,
+                                    stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(stream)) != hipSuccess)
+                return hip_fail(e, "training loop");
+            double se = 0.0, sy = 0.0;
+            for (uint32_t b = 0; b < t.rblocks; ++b) {
+                se += part[2 * b];
+                sy += part[2 * b + 1];
+            }
+            rel = se / sy;
+            if (!std::isfinite(rel)) {
+                if (std::isfinite(best)) break;  // keep the best factors so far
+                return fail(QMC_ENONFINITE, "training diverged");
+            }
+            if (rel < best) {  // the factors of the lowest loss are the result
+                best = rel;
+                if ((e = hipMemcpy(w_best.data(), t.w64, w_best.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+                    return hip_fail(e, "training download");
+            }
+            if (prev - rel < o.tol * prev) break;
+            prev = rel;
         }
-        rel = se / sy;
-        if (!std::isfinite(rel)) {
-            if (std::isfinite(best)) break;  // keep the best factors so far
-            return fail(QMC_ENONFINITE, "training diverged");
-        }
-        if (rel < best) {  // the factors of the lowest loss are the result
-            best = rel;
-            if ((e = hipMemcpy(w_best.data(), s.ptr[6], w_best.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
-                return hip_fail(e, "training download");
-        }
-        if (prev - rel < o.tol * prev) break;
-        prev = rel;
-    }
-    std::memcpy(w_out + (size_t)comp * R * d * K, w_best.data(), w_best.size() * 8);
-    for (uint32_t r = 0; r < R; ++r) c_out[(size_t)comp * R + r] = scale;
-    sweeps_total += sweeps;
-    rel_worst = std::max(rel_worst, best);
-    if (comp == 0) scale0 = scale;
+        std::memcpy(w_out + (size_t)comp * R * d * K, w_best.data(), w_best.size() * 8);
+        for (uint32_t r = 0; r < R; ++r) c_out[(size_t)comp * R + r] = scale;
+        sweeps_total += sweeps;
+        rel_worst = std::max(rel_worst, best);
+        if (comp == 0) scale0 = scale;
     }  // components
     (void)hipEventRecord(ev.t1, stream);
     (void)hipStreamSynchronize(stream);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev.t0, ev.t1);
     if (rep) *rep = qmc_cv_train_report{sweeps_total, rel_worst, scale0, ms / 1e3};
+    return QMC_OK;
+}
+
+qmc_status qmc_cv_samples(qmc_plan_t p, qmc_family family, const void *params, uint32_t part, float *z_out,
+                          float *sw_out, float *yw_out) {
+    if (!p || !z_out || !sw_out || !yw_out) return fail(QMC_EINVAL, "null argument");
+    if (family != QMC_F_SECTOR) return fail(QMC_EUNSUPPORTED, "control variates are built for QMC_F_SECTOR");
+    if (p->d > 12) return fail(QMC_EUNSUPPORTED, "d > 12");
+    Packed pk;
+    qmc_status st = pack_params((int)family, p->d, params, pk);
+    if (st) return st;
+    if (pk.orders >= 2 || pk.deform)
+        return fail(QMC_EUNSUPPORTED, "control variates take the plain, undeformed integrand");
+    if (part >= pk.np) return fail(QMC_EINVAL, "part %u of a %s integrand", part, pk.cplx ? "complex" : "real");
+    std::string err;
+    hipFunction_t sample = jit_sample_kernel(pk.blob, p->d, p->tr, pk.cplx, p->device, err);
+    if (!sample) return fail(QMC_EUNSUPPORTED, "training sampler: %s", err.c_str());
+    if ((st = plan_upload_params(p, pk))) return st;
+    const uint32_t n = p->n, d = p->d, blocks = (n + kBlock - 1) / kBlock;
+    DeviceScratch s;
+    if ((st = s.alloc((size_t)n * d * 4)) || (st = s.alloc((size_t)n * 4)) || (st = s.alloc((size_t)n * 4)))
+        return st;
+    CvSampleArgs sa{};
+    sa.n = n;
+    sa.d = d;
+    sa.inv_n = p->inv_n;
+    sa.g = p->d_g;
+    sa.shift = p->d_shifts;
+    sa.params = p->d_params;
+    sa.z = (float *)s.ptr[0];
+    sa.sw = (float *)s.ptr[1];
+    sa.yw = (float *)s.ptr[2];
+    sa.part = part;
+    sa.tscale = transform_scale(p->tr, d);
+    hipError_t e = jit_launch_sample(sample, sa, blocks, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(z_out, s.ptr[0], (size_t)n * d * 4, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sw_out, s.ptr[1], (size_t)n * 4, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(yw_out, s.ptr[2], (size_t)n * 4, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "training samples");
+    return QMC_OK;
+}
+
+qmc_status qmc_cv_features(uint32_t n, uint32_t d, uint32_t R, uint32_t K, uint32_t i, const float *z,
+                           const float *sw, const double *w, double *rho_out, double *phi_out) {
+    if (!z || !sw || !w || !rho_out || !phi_out) return fail(QMC_EINVAL, "null argument");
+    qmc_status st = check_step_sizes(n, d, R, K, i);
+    if (st) return st;
+    for (size_t t = 0; t < (size_t)R * d * K; ++t)
+        if (!std::isfinite(w[t])) return fail(QMC_EINVAL, "W not finite");
+    CvTrainer t;
+    if ((st = t.init(n, d, R, K, true, true)) || (st = t.set_weights(w))) return st;
+    hipError_t e;
+    if ((e = hipMemcpy(t.z, z, (size_t)n * d * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.sw, sw, (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "features upload");
+    t.features(i, nullptr);
+    if ((e = hipMemcpy(rho_out, t.rho, (size_t)n * R * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(phi_out, t.phi, (size_t)n * K * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "features download");
+    return QMC_OK;
+}
+
+qmc_status qmc_cv_normal(uint32_t n, uint32_t R, uint32_t K, const double *rho, const double *phi, const double *y,
+                         double *gram_out, double *rhs_out, uint32_t *acc_len_out) {
+    if (!rho || !phi || !y || !gram_out || !rhs_out) return fail(QMC_EINVAL, "null argument");
+    qmc_status st = check_step_sizes(n, 1, R, K, 0);
+    if (st) return st;
+    CvTrainer t;
+    if ((st = t.init(n, 1, R, K, false, true))) return st;
+    hipError_t e;
+    if ((e = hipMemcpy(t.rho, rho, (size_t)n * R * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.phi, phi, (size_t)n * K * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.resid, y, (size_t)n * 8, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "normal-equation upload");
+    t.gram(nullptr);
+    t.rhs(nullptr, 1.0, t.resid, nullptr);
+    const uint32_t F = t.F;
+    std::vector<double> A((size_t)F * F);
+    if ((e = hipMemcpy(A.data(), t.A0, A.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(rhs_out, t.b, (size_t)F * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "normal-equation download");
+    for (uint32_t u = 0; u < F; ++u)
+        for (uint32_t v = 0; v <= u; ++v) gram_out[(size_t)u * F + v] = gram_out[(size_t)v * F + u] = A[(size_t)u * F + v];
+    if (acc_len_out) {
+        acc_len_out[0] = (n + t.splits - 1) / t.splits;
+        acc_len_out[1] = (n + t.rsplits - 1) / t.rsplits;
+    }
+    return QMC_OK;
+}
+
+qmc_status qmc_cv_solve(uint32_t R, uint32_t K, const double *gram, const double *rhs, double ridge,
+                        double *lam_out, double *x_out, int32_t *escalations) {
+    if (!gram || !rhs || !x_out) return fail(QMC_EINVAL, "null argument");
+    if (!(ridge > 0.0) || !std::isfinite(ridge)) return fail(QMC_EINVAL, "ridge must be positive and finite");
+    qmc_status st = check_step_sizes(1, 1, R, K, 0);
+    if (st) return st;
+    const uint32_t F = R * K;
+    for (size_t t = 0; t < (size_t)F * F; ++t)
+        if (!std::isfinite(gram[t])) return fail(QMC_EINVAL, "matrix not finite");
+    for (uint32_t u = 0; u < F; ++u)
+        if (!std::isfinite(rhs[u])) return fail(QMC_EINVAL, "right-hand side not finite");
+    CvTrainer t;
+    if ((st = t.init(1, 1, R, K, false, false))) return st;
+    hipError_t e;
+    if ((e = hipMemcpy(t.A0, gram, (size_t)F * F * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.b, rhs, (size_t)F * 8, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "solve upload");
+    t.solve(1, 0, ridge, 0, nullptr);
+    int32_t esc = 0;
+    double lam = 0.0;
+    if ((e = hipMemcpy(x_out, t.w64, (size_t)F * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(&esc, t.status, 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(&lam, t.lam, 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "solve download");
+    if (lam_out) *lam_out = lam;
+    if (escalations) *escalations = esc;
+    if (esc < 0) return fail(QMC_ENONFINITE, "matrix not positive definite after raising the ridge 10^6-fold");
+    return QMC_OK;
+}
+
+qmc_status qmc_cv_als_step(uint32_t n, uint32_t d, uint32_t R, uint32_t K, uint32_t i, const float *z,
+                           const float *sw, const float *yw, double scale, const double *w_in, double ridge,
+                           uint32_t refine, double *w_out, double *lam_out) {
+    if (!z || !sw || !yw || !w_in || !w_out) return fail(QMC_EINVAL, "null argument");
+    qmc_status st = check_step_sizes(n, d, R, K, i);
+    if (st) return st;
+    if (!(scale > 0.0) || !std::isfinite(scale)) return fail(QMC_EINVAL, "scale must be positive and finite");
+    if (!(ridge > 0.0) || !std::isfinite(ridge)) return fail(QMC_EINVAL, "ridge must be positive and finite");
+    if (refine > 8) return fail(QMC_EINVAL, "refine > 8");
+    for (size_t t = 0; t < (size_t)R * d * K; ++t)
+        if (!std::isfinite(w_in[t])) return fail(QMC_EINVAL, "W not finite");
+    CvTrainer t;
+    if ((st = t.init(n, d, R, K, true, true)) || (st = t.set_weights(w_in))) return st;
+    hipError_t e;
+    if ((e = hipMemcpy(t.z, z, (size_t)n * d * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.sw, sw, (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.yw, yw, (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "step upload");
+    t.step(i, 1.0 / scale, ridge, refine, nullptr);
+    int32_t esc = 0;
+    double lam = 0.0;
+    if ((e = hipMemcpy(w_out, t.w64, (size_t)R * d * K * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(&esc, t.status, 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(&lam, t.lam, 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "step download");
+    if (lam_out) *lam_out = lam;
+    if (esc < 0) return fail(QMC_ENONFINITE, "normal matrix not positive definite after raising the ridge");
     return QMC_OK;
 }
 
@@ -793,10 +1224,8 @@ qmc_status qmc_integrate_cv(qmc_plan_t p, qmc_family family, const void *params,
                             double *per_shift) {
     if (!p || !w || !c || !out) return fail(QMC_EINVAL, "null argument");
     if (family != QMC_F_SECTOR) return fail(QMC_EUNSUPPORTED, "control variates are built for QMC_F_SECTOR");
-    RhoFn rf;
-    LossFn lf;
-    ResidFn ef;
-    if (!cv_fns(R, K, rf, lf, ef)) return fail(QMC_EUNSUPPORTED, "(R, K) = (%u, %u) not compiled", R, K);
+    CvFns fns;
+    if (!cv_fns(R, K, fns)) return fail(QMC_EUNSUPPORTED, "(R, K) = (%u, %u) not compiled", R, K);
     if (p->d > 12) return fail(QMC_EUNSUPPORTED, "d > 12");
     Packed pk;
     qmc_status st = pack_params((int)family, p->d, params, pk);

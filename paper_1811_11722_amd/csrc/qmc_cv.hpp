@@ -178,6 +178,7 @@ struct CvSampleArgs {
     float *sw;            // (n) Jacobian J: square root of the loss weight
     float *yw;            // (n) fhat = J f(z): the weighted target (component `part`)
     uint32_t part;        // 0 real part, 1 imaginary part of a complex integrand
+    double tscale;        // the transform's constant (the functors leave it out of J and fhat)
 };
 
 // Points of the training lattice {j g / n + shift}, j < n: z(x), J(x) and
@@ -197,8 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_cv_sample(const CvSampleArgs a) {
     apply_transform<Tr, D, 1>(x, z, jac);
 #pragma unroll
     for (int i = 0; i < D; ++i) a.z[(size_t)j * D + i] = (float)z[0][i];
-    a.sw[j] = (float)jac[0];
-    a.yw[j] = (float)(Fam::NP == 1 || a.part == 0 ? v[0][0] : v[0][Fam::NP - 1]);
+    a.sw[j] = (float)(jac[0] * a.tscale);
+    a.yw[j] = (float)((Fam::NP == 1 || a.part == 0 ? v[0][0] : v[0][Fam::NP - 1]) * a.tscale);
 }
 
 }  // namespace qmc

@@ -73,6 +73,8 @@ qmc_status fail(qmc_status s, const char *fmt, ...);
 qmc_status hip_fail(hipError_t e, const char *what);
 int device_cu_count(int dev);
 qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk);
+qmc_status validate_rule(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
+                         qmc_transform &t);
 // order in which the specialised sector code reads a polynomial's terms
 std::vector<uint32_t> horner_term_order(const std::vector<uint64_t> &codes, uint32_t d);
 double transform_scale(const qmc_transform &t, uint32_t d);

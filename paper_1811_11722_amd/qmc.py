@@ -66,7 +66,7 @@ class qmc_result(C.Structure):
 
 class qmc_cv_train_opts(C.Structure):
     _fields_ = [("max_sweeps", C.c_uint32), ("ridge", C.c_double), ("tol", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("refine", C.c_uint32)]
 
 
 class qmc_cv_train_report(C.Structure):
@@ -115,6 +115,12 @@ SIGNATURES = {
                                                 _vp]),
     "qmc_lattice_merge": (C.c_int, [C.c_uint32, C.c_uint32, _vp, _vp, _vp, _vp]),
     "qmc_deform_select": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_uint32, _vp, _vp]),
+    "qmc_cv_samples": (C.c_int, [_vp, C.c_int, _vp, _u32, _vp, _vp, _vp]),
+    "qmc_cv_features": (C.c_int, [_u32, _u32, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
+    "qmc_cv_normal": (C.c_int, [_u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "qmc_cv_solve": (C.c_int, [_u32, _u32, _vp, _vp, _dbl, _vp, _vp, _vp]),
+    "qmc_cv_als_step": (C.c_int, [_u32, _u32, _u32, _u32, _u32, _vp, _vp, _vp, _dbl, _vp, _dbl, _u32, _vp,
+                                  _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
     "qmc_last_error": (C.c_char_p, []),
@@ -280,7 +286,7 @@ class Plan:
         return st, res, per
 
     def cv_train(self, params: Params, R: int, K: int, max_sweeps: int = 0, ridge: float = 0.0,
-                 tol: float = 1e-4, seed: int = 1):
+                 tol: float = 1e-4, seed: int = 1, refine: int = 0):
         """Fit the Legendre control variate on this plan's lattice (first shift).
         Returns (W, c, report): W (R, d, K) and c (R,) for a real integrand,
         W (2, R, d, K) and c (2, R) (real-part model, imaginary-part model)
@@ -288,13 +294,23 @@ class Plan:
         nm = 2 if params.is_complex else 1
         W = np.zeros((nm, R, self.d, K))
         c = np.zeros((nm, R))
-        opts = qmc_cv_train_opts(max_sweeps, ridge, tol, seed)
+        opts = qmc_cv_train_opts(max_sweeps, ridge, tol, seed, refine)
         rep = qmc_cv_train_report()
         check(lib().qmc_cv_train(self.handle, params.family, params.ptr, R, K, C.byref(opts), _p(W),
                                  _p(c), C.byref(rep)), "qmc_cv_train")
         if nm == 1:
             return W[0], c[0], rep
         return W, c, rep
+
+    def cv_samples(self, params: Params, part: int = 0):
+        """Training samples of this plan's lattice with its first shift:
+        (z (n, d), sw (n,), yw (n,)) in single precision."""
+        z = np.zeros((self.n, self.d), np.float32)
+        sw = np.zeros(self.n, np.float32)
+        yw = np.zeros(self.n, np.float32)
+        check(lib().qmc_cv_samples(self.handle, params.family, params.ptr, part, _p(z), _p(sw), _p(yw)),
+              "qmc_cv_samples")
+        return z, sw, yw
 
     def integrate_cv(self, params: Params, W, c):
         """Returns (result, plain result, plain per-shift Q_k, residual
@@ -392,6 +408,52 @@ def cv_integral(W, c) -> float:
     out = C.c_double()
     check(lib().qmc_cv_integral(R, d, K, _p(W), _p(c), C.byref(out)), "qmc_cv_integral")
     return out.value
+
+
+def cv_features(z, sw, W, i: int):
+    """(rho (n, R), phi (n, K)) in FP64 of the training step for dimension i."""
+    z, sw, W = _arr(z, np.float32), _arr(sw, np.float32), _arr(W, np.float64)
+    n, d = z.shape
+    R, _, K = W.shape
+    rho = np.zeros((n, R))
+    phi = np.zeros((n, K))
+    check(lib().qmc_cv_features(n, d, R, K, i, _p(z), _p(sw), _p(W), _p(rho), _p(phi)), "qmc_cv_features")
+    return rho, phi
+
+
+def cv_normal(rho, phi, y):
+    """(G (F, F), b (F,), acc_len (2,)) of the BF16 normal matrix and the
+    FP64 right-hand side, u = r K + k."""
+    rho, phi, y = _arr(rho, np.float64), _arr(phi, np.float64), _arr(y, np.float64)
+    n, R = rho.shape
+    K = phi.shape[1]
+    G = np.zeros((R * K, R * K))
+    b = np.zeros(R * K)
+    acc = np.zeros(2, np.uint32)
+    check(lib().qmc_cv_normal(n, R, K, _p(rho), _p(phi), _p(y), _p(G), _p(b), _p(acc)), "qmc_cv_normal")
+    return G, b, acc
+
+
+def cv_solve(G, b, R: int, K: int, ridge: float):
+    """(x, lam, escalations) of (G + lam I) x = b on the device."""
+    G, b = _arr(G, np.float64), _arr(b, np.float64)
+    x = np.zeros(R * K)
+    lam = C.c_double()
+    esc = C.c_int32()
+    check(lib().qmc_cv_solve(R, K, _p(G), _p(b), float(ridge), C.byref(lam), _p(x), C.byref(esc)), "qmc_cv_solve")
+    return x, lam.value, esc.value
+
+
+def cv_als_step(z, sw, yw, scale: float, W, i: int, ridge: float, refine: int = 2):
+    """One training step for dimension i: (W_new, lam)."""
+    z, sw, yw, W = _arr(z, np.float32), _arr(sw, np.float32), _arr(yw, np.float32), _arr(W, np.float64)
+    n, d = z.shape
+    R, _, K = W.shape
+    out = np.zeros_like(W)
+    lam = C.c_double()
+    check(lib().qmc_cv_als_step(n, d, R, K, i, _p(z), _p(sw), _p(yw), float(scale), _p(W), float(ridge), refine,
+                                _p(out), C.byref(lam)), "qmc_cv_als_step")
+    return out, lam.value
 
 
 def korobov_vector(n: int, d: int, a: int) -> np.ndarray:

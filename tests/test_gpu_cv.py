@@ -122,7 +122,10 @@ def test_cv_training_recovers_separable_integrand(Q):
     # the ridge (1e-5 of the mean diagonal) bounds how closely the fit can
     # approach the exact rank-1 model (relative loss ~1e-7), and the
     # lattice error of what remains is what the shifts measure
-    assert out.err_re < 0.5 * plain.err_re
+    print(f"  rel loss {rep.rel_loss:.3g}, error ratio cv / plain {out.err_re / plain.err_re:.3g}, "
+          f"plain rel err {plain.err_re / exact:.3g}, cv rel err {out.err_re / exact:.3g}, "
+          f"|mean - exact| / exact {abs(out.mean_re - exact) / exact:.3g}")
+    assert out.err_re <= 1e-2 * plain.err_re
     assert abs(out.mean_re - exact) <= 6 * out.err_re + 1e-13 * exact
 
 
