@@ -322,6 +322,26 @@ typedef struct {
 qmc_status qmc_cv_train(qmc_plan_t train_plan, qmc_family family, const void *params, uint32_t R, uint32_t K,
                         const qmc_cv_train_opts *opts, double *w_out, double *c_out, qmc_cv_train_report *rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): one
+   estimate of eqs. (2)-(3), as qmc_plan_create + qmc_integrate +
+   qmc_plan_destroy would give it, that allocates nothing on the device.
+   The rule's device copies, the parameter blob, the block partial sums and
+   the results live in a fixed 1 MiB device array inside the library (one
+   per device, held until the process ends); its address is looked up once
+   per device on the first call.  Limits of that array: m <= 64 shifts and a
+   parameter blob of at most 8192 doubles (EUNSUPPORTED beyond).  It runs
+   the precompiled kernels only (sector integrands use the table-driven
+   kernel, never the run-time specialised one, whose code-object load
+   allocates), and no expansion orders or contour deformation.  The inputs
+   are host memory as for qmc_plan_create / qmc_integrate; `stream` is a
+   hipStream_t (NULL: the null stream); the call returns after the stream
+   has finished it.  Calls that overlap on one device share the array and
+   race: serialise them.  out, per_shift: as qmc_integrate. */
+qmc_status qmc_integrate_static(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
+                                qmc_transform t, qmc_family family, const void *params, void *stream,
+                                qmc_result *out, double *per_shift);
+
 /* The steps of one training update, callable on their own (same kernels as
    qmc_cv_train).  Training samples are n points z (n, d) in [0,1]^d with
    the transform's Jacobian sw (n) and the weighted targets yw = fhat (n),

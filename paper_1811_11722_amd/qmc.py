@@ -121,6 +121,7 @@ SIGNATURES = {
     "qmc_cv_solve": (C.c_int, [_u32, _u32, _vp, _vp, _dbl, _vp, _vp, _vp]),
     "qmc_cv_als_step": (C.c_int, [_u32, _u32, _u32, _u32, _u32, _vp, _vp, _vp, _dbl, _vp, _dbl, _u32, _vp,
                                   _vp]),
+    "qmc_integrate_static": (C.c_int, [_u32, _u64, _vp, _u32, _vp, qmc_transform, C.c_int, _vp, _vp, _vp, _vp]),
     "qmc_plan_destroy": (None, [_vp]),
     "qmc_status_string": (C.c_char_p, [C.c_int]),
     "qmc_last_error": (C.c_char_p, []),
@@ -408,6 +409,26 @@ def cv_integral(W, c) -> float:
     out = C.c_double()
     check(lib().qmc_cv_integral(R, d, K, _p(W), _p(c), C.byref(out)), "qmc_cv_integral")
     return out.value
+
+
+def integrate_static(d: int, n: int, g, shifts, params: "Params", transform: str = "none", alpha: int = 0,
+                     stream: int = 0, status_only: bool = False):
+    """One estimate through qmc_integrate_static (no device allocation):
+    (result, per-shift Q_k), complex Q_k for complex sectors.  With
+    status_only the status is returned in front instead of raised."""
+    g = _arr(g, np.uint64)
+    sh = _arr(shifts, np.float64)
+    m = int(sh.shape[0])
+    res = qmc_result()
+    per = np.zeros(2 * m)
+    st = lib().qmc_integrate_static(int(d), int(n), _p(g), m, _p(sh), qmc_transform(TRANSFORM[transform], alpha),
+                                    params.family, params.ptr, C.c_void_p(stream), C.byref(res), _p(per))
+    if status_only:
+        return st, res, per
+    check(st, "qmc_integrate_static")
+    if res.is_complex:
+        return res, per[0::2] + 1j * per[1::2]
+    return res, per[:m].copy()
 
 
 def cv_features(z, sw, W, i: int):
