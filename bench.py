@@ -10,7 +10,16 @@ timed region; each step copies back m + 4 doubles.
 Default workload: sector-decomposed Feynman-parameter integrand
 x^nu U^-2 F^-1.3, d = 6, U with 12 and F with 30 monomials (positive
 coefficients), baker's transform, n = 16777213 (largest prime < 2^24),
-m = 32 shifts; synthetic seeded inputs.  Prints one JSON line.
+m = 32 shifts; synthetic seeded inputs.  Prints one JSON line, which also
+carries the metric's other parts, each on its own workload:
+- product_peak_batch512: 512 Genz product-peak instances (d = 4,
+  Korobov weight 3, n = 131071, m = 16) in one launch;
+- sector_complex_d10: the complex sector (d = 10, U 20 / F 60 monomials,
+  mixed-sign F - 0.01i, baker) at n = 1073741789, m = 32;
+- time_to_error: wall time to a relative error of 1e-7 on the d = 8 sector,
+  plain estimator against the learned control variate, with the transform
+  picked automatically;
+- cpu_baseline: the CPU oracle at 1 thread and at the machine's CPU share.
 """
 from __future__ import annotations
 
@@ -25,12 +34,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lattice-point evals/sec (FP64) + % FP64 peak; time-to-error plain vs control-variate"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 64 FMA/clk x 2 x 2.4 GHz
+CPU_THREADS_MAX = 16            # the host CPU share of one GPU on the measurement boxes
 
-
-def flops_per_eval(workload: str) -> float:
-    """Modelled algorithmic FP64 flops per lattice-point evaluation (FMA = 2)."""
-    return {"sector": 280.0, "product_peak": 91.0}[workload]
-
+# Modelled algorithmic FP64 flops per evaluation (FMA = 2) and the FP64 flops
+# the counters count per evaluation (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes per
+# wave-evaluation, rocprofv3 --pmc on the same launches; profiles/ holds the
+# runs), per workload.
+FLOPS_MODEL = {"sector": 280.0, "product_peak": 91.0, "sector_complex": 540.0}
+FLOPS_COUNTED = {"sector": 165.9, "product_peak": 80.6, "sector_complex": 374.1}
+# engine cycles of one launch of the headline kernel: GRBM_GUI_ACTIVE per XCD
+# (rocprofv3 --pmc, profiles/); divided by the kernel time measured here it
+# gives the clock the kernel ran at
+CYCLES_PER_XCD = {"sector": 4.79e6}
 
 # HBM bytes per lattice-kernel launch from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy of known size); recorded for
@@ -61,13 +76,28 @@ def oracle_params(O, w):
     return O.Params(w.family, w.d, a=w.genz_a, u=w.genz_u)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, tk, alpha, g, seconds: float):
     """The CPU oracle on a bounded sample of the same workload: the first k
-    shifts at the full lattice size, k chosen to take about `seconds`."""
+    shifts at the full lattice size, k chosen to take about `seconds`, at the
+    box's CPU share of threads; and one shift on one thread."""
     from oracle import oracle as O
     O.build(force=False)
-    threads = os.cpu_count() or 1
+    threads = max(1, min(CPU_THREADS_MAX, os.cpu_count() or 1))
     p = oracle_params(O, w)
+    t0 = time.perf_counter()
+    O.estimate(w.n, g, w.shifts[:1], p, tk, alpha, threads=1)
+    t_one = time.perf_counter() - t0
     t0 = time.perf_counter()
     O.estimate(w.n, g, w.shifts[:1], p, tk, alpha, threads=threads)
     t1 = time.perf_counter() - t0
@@ -77,8 +107,75 @@ def cpu_baseline(w, tk, alpha, g, seconds: float):
         O.estimate(w.n, g, w.shifts[:k], p, tk, alpha, threads=threads)
         t1 = time.perf_counter() - t0
     return {"value": w.n * k / t1, "unit": "lattice-point evals/s", "cores": threads,
-            "kind": "oracle", "sample": f"first {k} of {w.m} shifts at full n={w.n}, "
-                                        f"{t1:.2f} s wall on {threads} threads"}
+            "kind": "oracle",
+            "sample": f"first {k} of {w.m} shifts at full n={w.n}, {t1:.2f} s wall on {threads} threads; "
+                      f"1 shift on 1 thread {t_one:.2f} s",
+            "value_1thread": w.n / t_one, "cpu_model": cpu_model(), "cpu_count": os.cpu_count()}
+
+
+def roofline_fields(workload: str, evals: float, seconds: float) -> dict:
+    fm, fc = FLOPS_MODEL[workload], FLOPS_COUNTED[workload]
+    return {"flops_per_eval_model": fm, "counted_flops_per_eval": fc,
+            "frac_model": fm * evals / seconds / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "frac_counted": fc * evals / seconds / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
+
+
+def leg_product_peak_batch(qmc, drivers):
+    """Workload 1 on 512 seeded instances (own a_i, u_i; shared g and shifts)
+    in one multi-instance launch: median wall time of 5 batches, and the
+    batch's device time (HIP events around its graph on the batch stream)
+    for the roofline."""
+    r = drivers.product_peak_batch(count=512, reps=5)
+    out = {"workload": "genz_product_peak_d4_korobov3_n131071_m16_x512", "evals": r["evals"],
+           "seconds": r["seconds"], "evals_per_s": r["evals_per_s"], "device_ms": r["device_seconds"] * 1e3,
+           "device_evals_per_s": r["evals"] / r["device_seconds"]}
+    out.update(roofline_fields("product_peak", r["evals"], r["device_seconds"]))
+    return out
+
+
+def leg_complex_d10(qmc, steps: int):
+    """Workload 5 (complex sector, d = 10) at its full lattice size, plain
+    estimator: the plan's kernel time (HIP events) and wall time per
+    estimate over `steps` estimates after one warm-up."""
+    import torch
+    from paper_1811_11722_amd import synth
+    w = synth.sector_workload(n=1073741789, m=32, d=10, n_u=20, n_f=60, seed=synth.SEED_BASE + 5,
+                              complex_kinematics=True)
+    a, _, _ = qmc.korobov_search(w.n, w.d, w.candidates[:8])
+    plan = qmc.Plan(w.d, w.n, qmc.korobov_vector(w.n, w.d, a), w.shifts, "baker")
+    params = qmc.Params("sector", w.d, sector=w.sector)
+    res, _ = plan.integrate(params)
+    if not plan.last_launch()[2]:
+        raise SystemExit("the complex sector did not run its run-time specialised kernel")
+    plan.set_timing(True)
+    plan.kernel_time(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, _ = plan.integrate(params)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    kms, launches = plan.kernel_time()
+    ks = kms / max(launches, 1) / 1e3
+    evals = w.n * w.m
+    out = {"workload": w.name, "evals": evals, "seconds_per_estimate": wall, "kernel_ms": ks * 1e3,
+           "evals_per_s": evals / wall, "mean": [res.mean_re, res.mean_im], "err": [res.err_re, res.err_im]}
+    out.update(roofline_fields("sector_complex", evals, ks))
+    plan.close()
+    return out
+
+
+def leg_time_to_error(drivers, goal: float):
+    tte = drivers.time_to_error(goal=goal, kmax=30, cv_kmax=28, candidates=16,
+                                choices=[("baker", 0), ("korobov", 2), ("korobov", 3), ("korobov", 4)])
+    keep = ("goal_met", "n", "rel_err", "seconds_at_n", "ladder_seconds")
+    return {"goal_rel_err": goal, "transform": tte["transform"],
+            "workload": f"sector_real_d{tte['d']}_nu{tte['n_u']}_nf{tte['n_f']}", "m": tte["m"],
+            "transform_choice": tte["transform_choice"],
+            "plain": {k: tte["plain"][k] for k in keep},
+            "cv": dict({k: tte["cv"][k] for k in keep},
+                       **{k: tte["cv"][k] for k in ("train_seconds", "train_rel_loss", "R", "K")},
+                       used_cv=[r["used_cv"] for r in tte["cv"]["rungs"]])}
 
 
 def main():
@@ -87,11 +184,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sector", choices=["sector", "product_peak"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-error", action="store_true",
                     help="skip the time-to-error comparison of the plain estimator and the control variate")
-    ap.add_argument("--tte-goal", type=float, default=1e-4, help="relative error goal of the time-to-error leg")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the product-peak batch and the complex d = 10 legs")
+    ap.add_argument("--tte-goal", type=float, default=1e-7, help="relative error goal of the time-to-error leg")
     ap.add_argument("--tile", type=int, default=0, help="shift tile override (0 = tuned/default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -114,7 +213,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_mib": args.copy_probe, "copies": 4}))
         return
-    from paper_1811_11722_amd import qmc
+    from paper_1811_11722_amd import drivers, qmc
 
     w, tk, alpha = make_workload(args.workload)
     print(f"[bench] workload {w.name}", file=sys.stderr, flush=True)
@@ -129,8 +228,10 @@ def main():
 
     for _ in range(args.warmup):
         res, q = plan.integrate(params)
-    print(f"[bench] warmup done: mean {res.mean_re!r} err {res.err_re!r}", file=sys.stderr,
-          flush=True)
+    if w.family == "sector" and not plan.last_launch()[2]:
+        raise SystemExit("the sector estimate did not run its run-time specialised kernel "
+                         "(hipRTC unavailable?): refusing to report the table-driven fallback")
+    print(f"[bench] warmup done: mean {res.mean_re!r} err {res.err_re!r}", file=sys.stderr, flush=True)
     plan.set_timing(True)
     plan.kernel_time(reset=True)
     torch.cuda.synchronize()
@@ -143,8 +244,18 @@ def main():
     evals = w.n * w.m
     value = evals * args.steps / wall
     avg_kernel_s = kernel_ms / max(launches, 1) / 1e3
-    fpe = flops_per_eval(args.workload)
+    fpe = FLOPS_MODEL[args.workload]
     achieved = fpe * evals / avg_kernel_s / 1e12
+    rf = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+          "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+          "traffic": TRAFFIC_BYTES.get(args.workload), "kernel": "k_lattice",
+          "kernel_ms": avg_kernel_s * 1e3, "flops_per_eval": fpe,
+          "counted_flops_per_eval": FLOPS_COUNTED[args.workload],
+          "achieved_counted": FLOPS_COUNTED[args.workload] * evals / avg_kernel_s / 1e12,
+          "frac_counted": FLOPS_COUNTED[args.workload] * evals / avg_kernel_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+          "cycles_per_xcd": CYCLES_PER_XCD.get(args.workload),
+          "clock_ghz_implied": (CYCLES_PER_XCD[args.workload] / avg_kernel_s / 1e9
+                                if args.workload in CYCLES_PER_XCD else None)}
     out = {
         "metric": METRIC,
         "value": value,
@@ -160,27 +271,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "d": w.d, "n": w.n, "m": w.m,
                    "transform": tk if tk != "korobov" else f"korobov{alpha}",
-                   "family": w.family, "evals_per_step": evals, "generator_a": a},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": TRAFFIC_BYTES.get(args.workload), "kernel": "k_lattice",
-                     "kernel_ms": avg_kernel_s * 1e3,
-                     "flops_per_eval": fpe},
+                   "family": w.family, "evals_per_step": evals, "generator_a": a,
+                   "kernel_specialised": bool(plan.last_launch()[2]) if w.family == "sector" else None},
+        "roofline": rf,
         "result": {"mean": res.mean_re, "err": res.err_re},
     }
+    plan.close()
+    if not args.no_legs and args.workload == "sector":
+        print("[bench] product-peak batch of 512", file=sys.stderr, flush=True)
+        out["product_peak_batch512"] = leg_product_peak_batch(qmc, drivers)
+        print("[bench] complex sector d = 10 at n = 2^30 - 35", file=sys.stderr, flush=True)
+        out["sector_complex_d10"] = leg_complex_d10(qmc, steps=3)
     if not args.no_time_to_error and args.workload == "sector":
-        # the metric's second part: wall time to a relative error goal, plain
-        # estimator against the learned control variate (training included),
-        # on the d = 8 sector workload, each up the ladder of primes below 2^k
-        from paper_1811_11722_amd import drivers
         print("[bench] time-to-error ladders", file=sys.stderr, flush=True)
-        tte = drivers.time_to_error(goal=args.tte_goal, kmax=26)
-        out["time_to_error"] = {
-            "goal_rel_err": args.tte_goal, "workload": f"sector_real_d{tte['d']}_nu{tte['n_u']}_nf{tte['n_f']}_baker",
-            "m": tte["m"],
-            "plain": {k: tte["plain"][k] for k in ("goal_met", "n", "rel_err", "seconds_at_n", "ladder_seconds")},
-            "cv": {k: tte["cv"][k] for k in ("goal_met", "n", "rel_err", "seconds_at_n", "ladder_seconds",
-                                             "train_seconds", "R", "K")}}
+        out["time_to_error"] = leg_time_to_error(drivers, args.tte_goal)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, tk, alpha, g, args.cpu_seconds)

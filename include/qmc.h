@@ -196,7 +196,9 @@ qmc_status qmc_integrate(qmc_plan_t plan, qmc_family family, const void *params,
 
 /* Device time of the lattice kernels launched through this plan since the
    last reset, measured with HIP events on the plan's stream.  Timing is off
-   until qmc_plan_set_timing(plan, 1). */
+   until qmc_plan_set_timing(plan, 1).  A batch (qmc_integrate_batch) whose
+   first plan has timing on adds its device time (its kernels on the batch
+   stream, from the launch to the end of the last one) to that plan. */
 qmc_status qmc_plan_set_timing(qmc_plan_t plan, int32_t enable);
 qmc_status qmc_plan_kernel_time(qmc_plan_t plan, double *total_ms, uint64_t *launches, int32_t reset);
 

@@ -481,13 +481,26 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
             }
         }
     } else {
+        // with timing on the first plan, the device time of the batch's
+        // kernels (graph launch to its end, on the batch stream) is added to
+        // that plan's kernel time
+        qmc_plan_s *p0 = plans[0];
+        if (p0->timing) (void)hipEventRecord(p0->ev0, c->stream);
         qmc_status st = run_graph(*c, o.use_graph != 0);
         if (st) return st;
+        if (p0->timing) (void)hipEventRecord(p0->ev1, c->stream);
         if ((e = hipMemcpyAsync(c->h_q, c->fargs.q, c->nq * 8, hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
             (e = hipMemcpyAsync(c->h_res, c->fargs.res, (size_t)count * 32, hipMemcpyDeviceToHost, c->stream)) !=
                 hipSuccess ||
             (e = hipStreamSynchronize(c->stream)) != hipSuccess)
             return hip_fail(e, "batch results");
+        if (p0->timing) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p0->ev0, p0->ev1) == hipSuccess) {
+                p0->kernel_ms += ms;
+                p0->kernel_launches += 1;
+            }
+        }
         for (uint32_t i = 0; i < count; ++i) {
             const BatchSector &s = c->hs[i];
             bool fin = true;

@@ -326,12 +326,17 @@ def product_peak_batch(count: int = 512, n: int = 131071, m: int = 16, d: int = 
         if shift_tile or blocks_per_cu:
             plans[-1].set_launch(shift_tile, blocks_per_cu)
         params.append(qmc.Params("genz_product_peak", d, a=aa, u=uu))
+    qmc.integrate_batch(plans, params, tile_points=tile_points)  # builds and captures the batch
+    plans[0].set_timing(True)
+    plans[0].kernel_time(reset=True)
     res, t = _timed(lambda: qmc.integrate_batch(plans, params, tile_points=tile_points), reps)
+    kms, launches = plans[0].kernel_time()
     evals = count * n * m
     for p in plans:
         p.close()
     return {"instances": count, "n": n, "m": m, "d": d, "evals": evals, "seconds": t,
-            "evals_per_s": evals / t, "generator_a": a, "shift_tile": shift_tile, "blocks_per_cu": blocks_per_cu}
+            "evals_per_s": evals / t, "device_seconds": kms / max(launches, 1) / 1e3, "generator_a": a,
+            "shift_tile": shift_tile, "blocks_per_cu": blocks_per_cu}
 
 
 def _sync():
@@ -341,34 +346,51 @@ def _sync():
 
 def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 4,
                   goal: float = 1e-7, m: int = 32, R: int = 32, K: int = 12, n_train: int = 1048573,
-                  kmin: int = 14, kmax: int = 26, max_sweeps: int = 12, log=None) -> dict:
+                  kmin: int = 14, kmax: int = 30, cv_kmax: int = 28, max_sweeps: int = 12, transform=None,
+                  pilot_n: int = 65521, candidates: int = 64, choices=None, log=None) -> dict:
     """Time to a relative error goal, plain estimator against the control
-    variate (real sector integrand, baker's transform).  Each form runs the
-    ladder of primes below 2^k upwards until err / |mean| <= goal; reported:
-    the wall time of the first lattice size that meets the goal (CV training
-    included for the CV form), the cumulative ladder time, and every rung.
-    Generating vectors are searched once per (n, d) beforehand (tabulated in
-    practice) and their time is reported on its own; the first call of each
-    form compiles its specialised kernel and is not timed."""
+    variate (real sector integrand).  The periodising transform is
+    `transform` = (kind, alpha), or (None) the one choose_transform picks on
+    a pilot lattice of pilot_n points, timed and reported on its own.  Each
+    form runs the ladder of primes below 2^k upwards (plain to kmax, the
+    control variate to cv_kmax) until err / |mean| <= goal; reported: the
+    wall time of the first lattice size that meets the goal (CV training
+    included for the CV form) or of the last rung, the cumulative ladder
+    time, and every rung.  Generating vectors (P2 search over `candidates`
+    Korobov multipliers) are searched once per (n, d) beforehand (tabulated
+    in practice) and their time is reported on its own; the first call of
+    each form compiles its specialised kernel and is not timed.  choices:
+    the candidate transforms (None: every transform choose_transform
+    knows)."""
     tab = synth.sector_tables(seed, d, n_u, n_f)
     params = qmc.Params("sector", d, sector=tab)
     ladder = synth.prime_ladder(kmin, kmax)
     sh = synth.shifts(seed, m, d)
-    gv = GeneratingVectors(seed)
+    gv = GeneratingVectors(seed, candidates=candidates)
     say = log or (lambda msg: None)
     t0 = time.perf_counter()
     for n in ladder:
         gv(n, d)
     t_search = time.perf_counter() - t0
     say(f"generating vectors for {len(ladder)} rungs: {t_search:.2f} s")
+    choice, t_choice = None, 0.0
+    if transform is None:
+        t0 = time.perf_counter()
+        choice = choose_transform(params, d, pilot_n, m=16, seed=seed, choices=choices, gv=gv)
+        t_choice = time.perf_counter() - t0
+        transform = (choice["best"]["transform"], choice["best"]["alpha"])
+        say(f"transform choice at n={pilot_n}: {transform} ({t_choice:.2f} s)")
+    tk, alpha = transform
 
-    warm = qmc.Plan(d, ladder[0], gv(ladder[0], d), sh, "baker")
+    warm = qmc.Plan(d, ladder[0], gv(ladder[0], d), sh, tk, alpha)
     warm.integrate(params)
 
-    def ladder_run(step):
+    def ladder_run(step, top):
         rows, cum, hit = [], 0.0, None
         for n in ladder:
-            plan = qmc.Plan(d, n, gv(n, d), sh, "baker")
+            if n >= (1 << top):
+                break
+            plan = qmc.Plan(d, n, gv(n, d), sh, tk, alpha)
             _sync()
             t = time.perf_counter()
             res = step(plan)
@@ -386,10 +408,10 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
         return rows, cum, hit
 
     say("plain")
-    rows_p, cum_p, hit_p = ladder_run(lambda plan: plan.integrate(params)[0])
+    rows_p, cum_p, hit_p = ladder_run(lambda plan: plan.integrate(params)[0], kmax)
 
     say("control variate: training")
-    train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), "baker")
+    train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), tk, alpha)
     _sync()
     t = time.perf_counter()
     W, c, rep = train.cv_train(params, R, K, max_sweeps=max_sweeps)
@@ -400,7 +422,7 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
     warm.integrate_cv(params, W, c)
     warm.close()
     say("control variate: ladder")
-    rows_c, cum_c, hit_c = ladder_run(lambda plan: plan.integrate_cv(params, W, c)[0])
+    rows_c, cum_c, hit_c = ladder_run(lambda plan: plan.integrate_cv(params, W, c)[0], cv_kmax)
 
     def summary(rows, cum, hit, extra):
         return {"goal_met": hit is not None, "n": (hit or rows[-1])["n"],
@@ -408,7 +430,10 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
                 "seconds_at_n": (hit or rows[-1])["seconds"] + extra,
                 "ladder_seconds": cum + extra, "rungs": rows}
 
-    return {"d": d, "n_u": n_u, "n_f": n_f, "m": m, "goal": goal, "transform": "baker",
+    return {"d": d, "n_u": n_u, "n_f": n_f, "m": m, "goal": goal, "transform": f"{tk}{alpha or ''}",
+            "transform_choice": None if choice is None else
+            {"pilot_n": pilot_n, "seconds": t_choice,
+             "rel_err": {f"{r['transform']}{r['alpha'] or ''}": r["rel_err"] for r in choice["rows"]}},
             "generating_vector_search_seconds": t_search,
             "plain": summary(rows_p, cum_p, hit_p, 0.0),
             "cv": dict(summary(rows_c, cum_c, hit_c, t_train), R=R, K=K, n_train=n_train,
@@ -737,7 +762,7 @@ def main(argv=None):
     elif args.what == "fig3":
         out = fig3(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "time_to_error":
-        out = time_to_error(kmax=args.kmax or 26, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+        out = time_to_error(kmax=args.kmax or 30, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     else:
         kmax = args.kmax or 30
         out = convergence(kmax=kmax, cv_kmax=kmax if args.cv_kmax < 0 else args.cv_kmax,
