@@ -71,6 +71,7 @@ class _Params(C.Structure):
         ("deform_lambda", C.c_double),
         ("deform_check", C.c_int32),
         ("point_mode", C.c_int32),
+        ("precise", C.c_int32),
     ]
 
 
@@ -100,6 +101,10 @@ def lib() -> C.CDLL:
         L.or_fhat.argtypes = [vp, u32, i32, i32, vp, vp, vp]
         L.or_estimate.restype = C.c_int
         L.or_estimate.argtypes = [u32, u64, vp, u32, vp, i32, i32, vp, i32, vp, vp, vp]
+        L.or_estimate_cond.restype = C.c_int
+        L.or_estimate_cond.argtypes = [u32, u64, vp, u32, vp, i32, i32, vp, i32, vp, vp, vp, vp]
+        L.or_sector_condition.restype = dbl
+        L.or_sector_condition.argtypes = [vp, u32, vp]
         L.or_mean_error.argtypes = [u32, vp, vp]
         L.or_korobov_vector.argtypes = [u64, u32, u64, vp]
         L.or_p2.restype = dbl
@@ -137,14 +142,16 @@ class Params:
 
     def __init__(self, family: str, d: int, *, c: float = 1.0, a=None, u=None, trig=None,
                  sector=None, cv=None, point_mode: int = 0, eps=None, deform: float = 0.0,
-                 deform_check: bool = False):
+                 deform_check: bool = False, precise: bool = False):
         """eps (sector): (eps_u, eps_f, k) selects the coefficient of e^k of the
-        integrand with exponents pow_u + eps_u e, pow_f + eps_f e."""
+        integrand with exponents pow_u + eps_u e, pow_f + eps_f e.  precise
+        (plain sector): U, F, the powers and logarithms in long double."""
         self.keep = []
         p = _Params()
         p.family = FAMILIES[family]
         p.c = float(c)
         p.point_mode = int(point_mode)
+        p.precise = int(bool(precise))
         if eps is not None:
             p.eps_u, p.eps_f, p.eps_order = float(eps[0]), float(eps[1]), int(eps[2])
         p.deform_lambda = float(deform)  # contour deformation of a sector (0 = none)
@@ -268,8 +275,9 @@ def fhat(params: Params, x, tkind: str = "none", alpha: int = 0) -> complex:
 
 
 class Estimate:
-    def __init__(self, q_re, q_im, q_abs, status):
+    def __init__(self, q_re, q_im, q_abs, status, q_cond=None):
         self.q_re, self.q_im, self.q_abs, self.status = q_re, q_im, q_abs, status
+        self.q_cond = q_cond
 
     @property
     def q(self) -> np.ndarray:
@@ -282,8 +290,10 @@ class Estimate:
 
 
 def estimate(n: int, g, shifts, params: Params, tkind: str = "none", alpha: int = 0,
-             threads: int = 0) -> Estimate:
-    """Per-shift Q_k of eq. (2) for every shift row."""
+             threads: int = 0, condition: bool = False) -> Estimate:
+    """Per-shift Q_k of eq. (2) for every shift row.  condition (sectors):
+    also q_cond[k] = (1/n) sum_j |fhat_j| c_j, c_j the sector's rounding
+    condition at the point (sector_condition)."""
     g = np.ascontiguousarray(np.asarray(g, dtype=np.uint64))
     sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64))
     m, d = sh.shape
@@ -291,9 +301,18 @@ def estimate(n: int, g, shifts, params: Params, tkind: str = "none", alpha: int 
     if threads <= 0:
         threads = os.cpu_count() or 1
     q_re, q_im, q_abs = np.zeros(m), np.zeros(m), np.zeros(m)
-    st = lib().or_estimate(d, n, _ptr(g), m, _ptr(sh), TRANSFORMS[tkind], alpha, params.ref,
-                           threads, _ptr(q_re), _ptr(q_im), _ptr(q_abs))
-    return Estimate(q_re, q_im, q_abs, st)
+    q_cond = np.zeros(m) if condition else None
+    st = lib().or_estimate_cond(d, n, _ptr(g), m, _ptr(sh), TRANSFORMS[tkind], alpha, params.ref,
+                                threads, _ptr(q_re), _ptr(q_im), _ptr(q_abs), _ptr(q_cond))
+    return Estimate(q_re, q_im, q_abs, st, q_cond)
+
+
+def sector_condition(params: Params, z) -> float:
+    """|pU| S_U / |U| + |pF| S_F / |F - i delta| at z (S: sums of the terms'
+    magnitudes): the relative change of the sector's value per unit
+    roundoff in the terms of U and F."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    return float(lib().or_sector_condition(params.ref, z.size, _ptr(z)))
 
 
 def mean_error(q) -> tuple:

@@ -113,6 +113,11 @@ typedef struct {
     int32_t deform_check;
     /* coordinate rounding: 0 -> idx / n (IEEE division), 1 -> idx * (1/n) */
     int32_t point_mode;
+    /* precise != 0: a plain (undeformed) sector is evaluated in long double
+       (U, F, the monomials, the powers and logarithms), so that the
+       reference's own rounding stays far below double precision even where
+       the terms of a mixed-sign F cancel */
+    int32_t precise;
 } or_params;
 
 /* ------------------------------------------------------------------ */
@@ -230,6 +235,32 @@ static double or_ipow(double v, int e)
     for (int t = 0; t < e; ++t)
         r *= v;
     return r;
+}
+
+static long double or_ipowl(long double v, int e)
+{
+    long double r = 1.0L;
+    for (int t = 0; t < e; ++t)
+        r *= v;
+    return r;
+}
+
+/* sum_t coef[t] prod_i z_i^exp[t,i] in long double, and the sum of the
+   terms' magnitudes */
+static long double or_polyl(uint32_t d, uint32_t nt, const double *coef, const uint8_t *ex,
+                            const double *z, long double *mag)
+{
+    long double s = 0.0L, a = 0.0L;
+    for (uint32_t t = 0; t < nt; ++t) {
+        long double mono = coef[t];
+        for (uint32_t i = 0; i < d; ++i)
+            mono *= or_ipowl((long double)z[i], ex[t * d + i]);
+        s += mono;
+        a += fabsl(mono);
+    }
+    if (mag)
+        *mag = a;
+    return s;
 }
 
 /* sparse polynomial sum_t coef[t] prod_i z_i^exp[t,i] */
@@ -491,6 +522,28 @@ void or_integrand(const or_params *p, uint32_t d, const double *z, double *re, d
             vi = cimag(v);
             break;
         }
+        if (p->precise) {
+            long double monol = 1.0L;
+            for (uint32_t i = 0; i < d; ++i)
+                monol *= or_ipowl((long double)z[i], p->nu[i]);
+            const long double Ul = or_polyl(d, p->n_u, p->coef_u, p->exp_u, z, NULL);
+            const long double Fl = or_polyl(d, p->n_f, p->coef_f, p->exp_f, z, NULL);
+            const long double prel = monol * powl(Ul, (long double)p->pow_u);
+            long double complex vl, Ll;
+            if (p->is_complex) {
+                const long double complex Fcl = Fl - I * (long double)p->delta_im;
+                vl = prel * cpowl(Fcl, (long double)p->pow_f);
+                Ll = (long double)p->eps_u * logl(Ul) + (long double)p->eps_f * clogl(Fcl);
+            } else {
+                vl = prel * powl(Fl, (long double)p->pow_f);
+                Ll = (long double)p->eps_u * logl(Ul) + (long double)p->eps_f * logl(Fl);
+            }
+            for (int32_t k = 1; k <= p->eps_order; ++k)
+                vl = vl * Ll / (long double)k;
+            vr = (double)creall(vl);
+            vi = p->is_complex ? (double)cimagl(vl) : 0.0;
+            break;
+        }
         double mono = 1.0;
         for (uint32_t i = 0; i < d; ++i)
             mono *= or_ipow(z[i], p->nu[i]);
@@ -566,6 +619,23 @@ int or_cv_samples(uint32_t d, uint64_t n, const uint64_t *g, const double *shift
     return 0;
 }
 
+/* How strongly double-precision rounding in the sums of a plain sector's
+   polynomials moves its value, relative to |f|: a relative error u in every
+   term of U and F changes U^pU (F - i delta)^pF by at most
+   u (|pU| S_U / |U| + |pF| S_F / |F - i delta|), S the sum of the terms'
+   magnitudes.  Returns that factor (without u); 0 for other families. */
+double or_sector_condition(const or_params *p, uint32_t d, const double *z)
+{
+    if (p->family != OR_F_SECTOR || p->deform_lambda != 0.0)
+        return 0.0;
+    long double su, sf;
+    const long double U = or_polyl(d, p->n_u, p->coef_u, p->exp_u, z, &su);
+    const long double F = or_polyl(d, p->n_f, p->coef_f, p->exp_f, z, &sf);
+    const long double delta = p->is_complex ? (long double)p->delta_im : 0.0L;
+    const long double fmod_ = sqrtl(F * F + delta * delta);
+    return (double)(fabsl((long double)p->pow_u) * su / fabsl(U) + fabsl((long double)p->pow_f) * sf / fmod_);
+}
+
 /* ------------------------------------------------------------------ */
 /* Compensated long-double accumulation                                 */
 /* ------------------------------------------------------------------ */
@@ -594,6 +664,7 @@ typedef struct {
     int32_t tkind, alpha;
     const or_params *p;
     or_acc *part_re, *part_im, *part_abs; /* [m][NCHUNK] */
+    or_acc *part_cond;                    /* [m][NCHUNK], NULL: not wanted */
     int next;                             /* next work item, guarded by lock */
     pthread_mutex_t lock;
 } or_job;
@@ -603,20 +674,30 @@ static void or_work_item(or_job *jb, int item)
     uint32_t k = (uint32_t)(item / OR_NCHUNK);
     uint64_t c = (uint64_t)(item % OR_NCHUNK);
     uint64_t j0 = jb->n * c / OR_NCHUNK, j1 = jb->n * (c + 1) / OR_NCHUNK;
-    or_acc re = {0, 0}, im = {0, 0}, ab = {0, 0};
-    double x[64];
+    or_acc re = {0, 0}, im = {0, 0}, ab = {0, 0}, co = {0, 0};
+    double x[64], z[64];
     const double *sh = jb->shifts + (size_t)k * jb->d;
     for (uint64_t j = j0; j < j1; ++j) {
         or_point(jb->d, jb->n, jb->g, j, sh, jb->p->point_mode, x);
         double vr, vi;
         or_fhat(jb->p, jb->d, jb->tkind, jb->alpha, x, &vr, &vi);
+        const double av = sqrt(vr * vr + vi * vi);
         or_acc_add(&re, vr);
         or_acc_add(&im, vi);
-        or_acc_add(&ab, sqrt(vr * vr + vi * vi));
+        or_acc_add(&ab, av);
+        if (jb->part_cond) {
+            for (uint32_t i = 0; i < jb->d; ++i) {
+                double w;
+                or_transform(jb->tkind, jb->alpha, x[i], &z[i], &w);
+            }
+            or_acc_add(&co, av * or_sector_condition(jb->p, jb->d, z));
+        }
     }
     jb->part_re[item] = re;
     jb->part_im[item] = im;
     jb->part_abs[item] = ab;
+    if (jb->part_cond)
+        jb->part_cond[item] = co;
 }
 
 static void *or_worker(void *arg)
@@ -637,9 +718,24 @@ static void *or_worker(void *arg)
 /* Per-shift estimates Q_k (re, im) and sum_j |fhat| / n (for the condition
    number).  Returns 0, or 5 when a per-shift sum is not finite, or 1 on bad
    arguments. */
+int or_estimate_cond(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
+                     int32_t tkind, int32_t alpha, const or_params *p, int32_t nthreads, double *q_re,
+                     double *q_im, double *q_abs, double *q_cond);
+
 int or_estimate(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
                 int32_t tkind, int32_t alpha, const or_params *p, int32_t nthreads, double *q_re,
                 double *q_im, double *q_abs)
+{
+    return or_estimate_cond(d, n, g, m, shifts, tkind, alpha, p, nthreads, q_re, q_im, q_abs, NULL);
+}
+
+/* or_estimate, and (q_cond non-NULL) per shift (1/n) sum_j |fhat_j| c_j with
+   c_j = or_sector_condition at the point's transformed coordinates: times
+   the unit roundoff, a bound on how far double-precision sums of U and F
+   can move Q_k */
+int or_estimate_cond(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const double *shifts,
+                     int32_t tkind, int32_t alpha, const or_params *p, int32_t nthreads, double *q_re,
+                     double *q_im, double *q_abs, double *q_cond)
 {
     if (d == 0 || d > 64 || n < 1 || m < 1)
         return 1;
@@ -662,6 +758,7 @@ int or_estimate(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const dou
     jb.part_re = (or_acc *)calloc(items, sizeof(or_acc));
     jb.part_im = (or_acc *)calloc(items, sizeof(or_acc));
     jb.part_abs = (or_acc *)calloc(items, sizeof(or_acc));
+    jb.part_cond = q_cond ? (or_acc *)calloc(items, sizeof(or_acc)) : NULL;
     jb.next = 0;
     pthread_mutex_init(&jb.lock, NULL);
     if (nthreads < 1)
@@ -694,12 +791,21 @@ int or_estimate(uint32_t d, uint64_t n, const uint64_t *g, uint32_t m, const dou
         q_im[k] = (double)((im.s + im.c) / (long double)n);
         if (q_abs)
             q_abs[k] = (double)((ab.s + ab.c) / (long double)n);
+        if (q_cond) {
+            or_acc co = {0, 0};
+            for (int c = 0; c < OR_NCHUNK; ++c) {
+                or_acc_add(&co, jb.part_cond[(size_t)k * OR_NCHUNK + c].s);
+                or_acc_add(&co, jb.part_cond[(size_t)k * OR_NCHUNK + c].c);
+            }
+            q_cond[k] = (double)((co.s + co.c) / (long double)n);
+        }
         if (!isfinite(q_re[k]) || !isfinite(q_im[k]))
             status = 5;
     }
     free(jb.part_re);
     free(jb.part_im);
     free(jb.part_abs);
+    free(jb.part_cond);
     return status;
 }
 

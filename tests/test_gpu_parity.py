@@ -14,6 +14,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1811_11722_amd import synth
+from parity_bounds import complex_sector_check
 
 pytestmark = pytest.mark.gpu
 
@@ -329,11 +330,12 @@ def test_specialised_default_tile(Q, d, cplx, want):
     res, q = plan.integrate(Q.Params("sector", d, sector=tab))
     T, _, used = plan.last_launch()
     assert used and T == want
-    est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
-    ref = est.q if cplx else est.q_re
-    # a mixed-sign complex F: the bar is the oracle's own reordering floor
-    tol = max(TOL, 4 * _reorder_floor(tab, n, g, sh)) if cplx else TOL
-    assert np.all(_rel(q, ref) < tol), (_rel(q, ref).max(), tol)
+    if cplx:
+        # a mixed-sign complex F: the bound of its rounding condition
+        complex_sector_check(q, n, g, sh, tab, label=f"default tile d={d}")
+    else:
+        est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
+        assert np.all(_rel(q, est.q_re) < TOL), _rel(q, est.q_re).max()
     plan.close()
 
 
@@ -358,38 +360,25 @@ def test_orders_default_tile(Q, d, want):
     plan.close()
 
 
-def _reorder_floor(tab, n, g, sh):
-    """FP64 evaluation floor of a mixed-sign complex sector: the largest
-    relative change of the oracle's Q_k when F's monomials are summed in
-    three other orders (same polynomial, different rounding)."""
-    import dataclasses
-    d = tab.d
-    base = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS).q
-    worst = 0.0
-    for s in range(3):
-        perm = np.random.default_rng(s).permutation(tab.n_f)
-        t2 = dataclasses.replace(tab, coef_f=tab.coef_f[perm], exp_f=tab.exp_f[perm])
-        q2 = O.estimate(n, g, sh, O.Params("sector", d, sector=t2), "baker", threads=THREADS).q
-        worst = max(worst, float(np.max(np.abs(q2 - base) / np.abs(base))))
-    return worst
-
-
 @pytest.mark.parametrize("jit", [0, 2])
 @pytest.mark.parametrize("launch", [None, (1, 0), (2, 0)])
 def test_sector_complex(Q, launch, jit):
-    """Complex kinematics (mixed-sign F, F - 0.01i), d = 10.  F's terms
-    (magnitude up to ~100) cancel to |F - i delta| ~ 0.01 near its zero set, so
-    the oracle itself moves by up to ~1e-11 relative under a reordering of F;
-    the bar is the larger of 1e-12 and 4x that measured floor."""
+    """Complex kinematics (mixed-sign F, F - 0.01i), d = 10 (workload 5's
+    shape), against the long-double oracle within the rounding-condition
+    bound of complex_sector_check."""
     n, m, d = 16381, 6, 10
-    res, q, est = _sector_case(Q, d, n, m, 20, 60, 505, complex_kinematics=True,
-                               launch=launch, jit=jit)
     tab = synth.sector_tables(505, d, 20, 60, complex_kinematics=True)
     ab, _, _ = O.korobov_search(n, d, synth.korobov_candidates(505, n, 8), threads=THREADS)
-    tol = max(TOL, 4 * _reorder_floor(tab, n, O.korobov_vector(n, d, ab), synth.shifts(505, m, d)))
-    qo = est.q
-    assert tol < 1e-9
-    assert np.all(np.abs(q - qo) <= tol * np.abs(qo)), ((np.abs(q - qo) / np.abs(qo)).max(), tol)
+    g = O.korobov_vector(n, d, ab)
+    sh = synth.shifts(505, m, d)
+    plan = Q.Plan(d, n, g, sh, "baker")
+    if launch:
+        plan.set_launch(*launch)
+    plan.set_jit(jit)
+    _say(f"complex sector d={d} launch={launch} jit={jit}")
+    res, q = plan.integrate(Q.Params("sector", d, sector=tab))
+    plan.close()
+    complex_sector_check(q, n, g, sh, tab, label=f"launch={launch} jit={jit}")
 
 
 def test_xmy_toy_integral(Q):

@@ -824,3 +824,32 @@ def test_cbc_weights_change_the_choice():
     assert e2[0] == e21[0] and np.all(e2[1:] < e21[1:])
     z3, e23 = O.cbc(n, 3, gamma=gam[:3])
     assert list(z3) == list(z[:3]) and np.array_equal(e23, e2[:3])
+
+
+# ------------------------------------------------- precise (long double) sector mode
+def test_precise_sector_mode_and_condition():
+    """The long-double evaluation of a plain sector agrees with the double
+    one where nothing cancels (positive coefficients) and with the eq. (7)
+    closed form's integrand pointwise; the rounding condition of F = 1 - x1
+    (pF = -1.3, pU = -2, U = 1) is 2 + 1.3 (1 + x1) / |1 - x1 - i delta|."""
+    d = 2
+    rng = np.random.default_rng(3)
+    tab = synth.sector_tables(61, d, 3, 5)
+    for _ in range(50):
+        z = rng.random(d)
+        a = O.integrand(O.Params("sector", d, sector=tab), z)
+        b = O.integrand(O.Params("sector", d, sector=tab, precise=True), z)
+        assert abs(a - b) <= 1e-14 * abs(b)
+    xmy = _sector(d, [1.0], [[0, 0]], [1.0, -1.0], [[1, 0], [0, 1]], [0, 0], pow_u=-2.0, pow_f=-1.7,
+                  delta=1e-2, cplx=True)
+    for _ in range(50):
+        z = rng.random(d)
+        b = O.integrand(O.Params("sector", d, sector=xmy, precise=True), z)
+        want = complex(z[0] - z[1], -1e-2) ** -1.7
+        assert abs(b - want) <= 1e-15 * abs(want)
+    lin = _sector(d, [1.0], [[0, 0]], [1.0, -1.0], [[0, 0], [1, 0]], [0, 0], pow_u=-2.0, pow_f=-1.3,
+                  delta=1e-2, cplx=True)
+    for x1 in (0.1, 0.5, 0.99):
+        c = O.sector_condition(O.Params("sector", d, sector=lin), [x1, 0.3])
+        want = 2.0 + 1.3 * (1 + x1) / abs(complex(1 - x1, -1e-2))
+        assert abs(c - want) <= 1e-14 * want
