@@ -41,7 +41,9 @@ typedef enum {
     QMC_EUNSUPPORTED = 2,  /* valid but outside what this build supports */
     QMC_ENOMEM = 3,        /* device or host allocation failed */
     QMC_EDEVICE = 4,       /* HIP runtime error; detail in qmc_last_error() */
-    QMC_ENONFINITE = 5     /* a per-shift sum is not finite; means/errors set to NaN */
+    QMC_ENONFINITE = 5,    /* a per-shift sum is not finite; means/errors set to NaN */
+    QMC_ECONTOUR = 6       /* a deformed contour reaches Im(F - i delta) > 0 at some points
+                              (Sec. 3); the result is filled in, contour_crossed > 0 */
 } qmc_status;
 
 /* Periodising transforms, eqs. (4) and (5).  QMC_T_TENT is the same map as
@@ -138,6 +140,10 @@ typedef struct {
     double err_re, err_im;
     int32_t is_complex;
     int32_t used_cv;  /* 1 when a control-variate estimate was returned */
+    /* Contour-deformed sectors: the fraction of the points (over all
+       shifts) at which the deformed F(z) - i delta has a positive imaginary
+       part, counted in the same pass as the estimate; 0 otherwise. */
+    double contour_crossed;
 } qmc_result;
 
 /* Launch shape of the lattice kernel.  shift_tile is the number of shifts
@@ -190,7 +196,11 @@ qmc_status qmc_plan_get_launch(qmc_plan_t plan, qmc_launch *cfg, int32_t *used_j
    per_shift  nullable; receives Q_k for k = 0..m-1 (real) or 2m doubles
               (re, im interleaved) for a complex sector integrand.
    Errors: EINVAL for a bad family/params, ENONFINITE if any Q_k is not
-   finite (then means and errors are NaN), EDEVICE on a HIP error. */
+   finite (then means and errors are NaN), EDEVICE on a HIP error.  A sector
+   with deform_lambda != 0 returns ECONTOUR when the deformed contour is on
+   the wrong side of the cut (Im(F(z) - i delta) > 0) at any lattice point:
+   out and per_shift are still filled, out->contour_crossed gives the
+   fraction, and the value is not the -i0 integral (Sec. 3). */
 qmc_status qmc_integrate(qmc_plan_t plan, qmc_family family, const void *params, qmc_result *out,
                          double *per_shift);
 
@@ -245,7 +255,8 @@ typedef enum {
        reused for every later call and coefficient set with that structure, so
        this pays when the same sectors are integrated repeatedly (new
        kinematics, new shifts); EUNSUPPORTED when a specialised kernel cannot
-       be built.  The only schedule that takes contour-deformed sectors. */
+       be built.  The only schedule that takes contour-deformed sectors;
+       ECONTOUR as in qmc_integrate when any of them crosses the cut. */
     QMC_BATCH_SPECIALISED = 3
 } qmc_batch_schedule;
 
@@ -424,7 +435,9 @@ qmc_status qmc_integrate_cv(qmc_plan_t plan, qmc_family family, const void *para
    eps_u, eps_f.  out: n_orders results (caller-owned); per_shift (nullable):
    m * parts doubles, per shift the orders in turn, (Re, Im) for complex.
    Needs the specialised kernel (EUNSUPPORTED with qmc_plan_set_jit(0));
-   qmc_integrate rejects n_orders >= 2 with EINVAL. */
+   qmc_integrate rejects n_orders >= 2 with EINVAL.  With deform_lambda != 0
+   every result carries the crossing fraction and the call returns ECONTOUR
+   as qmc_integrate does. */
 qmc_status qmc_integrate_orders(qmc_plan_t plan, qmc_family family, const void *params, qmc_result *out,
                                 double *per_shift);
 
@@ -491,6 +504,15 @@ qmc_status qmc_cbc_search(uint64_t n, uint32_t d, const double *gamma, const uin
    candidate's P2 per rung.  Host memory. */
 qmc_status qmc_korobov_search_extensible(uint32_t kmin, uint32_t kmax, uint32_t d, const uint64_t *cand,
                                          uint32_t ncand, uint64_t *a_best, double *score, double *p2_levels);
+
+/* The shifts that make the n-point lattice (n = n2 / 2, generator g) the
+   odd points of the n2-point one: {shift_k + (g mod n2) / n2} per shift and
+   coordinate, the construction of the embedded lattices above.  n2: a power
+   of two in [2, 2^32] (EINVAL otherwise); g: d values; shifts, out: m * d
+   doubles row-major, each shift in [0, 1) (EINVAL otherwise); out may alias
+   shifts.  Host memory, no device call. */
+qmc_status qmc_lattice_moved_shifts(uint64_t n2, uint32_t d, const uint64_t *g, uint32_t m, const double *shifts,
+                                    double *out);
 
 /* Merge of two half-lattice estimates into the estimate of their union
    (eqs. (2)-(3)): q_out = (q_a + q_b) / 2 per shift and part, then the mean

@@ -385,9 +385,9 @@ static qmc_status batch_specialised(uint32_t count, const qmc_plan_t *plans, con
         if (st) return st;
     }
     for (uint32_t i = 0; i < count; ++i) {
-        qmc_status st = plan_collect(plans[i], pk[i].np, &out[i], nullptr);
-        if (st == QMC_ENONFINITE) {
-            if (!first_bad) first_bad = st;
+        qmc_status st = plan_collect(plans[i], pk[i].np, &out[i], nullptr, pk[i].crossing);
+        if (st == QMC_ENONFINITE || st == QMC_ECONTOUR) {
+            if (!first_bad || st == QMC_ENONFINITE) first_bad = st;
         } else if (st) {
             return st;
         }
@@ -474,7 +474,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
             bool fin = true;
             for (uint32_t k = 0; k < p->m * pk[i].np; ++k) fin = fin && std::isfinite(q[k]);
             out[i] = qmc_result{res[0], pk[i].np == 2 ? res[1] : 0.0, res[2], pk[i].np == 2 ? res[3] : 0.0,
-                                (int32_t)(pk[i].np == 2), 0};
+                                (int32_t)(pk[i].np == 2), 0, 0.0};
             if (!fin) {
                 out[i].mean_re = out[i].mean_im = out[i].err_re = out[i].err_im = NAN;
                 any_nonfinite = true;
@@ -506,7 +506,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
             bool fin = true;
             for (uint32_t k = 0; k < s.m * c->np; ++k) fin = fin && std::isfinite(c->h_q[s.q_off + k]);
             const double *r = c->h_res + 4 * i;
-            out[i] = qmc_result{r[0], c->np == 2 ? r[1] : 0.0, r[2], c->np == 2 ? r[3] : 0.0, (int32_t)(c->np == 2), 0};
+            out[i] = qmc_result{r[0], c->np == 2 ? r[1] : 0.0, r[2], c->np == 2 ? r[3] : 0.0, (int32_t)(c->np == 2), 0, 0.0};
             if (!fin) {
                 out[i].mean_re = out[i].mean_im = out[i].err_re = out[i].err_im = NAN;
                 any_nonfinite = true;

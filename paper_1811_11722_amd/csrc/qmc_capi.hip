@@ -200,7 +200,9 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
             pk.deform = true;
             pk.cplx = true;
             pk.key_family = kFamSectorComplex;
-            pk.np = 2 * (p->n_orders >= 2 ? p->n_orders : 1u);
+            // Re, Im per order, then the count of points on the wrong side
+            pk.np = 2 * (p->n_orders >= 2 ? p->n_orders : 1u) + 1;
+            pk.crossing = true;
         }
         break;
     }
@@ -433,8 +435,7 @@ qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32
     return plan_launch(p, pk, fn, jfn, T, bpc);
 }
 
-qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift) {
-    const size_t nq = (size_t)p->m * np;
+qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift, bool crossing) {
     hipError_t e = hipMemcpyAsync(p->h_out, p->d_out, out_doubles(p->m) * sizeof(double), hipMemcpyDeviceToHost,
                                   p->stream);
     if (e != hipSuccess) return hip_fail(e, "copy results");
@@ -447,20 +448,38 @@ qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per
             p->kernel_launches += 1;
         }
     }
+    // with a crossing count the last of the np parts is the count, not a
+    // value: it is left out of per_shift and of the finiteness check
+    const uint32_t nv = crossing ? np - 1 : np;
     const double *q = p->h_out, *res = p->h_out + out_res_offset(p->m);
     bool finite = true;
-    for (size_t i = 0; i < nq; ++i) finite = finite && std::isfinite(q[i]);
-    if (per_shift) std::memcpy(per_shift, q, nq * sizeof(double));
-    out->is_complex = np >= 2;
+    for (uint32_t k = 0; k < p->m; ++k)
+        for (uint32_t j = 0; j < nv; ++j) {
+            const double v = q[(size_t)k * np + j];
+            finite = finite && std::isfinite(v);
+            if (per_shift) per_shift[(size_t)k * nv + j] = v;
+        }
+    double crossed = 0.0;
+    if (crossing) {
+        // finalize scaled every part by the transform's constant and 1/n
+        long double s = 0.0L;
+        for (uint32_t k = 0; k < p->m; ++k) s += q[(size_t)k * np + nv];
+        crossed = (double)(s / ((long double)p->m * transform_scale(p->tr, p->d)));
+    }
+    out->is_complex = nv >= 2;
     out->used_cv = 0;
+    out->contour_crossed = crossed;
     if (!finite) {
         out->mean_re = out->mean_im = out->err_re = out->err_im = NAN;
         return fail(QMC_ENONFINITE, "a per-shift sum is not finite");
     }
     out->mean_re = res[0];
-    out->mean_im = np >= 2 ? res[1] : 0.0;
+    out->mean_im = nv >= 2 ? res[1] : 0.0;
     out->err_re = res[2];
-    out->err_im = np >= 2 ? res[3] : 0.0;
+    out->err_im = nv >= 2 ? res[3] : 0.0;
+    if (crossed > 0.0)
+        return fail(QMC_ECONTOUR, "the deformed contour has Im(F - i delta) > 0 at a fraction %.3g of the points",
+                    crossed);
     return QMC_OK;
 }
 
@@ -506,6 +525,7 @@ const char *qmc_status_string(qmc_status s) {
     case QMC_ENOMEM: return "out of memory";
     case QMC_EDEVICE: return "device error";
     case QMC_ENONFINITE: return "non-finite result";
+    case QMC_ECONTOUR: return "deformed contour crosses the cut";
     }
     return "unknown status";
 }
@@ -642,7 +662,7 @@ qmc_status qmc_integrate(qmc_plan_t p, qmc_family family, const void *params, qm
         if (tune_lookup(p, pk, sector && p->jit_mode != 0, tuned)) L = tuned;
     }
     if ((st = plan_enqueue(p, pk, L.shift_tile, L.blocks_per_cu))) return st;
-    return plan_collect(p, pk.np, out, per_shift);
+    return plan_collect(p, pk.np, out, per_shift, pk.crossing);
 }
 
 qmc_status qmc_integrate_orders(qmc_plan_t p, qmc_family family, const void *params, qmc_result *out,
@@ -656,16 +676,18 @@ qmc_status qmc_integrate_orders(qmc_plan_t p, qmc_family family, const void *par
     const uint32_t no = pk.orders >= 2 ? pk.orders : 1u;
     if ((st = plan_enqueue(p, pk, p->launch.shift_tile, p->launch.blocks_per_cu))) return st;
     qmc_result first;
-    st = plan_collect(p, pk.np, &first, per_shift);
+    st = plan_collect(p, pk.np, &first, per_shift, pk.crossing);
+    if (st && st != QMC_ENONFINITE && st != QMC_ECONTOUR) return st;
     const double *res = p->h_out + out_res_offset(p->m);
     for (uint32_t k = 0; k < no; ++k) {
         if (pk.cplx) {  // parts (2k, 2k+1) = (Re, Im) of order k form pair k
-            out[k] = qmc_result{res[4 * k], res[4 * k + 1], res[4 * k + 2], res[4 * k + 3], 1, 0};
+            out[k] = qmc_result{res[4 * k], res[4 * k + 1], res[4 * k + 2], res[4 * k + 3], 1, 0, 0.0};
         } else {        // part k = order k, pairs of orders share a result block
             const uint32_t b = 4 * (k / 2), o = k % 2;
-            out[k] = qmc_result{res[b + o], 0.0, res[b + 2 + o], 0.0, 0, 0};
+            out[k] = qmc_result{res[b + o], 0.0, res[b + 2 + o], 0.0, 0, 0, 0.0};
         }
-        if (st == QMC_ENONFINITE) out[k] = qmc_result{NAN, NAN, NAN, NAN, pk.cplx ? 1 : 0, 0};
+        if (st == QMC_ENONFINITE) out[k] = qmc_result{NAN, NAN, NAN, NAN, pk.cplx ? 1 : 0, 0, 0.0};
+        out[k].contour_crossed = first.contour_crossed;
     }
     return st;
 }
@@ -717,6 +739,7 @@ qmc_status qmc_deform_check(qmc_plan_t p, const qmc_sector_params *params, doubl
     pk.blob[2] = bits(flags | kSectorDeformCheck);
     pk.np = 1;
     pk.cplx = false;
+    pk.crossing = false;
     pk.orders = 0;
     if ((st = plan_enqueue(p, pk, p->launch.shift_tile, p->launch.blocks_per_cu))) return st;
     qmc_result r;
@@ -750,7 +773,7 @@ qmc_status qmc_deform_select(qmc_plan_t p, const qmc_sector_params *params, doub
         if (frac > 0.0) continue;
         qmc_result r;
         st = qmc_integrate(p, QMC_F_SECTOR, &q, &r, nullptr);
-        if (st == QMC_ENONFINITE) continue;
+        if (st == QMC_ENONFINITE || st == QMC_ECONTOUR) continue;
         if (st) return st;
         const double err = std::hypot(r.err_re, r.err_im);
         if (!found || err < best_err) {

@@ -49,6 +49,27 @@ extern "C" qmc_status qmc_korobov_search_extensible(uint32_t kmin, uint32_t kmax
     return QMC_OK;
 }
 
+extern "C" qmc_status qmc_lattice_moved_shifts(uint64_t n2, uint32_t d, const uint64_t *g, uint32_t m,
+                                              const double *shifts, double *out) {
+    if (!g || !shifts || !out) return fail(QMC_EINVAL, "null argument");
+    if (n2 < 2 || (n2 & (n2 - 1))) return fail(QMC_EINVAL, "n2 must be a power of two >= 2");
+    if (n2 > (1ull << 32)) return fail(QMC_EUNSUPPORTED, "n2 > 2^32");
+    if (d == 0 || d > kMaxDim) return fail(d ? QMC_EUNSUPPORTED : QMC_EINVAL, "d = %u outside 1..%u", d, kMaxDim);
+    for (size_t i = 0; i < (size_t)m * d; ++i)
+        if (!(shifts[i] >= 0.0 && shifts[i] < 1.0)) return fail(QMC_EINVAL, "shift %zu outside [0,1)", i);
+    // (g_i mod n2) / n2 is exact (n2 a power of two, g_i mod n2 < 2^32);
+    // the sum is rounded once, and a sum in [1, 2) wraps by an exact
+    // subtraction
+    const double inv = 1.0 / (double)n2;
+    for (uint32_t k = 0; k < m; ++k)
+        for (uint32_t i = 0; i < d; ++i) {
+            double v = shifts[(size_t)k * d + i] + (double)(g[i] & (n2 - 1)) * inv;
+            if (v >= 1.0) v -= 1.0;
+            out[(size_t)k * d + i] = v;
+        }
+    return QMC_OK;
+}
+
 extern "C" qmc_status qmc_lattice_merge(uint32_t m, uint32_t np, const double *q_a, const double *q_b, double *q_out,
                                         qmc_result *out) {
     if (!q_a || !q_b || !q_out || !out) return fail(QMC_EINVAL, "null argument");
@@ -62,6 +83,7 @@ extern "C" qmc_status qmc_lattice_merge(uint32_t m, uint32_t np, const double *q
     }
     out->is_complex = np == 2;
     out->used_cv = 0;
+    out->contour_crossed = 0.0;
     if (!finite) {
         out->mean_re = out->mean_im = out->err_re = out->err_im = NAN;
         return fail(QMC_ENONFINITE, "a per-shift sum is not finite");

@@ -92,7 +92,8 @@ const char *transform_type(const qmc_transform &t) {
 // the gradient and Hessian of F at the real point (their monomials share a
 // real product trie), the deformed point z - i lam s grad F, the complex
 // monomials of U, F and z^nu at that point (a complex product trie), the
-// symmetrised Jacobian and its determinant, then sector_deformed.
+// symmetrised Jacobian and its determinant, then sector_deformed; a last
+// part counts the points where Im(F(z) - i delta) > 0.
 static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
                                    size_t eps_at, size_t lam_at, const std::vector<std::vector<int>> &fu,
                                    const std::vector<std::vector<int>> &ff, const std::vector<int> &nuf) {
@@ -133,7 +134,7 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
     const bool check = (flags & kSectorDeformCheck) != 0;
     std::ostringstream s;
     s << "struct FamJit {\n"
-      << "    static constexpr int NP = " << (check ? 1u : 2 * no) << ";\n"
+      << "    static constexpr int NP = " << (check ? 1u : 2 * no + 1) << ";\n"
       << "    template <class Tr, int D, int T>\n"
       << "    __device__ static void eval(const double *__restrict__ p, const double (&x)[T][D],"
          " double (&v)[T][NP]) {\n"
@@ -228,10 +229,15 @@ static std::string deformed_source(uint32_t d, uint32_t flags, uint32_t orders,
             else
                 s << "((q" << i << " * q" << j << ") * h" << i << "_" << j << ");\n";
         }
-    s << "            double dr, di;\n"
+    // the value parts, then 1 where the contour is on the wrong side (the
+    // sign check of the deformation, counted in the same pass)
+    s << "            double dr, di, w[" << 2 * no << "];\n"
       << "            csym_det<D>(ar, ai, dr, di);\n"
       << "            sector_deformed<" << no
-      << ">(mr, mi, dr, di, Ur, Ui, Fr, Fi, flags, pow_u, pow_f, delta, eps_u, eps_f, v[k]);\n"
+      << ">(mr, mi, dr, di, Ur, Ui, Fr, Fi, flags, pow_u, pow_f, delta, eps_u, eps_f, w);\n"
+      << "#pragma unroll\n"
+      << "            for (int j = 0; j < " << 2 * no << "; ++j) v[k][j] = w[j];\n"
+      << "            v[k][" << 2 * no << "] = Fi - delta > 0.0 ? 1.0 : 0.0;\n"
       << "        }\n    }\n};\n";
     return s.str();
 }

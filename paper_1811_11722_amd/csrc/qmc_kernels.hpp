@@ -313,7 +313,7 @@ struct FinalizeArgs {
 };
 
 constexpr uint32_t kMaxRows = 4096;  // m * np per instance
-constexpr uint32_t kMaxParts = 8;    // parts per shift (k_finalize, result buffers)
+constexpr uint32_t kMaxParts = 10;   // parts per shift (k_finalize, result buffers): 4 complex orders + crossings
 
 struct DumpArgs {
     uint32_t n, d;

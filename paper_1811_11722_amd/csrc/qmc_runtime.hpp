@@ -67,6 +67,7 @@ struct Packed {
     bool cplx = false;     // complex sector
     uint32_t orders = 0;   // expansion orders (>= 2: qmc_integrate_orders)
     bool deform = false;   // contour deformation (complex result, specialised kernel only)
+    bool crossing = false; // last part: 1 where the deformed contour has Im(F - i delta) > 0
 };
 
 qmc_status fail(qmc_status s, const char *fmt, ...);
@@ -86,7 +87,7 @@ qmc_status ensure_buffer(void **ptr, size_t &cap, size_t bytes, const char *what
 qmc_status plan_upload_params(qmc_plan_s *p, const Packed &pk);
 qmc_status plan_set_gstep(qmc_plan_s *p, uint32_t S);
 qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32_t blocks_per_cu);
-qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift);
+qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift, bool crossing = false);
 void plan_release_extra(qmc_plan_s *p);
 uint32_t padded_rows(uint32_t m);
 std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows,

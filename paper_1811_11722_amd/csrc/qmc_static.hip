@@ -147,6 +147,7 @@ extern "C" qmc_status qmc_integrate_static(uint32_t d, uint64_t n, const uint64_
     const double *res = h + out_res_offset(m);
     out->is_complex = pk.np >= 2;
     out->used_cv = 0;
+    out->contour_crossed = 0.0;
     if (!finite) {
         out->mean_re = out->mean_im = out->err_re = out->err_im = NAN;
         return fail(QMC_ENONFINITE, "a per-shift sum is not finite");

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqmc.so")
 
 # status codes
-QMC_OK, QMC_EINVAL, QMC_EUNSUPPORTED, QMC_ENOMEM, QMC_EDEVICE, QMC_ENONFINITE = range(6)
+QMC_OK, QMC_EINVAL, QMC_EUNSUPPORTED, QMC_ENOMEM, QMC_EDEVICE, QMC_ENONFINITE, QMC_ECONTOUR = range(7)
 # transforms
 QMC_T_NONE, QMC_T_KOROBOV, QMC_T_BAKER, QMC_T_SIDI = 0, 1, 2, 3
 QMC_T_TENT = QMC_T_BAKER
@@ -61,7 +61,8 @@ class qmc_sector_params(C.Structure):
 
 class qmc_result(C.Structure):
     _fields_ = [("mean_re", C.c_double), ("mean_im", C.c_double), ("err_re", C.c_double),
-                ("err_im", C.c_double), ("is_complex", C.c_int32), ("used_cv", C.c_int32)]
+                ("err_im", C.c_double), ("is_complex", C.c_int32), ("used_cv", C.c_int32),
+                ("contour_crossed", C.c_double)]
 
 
 class qmc_cv_train_opts(C.Structure):
@@ -114,6 +115,7 @@ SIGNATURES = {
     "qmc_korobov_search_extensible": (C.c_int, [C.c_uint32, C.c_uint32, C.c_uint32, _vp, C.c_uint32, _vp, _vp,
                                                 _vp]),
     "qmc_lattice_merge": (C.c_int, [C.c_uint32, C.c_uint32, _vp, _vp, _vp, _vp]),
+    "qmc_lattice_moved_shifts": (C.c_int, [_u64, _u32, _vp, _u32, _vp, _vp]),
     "qmc_deform_select": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_uint32, _vp, _vp]),
     "qmc_cv_samples": (C.c_int, [_vp, C.c_int, _vp, _u32, _vp, _vp, _vp]),
     "qmc_cv_features": (C.c_int, [_u32, _u32, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp]),
@@ -269,12 +271,16 @@ class Plan:
               "kernel_time")
         return ms.value, cnt.value
 
-    def integrate(self, params: Params):
-        """Returns (qmc_result, per-shift array: real (m,) or complex (m,))."""
+    def integrate(self, params: Params, allow_crossing: bool = False):
+        """Returns (qmc_result, per-shift array: real (m,) or complex (m,)).
+        A deformed contour that crosses the cut raises QMCError (ECONTOUR)
+        unless allow_crossing, which returns the result with
+        res.contour_crossed > 0."""
         res = qmc_result()
         per = np.zeros(2 * self.m)
-        check(lib().qmc_integrate(self.handle, params.family, params.ptr, C.byref(res), _p(per)),
-              "qmc_integrate")
+        st = lib().qmc_integrate(self.handle, params.family, params.ptr, C.byref(res), _p(per))
+        if not (allow_crossing and st == QMC_ECONTOUR):
+            check(st, "qmc_integrate")
         if res.is_complex:
             return res, per[0::2] + 1j * per[1::2]
         return res, per[: self.m].copy()
@@ -334,15 +340,17 @@ class Plan:
         per = per.reshape(self.m, 4)
         return out, plain, per[:, 0] + 1j * per[:, 1], per[:, 2] + 1j * per[:, 3]
 
-    def integrate_orders(self, params: Params):
+    def integrate_orders(self, params: Params, allow_crossing: bool = False):
         """Expansion coefficients in one pass: (list of n_orders results,
-        per-shift array (m, n_orders), complex for complex sectors)."""
+        per-shift array (m, n_orders), complex for complex sectors);
+        allow_crossing as in integrate."""
         no = max(params.n_orders, 1)
         out = (qmc_result * no)()
         parts = no * (2 if params.is_complex else 1)
         per = np.zeros(self.m * parts)
-        check(lib().qmc_integrate_orders(self.handle, params.family, params.ptr, out, _p(per)),
-              "qmc_integrate_orders")
+        st = lib().qmc_integrate_orders(self.handle, params.family, params.ptr, out, _p(per))
+        if not (allow_crossing and st == QMC_ECONTOUR):
+            check(st, "qmc_integrate_orders")
         per = per.reshape(self.m, parts)
         if params.is_complex:
             per = per[:, 0::2] + 1j * per[:, 1::2]
@@ -494,18 +502,20 @@ def korobov_search(n: int, d: int, cand):
 
 
 def integrate_batch(plans: Sequence[Plan], params: Sequence[Params], use_graph: bool = True,
-                    per_plan_launches: bool = False, tile_points: int = 0, schedule: str = "default"):
+                    per_plan_launches: bool = False, tile_points: int = 0, schedule: str = "default",
+                    allow_crossing: bool = False):
     """schedule: "default", "persistent" (workgroups loop over the work list),
     "per_tile" (one workgroup per tile) or "specialised" (sectors: one launch
     per plan of its run-time specialised kernel, compiled once per exponent
-    structure)."""
+    structure); allow_crossing as in Plan.integrate."""
     fam = params[0].family
     handles = (C.c_void_p * len(plans))(*[p.handle for p in plans])
     pp = (C.c_void_p * len(params))(*[p.ptr for p in params])
     opts = qmc_batch_opts(int(use_graph), int(per_plan_launches), tile_points, BATCH_SCHEDULE[schedule])
     out = (qmc_result * len(plans))()
-    check(lib().qmc_integrate_batch(len(plans), handles, fam, pp, C.byref(opts), out),
-          "qmc_integrate_batch")
+    st = lib().qmc_integrate_batch(len(plans), handles, fam, pp, C.byref(opts), out)
+    if not (allow_crossing and st == QMC_ECONTOUR):
+        check(st, "qmc_integrate_batch")
     return list(out)
 
 
@@ -558,13 +568,12 @@ class ExtensibleLattice:
         self.transform, self.alpha = transform, alpha
         self.g = korobov_vector(1 << self.kmax, d, self.a)
 
-    def generator(self, k: int) -> np.ndarray:
-        return self.g % np.uint64(1 << k)
-
     def moved_shifts(self, k: int) -> np.ndarray:
         """Shifts that turn the 2^k-point lattice into the odd points of 2^(k+1)."""
-        n2 = 1 << (k + 1)
-        return np.mod(self.shifts + (self.g % np.uint64(n2)).astype(np.float64) / n2, 1.0)
+        out = np.empty_like(self.shifts)
+        check(lib().qmc_lattice_moved_shifts(1 << (k + 1), self.d, _p(self.g), self.m, _p(self.shifts), _p(out)),
+              "qmc_lattice_moved_shifts")
+        return out
 
     def ladder(self, params: "Params", kmin: int, kmax: int = None, setup=None):
         """[(n, result, per-shift)] for n = 2^kmin .. 2^kmax; setup(plan) may
@@ -575,7 +584,8 @@ class ExtensibleLattice:
         np_ = 2 if params.is_complex else 1
 
         def run(k, shifts):
-            plan = Plan(self.d, 1 << k, self.generator(k), shifts, self.transform, self.alpha)
+            # the plan reads g mod 2^k itself
+            plan = Plan(self.d, 1 << k, self.g, shifts, self.transform, self.alpha)
             if setup:
                 setup(plan)
             res, q = plan.integrate(params)

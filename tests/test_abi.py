@@ -100,8 +100,8 @@ def test_null_plan_and_status_strings(Q):
     assert L.qmc_plan_set_launch(None, None) == Q.QMC_EINVAL
     assert L.qmc_lattice_dump(None, 0, 0, None, None) == Q.QMC_EINVAL
     L.qmc_plan_destroy(None)
-    for s in range(6):
-        assert L.qmc_status_string(s)
+    for s in range(7):
+        assert L.qmc_status_string(s) != b"unknown status"
     assert L.qmc_status_string(99) == b"unknown status"
 
 
@@ -138,6 +138,50 @@ def test_construction_and_merge_validation(Q):
     assert L.qmc_deform_select(None, None, 1.0, 0.5, 4, C.byref(lam), C.byref(r)) == Q.QMC_EINVAL
     frac = C.c_double()
     assert L.qmc_deform_check(None, None, C.byref(frac), None) == Q.QMC_EINVAL
+
+
+def test_moved_shifts_exact(Q):
+    """qmc_lattice_moved_shifts (host code): {shift + (g mod 2n)/2n} against
+    exact rationals, and the nesting it serves: the n-point lattice with the
+    moved shifts is exactly the odd half of the 2n-point lattice."""
+    from fractions import Fraction as Fr
+    L = Q.lib()
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    d, m, a = 3, 5, 1093
+    rng = np.random.default_rng(7)
+    sh = rng.random((m, d))
+    sh[0, 0] = 1.0 - 2.0 ** -53       # a sum that rounds up to 1 wraps to 0
+    for k in (1, 5, 12, 31):
+        n2 = 1 << (k + 1)
+        g = np.array([pow(a, i, 1 << 40) for i in range(d)], dtype=np.uint64)   # read mod n2
+        out = np.empty_like(sh)
+        assert L.qmc_lattice_moved_shifts(n2, d, p(g), m, p(sh), p(out)) == Q.QMC_OK
+        for kk in range(m):
+            for i in range(d):
+                want = float(Fr(float(sh[kk, i])) + Fr(int(g[i]) % n2, n2))   # one rounding
+                want = want - 1.0 if want >= 1.0 else want                   # then the wrap
+                assert out[kk, i] == want, (k, kk, i)
+    # nesting, in exact rationals on a tiny lattice with dyadic shifts
+    n, d = 16, 2
+    g = np.array([1, 5], dtype=np.uint64)
+    sh = np.array([[0.25, 0.5], [0.125, 0.875]])
+    out = np.empty_like(sh)
+    assert L.qmc_lattice_moved_shifts(2 * n, d, p(g), 2, p(sh), p(out)) == Q.QMC_OK
+    for kk in range(2):
+        pts = lambda N, s: {tuple((Fr(j * int(gi), N) + Fr(float(si))) % 1 for gi, si in zip(g, s)) for j in range(N)}
+        odd = {tuple((Fr((2 * j + 1) * int(gi), 2 * n) + Fr(float(si))) % 1 for gi, si in zip(g, sh[kk]))
+               for j in range(n)}
+        assert pts(n, out[kk]) == odd
+        assert pts(n, sh[kk]) | odd == pts(2 * n, sh[kk])
+    # validation
+    assert L.qmc_lattice_moved_shifts(24, d, p(g), 2, p(sh), p(out)) == Q.QMC_EINVAL        # not a power of 2
+    assert L.qmc_lattice_moved_shifts(1, d, p(g), 2, p(sh), p(out)) == Q.QMC_EINVAL
+    assert L.qmc_lattice_moved_shifts(1 << 33, d, p(g), 2, p(sh), p(out)) == Q.QMC_EUNSUPPORTED
+    assert L.qmc_lattice_moved_shifts(32, 0, p(g), 2, p(sh), p(out)) == Q.QMC_EINVAL
+    assert L.qmc_lattice_moved_shifts(32, 17, p(g), 2, p(sh), p(out)) == Q.QMC_EUNSUPPORTED
+    assert L.qmc_lattice_moved_shifts(32, d, None, 2, p(sh), p(out)) == Q.QMC_EINVAL
+    bad = np.array([[0.5, 1.0], [0.0, 0.0]])
+    assert L.qmc_lattice_moved_shifts(32, d, p(g), 2, p(bad), p(out)) == Q.QMC_EINVAL
 
 
 def _math_table():

@@ -39,6 +39,10 @@ def _say(msg):
 @pytest.fixture(scope="module")
 def Q():
     O.build(force=False)
+    return Q_()
+
+
+def Q_():
     from paper_1811_11722_amd import qmc
     qmc.lib()
     return qmc
@@ -76,10 +80,26 @@ def _gpu(Q, d, n, g, sh, tab, lam, tk, alpha, launch=None):
     plan = Q.Plan(d, n, g, sh, tk, alpha)
     if launch:
         plan.set_launch(*launch)
-    res, q = plan.integrate(Q.Params("sector", d, sector=tab, deform=lam))
+    res, q = plan.integrate(Q.Params("sector", d, sector=tab, deform=lam), allow_crossing=True)
     assert plan.last_launch()[2], "deformation runs on the specialised kernel"
     plan.close()
+    _crossings_match(res.contour_crossed, n, g, sh, tab, lam, tk, alpha)
     return res, np.asarray(q)
+
+
+def _crossings_match(crossed, n, g, sh, tab, lam, tk, alpha):
+    """The crossing count of the estimate's own pass equals the oracle's sign
+    check (at most 2^22 points; beyond, the GPU's separate check)."""
+    if n * len(sh) <= 1 << 22:
+        chk = O.estimate(n, g, sh, O.Params("sector", tab.d, sector=tab, deform=lam, deform_check=True), tk, alpha,
+                         threads=THREADS)
+        want = int(np.rint(chk.q_re * n).sum())
+    else:
+        plan = Q_().Plan(tab.d, n, g, sh, tk, alpha)
+        frac, per = plan.deform_check(Q_().Params("sector", tab.d, sector=tab, deform=lam))
+        plan.close()
+        want = int(np.rint(per * n).sum())
+    assert round(crossed * len(sh) * n) == want, (crossed, want)
 
 
 @pytest.mark.parametrize("lam", [0.005, 0.02])
@@ -203,9 +223,12 @@ def test_deform_orders_match_oracle(Q):
     sh = synth.shifts(93, m, d)
     plan = Q.Plan(d, n, g, sh, "korobov", 3)
     _say("deform orders")
-    res, per = plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(3, 0.7, -1.2), deform=0.5))
+    res, per = plan.integrate_orders(Q.Params("sector", d, sector=tab, orders=(3, 0.7, -1.2), deform=0.5),
+                                     allow_crossing=True)
     plan.close()
     assert len(res) == 3 and per.shape == (m, 3)
+    assert len({r.contour_crossed for r in res}) == 1
+    _crossings_match(res[0].contour_crossed, n, g, sh, tab, 0.5, "korobov", 3)
     fl = _floor(n, g, sh, tab, 0.5, "korobov", 3)
     for k in range(3):
         ok, worst = _ok(per[:, k], _oracle_q(n, g, sh, tab, 0.5, "korobov", 3, eps=(0.7, -1.2, k)), fl)
@@ -278,6 +301,45 @@ def test_deform_full_size_sampled(Q):
     fl = _floor(16381, O.korobov_vector(16381, w.d, 1234), w.shifts[pick], tab, 0.5, "korobov", 3)
     ok, worst = _ok(q2[pick], est, fl)
     assert ok, (worst, fl)
+
+
+@pytest.mark.parametrize("lam", [3.0, 20.0])
+def test_deform_crossing_reported(Q, lam):
+    """qmc_integrate counts the sign check in its own pass: at lambda = 20 the
+    quartic F = x1^2 x2^2 - 0.05 crosses the cut on a region, and the call
+    returns ECONTOUR with the result filled in and the fraction equal to the
+    separate check's (and the oracle's); at lambda = 3 it does not.  Orders
+    and the specialised batch report it the same way."""
+    n, d = 65521, 2
+    g = O.korobov_vector(n, d, 17364)
+    sh = synth.shifts(21, 4, d)
+    tab = synth.SectorTables(d=d, coef_u=np.array([1.0]), exp_u=np.zeros((1, d), np.uint8),
+                             coef_f=np.array([-0.05, 1.0]), exp_f=np.array([[0, 0], [2, 2]], np.uint8),
+                             nu=np.zeros(d, np.uint8), pow_u=-2.0, pow_f=-1.5, delta_im=0.0, is_complex=True)
+    pa = Q.Params("sector", d, sector=tab, deform=lam)
+    plan = Q.Plan(d, n, g, sh, "none")
+    _say(f"deform crossing lam={lam}")
+    frac, _ = plan.deform_check(pa)
+    st, res, per = plan.integrate_status(pa)
+    if lam == 3.0:
+        assert st == Q.QMC_OK and res.contour_crossed == 0.0 and frac == 0.0
+    else:
+        assert st == Q.QMC_ECONTOUR and frac > 0.01
+        assert abs(res.contour_crossed - frac) <= 1e-15
+        assert np.all(np.isfinite(per[: 2 * len(sh)])) and np.isfinite(res.mean_re) and res.err_re > 0
+        with pytest.raises(Q.QMCError) as e:
+            plan.integrate(pa)
+        assert e.value.status == Q.QMC_ECONTOUR
+    r2, q2 = plan.integrate(pa, allow_crossing=True)
+    assert (r2.mean_re, r2.mean_im, r2.contour_crossed) == (res.mean_re, res.mean_im, res.contour_crossed)
+    assert np.array_equal(q2, per[0::2] + 1j * per[1::2])
+    _crossings_match(res.contour_crossed, n, g, sh, tab, lam, "none", 0)
+    po = Q.Params("sector", d, sector=tab, deform=lam, orders=(2, 0.3, -0.4))
+    ro, _ = plan.integrate_orders(po, allow_crossing=True)
+    assert all(abs(r.contour_crossed - frac) <= 1e-15 for r in ro)
+    rb = Q.integrate_batch([plan], [pa], schedule="specialised", allow_crossing=True)
+    assert abs(rb[0].contour_crossed - frac) <= 1e-15
+    plan.close()
 
 
 @pytest.mark.parametrize("lam", [3.0, 6.0, 20.0])

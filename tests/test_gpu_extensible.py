@@ -43,14 +43,13 @@ def test_ladder_product_peak(Q):
     rungs = lat.ladder(params, kmin)
     assert [n for n, _, _ in rungs] == [1 << k for k in range(kmin, kmax + 1)]
     for n, res, q in rungs:
-        k = n.bit_length() - 1
-        est = O.estimate(n, lat.generator(k), lat.shifts, O.Params("genz_product_peak", d, a=a_, u=u_),
-                         "korobov", 3, threads=THREADS)
+        est = O.estimate(n, O.korobov_vector(n, d, lat.a), lat.shifts,
+                         O.Params("genz_product_peak", d, a=a_, u=u_), "korobov", 3, threads=THREADS)
         assert np.all(_rel(q, est.q_re) < TOL), (n, _rel(q, est.q_re).max())
         mean, err, _ = est.mean_error()
         assert abs(res.mean_re - mean.real) <= TOL * abs(mean.real)
     # the top rung against a direct plan on the GPU
-    plan = Q.Plan(d, 1 << kmax, lat.generator(kmax), lat.shifts, "korobov", 3)
+    plan = Q.Plan(d, 1 << kmax, lat.g, lat.shifts, "korobov", 3)
     _, qd = plan.integrate(params)
     plan.close()
     assert np.all(_rel(rungs[-1][2], qd) < 1e-13)
@@ -70,7 +69,7 @@ def test_ladder_sector(Q, cplx):
     _say(f"ladder sector complex={cplx}")
     rungs = lat.ladder(Q.Params("sector", d, sector=tab), kmin)
     n, res, q = rungs[-1]
-    est = O.estimate(n, lat.generator(kmax), lat.shifts, O.Params("sector", d, sector=tab), "baker",
+    est = O.estimate(n, O.korobov_vector(n, d, lat.a), lat.shifts, O.Params("sector", d, sector=tab), "baker",
                      threads=THREADS)
     assert np.all(_rel(q, est.q) < TOL), _rel(q, est.q).max()
 
