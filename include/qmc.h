@@ -532,7 +532,9 @@ qmc_status qmc_math_eval(int32_t fn, uint64_t count, const double *x, double *y)
 /* Release a plan and its device memory (NULL is ignored). */
 void qmc_plan_destroy(qmc_plan_t plan);
 
-const char *qmc_status_string(qmc_status s);
+/* Name of a status code ("unknown status" for any other value; an int so
+   that any value is a valid argument). */
+const char *qmc_status_string(int32_t status);
 const char *qmc_last_error(void);
 
 #ifdef __cplusplus

@@ -18,7 +18,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "qmc_oracle.c")
 SRC_CV = os.path.join(HERE, "qmc_oracle_cvtrain.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB names another build of the same sources (the sanitizer test's)
+LIB = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 FAMILIES = {
     "const": 0, "trig": 1, "p2kernel": 2, "genz_product_peak": 3, "genz_oscillatory": 4,
@@ -28,13 +29,27 @@ TRANSFORMS = {"none": 0, "korobov": 1, "baker": 2, "sidi": 3}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with plain gcc (no fast-math, no FP contraction)."""
+    """Compile the oracle with plain gcc (no fast-math, no FP contraction);
+    with ORACLE_LIB set, use that build as it is."""
+    if os.environ.get("ORACLE_LIB"):
+        return LIB
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
                "-shared", SRC, SRC_CV, "-o", LIB + ".tmp", "-lm", "-lpthread"]
         subprocess.check_call(cmd)
         os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+def build_sanitized(out: str) -> str:
+    """The same sources with AddressSanitizer and UndefinedBehaviorSanitizer
+    (clang, shared sanitizer runtime; any finding aborts), for a CPU test run
+    with that runtime preloaded and ORACLE_LIB pointing at `out`."""
+    cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-shared-libsan",
+           "-shared", SRC, SRC_CV, "-o", out, "-lm", "-lpthread"]
+    subprocess.check_call(cmd)
+    return out
 
 
 class _Params(C.Structure):

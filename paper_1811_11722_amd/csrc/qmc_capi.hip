@@ -517,8 +517,9 @@ using namespace qmc;
 // ==================================================================== C ABI
 extern "C" {
 
-const char *qmc_status_string(qmc_status s) {
-    switch (s) {
+const char *qmc_status_string(int32_t status) {
+    // an int, not the enum: any value a caller passes is defined behaviour
+    switch (status) {
     case QMC_OK: return "ok";
     case QMC_EINVAL: return "invalid argument";
     case QMC_EUNSUPPORTED: return "unsupported";

@@ -648,8 +648,8 @@ __device__ __forceinline__ double qlog(double x) {
 // For the complex sector integrand (F - i delta)^p = |.|^p e^{i p arg}: the
 // phase needs arg(F - i delta) = atan2(-delta, F) and the sine and cosine of
 // p times it, a bounded argument.  Both are branch-free; their polynomials
-// are Chebyshev fits (near-minimax) made for this library with multiprecision
-// arithmetic, each below 3e-17 in its reduced range.
+// are Chebyshev interpolants (near-minimax) in 50-digit arithmetic, each
+// below 3.2e-17 in its reduced range, written by make_math_tables.py --poly.
 
 // atan2(y, x) for finite (x, y) not both zero.  With n = min(|x|, |y|) and
 // d = max(|x|, |y|), t = n / d lies in [0, 1]; above tan(pi/8) it is replaced

@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqmc.so")
+# QMC_LIB names another build of the library (the host-sanitizer test's)
+LIB_PATH = os.environ.get("QMC_LIB") or os.path.join(HERE, "libqmc.so")
 
 # status codes
 QMC_OK, QMC_EINVAL, QMC_EUNSUPPORTED, QMC_ENOMEM, QMC_EDEVICE, QMC_ENONFINITE, QMC_ECONTOUR = range(7)

@@ -3,6 +3,7 @@ declares, and rejects bad arguments before touching a device."""
 import ctypes as C
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -192,6 +193,34 @@ def _math_table():
     vals = [float.fromhex(v) for v in re.findall(r"(-?0x[0-9a-fp.+-]+),", body)]
     assert len(vals) == 1024
     return vals
+
+
+def test_device_polynomials_are_the_generators_output():
+    """The coefficients of qatan2 and qsincos in qmc_device.hpp are exactly
+    what make_math_tables.py --poly writes (Chebyshev interpolants of the
+    atan, sin and cos remainders in 50-digit arithmetic, and the split of
+    pi/2)."""
+    sys.path.insert(0, os.path.join(ROOT, "paper_1811_11722_amd", "csrc"))
+    import make_math_tables as M
+    want = M.polynomials()
+    text = open(os.path.join(ROOT, "paper_1811_11722_amd", "csrc", "qmc_device.hpp")).read()
+
+    def consts(fn):
+        body = text[text.index(f"__device__ __forceinline__ {fn}"):]
+        body = body[: body.index("\n}\n")]
+        return [float.fromhex(v) for v in re.findall(r"(-?0x[0-9a-f]\.[0-9a-f]+p[+-]\d+)", body)]
+
+    at = consts("double qatan2")
+    # kTanPi8, pi/4, pi/2, pi, then the polynomial from its leading term
+    import mpmath
+    with mpmath.workdps(40):
+        assert at[:4] == [float(mpmath.tan(mpmath.pi / 8)), float(mpmath.pi / 4), float(mpmath.pi / 2),
+                          float(mpmath.pi)]
+    assert at[4:] == want["atan"]
+    sc = consts("void qsincos")
+    assert sc[0] == want["two_over_pi"][0]
+    assert sc[1:4] == want["half_pi_split"]
+    assert sc[4:10] == want["sin"] and sc[10:16] == want["cos"]
 
 
 def test_device_log_table():
