@@ -5,10 +5,10 @@ Every estimate runs in the HIP library (qmc_integrate / qmc_integrate_batch);
 this module only chooses lattice sizes and generating vectors, builds plans
 and times calls.
 
-    python -m paper_1811_11722_amd.drivers sector_batch [--count 2000]
+    python -m paper_1811_11722_amd.drivers sector_batch [--count 2000] [--out rows.jsonl]
     python -m paper_1811_11722_amd.drivers product_peak_batch [--count 512]
     python -m paper_1811_11722_amd.drivers time_to_error
-    python -m paper_1811_11722_amd.drivers convergence
+    python -m paper_1811_11722_amd.drivers convergence [--out rows.jsonl]
     python -m paper_1811_11722_amd.drivers cv_estimate
     python -m paper_1811_11722_amd.drivers fig3
     python -m paper_1811_11722_amd.drivers allocation_compare [--count 2000]
@@ -45,6 +45,44 @@ class GeneratingVectors:
             a, _, _ = qmc.korobov_search(n, d, synth.korobov_candidates(self.seed, n, self.candidates))
             self.cache[key] = qmc.korobov_vector(n, d, a)
         return self.cache[key]
+
+
+class JsonlRows:
+    """Append-only JSON-lines record of finished results, one object per
+    line, keyed by `key_fields`.  A rerun with the same file reuses every row
+    already written, so an interrupted sweep resumes where it stopped; a last
+    line cut short by a crash is dropped."""
+
+    def __init__(self, path, key_fields):
+        self.path, self.key_fields = path, tuple(key_fields)
+        self.rows = {}
+        if path and os.path.exists(path):
+            with open(path, "rb") as f:
+                data = f.read()
+            keep = data[: data.rfind(b"\n") + 1]
+            if len(keep) != len(data):
+                with open(path, "wb") as f:
+                    f.write(keep)
+            for line in keep.decode().splitlines():
+                if line.strip():
+                    r = json.loads(line)
+                    self.rows[self.key(r)] = r
+        self.resumed = len(self.rows)
+
+    def key(self, row):
+        return tuple(row[f] for f in self.key_fields)
+
+    def get(self, *key):
+        return self.rows.get(tuple(key))
+
+    def add(self, row):
+        self.rows[self.key(row)] = row
+        if self.path:
+            with open(self.path, "a") as f:
+                f.write(json.dumps(row) + "\n")
+                f.flush()
+                os.fsync(f.fileno())
+        return row
 
 
 def allocate_n(rel_err0: float, n0: int, goal: float, rate: float = 2.0) -> int:
@@ -181,6 +219,58 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
     for p in plans:
         p.close()
     return out
+
+
+def sector_batch_rows(path: str, count: int = 2000, m: int = 16, goal: float = 1e-8,
+                      seed: int = synth.SEED_BASE + 3, chunk: int = 250, tile_points: int = 8192,
+                      log=None) -> dict:
+    """Configuration 3 as a resumable sweep: pilot estimates at n0 = 16381 and
+    then every sector at the lattice size the error-goal rule gives it, each
+    in graph-replayed batches of `chunk` sectors, with one JSON line per
+    sector and phase appended to `path` (JsonlRows: a rerun skips every
+    sector already written).  Pilot rows: sector, d, pilot rel_err, allocated
+    n; final rows: sector, d, n, mean, err, per-shift Q_k."""
+    say = log or (lambda msg: None)
+    rows = JsonlRows(path, ("phase", "sector"))
+    tabs = synth.sector_batch(seed, count)
+    gv = GeneratingVectors(seed)
+    n0 = LADDER[0]
+    t0 = time.perf_counter()
+    computed = 0
+
+    def run_chunks(phase, todo, plan_for, row_for):
+        nonlocal computed
+        for c0 in range(0, len(todo), chunk):
+            part = todo[c0:c0 + chunk]
+            plans = [plan_for(s) for s in part]
+            params = [qmc.Params("sector", tabs[s].d, sector=tabs[s]) for s in part]
+            res = qmc.integrate_batch(plans, params, use_graph=True, tile_points=tile_points)
+            per = qmc.batch_per_shift(plans)
+            for s, p, r, q in zip(part, plans, res, per):
+                rows.add(row_for(s, p, r, q))
+                p.close()
+            computed += len(part)
+            say(f"  {phase}: {c0 + len(part)}/{len(todo)} sectors, {time.perf_counter() - t0:.1f} s")
+
+    todo = [s for s in range(count) if rows.get("pilot", s) is None]
+    run_chunks("pilot", todo,
+               lambda s: qmc.Plan(tabs[s].d, n0, gv(n0, tabs[s].d),
+                                  synth.shifts(seed, m, tabs[s].d, stream=16 + s, sub=3), "baker"),
+               lambda s, p, r, q: {"phase": "pilot", "sector": s, "d": tabs[s].d, "n": n0,
+                                   "rel_err": abs(r.err_re) / abs(r.mean_re),
+                                   "n_alloc": allocate_n(abs(r.err_re) / abs(r.mean_re), n0, goal)})
+    todo = [s for s in range(count) if rows.get("final", s) is None]
+    n_of = {s: rows.get("pilot", s)["n_alloc"] for s in range(count)}
+    run_chunks("final", todo,
+               lambda s: qmc.Plan(tabs[s].d, n_of[s], gv(n_of[s], tabs[s].d),
+                                  synth.sector_batch_shifts(seed, s, m, tabs[s].d), "baker"),
+               lambda s, p, r, q: {"phase": "final", "sector": s, "d": tabs[s].d, "n": n_of[s],
+                                   "mean": r.mean_re, "err": r.err_re, "q": [float(v) for v in q]})
+    finals = [rows.get("final", s) for s in range(count)]
+    return {"sectors": count, "m": m, "goal": goal, "path": path, "rows_resumed": rows.resumed,
+            "sectors_computed": computed, "seconds": time.perf_counter() - t0,
+            "evals": int(sum(r["n"] * m for r in finals)),
+            "rel_err_max": float(max(abs(r["err"]) / abs(r["mean"]) for r in finals))}
 
 
 def _precompile_worker(args):
@@ -442,13 +532,16 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
 
 def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEED_BASE + 5, m: int = 32,
                 kmin: int = 16, kmax: int = 30, cv_kmax: int = 30, R: int = 64, K: int = 12,
-                n_train: int = 1048573, max_sweeps: int = 12, log=None) -> dict:
+                n_train: int = 1048573, max_sweeps: int = 12, out_path: str = None, log=None) -> dict:
     """Convergence table of the complex sector integrand (F - 0.01 i,
     mixed-sign F, baker's transform) over the ladder of primes below 2^k:
     n, mean, error, relative error, wall time and lattice-point evaluations
     per second for every rung, for the plain estimator and (up to 2^cv_kmax)
     the control variate (one model per component, trained on n_train points
-    of an independent lattice)."""
+    of an independent lattice).  With out_path every rung and the trained
+    model are appended there as JSON lines (JsonlRows), and a rerun resumes:
+    rungs already written are reused, and so is the model."""
+    log_rows = JsonlRows(out_path, ("form", "n"))
     w = synth.sector_workload(n=synth.largest_prime_below(1 << kmax), m=m, d=d, n_u=n_u, n_f=n_f,
                               seed=seed, complex_kinematics=True)
     params = qmc.Params("sector", d, sector=w.sector)
@@ -465,6 +558,11 @@ def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEE
     def ladder(step, top, label):
         rows = []
         for n in synth.prime_ladder(kmin, top):
+            done = log_rows.get(label, n)
+            if done is not None:
+                rows.append({k: v for k, v in done.items() if k != "form"})
+                say(f"  {label} n={n} resumed")
+                continue
             ts = time.perf_counter()
             g = gv(n, d)
             t_search = time.perf_counter() - ts
@@ -478,6 +576,7 @@ def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEE
             t = time.perf_counter() - t
             plan.close()
             rows.append(row(n, res, t, t_search))
+            log_rows.add(dict(rows[-1], form=label))
             r = rows[-1]
             say(f"  {label} n={n} mean={complex(res.mean_re, res.mean_im)!r} rel_err={r['rel_err']:.3e} "
                 f"used_cv={res.used_cv} {t * 1e3:.2f} ms {n * m / t:.3e} evals/s")
@@ -488,18 +587,29 @@ def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEE
     out = {"d": d, "n_u": n_u, "n_f": n_f, "m": m, "transform": "baker", "complex": True,
            "name": w.name, "rows": rows_p}
     if cv_kmax >= kmin:
-        say("control variate: training")
-        train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), "baker")
-        _sync()
-        t = time.perf_counter()
-        W, c, rep = train.cv_train(params, R, K, max_sweeps=max_sweeps)
-        _sync()
-        t_train = time.perf_counter() - t
-        train.close()
-        say(f"  sweeps={rep.sweeps} rel_loss={rep.rel_loss:.3e} {t_train:.3f} s")
-        out["cv"] = {"R": R, "K": K, "n_train": n_train, "train_seconds": t_train,
-                     "train_sweeps": rep.sweeps, "train_rel_loss": rep.rel_loss,
+        model = log_rows.get("cv_model", n_train)
+        if model is None:
+            say("control variate: training")
+            train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), "baker")
+            _sync()
+            t = time.perf_counter()
+            W, c, rep = train.cv_train(params, R, K, max_sweeps=max_sweeps)
+            _sync()
+            t_train = time.perf_counter() - t
+            train.close()
+            say(f"  sweeps={rep.sweeps} rel_loss={rep.rel_loss:.3e} {t_train:.3f} s")
+            model = log_rows.add({"form": "cv_model", "n": n_train, "R": R, "K": K, "train_seconds": t_train,
+                                  "train_sweeps": rep.sweeps, "train_rel_loss": rep.rel_loss,
+                                  "W": np.asarray(W).ravel().tolist(), "c": np.asarray(c).ravel().tolist(),
+                                  "W_shape": list(np.shape(W)), "c_shape": list(np.shape(c))})
+        else:
+            say("control variate: model resumed")
+        W = np.array(model["W"]).reshape(model["W_shape"])
+        c = np.array(model["c"]).reshape(model["c_shape"])
+        out["cv"] = {"R": R, "K": K, "n_train": n_train, "train_seconds": model["train_seconds"],
+                     "train_sweeps": model["train_sweeps"], "train_rel_loss": model["train_rel_loss"],
                      "rows": ladder(lambda plan: plan.integrate_cv(params, W, c)[0], cv_kmax, "cv")}
+    out["rows_resumed"] = log_rows.resumed
     return out
 
 
@@ -735,8 +845,14 @@ def main(argv=None):
     ap.add_argument("--tile-points", type=int, default=-1)
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--workers", type=int, default=0, help="compile processes (sector_batch_specialised)")
+    ap.add_argument("--out", default=None, help="JSON-lines file of results; a rerun resumes from it "
+                                                "(sector_batch, convergence)")
     args = ap.parse_args(argv)
-    if args.what == "sector_batch":
+    if args.what == "sector_batch" and args.out:
+        out = sector_batch_rows(args.out, count=args.count or 2000,
+                                tile_points=8192 if args.tile_points < 0 else args.tile_points,
+                                log=lambda msg: print(msg, file=sys.stderr, flush=True))
+    elif args.what == "sector_batch":
         out = sector_batch(count=args.count or 2000,
                            tile_points=8192 if args.tile_points < 0 else args.tile_points,
                            compare=not args.no_compare)
@@ -765,7 +881,7 @@ def main(argv=None):
         out = time_to_error(kmax=args.kmax or 30, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     else:
         kmax = args.kmax or 30
-        out = convergence(kmax=kmax, cv_kmax=kmax if args.cv_kmax < 0 else args.cv_kmax,
+        out = convergence(kmax=kmax, cv_kmax=kmax if args.cv_kmax < 0 else args.cv_kmax, out_path=args.out,
                           log=lambda msg: print(msg, file=sys.stderr, flush=True))
     print(json.dumps(out))
 

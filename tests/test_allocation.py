@@ -92,3 +92,27 @@ def test_estimate_rates():
     r = estimate_rates([1e-4, 1e-4, 1e-4, 0.0], [1e-6, 1e-3, 1e-4 * 4 ** -1.5, 0.0], 1000, 4000)
     assert np.allclose(r[:3], [2.5, 0.25, 1.5])
     assert r[3] == 0.25
+
+
+def test_jsonl_rows_resume(tmp_path):
+    """The sweep record: rows written are found again by key after a reopen,
+    a last line cut short by a crash is dropped (and the file truncated to
+    the last whole row, so the next append starts a clean line), and a
+    missing path keeps rows in memory only."""
+    from paper_1811_11722_amd.drivers import JsonlRows
+    path = str(tmp_path / "rows.jsonl")
+    r = JsonlRows(path, ("phase", "sector"))
+    assert r.resumed == 0 and r.get("pilot", 0) is None
+    for s in range(3):
+        r.add({"phase": "pilot", "sector": s, "n": 16381, "rel_err": 0.1 * s})
+    with open(path, "a") as f:
+        f.write('{"phase": "pilot", "sector": 3, "n"')          # interrupted write
+    r2 = JsonlRows(path, ("phase", "sector"))
+    assert r2.resumed == 3 and r2.get("pilot", 3) is None
+    assert r2.get("pilot", 2) == {"phase": "pilot", "sector": 2, "n": 16381, "rel_err": 0.2}
+    r2.add({"phase": "pilot", "sector": 3, "n": 16381, "rel_err": 0.3})
+    r3 = JsonlRows(path, ("phase", "sector"))
+    assert r3.resumed == 4 and r3.get("pilot", 3)["rel_err"] == 0.3
+    mem = JsonlRows(None, ("form", "n"))
+    mem.add({"form": "plain", "n": 5})
+    assert mem.get("plain", 5) == {"form": "plain", "n": 5} and mem.resumed == 0
