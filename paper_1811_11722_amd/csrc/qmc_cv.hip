@@ -9,12 +9,13 @@
 // rho_j[r] = sw_j prod_{i' != i} h_{r,i'}(z_{j,i'}),  phi_j[k] = P~_k(z_{j,i}).
 // A^T A has Kronecker structure: its (k, k') block is
 //   sum_j phi_j[k] phi_j[k'] rho_j rho_j^T,
-// a rank-N sum of R x R outer products, which k_cv_gram accumulates with
+// a rank-N sum of R x R outer products, which k_cv_syrk accumulates with
 // BF16 MFMA (v_mfma_f32_32x32x16_bf16: 32 x 32 tiles, 16 points per
 // instruction, FP32 accumulation).  The per-split tiles are added in a fixed
-// order in FP64 and the (R K) x (R K) system is solved in FP64 by a Cholesky
-// factorisation on the device.  Features and factors are FP32 during
-// training; the trained model is evaluated in FP64 inside the estimator.
+// order in FP64 and factorised in FP64 on the device (k_cv_factor).  That
+// factor preconditions passes against the FP64 design matrix (k_cv_pass,
+// FP64 MFMA, and k_cv_subst), so each step converges to the FP64 ridge
+// solution.  The trained model is evaluated in FP64 inside the estimator.
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -29,7 +30,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------- kernels
 // Design-matrix factors of dimension i in FP64:
-//   rho_j[r] = sw_j prod_{i' != i} h_{r,i'}(z_{j,i'}),  phi_j[k] = P~_k(z_{j,i}).
+//   rho_j[r] = sw_j prod_{i' != i} h_{r,i'}(z_{j,i'}),  phi_j[k] = P~_k(z_{j,i}),
+// h_{r,i'}(z) = sum_k ws[r, i', k] P_k(z) on v_mfma_f64_16x16x4f64, 16 points
+// per wave at a time: A = the Legendre values (lane l: point l % 16, degree
+// 4 s + l / 16, each lane running the recurrence for its point), B = the
+// weights (fragments staged in LDS once per workgroup).  The product over
+// dimensions is taken elementwise on the output tiles (element v of lane l:
+// point 4 v + l / 16, rank 16 t + l % 16), which are also the layout of the
+// 128-byte rows of rho the lanes store.
 struct CvRhoArgs {
     uint32_t n, d, i;       // points, dimension, the dimension being solved
     const float *z, *sw;    // (n, d), (n)
@@ -38,33 +46,63 @@ struct CvRhoArgs {
     double *phi;            // (n, K) (normalised)
 };
 
+constexpr uint32_t kCvMaxD = 12;
+
 template <int R, int K>
 __global__ __launch_bounds__(kBlock) void k_cv_rho(const CvRhoArgs a) {
-    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= a.n) return;
-    double prod[R];
-    const double s = a.sw[j];
+    constexpr int RT = (R + 15) / 16, KS = (K + 3) / 4;
+    __shared__ double wf[kCvMaxD * RT * KS * kWave];  // ((i RT + t) KS + s) 64 + lane
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t li = lane & 15, lg = lane >> 4;
+    for (uint32_t f = tid; f < a.d * RT * KS * kWave; f += kBlock) {
+        const uint32_t fl = f % kWave, idx = f / kWave, s = idx % KS, t = (idx / KS) % RT, i = idx / (KS * RT);
+        const uint32_t r = 16 * t + fl % 16, k = 4 * s + fl / 16;
+        wf[f] = (r < (uint32_t)R && k < (uint32_t)K) ? a.ws[((size_t)r * a.d + i) * K + k] : 0.0;
+    }
+    __syncthreads();
+    const bool s1 = lg == 1, s2 = lg == 2, s3 = lg == 3;
+    for (uint32_t p0 = (blockIdx.x * 4 + wave) * 16; p0 < a.n; p0 += gridDim.x * 64) {
+        cv_d4 prod[RT];
 #pragma unroll
-    for (int r = 0; r < R; ++r) prod[r] = s;
-    for (uint32_t i = 0; i < a.d; ++i) {
-        double p[K];
-        legendre_raw<K, double>((double)a.z[(size_t)j * a.d + i], p);
-        if (i == a.i) {
+        for (int t = 0; t < RT; ++t) prod[t] = cv_d4{1.0, 1.0, 1.0, 1.0};
+        const uint32_t pa = p0 + li;  // this lane's point in the A operand
+        for (uint32_t i = 0; i < a.d; ++i) {
+            const double zz = pa < a.n ? (double)a.z[(size_t)pa * a.d + i] : 0.5;
+            double pk[4 * KS];
+            legendre_raw<4 * KS, double>(zz, pk);
+            double fa[KS];
 #pragma unroll
-            for (int k = 0; k < K; ++k) a.phi[(size_t)j * K + k] = p[k] * sqrt((double)(2 * k + 1));
-            continue;
+            for (int s = 0; s < KS; ++s) fa[s] = cv_pick4(pk[4 * s], pk[4 * s + 1], pk[4 * s + 2], pk[4 * s + 3], s1, s2, s3);
+            if (i == a.i) {
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const uint32_t k = 4 * s + lg;
+                    if (pa < a.n && k < (uint32_t)K) a.phi[(size_t)pa * K + k] = fa[s] * sqrt((double)(2 * k + 1));
+                }
+                continue;
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                cv_d4 h = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    h = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s], wf[((i * RT + t) * KS + s) * kWave + lane], h, 0, 0, 0);
+                prod[t] *= h;
+            }
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double *w = a.ws + ((size_t)r * a.d + i) * K;
-            double h = w[K - 1] * p[K - 1];
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t p = p0 + 4 * v + lg;
+            if (p < a.n) {
+                const double sw = a.sw[p];
 #pragma unroll
-            for (int k = K - 2; k >= 0; --k) h = fma(w[k], p[k], h);
-            prod[r] *= h;
+                for (int t = 0; t < RT; ++t) {
+                    const uint32_t r = 16 * t + li;
+                    if (r < (uint32_t)R) a.rho[(size_t)p * R + r] = sw * prod[t][v];
+                }
+            }
         }
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) a.rho[(size_t)j * R + r] = prod[r];
 }
 
 // ----------------------------------------------------------- Gram (SYRK)
@@ -275,81 +313,159 @@ __global__ __launch_bounds__(kBlock, 2) void k_cv_syrk(const CvSyrkArgs a) {
 
 // Sum the per-split tiles in split order, in FP64, into the lower triangle
 // of the normal matrix A0 (F x F row-major, rows and columns u = r K + k):
-// row u = blockIdx.y, column v = blockIdx.x * kBlock + thread.  Column u of
-// A0 is column u' = k R + r of the tiles.
+// one thread per tile element (consecutive threads read consecutive
+// elements of each split), adding the splits in order.  Tile element
+// (i, j) of slot bu (bu + 1) / 2 + bv is columns u' = 32 bu + i, 32 bv + j
+// in the order u' = k R + r; the upper part of a diagonal tile is skipped.
 __global__ __launch_bounds__(kBlock) void k_cv_gather(const float *partial, uint32_t splits, uint32_t nslots,
                                                      uint32_t R, uint32_t K, double *A0) {
-    // one wave per entry (u, v), v <= u: lanes take splits lane, lane + 64,
-    // ... in order, then a fixed butterfly over the lanes
-    const uint32_t F = R * K, lane = threadIdx.x & (kWave - 1);
-    const uint64_t e = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (e >= (uint64_t)F * (F + 1) / 2) return;
-    uint32_t u = (uint32_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-    while ((uint64_t)u * (u + 1) / 2 > e) --u;
-    while ((uint64_t)(u + 1) * (u + 2) / 2 <= e) ++u;
-    const uint32_t v = (uint32_t)(e - (uint64_t)u * (u + 1) / 2);
-    const uint32_t r = u / K, k = u - r * K, rp = v / K, kp = v - rp * K;
-    uint32_t a = k * R + r, b = kp * R + rp;
-    if (a < b) {
-        const uint32_t t = a;
-        a = b;
-        b = t;
-    }
-    const uint32_t ba = a / 32, bb = b / 32;
-    const size_t o = (((size_t)ba * (ba + 1) / 2 + bb) << 10) + (a % 32) * 32 + b % 32;
+    const uint32_t F = R * K, g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= nslots * 1024) return;
+    const uint32_t slot = g >> 10, i = (g >> 5) & 31, j = g & 31;
+    uint32_t bu = (uint32_t)((sqrt(8.0 * (double)slot + 1.0) - 1.0) * 0.5);
+    while (bu * (bu + 1) / 2 > slot) --bu;
+    while ((bu + 1) * (bu + 2) / 2 <= slot) ++bu;
+    const uint32_t bv = slot - bu * (bu + 1) / 2;
+    const uint32_t a = 32 * bu + i, b = 32 * bv + j;
+    if (b > a) return;
+    const size_t stride = (size_t)nslots * 1024;
     double s = 0.0;
-    for (uint32_t sp = lane; sp < splits; sp += kWave) s += (double)partial[(size_t)sp * nslots * 1024 + o];
-#pragma unroll
-    for (int w = kWave / 2; w > 0; w >>= 1) s += __shfl_xor(s, w);
-    if (lane == 0) A0[(size_t)u * F + v] = s;
+#pragma unroll 16
+    for (uint32_t sp = 0; sp < splits; ++sp) s += (double)partial[sp * stride + g];
+    const uint32_t ka = a / R, ra = a - ka * R, kb = b / R, rb = b - kb * R;
+    const uint32_t u = ra * K + ka, v = rb * K + kb;
+    if (u >= v) A0[(size_t)u * F + v] = s;
+    else A0[(size_t)v * F + u] = s;
 }
 
-// Right-hand side partial sums of the FP64 design matrix:
-//   part[split][u] = sum_{j in split} (rho_j[r] phi_j[k]) y_j,  u = r K + k,
-// y_j = yd_j, or yf_j * y_scale when yd is null; FP64, points in order (one
-// thread per column; a block of 32 points is staged in LDS).
-// R <= 64, K <= 16, R K <= 3 kBlock.
-constexpr uint32_t kRhsStage = 32;
-__global__ __launch_bounds__(kBlock) void k_cv_rhs(uint32_t n, uint32_t R, uint32_t K, uint32_t splits,
-                                                  const double *rho, const double *phi, const float *yf,
-                                                  double y_scale, const double *yd, double *part) {
-    const uint32_t F = R * K, tid = threadIdx.x;
-    const uint32_t j0 = (uint32_t)((uint64_t)n * blockIdx.x / splits);
-    const uint32_t j1 = (uint32_t)((uint64_t)n * (blockIdx.x + 1) / splits);
-    __shared__ double srho[kRhsStage * 64], sphi[kRhsStage * 16], sy[kRhsStage];
-    double acc[3] = {0.0, 0.0, 0.0};
-    uint32_t ru[3], ku[3];
+// One pass over the training set for the right-hand side of dimension i:
+//   part[split][u] = sum_{j in split} rho_j[r] phi_j[k] e_j,  u = r K + k,
+//   e_j = y_j - sum_{r,k} rho_j[r] phi_j[k] w[r, i, k]   (e_j = y_j when w is null),
+// y_j = yd_j, or yf_j * y_scale when yd is null; FP64 throughout, on
+// v_mfma_f64_16x16x4f64 (A[i][k] and B[k][j] at lane i (or j) + 16 k;
+// output element v of lane l at row 4 v + l / 16, column l % 16).  A wave
+// takes 16 points at a time:
+//   1. H = Phi W^T (16 points x 16 ranks per tile; A: lane l holds
+//      phi[point l % 16][4 s + l / 16], B: the weights, kept in registers),
+//      so lane l holds H at point 4 v + l / 16 and rank 16 t + l % 16;
+//   2. rho is read in that layout (128-byte rows), and the 16 lanes of a
+//      point add rho H with a butterfly: e of the point;
+//   3. the right-hand side tile accumulates (rho e)^T Phi, 4 points per
+//      instruction: A = rho e as held, B = phi[point 4 g + l / 16][l % 16]
+//      (0 for Legendre indices >= K).
+// Waves take 16-point chunks in turn over the workgroup's range; their tiles
+// are added in wave order.  Entry R K of a split's partials is its sum of
+// e_j^2 (the objective of the current factor).  A set *flag (a converged
+// solve) makes the kernel return at once.
+struct CvPassArgs {
+    uint32_t n, d, i, splits;
+    const double *rho, *phi;  // (n, R), (n, K)
+    const float *yf;          // targets (float) times y_scale, or
+    double y_scale;
+    const double *yd;         // targets (double), if not null
+    const double *w;          // (R, d, K) model in the normalised basis, or null
+    const int *flag;          // nullable
+    double *part;             // (splits, R K + 1)
+};
+
+template <int R, int K>
+__global__ __launch_bounds__(kBlock) void k_cv_pass(const CvPassArgs a) {
+    constexpr int RT = (R + 15) / 16, KS = (K + 3) / 4;
+    static_assert(K <= 16 && RT <= 4, "one B tile of Legendre indices, at most 4 rank tiles");
+    if (a.flag && *a.flag) return;
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t li = lane & 15, lg = lane >> 4;
+    const uint32_t j0 = (uint32_t)((uint64_t)a.n * blockIdx.x / a.splits);
+    const uint32_t j1 = (uint32_t)((uint64_t)a.n * (blockIdx.x + 1) / a.splits);
+    const bool use_w = a.w != nullptr;
+    double wb[RT][KS];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const uint32_t u = tid + q * kBlock;
-        ru[q] = u < F ? u / K : 0;
-        ku[q] = u < F ? u % K : 0;
-    }
-    for (uint32_t base = j0; base < j1; base += kRhsStage) {
-        const uint32_t cnt = min(kRhsStage, j1 - base);
-        __syncthreads();
-        for (uint32_t t = tid; t < cnt * R; t += kBlock) srho[t] = rho[(size_t)base * R + t];
-        for (uint32_t t = tid; t < cnt * K; t += kBlock) sphi[t] = phi[(size_t)base * K + t];
-        if (tid < cnt) sy[tid] = yd ? yd[base + tid] : (double)yf[base + tid] * y_scale;
-        __syncthreads();
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (tid + q * kBlock < F) {
-                double s = acc[q];
-                for (uint32_t p = 0; p < cnt; ++p) s = fma(srho[p * R + ru[q]] * sphi[p * K + ku[q]], sy[p], s);
-                acc[q] = s;
+        for (int s = 0; s < KS; ++s) {
+            const uint32_t r = 16 * t + li, k = 4 * s + lg;
+            wb[t][s] = (use_w && r < (uint32_t)R && k < (uint32_t)K) ? a.w[((size_t)r * a.d + a.i) * K + k] : 0.0;
+        }
+    cv_d4 acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = cv_d4{0.0, 0.0, 0.0, 0.0};
+    double e2 = 0.0;  // lanes l < 16 add e^2 of points 4 v + l / 16 ... one lane per point
+    for (uint32_t p0 = j0 + 16 * wave; p0 < j1; p0 += 64) {
+        double rh[RT][4], e[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t p = p0 + 4 * v + lg;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const uint32_t r = 16 * t + li;
+                rh[t][v] = (p < j1 && r < (uint32_t)R) ? a.rho[(size_t)p * R + r] : 0.0;
+            }
+            e[v] = p < j1 ? (a.yd ? a.yd[p] : (double)a.yf[p] * a.y_scale) : 0.0;
+        }
+        if (use_w) {
+            double fa[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const uint32_t p = p0 + li, k = 4 * s + lg;
+                fa[s] = (p < j1 && k < (uint32_t)K) ? a.phi[(size_t)p * K + k] : 0.0;
+            }
+            double dot[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                cv_d4 h = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) h = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s], wb[t][s], h, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dot[v] = fma(rh[t][v], h[v], dot[v]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) dot[v] += __shfl_xor(dot[v], o);
+                e[v] -= dot[v];
             }
         }
-    }
+        if (li == 0) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-        if (tid + q * kBlock < F) part[(size_t)blockIdx.x * F + tid + q * kBlock] = acc[q];
+            for (int v = 0; v < 4; ++v) e2 = fma(e[v], e[v], e2);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t p = p0 + 4 * g + lg;
+            const double fb = (p < j1 && li < (uint32_t)K) ? a.phi[(size_t)p * K + li] : 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rh[t][g] * e[g], fb, acc[t], 0, 0, 0);
+        }
+    }
+    // tiles of the 4 waves, added in wave order; element v of lane l is
+    // rank 16 t + 4 v + l / 16, Legendre index l % 16
+    __shared__ double red[4][RT * 256];
+    __shared__ double se2[4][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave][t * 256 + (4 * v + lg) * 16 + li] = acc[t][v];
+    if (li == 0) se2[wave][lg] = e2;
+    __syncthreads();
+    constexpr uint32_t FP = R * K + 1;
+    for (uint32_t u = tid; u < (uint32_t)(R * K); u += kBlock) {
+        const uint32_t r = u / K, k = u - r * K, o = (r / 16) * 256 + (r % 16) * 16 + k;
+        a.part[(size_t)blockIdx.x * FP + u] = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+    }
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int g = 0; g < 4; ++g) s += se2[w][g];
+        a.part[(size_t)blockIdx.x * FP + R * K] = s;
+    }
 }
 
-// b[u] = sum over splits of the right-hand side partials: one wave per
-// column, lanes take splits lane, lane + 64, ... in order, then a fixed
-// butterfly over the lanes
-__global__ __launch_bounds__(kBlock) void k_cv_rhs_reduce(const double *part, uint32_t splits, uint32_t F, double *b) {
+// b[u] = sum over splits of the partials: one wave per column, lanes take
+// splits lane, lane + 64, ... in order, then a fixed butterfly over the lanes
+// (F counts the extra entry of the pass: R K + 1 columns)
+__global__ __launch_bounds__(kBlock) void k_cv_rhs_reduce(const double *part, uint32_t splits, uint32_t F,
+                                                         const int *flag, double *b) {
+    if (flag && *flag) return;
     const uint32_t u = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     if (u >= F) return;
     double s = 0.0;
@@ -359,233 +475,369 @@ __global__ __launch_bounds__(kBlock) void k_cv_rhs_reduce(const double *part, ui
     if (lane == 0) b[u] = s;
 }
 
-// residual of the current fit of dimension i in FP64:
-//   e_j = yw_j / scale - sum_{r,k} rho_j[r] phi_j[k] W[r,i,k]
-// (the right-hand side of a refinement step is A^T e)
-template <int R, int K>
-__global__ __launch_bounds__(kBlock) void k_cv_resid(uint32_t n, uint32_t d, uint32_t i, const double *rho,
-                                                    const double *phi, const float *yw, double inv_scale,
-                                                    const double *w64, double *e) {
-    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    double ph[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) ph[k] = phi[(size_t)j * K + k];
-    double g = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const double *w = w64 + ((size_t)r * d + i) * K;
-        double h = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) h = fma(w[k], ph[k], h);
-        g = fma(rho[(size_t)j * R + r], h, g);
-    }
-    e[j] = (double)yw[j] * inv_scale - g;
-}
-
-struct CvSolveArgs {
-    uint32_t R, K, d, i;
+// ------------------------------------------------------------ the solve
+// (A0 + lam I) = L L^T by a blocked right-looking Cholesky in one workgroup
+// of 512 threads, panels of B columns (B = 32, or 16 when F > 512 so that
+// the panel fits in LDS):
+//   1. the diagonal block and the rows below are staged in LDS (coalesced
+//      reads); wave 0 factorises the block in registers (lane r holds row
+//      r; each column is scaled, then the lanes below take the rank-1
+//      update with the column's entries broadcast by readlane);
+//   2. wave 0 also forms W = L_pp^-1 (lane c: column c by forward
+//      substitution), and the rows below become X = A_panel W^T, a matrix
+//      product on FP64 MFMA; the panel goes back to A;
+//   3. the trailing lower triangle takes A -= P P^T in 16 x 16 tiles on
+//      FP64 MFMA; the panel sits in LDS transposed (column q of the panel
+//      contiguous), so consecutive lanes read consecutive rows.
+// lam = ridge * trace / F (trace summed in index order); a non-positive
+// pivot restarts with a 100x larger ridge (at most three times).  The
+// factor overwrites A (lower triangle), rdiag receives 1 / L_uu, *status the
+// number of escalations (-1: failed), *lam the ridge, and *flag is cleared
+// for the solves that follow.
+struct CvFactorArgs {
+    uint32_t F;
     double ridge;           // relative to the mean diagonal
-    int refine;             // 1: reuse the factor in A and add the solution to W[., i, .]
-    double *lam;            // absolute ridge of the current factorisation
     const double *A0;       // (F, F) assembled normal matrix, lower triangle
-    const double *b;        // (F) right-hand side
-    double *A;              // (F, F) factor, F = R K
-    double *w64;            // (R, d, K) model, normalised basis
-    double *ws;             // (R, d, K) model times sqrt(2k+1)
-    int *status;            // number of ridge escalations, or -1: not positive definite
+    double *A;              // (F, F) factor
+    double *rdiag;          // (F) reciprocals of the factor's diagonal
+    double *lam;
+    int *status;
+    int *flag;
 };
 
-// One workgroup solves the normal equations of dimension i.
-//
-// Assembly: the lower triangle of A0 is copied to A plus the ridge
-// lam = ridge * trace / F.  Factorisation: blocked right-looking Cholesky,
-// A = L L^T in place.  Each panel of kPanel columns is loaded into LDS and
-// factorised there; the trailing lower triangle is then updated by
-// A -= P P^T, each thread owning 4 x 4 blocks.  A non-positive pivot
-// restarts the factorisation with a 100x larger ridge (at most three
-// times).  Solves: blocked forward and backward substitution in LDS.  A
-// refinement call (refine = 1) reuses the factor left in A, solves
-// (A + lam I) delta = b - lam w (b = A^T e of the current residual e) and
-// adds delta to W[., i, .].
-constexpr uint32_t kPanel = 8;
 constexpr uint32_t kMaxF = 768;  // largest R K compiled: (64, 12)
+// 512 threads leave 256 registers per lane for the unrolled panel solve
+constexpr uint32_t kFactorThreads = 512;
 
-__device__ void cv_load_rhs(const CvSolveArgs &a, uint32_t F, double *y, double lam) {
-    for (uint32_t u = threadIdx.x; u < F; u += blockDim.x) {
-        const uint32_t r = u / a.K, k = u - r * a.K;
-        double v = a.b[u];
-        if (a.refine) v -= lam * a.w64[((size_t)r * a.d + a.i) * a.K + k];
-        y[u] = v;
-    }
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(1024) void k_cv_solve(const CvSolveArgs a) {
-    const uint32_t F = a.R * a.K, tid = threadIdx.x, nt = blockDim.x;
-    __shared__ double P[(kMaxF + 4) * kPanel];  // panel rows c0..F-1 (+4 rows of padding)
-    __shared__ double y[kMaxF];                 // right-hand side / solution
+template <int B>
+__global__ __launch_bounds__(kFactorThreads) void k_cv_factor(const CvFactorArgs a) {
+    // panel rows per LDS column: F - B at most, plus 2 so that the columns
+    // start in different banks (and stay 16-byte aligned)
+    constexpr uint32_t LD = (B == 32 ? 512u : kMaxF) - B + 2;
+    constexpr uint32_t nt = kFactorThreads;
+    const uint32_t F = a.F, tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    __shared__ __align__(16) double PT[B * LD];  // panel, PT[q * LD + row]
+    constexpr uint32_t DP = B + 1;               // padded row of the diagonal block
+    __shared__ double D[B * DP];                 // the diagonal block's factor
+    __shared__ double Wl[B * DP];                // its inverse, W = L_pp^-1
+    __shared__ double sdiag[kMaxF];              // the diagonal, for the trace in index order
     __shared__ double s_ridge;
     __shared__ int s_bad;
     double *A = a.A;
+    double ridge = a.ridge;
+    int attempt = 0;
+    for (; attempt < 4; ++attempt, ridge *= 100.0) {
+        for (uint32_t u = tid / 32; u < F; u += nt / 32)
+            for (uint32_t v = tid % 32; v <= u; v += 32) {
+                const double x = a.A0[(size_t)u * F + v];
+                A[(size_t)u * F + v] = x;
+                if (u == v) sdiag[u] = x;
+            }
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (uint32_t u = 0; u < F; ++u) t += sdiag[u];
+            s_ridge = ridge * t / F + 1e-300;
+            s_bad = 0;
+        }
+        __syncthreads();
+        for (uint32_t u = tid; u < F; u += nt) A[(size_t)u * F + u] += s_ridge;
+        __syncthreads();
 
-    if (!a.refine) {
-        double ridge = a.ridge;
-        int attempt = 0;
-        for (; attempt < 4; ++attempt, ridge *= 100.0) {
-            // lower triangle of the normal matrix
-            for (uint32_t u = tid / 32; u < F; u += nt / 32)
-                for (uint32_t v = tid % 32; v <= u; v += 32) A[(size_t)u * F + v] = a.A0[(size_t)u * F + v];
-            __syncthreads();
-            if (tid == 0) {
-                double tr = 0.0;
-                for (uint32_t u = 0; u < F; ++u) tr += A[(size_t)u * F + u];
-                s_ridge = ridge * tr / F + 1e-300;
-                s_bad = 0;
+        for (uint32_t c0 = 0; c0 < F; c0 += B) {
+            const uint32_t c1 = c0 + B, M = F - c1;
+            // 1. the diagonal block (to D) and the rows below (to PT) go to
+            // LDS, then wave 0 factorises the block
+            for (uint32_t t = tid; t < B * B; t += nt) {
+                const uint32_t r = t / B, q = t - r * B;
+                D[r * DP + q] = q <= r ? A[(size_t)(c0 + r) * F + c0 + q] : 0.0;
+            }
+            for (uint32_t t = tid; t < M * B; t += nt) {
+                const uint32_t r = t / B, q = t - r * B;
+                PT[q * LD + r] = A[(size_t)(c1 + r) * F + c0 + q];
             }
             __syncthreads();
-            for (uint32_t u = tid; u < F; u += nt) A[(size_t)u * F + u] += s_ridge;
-            __syncthreads();
-
-            for (uint32_t c0 = 0; c0 < F; c0 += kPanel) {
-                const uint32_t nb = min(kPanel, F - c0), rows = F - c0;
-                for (uint32_t t = tid; t < rows * kPanel; t += nt) {
-                    const uint32_t r = t / kPanel, q = t % kPanel;
-                    P[t] = (q < nb && q <= r) ? A[(size_t)(c0 + r) * F + c0 + q] : 0.0;
+            if (wave == 0) {
+                // lane r holds row r of the block; entries right of the
+                // diagonal are never read, so the updates need no masks
+                double row[B];
+#pragma unroll
+                for (int c = 0; c < B; ++c) row[c] = lane < (uint32_t)B ? D[lane * DP + c] : 0.0;
+                bool bad = false;
+#pragma unroll
+                for (int q = 0; q < B; ++q) {
+                    const double piv = readlane_d(row[q], q);
+                    bad = bad || !(piv > 0.0);
+                    const double dq = piv > 0.0 ? sqrt(piv) : 1.0, rq = 1.0 / dq;
+                    row[q] = lane == (uint32_t)q ? dq : row[q] * rq;
+#pragma unroll
+                    for (int c = q + 1; c < B; ++c) row[c] = fma(-row[q], readlane_d(row[q], c), row[c]);
                 }
-                __syncthreads();
-                // the panel is factorised by wave 0 alone (its lanes take
-                // rows lane, lane + 64, ...), ordered by wave-level fences
-                // instead of workgroup barriers
-                if (tid < kWave) {
-                    for (uint32_t q = 0; q < nb; ++q) {
-                        const double piv = P[q * kPanel + q];
-                        const double dq = piv > 0.0 ? sqrt(piv) : 1.0;
-                        if (tid == 0) {
-                            if (!(piv > 0.0)) s_bad = 1;
-                            P[q * kPanel + q] = dq;
-                        }
-                        const double inv = 1.0 / dq;
-                        for (uint32_t r = q + 1 + tid; r < rows; r += kWave) P[r * kPanel + q] *= inv;
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        for (uint32_t r = q + 1 + tid; r < rows; r += kWave) {
-                            const double l = P[r * kPanel + q];
-                            for (uint32_t q2 = q + 1; q2 < nb && q2 <= r; ++q2)
-                                P[r * kPanel + q2] -= l * P[q2 * kPanel + q];
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (bad && lane == 0) s_bad = 1;
+                if (lane < (uint32_t)B) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) D[lane * DP + c] = (uint32_t)c <= lane ? row[c] : 0.0;
+                    a.rdiag[c0 + lane] = 1.0 / D[lane * DP + lane];
+                }
+                // lane c: column c of W = L_pp^-1 by forward substitution,
+                // W[r][c] = (delta_rc - sum_{s < r} L[r][s] W[s][c]) / L[r][r]
+                // (entries above the diagonal come out 0); L from LDS
+                double wcol[B];
+#pragma unroll
+                for (int r = 0; r < B; ++r) {
+                    double v = lane == (uint32_t)r ? 1.0 : 0.0;
+#pragma unroll
+                    for (int q = 0; q < r; ++q) v = fma(-D[r * DP + q], wcol[q], v);
+                    wcol[r] = v / D[r * DP + r];
+                }
+                if (lane < (uint32_t)B) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) Wl[c * DP + lane] = wcol[c];
+                }
+            }
+            __syncthreads();
+            // 2. the panel below: X = A_panel W^T on v_mfma_f64_16x16x4f64
+            // (A: lane l holds panel row 16 ti + l % 16, column 4 s + l / 16;
+            // B: W[16 tj + l % 16][4 s + l / 16]); a wave owns all the column
+            // tiles of its rows, so it overwrites them in place after reading
+            {
+                const uint32_t li = lane & 15, lg = lane >> 4;
+                for (uint32_t ti = wave; ti < M / 16; ti += nt / kWave) {
+                    cv_d4 acc[B / 16];
+#pragma unroll
+                    for (int tj = 0; tj < B / 16; ++tj) acc[tj] = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < B / 4; ++s) {
+                        const double av = PT[(4 * s + lg) * LD + 16 * ti + li];
+#pragma unroll
+                        for (int tj = 0; tj < B / 16; ++tj)
+                            acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Wl[(16 * tj + li) * DP + 4 * s + lg],
+                                                                          acc[tj], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int tj = 0; tj < B / 16; ++tj)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) PT[(16 * tj + li) * LD + 16 * ti + 4 * v + lg] = acc[tj][v];
+                }
+            }
+            __syncthreads();
+            for (uint32_t t = tid; t < B * B; t += nt) {
+                const uint32_t r = t / B, q = t - r * B;
+                if (q <= r) A[(size_t)(c0 + r) * F + c0 + q] = D[r * DP + q];
+            }
+            for (uint32_t t = tid; t < M * B; t += nt) {
+                const uint32_t r = t / B, q = t - r * B;
+                A[(size_t)(c1 + r) * F + c0 + q] = PT[q * LD + r];
+            }
+            // 3. trailing update of rows / columns c1 .. F - 1 on
+            // v_mfma_f64_16x16x4f64, 16 x 16 tiles of the lower triangle, two
+            // per wave at a time (independent chains): A = 16 rows of the
+            // panel (lane l: row 16 ti + l % 16, column 4 s + l / 16), B = the
+            // same for tj; output element v of lane l is row 4 v + l / 16,
+            // column l % 16.  A tile's old values are loaded before its
+            // products.
+            {
+                const uint32_t li = lane & 15, lg = lane >> 4, nb16 = M / 16, ntl = nb16 * (nb16 + 1) / 2;
+                auto tile_of = [](uint32_t tI, uint32_t &ti, uint32_t &tj) {
+                    ti = (uint32_t)((sqrt(8.0 * (double)tI + 1.0) - 1.0) * 0.5);
+                    while (ti * (ti + 1) / 2 > tI) --ti;
+                    while ((ti + 1) * (ti + 2) / 2 <= tI) ++ti;
+                    tj = tI - ti * (ti + 1) / 2;
+                };
+                for (uint32_t t0 = wave; t0 < ntl; t0 += 2 * (nt / kWave)) {
+                    const uint32_t t1 = t0 + nt / kWave;
+                    const bool two = t1 < ntl;
+                    uint32_t ti0, tj0, ti1 = 0, tj1 = 0;
+                    tile_of(t0, ti0, tj0);
+                    if (two) tile_of(t1, ti1, tj1);
+                    const uint32_t col0 = c1 + 16 * tj0 + li, col1 = c1 + 16 * tj1 + li;
+                    double old0[4], old1[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const uint32_t u0 = c1 + 16 * ti0 + 4 * v + lg, u1 = c1 + 16 * ti1 + 4 * v + lg;
+                        old0[v] = col0 <= u0 ? A[(size_t)u0 * F + col0] : 0.0;
+                        old1[v] = (two && col1 <= u1) ? A[(size_t)u1 * F + col1] : 0.0;
+                    }
+                    cv_d4 acc0 = cv_d4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+#pragma unroll
+                    for (int s = 0; s < B / 4; ++s) {
+                        const double *pq = PT + (4 * s + lg) * LD;
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pq[16 * ti0 + li], pq[16 * tj0 + li], acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pq[16 * ti1 + li], pq[16 * tj1 + li], acc1, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const uint32_t u0 = c1 + 16 * ti0 + 4 * v + lg, u1 = c1 + 16 * ti1 + 4 * v + lg;
+                        if (col0 <= u0) A[(size_t)u0 * F + col0] = old0[v] - acc0[v];
+                        if (two && col1 <= u1) A[(size_t)u1 * F + col1] = old1[v] - acc1[v];
                     }
                 }
-                __syncthreads();
-                for (uint32_t t = tid; t < rows * kPanel; t += nt) {
-                    const uint32_t r = t / kPanel, q = t % kPanel;
-                    if (q < nb && q <= r) A[(size_t)(c0 + r) * F + c0 + q] = P[t];
-                }
-                // trailing update of rows / columns c1..F-1
-                const uint32_t c1 = c0 + nb;
-                if (c1 < F) {
-                    const uint32_t M = F - c1, nbk = (M + 3) / 4;
-                    for (uint32_t bu = tid / 32; bu < nbk; bu += nt / 32) {
-                        for (uint32_t bv = tid % 32; bv <= bu; bv += 32) {
-                            double acc[4][4] = {};
-                            for (uint32_t q = 0; q < nb; ++q) {
-                                double pu[4], pv[4];
-#pragma unroll
-                                for (int e = 0; e < 4; ++e) {
-                                    pu[e] = P[(nb + 4 * bu + e) * kPanel + q];
-                                    pv[e] = P[(nb + 4 * bv + e) * kPanel + q];
-                                }
-#pragma unroll
-                                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                                    for (int f = 0; f < 4; ++f) acc[e][f] = fma(pu[e], pv[f], acc[e][f]);
-                            }
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const uint32_t u = c1 + 4 * bu + e;
-#pragma unroll
-                                for (int f = 0; f < 4; ++f) {
-                                    const uint32_t v = c1 + 4 * bv + f;
-                                    if (u < F && v <= u) A[(size_t)u * F + v] -= acc[e][f];
-                                }
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
             }
-            const int bad = s_bad;
             __syncthreads();
-            if (!bad) break;
         }
-        if (tid == 0) {
-            *a.status = s_bad ? -1 : attempt;
-            *a.lam = s_ridge;
-        }
-        cv_load_rhs(a, F, y, 0.0);
-    } else {
-        cv_load_rhs(a, F, y, *a.lam);
+        const int bad = s_bad;
+        __syncthreads();
+        if (!bad) break;
     }
-    __syncthreads();
+    if (tid == 0) {
+        *a.status = s_bad ? -1 : attempt;
+        *a.lam = s_ridge;
+        *a.flag = 0;
+    }
+}
 
-    // forward substitution L z = y, one panel at a time: the panel's
-    // diagonal block goes to LDS, one thread solves it, then every thread
-    // updates its rows below
-    __shared__ double D[kPanel * kPanel];
-    for (uint32_t c0 = 0; c0 < F; c0 += kPanel) {
-        const uint32_t nb = min(kPanel, F - c0);
-        if (tid < nb * nb) D[tid] = A[(size_t)(c0 + tid / nb) * F + c0 + tid % nb];
+// One correction of dimension i's factor from the right-hand side b of the
+// current residual (k_cv_pass): solves L L^T delta = b - lam w and adds
+// delta to w[., i, .] (and its sqrt(2k+1)-scaled copy ws), in one
+// workgroup, blocks of B unknowns:
+//   forward:  the block's unknowns by wave 0 (lane r holds row r of the
+//             diagonal block, staged through LDS), then every row below
+//             takes the block's contribution (32 lanes per row);
+//   backward: the block's rows first take the contribution of the unknowns
+//             below (32 row groups by 32 columns, added in group order),
+//             then wave 0 solves with the transposed diagonal block.
+// The step's objective J = sum e^2 + lam ||w||^2 (entry F of b holds
+// sum e^2) falls by delta . g under the correction, g = b - lam w; with
+// delta . g <= tol J, *flag is set: the passes and solves left in this step
+// return at once (tol = 0 never stops early).  A set flag on entry does the
+// same.
+struct CvSubstArgs {
+    uint32_t F, R, K, d, i;
+    double tol;
+    const double *A;        // factor (lower triangle)
+    const double *rdiag;    // (F) 1 / L_uu
+    const double *b;        // (F + 1) right-hand side of the residual, sum e^2
+    const double *lam;
+    double *w64, *ws;       // (R, d, K)
+    int *flag;
+};
+
+template <int B>
+__global__ __launch_bounds__(1024) void k_cv_subst(const CvSubstArgs a) {
+    if (*a.flag) return;
+    const uint32_t F = a.F, tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    constexpr uint32_t nt = 1024;
+    __shared__ double y[kMaxF], gs[kMaxF];
+    __shared__ double D[B * (B + 1)];  // the diagonal block, rows padded against bank conflicts
+    __shared__ double red[32][33];
+    __shared__ double s_n[2][16];
+    const double lam = *a.lam;
+    for (uint32_t u = tid; u < F; u += nt) {
+        const uint32_t r = u / a.K, k = u - r * a.K;
+        y[u] = gs[u] = a.b[u] - lam * a.w64[((size_t)r * a.d + a.i) * a.K + k];
+    }
+    const double *A = a.A;
+    // forward substitution L z = y
+    for (uint32_t c0 = 0; c0 < F; c0 += B) {
+        if (tid < B * B) D[(tid / B) * (B + 1) + tid % B] = tid % B <= tid / B ? A[(size_t)(c0 + tid / B) * F + c0 + tid % B] : 0.0;
         __syncthreads();
-        if (tid == 0) {
-            for (uint32_t q = 0; q < nb; ++q) {
-                double v = y[c0 + q];
-                for (uint32_t q2 = 0; q2 < q; ++q2) v -= D[q * nb + q2] * y[c0 + q2];
-                y[c0 + q] = v / D[q * nb + q];
+        if (wave == 0) {
+            double row[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) row[c] = lane < (uint32_t)B ? D[lane * (B + 1) + c] : 0.0;
+            double v = lane < (uint32_t)B ? y[c0 + lane] : 0.0;
+            const double rd = lane < (uint32_t)B ? a.rdiag[c0 + lane] : 0.0;
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const double xq = readlane_d(v, q) * readlane_d(rd, q);
+                if (lane == (uint32_t)q) v = xq;
+                else if (lane > (uint32_t)q) v = fma(-row[q], xq, v);
             }
+            if (lane < (uint32_t)B) y[c0 + lane] = v;
         }
         __syncthreads();
-        for (uint32_t u = c0 + nb + tid; u < F; u += nt) {
-            double v = y[u];
-            for (uint32_t q = 0; q < nb; ++q) v -= A[(size_t)u * F + c0 + q] * y[c0 + q];
-            y[u] = v;
+        // rows below: y_u -= sum_{q < B} L[u][c0 + q] z_{c0 + q}, one thread
+        // per row (F <= 1024), its B entries read as 16-byte pairs
+        for (uint32_t u = c0 + B + tid; u < F; u += nt) {
+            const double2 *lr = reinterpret_cast<const double2 *>(A + (size_t)u * F + c0);
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < B / 2; ++q) {
+                const double2 l = lr[q];
+                s0 = fma(l.x, y[c0 + 2 * q], s0);
+                s1 = fma(l.y, y[c0 + 2 * q + 1], s1);
+            }
+            y[u] -= s0 + s1;
         }
         __syncthreads();
     }
-    // backward substitution L^T w = z by columns of L^T, panels from the
-    // last: solve the panel's diagonal block, then every thread removes the
-    // panel's unknowns from its rows above, z[r] -= sum_q L[c0 + q][r] w[c0 + q]
-    for (uint32_t c0 = ((F - 1) / kPanel) * kPanel;; c0 -= kPanel) {
-        const uint32_t nb = min(kPanel, F - c0);
-        if (tid < nb * nb) D[tid] = A[(size_t)(c0 + tid / nb) * F + c0 + tid % nb];
-        __syncthreads();
-        if (tid == 0) {
-            for (uint32_t q = nb; q-- > 0;) {
-                double v = y[c0 + q];
-                for (uint32_t q2 = q + 1; q2 < nb; ++q2) v -= D[q2 * nb + q] * y[c0 + q2];
-                y[c0 + q] = v / D[q * nb + q];
+    // backward substitution L^T x = z
+    for (uint32_t c0 = F - B;; c0 -= B) {
+        // the block's rows: z_{c0 + j} -= sum_{c >= c0 + B} L[c][c0 + j] x_c
+        {
+            // 32 row groups by 32 columns; every row of the group is read in
+            // one batch
+            const uint32_t j = tid & 31, g = tid / 32;
+            double s = 0.0;
+            if (j < (uint32_t)B) {
+#pragma unroll
+                for (uint32_t it = 0; it < kMaxF / 32; ++it) {
+                    const uint32_t c = c0 + B + g + 32 * it;
+                    if (c < F) s = fma(A[(size_t)c * F + c0 + j], y[c], s);
+                }
             }
+            red[g][j] = s;
         }
+        if (tid < B * B) D[(tid / B) * (B + 1) + tid % B] = tid % B <= tid / B ? A[(size_t)(c0 + tid / B) * F + c0 + tid % B] : 0.0;
         __syncthreads();
-        for (uint32_t r = tid; r < c0; r += nt) {
-            double v = y[r];
-            for (uint32_t q = 0; q < nb; ++q) v -= A[(size_t)(c0 + q) * F + r] * y[c0 + q];
-            y[r] = v;
+        if (wave == 0) {
+            double col[B];  // lane r: column r of the block, col[s] = L[c0 + s][c0 + r]
+#pragma unroll
+            for (int s = 0; s < B; ++s) col[s] = lane < (uint32_t)B ? D[s * (B + 1) + lane] : 0.0;
+            double v = 0.0;
+            if (lane < (uint32_t)B) {
+                double t = 0.0;
+                for (int g = 0; g < 32; ++g) t += red[g][lane];
+                v = y[c0 + lane] - t;
+            }
+            const double rd = lane < (uint32_t)B ? a.rdiag[c0 + lane] : 0.0;
+#pragma unroll
+            for (int q = B - 1; q >= 0; --q) {
+                const double xq = readlane_d(v, q) * readlane_d(rd, q);
+                if (lane == (uint32_t)q) v = xq;
+                else if (lane < (uint32_t)q) v = fma(-col[q], xq, v);
+            }
+            if (lane < (uint32_t)B) y[c0 + lane] = v;
         }
         __syncthreads();
         if (c0 == 0) break;
     }
+    // w += delta, and the convergence test
+    double dn = 0.0, wn = 0.0;
     for (uint32_t u = tid; u < F; u += nt) {
         const uint32_t r = u / a.K, k = u - r * a.K;
         const size_t o = ((size_t)r * a.d + a.i) * a.K + k;
-        const double w = a.refine ? a.w64[o] + y[u] : y[u];
+        const double w0 = a.w64[o], w = w0 + y[u];
         a.w64[o] = w;
         a.ws[o] = w * sqrt(2.0 * k + 1.0);
+        dn = fma(y[u], gs[u], dn);
+        wn = fma(w0, w0, wn);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        dn += __shfl_xor(dn, o);
+        wn += __shfl_xor(wn, o);
+    }
+    if (lane == 0) {
+        s_n[0][wave] = dn;
+        s_n[1][wave] = wn;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double d2 = 0.0, w2 = 0.0;
+        for (int w = 0; w < 16; ++w) {
+            d2 += s_n[0][w];
+            w2 += s_n[1][w];
+        }
+        if (d2 <= a.tol * (a.b[F] + lam * w2)) *a.flag = 1;
     }
 }
-
 // Rescales the factors of each rank to equal norms across dimensions (the
 // product, hence the model, is unchanged): keeps ALS well conditioned.
 __global__ void k_cv_balance(uint32_t R, uint32_t d, uint32_t K, double *w64, double *ws) {
@@ -679,8 +931,7 @@ namespace {
 using RhoFn = void (*)(const CvRhoArgs &, uint32_t, hipStream_t);
 using LossFn = void (*)(uint32_t, uint32_t, const float *, const float *, const float *, double, const double *,
                         double *, uint32_t, hipStream_t);
-using ResidFn = void (*)(uint32_t, uint32_t, uint32_t, const double *, const double *, const float *, double,
-                         const double *, double *, uint32_t, hipStream_t);
+using PassFn = void (*)(const CvPassArgs &, uint32_t, hipStream_t);
 using SyrkFn = void (*)(const CvSyrkArgs &, dim3, hipStream_t);
 
 template <int R, int K>
@@ -693,9 +944,8 @@ void launch_loss(uint32_t n, uint32_t d, const float *z, const float *sw, const 
     hipLaunchKernelGGL((k_cv_loss<R, K>), dim3(blocks), dim3(kBlock), 0, s, n, d, z, sw, yw, is, ws, part);
 }
 template <int R, int K>
-void launch_resid(uint32_t n, uint32_t d, uint32_t i, const double *rho, const double *phi, const float *yw,
-                  double is, const double *w64, double *e, uint32_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_cv_resid<R, K>), dim3(blocks), dim3(kBlock), 0, s, n, d, i, rho, phi, yw, is, w64, e);
+void launch_pass(const CvPassArgs &a, uint32_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_cv_pass<R, K>), dim3(blocks), dim3(kBlock), 0, s, a);
 }
 template <int R, int K, class S0, class S1>
 void launch_syrk(const CvSyrkArgs &a, dim3 grid, hipStream_t s) {
@@ -705,7 +955,7 @@ void launch_syrk(const CvSyrkArgs &a, dim3 grid, hipStream_t s) {
 struct CvFns {
     RhoFn rho;
     LossFn loss;
-    ResidFn resid;
+    PassFn pass;
     SyrkFn syrk;
 };
 
@@ -716,7 +966,7 @@ bool cv_fns(uint32_t R, uint32_t K, CvFns &f) {
     if (R == RR && K == KK) {                    \
         f.rho = &launch_rho<RR, KK>;             \
         f.loss = &launch_loss<RR, KK>;           \
-        f.resid = &launch_resid<RR, KK>;         \
+        f.pass = &launch_pass<RR, KK>;           \
         f.syrk = &launch_syrk<RR, KK, S0, S1>;   \
         return true;                             \
     }
@@ -779,7 +1029,12 @@ double splitmix_uniform(uint64_t &s) {
     return (double)(z >> 11) * 0x1.0p-53;
 }
 
-uint32_t rhs_splits(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>(1024, (n + 255) / 256)); }
+// workgroups of a right-hand side pass: about 8 per CU, at least 256 points each
+uint32_t rhs_splits(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>(2048, (n + 255) / 256)); }
+
+// a correction whose objective decrease is below this fraction of the
+// step's objective ends the step's passes
+constexpr double kSolveTol = 1e-7;
 
 // Device buffers of one training problem (n samples, d dimensions, rank R,
 // K Legendre degrees) and the launches of one alternating-least-squares
@@ -790,10 +1045,10 @@ struct CvTrainer {
     CvFns fn{};
     DeviceScratch s;
     float *z = nullptr, *sw = nullptr, *yw = nullptr, *partial = nullptr;
-    double *rho = nullptr, *phi = nullptr, *rpart = nullptr, *resid = nullptr, *ws = nullptr;
-    double *w64 = nullptr, *A0 = nullptr, *A = nullptr, *b = nullptr, *lam = nullptr;
+    double *rho = nullptr, *phi = nullptr, *rpart = nullptr, *ydev = nullptr, *ws = nullptr;
+    double *w64 = nullptr, *A0 = nullptr, *A = nullptr, *rdiag = nullptr, *b = nullptr, *lam = nullptr;
     double *loss_part = nullptr, *abs_part = nullptr;
-    int *status = nullptr;
+    int *status = nullptr, *flag = nullptr;
     CvSyrkTask *tasks = nullptr;
 
     // samples: allocate z, sw, yw too; features: rho, phi and the Gram's
@@ -826,14 +1081,19 @@ struct CvTrainer {
                          (st = take((size_t)n * 4, yw)))) ||
             (features && ((st = take((size_t)n * R * 8, rho)) || (st = take((size_t)n * K * 8, phi)) ||
                           (st = take((size_t)splits * nslots * 4096, partial)) ||
-                          (st = take((size_t)rsplits * F * 8, rpart)) || (st = take((size_t)n * 8, resid)))) ||
+                          (st = take((size_t)rsplits * (F + 1) * 8, rpart)) || (st = take((size_t)n * 8, ydev)))) ||
             (st = take((size_t)R * d * K * 8, ws)) || (st = take((size_t)R * d * K * 8, w64)) ||
             (st = take(tk.size() * sizeof(CvSyrkTask), tasks)) || (st = take((size_t)F * F * 8, A0)) ||
-            (st = take((size_t)F * F * 8, A)) || (st = take((size_t)F * 8, b)) || (st = take(8, lam)) ||
-            (st = take(8, status)) || (st = take((size_t)rblocks * 16, loss_part)) ||
+            (st = take((size_t)F * F * 8, A)) || (st = take((size_t)F * 8, rdiag)) || (st = take((size_t)(F + 1) * 8, b)) ||
+            (st = take(8, lam)) ||
+            (st = take(8, status)) || (st = take(8, flag)) || (st = take((size_t)rblocks * 16, loss_part)) ||
             (st = take((size_t)rblocks * 8, abs_part)))
             return st;
         hipError_t e = hipMemcpy(tasks, tk.data(), tk.size() * sizeof(CvSyrkTask), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(w64, 0, (size_t)R * d * K * 8);
+        if (e == hipSuccess) e = hipMemset(ws, 0, (size_t)R * d * K * 8);
+        if (e == hipSuccess) e = hipMemset(flag, 0, 8);
+        if (e == hipSuccess) e = hipMemset(b, 0, (size_t)(F + 1) * 8);
         if (e != hipSuccess) return hip_fail(e, "training setup");
         return QMC_OK;
     }
@@ -852,58 +1112,57 @@ struct CvTrainer {
 
     void features(uint32_t i, hipStream_t st) {
         const CvRhoArgs ra{n, d, i, z, sw, ws, rho, phi};
-        fn.rho(ra, rblocks, st);
+        fn.rho(ra, std::min<uint32_t>(rblocks, 1024), st);
     }
 
     // A0 = sum_j a~_j a~_j^T (BF16 MFMA, FP32 accumulation per split, FP64 over splits)
     void gram(hipStream_t st) {
         const CvSyrkArgs ga{n, splits, nslots, rho, phi, tasks, partial};
         fn.syrk(ga, dim3(splits, ntasks), st);
-        const uint64_t entries = (uint64_t)F * (F + 1) / 2, per = kBlock / kWave;
-        hipLaunchKernelGGL(k_cv_gather, dim3((uint32_t)((entries + per - 1) / per)), dim3(kBlock), 0, st,
-                           (const float *)partial, splits, nslots, R, K, A0);
+        hipLaunchKernelGGL(k_cv_gather, dim3(nslots * 1024 / kBlock), dim3(kBlock), 0, st, (const float *)partial,
+                           splits, nslots, R, K, A0);
     }
 
-    // b = sum_j rho_j phi_j^T y_j, y = yd, or yf * y_scale when yd is null
-    void rhs(const float *yf, double y_scale, const double *yd, hipStream_t st) {
-        hipLaunchKernelGGL(k_cv_rhs, dim3(rsplits), dim3(kBlock), 0, st, n, R, K, rsplits, (const double *)rho,
-                           (const double *)phi, yf, y_scale, yd, rpart);
-        hipLaunchKernelGGL(k_cv_rhs_reduce, dim3((F + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0, st,
-                           (const double *)rpart, rsplits, F, b);
+    // b = sum_j rho_j phi_j^T e_j with e = y - A w (the current factor of
+    // dimension i; e = y when use_w is false), y = yd, or yf * y_scale when
+    // yd is null
+    void rhs(uint32_t i, bool use_w, const float *yf, double y_scale, const double *yd, const int *fl,
+             hipStream_t st) {
+        const CvPassArgs pa{n, d, i, rsplits, rho, phi, yf, y_scale, yd, use_w ? w64 : nullptr, fl, rpart};
+        fn.pass(pa, rsplits, st);
+        hipLaunchKernelGGL(k_cv_rhs_reduce, dim3((F + 1 + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0,
+                           st, (const double *)rpart, rsplits, F + 1, fl, b);
     }
 
-    void solve(uint32_t dd, uint32_t i, double ridge, int refine, hipStream_t st) {
-        CvSolveArgs so{};
-        so.R = R;
-        so.K = K;
-        so.d = dd;
-        so.i = i;
-        so.ridge = ridge;
-        so.refine = refine;
-        so.lam = lam;
-        so.A0 = A0;
-        so.b = b;
-        so.A = A;
-        so.w64 = w64;
-        so.ws = ws;
-        so.status = status;
-        hipLaunchKernelGGL(k_cv_solve, dim3(1), dim3(1024), 0, st, so);
+    // L L^T = A0 + lam I; clears the convergence flag
+    void factor(double ridge, hipStream_t st) {
+        const CvFactorArgs fa{F, ridge, A0, A, rdiag, lam, status, flag};
+        if (F <= 512) hipLaunchKernelGGL(k_cv_factor<32>, dim3(1), dim3(kFactorThreads), 0, st, fa);
+        else hipLaunchKernelGGL(k_cv_factor<16>, dim3(1), dim3(kFactorThreads), 0, st, fa);
+    }
+
+    // w[., i, .] += (L L^T)^-1 (b - lam w[., i, .]); tol as in k_cv_subst
+    void subst(uint32_t dd, uint32_t i, double tol, hipStream_t st) {
+        const CvSubstArgs sa{F, R, K, dd, i, tol, A, rdiag, b, lam, w64, ws, flag};
+        if (F <= 512) hipLaunchKernelGGL(k_cv_subst<32>, dim3(1), dim3(1024), 0, st, sa);
+        else hipLaunchKernelGGL(k_cv_subst<16>, dim3(1), dim3(1024), 0, st, sa);
     }
 
     // One alternating-least-squares step for dimension i: FP64 features,
-    // the BF16 normal matrix, the FP64 solve, then `refine` refinements
-    // against the FP64 residual e = y - A w, whose right-hand side
-    // A^T e - lam w comes from the FP64 design matrix: the BF16 matrix only
-    // preconditions, so the fixed point is the FP64 least-squares solution.
-    void step(uint32_t i, double inv_scale, double ridge, uint32_t refine, hipStream_t st) {
+    // the BF16 normal matrix and its FP64 factorisation, then up to `passes`
+    // corrections starting from the current factor: each pass forms the
+    // FP64 residual e = y - A w and its right-hand side A^T e - lam w from
+    // the FP64 design matrix and solves with the factor.  The BF16 matrix
+    // only preconditions, so the fixed point is the FP64 ridge solution;
+    // the passes stop once a correction would lower the step's objective
+    // by less than tol of it (tol = 0: all passes run).
+    void step(uint32_t i, double inv_scale, double ridge, uint32_t passes, double tol, hipStream_t st) {
         features(i, st);
         gram(st);
-        rhs(yw, inv_scale, nullptr, st);
-        solve(d, i, ridge, 0, st);
-        for (uint32_t it = 0; it < refine; ++it) {
-            fn.resid(n, d, i, rho, phi, yw, inv_scale, w64, resid, rblocks, st);
-            rhs(nullptr, 1.0, resid, st);
-            solve(d, i, ridge, 1, st);
+        factor(ridge, st);
+        for (uint32_t it = 0; it < passes; ++it) {
+            rhs(i, true, yw, inv_scale, nullptr, flag, st);
+            subst(d, i, tol, st);
         }
     }
 };
@@ -1019,7 +1278,7 @@ qmc_status qmc_cv_train(qmc_plan_t p, qmc_family family, const void *params, uin
         uint32_t sweeps = 0;
         const double inv_scale = 1.0 / scale;
         for (; sweeps < max_sweeps;) {
-            for (uint32_t i = 0; i < d; ++i) t.step(i, inv_scale, ridge, refine, stream);
+            for (uint32_t i = 0; i < d; ++i) t.step(i, inv_scale, ridge, refine + 1, kSolveTol, stream);
             ++sweeps;
             hipLaunchKernelGGL(k_cv_balance, dim3((R + 63) / 64), dim3(64), 0, stream, R, d, K, t.w64, t.ws);
             t.fn.loss(n, d, t.z, t.sw, t.yw, inv_scale, t.ws, t.loss_part, t.rblocks, stream);
@@ -1129,10 +1388,10 @@ qmc_status qmc_cv_normal(uint32_t n, uint32_t R, uint32_t K, const double *rho, 
     hipError_t e;
     if ((e = hipMemcpy(t.rho, rho, (size_t)n * R * 8, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.phi, phi, (size_t)n * K * 8, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(t.resid, y, (size_t)n * 8, hipMemcpyHostToDevice)) != hipSuccess)
+        (e = hipMemcpy(t.ydev, y, (size_t)n * 8, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "normal-equation upload");
     t.gram(nullptr);
-    t.rhs(nullptr, 1.0, t.resid, nullptr);
+    t.rhs(0, false, nullptr, 1.0, t.ydev, nullptr, nullptr);
     const uint32_t F = t.F;
     std::vector<double> A((size_t)F * F);
     if ((e = hipMemcpy(A.data(), t.A0, A.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
@@ -1164,7 +1423,8 @@ qmc_status qmc_cv_solve(uint32_t R, uint32_t K, const double *gram, const double
     if ((e = hipMemcpy(t.A0, gram, (size_t)F * F * 8, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.b, rhs, (size_t)F * 8, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "solve upload");
-    t.solve(1, 0, ridge, 0, nullptr);
+    t.factor(ridge, nullptr);
+    t.subst(1, 0, 0.0, nullptr);
     int32_t esc = 0;
     double lam = 0.0;
     if ((e = hipMemcpy(x_out, t.w64, (size_t)F * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
@@ -1195,7 +1455,7 @@ qmc_status qmc_cv_als_step(uint32_t n, uint32_t d, uint32_t R, uint32_t K, uint3
         (e = hipMemcpy(t.sw, sw, (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.yw, yw, (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "step upload");
-    t.step(i, 1.0 / scale, ridge, refine, nullptr);
+    t.step(i, 1.0 / scale, ridge, refine + 1, 0.0, nullptr);
     int32_t esc = 0;
     double lam = 0.0;
     if ((e = hipMemcpy(w_out, t.w64, (size_t)R * d * K * 8, hipMemcpyDeviceToHost)) != hipSuccess ||
