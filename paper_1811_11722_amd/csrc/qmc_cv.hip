@@ -132,7 +132,7 @@ struct CvSyrkTask {
 };
 
 struct CvSyrkArgs {
-    uint32_t n, splits, nslots;
+    uint32_t n, splits, nslots, ntasks;
     const double *rho, *phi;
     const CvSyrkTask *tasks;
     float *partial;  // (splits, nslots, 32, 32)
@@ -308,6 +308,116 @@ __global__ __launch_bounds__(kBlock, 2) void k_cv_syrk(const CvSyrkArgs a) {
         syrk_task<R, K, S0>(a, task, srho, sphi, frag);
     } else if constexpr (!std::is_same<S1, void>::value) {
         syrk_task<R, K, S1>(a, task, srho, sphi, frag);
+    }
+}
+
+// The same accumulation with two tasks per workgroup of 8 waves (waves 0-3
+// take task 2 y, waves 4-7 task 2 y + 1), so that each round's rho and phi
+// are read and turned into fragments once for both: for the triangle of 12
+// blocks (its two halves) the features are read once in all.  All NB
+// blocks' fragments are built (wave w: 16-point group w % 4, blocks
+// w / 4, w / 4 + 2, ...).  One workgroup per CU.
+template <int R, int K, class S0, class S1>
+__global__ __launch_bounds__(2 * kBlock, 1) void k_cv_syrk2(const CvSyrkArgs a) {
+    constexpr int NB = R * K / 32;
+    constexpr uint32_t nt = 2 * kBlock;
+    constexpr int NV = (kSyrkPts * (R + K) + nt - 1) / nt;  // staged values per thread
+    __shared__ float srho[kSyrkPts * R], sphi[kSyrkPts * K];
+    __shared__ bf16x8 frag[NB * 4 * kWave];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave, w4 = wave & 3;
+    const uint32_t ti = 2 * blockIdx.y + (wave >> 2);
+    const bool active = ti < a.ntasks;
+    const uint32_t type = active ? a.tasks[ti].type : 0;
+    // the wave's bases straight from memory (indexing a private copy by the
+    // wave number would put it in scratch)
+    const uint32_t r0 = active ? a.tasks[ti].r0[w4] : 0, c0 = active ? a.tasks[ti].c0[w4] : 0;
+    const uint32_t j_begin = (uint32_t)((uint64_t)a.n * blockIdx.x / a.splits);
+    const uint32_t j_end = (uint32_t)((uint64_t)a.n * (blockIdx.x + 1) / a.splits);
+
+    f32x16 acc[kSyrkMaxTiles];
+#pragma unroll
+    for (int t = 0; t < kSyrkMaxTiles; ++t)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+
+    double nxt[NV];
+    auto load_round = [&](uint32_t base) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const uint32_t v = tid + q * nt;
+            double x = 0.0;
+            if (v < (uint32_t)(kSyrkPts * R)) {
+                if (base + v / R < j_end) x = a.rho[(size_t)base * R + v];
+            } else if (v < (uint32_t)(kSyrkPts * (R + K))) {
+                const uint32_t w = v - kSyrkPts * R;
+                if (base + w / K < j_end) x = a.phi[(size_t)base * K + w];
+            }
+            nxt[q] = x;
+        }
+    };
+    if (j_begin < j_end) load_round(j_begin);
+    for (uint32_t base = j_begin; base < j_end; base += kSyrkPts) {
+        __syncthreads();  // the previous round's fragments are consumed
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const uint32_t v = tid + q * nt;
+            if (v < (uint32_t)(kSyrkPts * R)) srho[v] = (float)nxt[q];
+            else if (v < (uint32_t)(kSyrkPts * (R + K))) sphi[v - kSyrkPts * R] = (float)nxt[q];
+        }
+        if (base + kSyrkPts < j_end) load_round(base + kSyrkPts);
+        __syncthreads();
+        {
+            const uint32_t half = lane >> 5, c = lane & 31;
+            for (uint32_t b = wave >> 2; b < (uint32_t)NB; b += 2) {
+                const uint32_t u = 32 * b + c, k = u / R, r = u - k * R;
+                bf16x8 f;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t p = 16 * w4 + 8 * half + e;
+                    f[e] = (__bf16)(srho[p * R + r] * sphi[p * K + k]);
+                }
+                frag[(b * 4 + w4) * kWave + lane] = f;
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bf16x8 *fr = frag + s * kWave;
+                if (type == 0) {
+                    switch (w4) {
+                    case 0: syrk_step<S0, 0>(fr, lane, r0, c0, acc); break;
+                    case 1: syrk_step<S0, 1>(fr, lane, r0, c0, acc); break;
+                    case 2: syrk_step<S0, 2>(fr, lane, r0, c0, acc); break;
+                    default: syrk_step<S0, 3>(fr, lane, r0, c0, acc); break;
+                    }
+                } else if constexpr (!std::is_same<S1, void>::value) {
+                    switch (w4) {
+                    case 0: syrk_step<S1, 0>(fr, lane, r0, c0, acc); break;
+                    case 1: syrk_step<S1, 1>(fr, lane, r0, c0, acc); break;
+                    case 2: syrk_step<S1, 2>(fr, lane, r0, c0, acc); break;
+                    default: syrk_step<S1, 3>(fr, lane, r0, c0, acc); break;
+                    }
+                }
+            }
+        }
+    }
+    if (!active) return;
+    float *out = a.partial + (size_t)blockIdx.x * a.nslots * 1024;
+    if (type == 0) {
+        switch (w4) {
+        case 0: syrk_store<S0, 0>(lane, r0, c0, acc, out); break;
+        case 1: syrk_store<S0, 1>(lane, r0, c0, acc, out); break;
+        case 2: syrk_store<S0, 2>(lane, r0, c0, acc, out); break;
+        default: syrk_store<S0, 3>(lane, r0, c0, acc, out); break;
+        }
+    } else if constexpr (!std::is_same<S1, void>::value) {
+        switch (w4) {
+        case 0: syrk_store<S1, 0>(lane, r0, c0, acc, out); break;
+        case 1: syrk_store<S1, 1>(lane, r0, c0, acc, out); break;
+        case 2: syrk_store<S1, 2>(lane, r0, c0, acc, out); break;
+        default: syrk_store<S1, 3>(lane, r0, c0, acc, out); break;
+        }
     }
 }
 
@@ -947,9 +1057,12 @@ template <int R, int K>
 void launch_pass(const CvPassArgs &a, uint32_t blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_cv_pass<R, K>), dim3(blocks), dim3(kBlock), 0, s, a);
 }
+// one task per workgroup of 4 waves when the triangle is one task, two
+// per workgroup of 8 waves otherwise (grid.y = tasks / 2)
 template <int R, int K, class S0, class S1>
 void launch_syrk(const CvSyrkArgs &a, dim3 grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_cv_syrk<R, K, S0, S1>), grid, dim3(kBlock), 0, s, a);
+    if (a.ntasks == 1) hipLaunchKernelGGL((k_cv_syrk<R, K, S0, S1>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_cv_syrk2<R, K, S0, S1>), grid, dim3(2 * kBlock), 0, s, a);
 }
 
 struct CvFns {
@@ -1041,7 +1154,7 @@ constexpr double kSolveTol = 1e-7;
 // step.  Everything is freed with the object.
 struct CvTrainer {
     uint32_t n = 0, d = 0, R = 0, K = 0, F = 0, NB = 0;
-    uint32_t splits = 1, rsplits = 1, rblocks = 1, nslots = 0, ntasks = 0;
+    uint32_t splits = 1, rsplits = 1, rblocks = 1, nslots = 0, ntasks = 0, gy = 1;
     CvFns fn{};
     DeviceScratch s;
     float *z = nullptr, *sw = nullptr, *yw = nullptr, *partial = nullptr;
@@ -1066,9 +1179,12 @@ struct CvTrainer {
         if (tk.empty()) return fail(QMC_EUNSUPPORTED, "no Gram task layout for %u blocks", NB);
         ntasks = (uint32_t)tk.size();
         nslots = NB * (NB + 1) / 2;
-        // two workgroups per CU in flight: about 512 workgroups in all, each
-        // with at least one round of points
-        splits = std::max<uint32_t>(1, std::min<uint32_t>(512 / ntasks, (n + kSyrkPts - 1) / kSyrkPts));
+        // about 512 workgroups of 4 waves (one task each, two per CU) or 256
+        // of 8 waves (two tasks each, one per CU) in all, each with at least
+        // one round of points
+        gy = ntasks == 1 ? 1 : (ntasks + 1) / 2;
+        splits = std::max<uint32_t>(1, std::min<uint32_t>((ntasks == 1 ? 512 : 256) / gy,
+                                                          (n + kSyrkPts - 1) / kSyrkPts));
         rsplits = rhs_splits(n);
         rblocks = (n + kBlock - 1) / kBlock;
         qmc_status st;
@@ -1117,8 +1233,8 @@ struct CvTrainer {
 
     // A0 = sum_j a~_j a~_j^T (BF16 MFMA, FP32 accumulation per split, FP64 over splits)
     void gram(hipStream_t st) {
-        const CvSyrkArgs ga{n, splits, nslots, rho, phi, tasks, partial};
-        fn.syrk(ga, dim3(splits, ntasks), st);
+        const CvSyrkArgs ga{n, splits, nslots, ntasks, rho, phi, tasks, partial};
+        fn.syrk(ga, dim3(splits, gy), st);
         hipLaunchKernelGGL(k_cv_gather, dim3(nslots * 1024 / kBlock), dim3(kBlock), 0, st, (const float *)partial,
                            splits, nslots, R, K, A0);
     }
