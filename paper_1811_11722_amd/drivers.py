@@ -10,6 +10,7 @@ and times calls.
     python -m paper_1811_11722_amd.drivers time_to_error
     python -m paper_1811_11722_amd.drivers convergence [--out rows.jsonl]
     python -m paper_1811_11722_amd.drivers cv_estimate
+    python -m paper_1811_11722_amd.drivers cv_train [--workload 4|5] [--sweeps 12]
     python -m paper_1811_11722_amd.drivers fig3
     python -m paper_1811_11722_amd.drivers allocation_compare [--count 2000]
 """
@@ -637,6 +638,38 @@ def cv_estimate(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED
             "err_cv": out.err_re, "err_plain": plain.err_re, "mean_cv": out.mean_re, "mean_plain": plain.mean_re}
 
 
+def cv_train(workload: int = 4, reps: int = 2, max_sweeps: int = 12, n_train: int = 1048573, log=None) -> dict:
+    """Control-variate training alone, timed: workload 4's real d = 8 sector
+    (R = 32, K = 12, the Korobov-2 transform the time-to-error run picks) or
+    workload 5's complex d = 10 sector (R = 64, K = 12, baker, one model per
+    component), on n_train points of the independent training lattice.  The
+    first call compiles the sampler and is reported as rep 0."""
+    say = log or (lambda msg: None)
+    if workload == 4:
+        d, R, K, seed, tk, alpha = 8, 32, 12, synth.SEED_BASE + 4, "korobov", 2
+        tab = synth.sector_tables(seed, d, 12, 30)
+    else:
+        d, R, K, seed, tk, alpha = 10, 64, 12, synth.SEED_BASE + 5, "baker", 0
+        tab = synth.sector_workload(n=16381, m=2, d=d, n_u=20, n_f=60, seed=seed, complex_kinematics=True).sector
+    params = qmc.Params("sector", d, sector=tab)
+    gv = GeneratingVectors(seed, candidates=8)
+    plan = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), tk, alpha)
+    rows = []
+    for r in range(reps):
+        _sync()
+        t = time.perf_counter()
+        _, _, rep = plan.cv_train(params, R, K, max_sweeps=max_sweeps)
+        _sync()
+        t = time.perf_counter() - t
+        rows.append({"wall_seconds": t, "device_seconds": rep.seconds, "sweeps": rep.sweeps,
+                     "rel_loss": rep.rel_loss})
+        say(f"  rep {r}: {t:.4f} s wall, {rep.seconds:.4f} s device, {rep.sweeps} sweeps, "
+            f"rel_loss {rep.rel_loss:.3e}")
+    plan.close()
+    return {"workload": workload, "d": d, "R": R, "K": K, "n_train": n_train, "transform": f"{tk}{alpha or ''}",
+            "reps": rows}
+
+
 def fig3(dims=(6, 9, 10), alphas=(3, 6), kmin: int = 10, kmax: int = 26, m: int = 32,
          seed: int = synth.SEED_BASE + 6, log=None) -> dict:
     """The error study of Sec. 2 (Fig. 3): the constant 1 integrated with the
@@ -836,7 +869,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
                                      "cv_estimate", "fig3", "allocation_compare", "deform", "transforms",
-                                     "lattices", "sector_batch_specialised", "sector_sum"])
+                                     "lattices", "sector_batch_specialised", "sector_sum", "cv_train"])
     ap.add_argument("--kmax", type=int, default=0)
     ap.add_argument("--cv-kmax", type=int, default=-1, help="largest 2^k of the CV ladder (convergence)")
     ap.add_argument("--shift-tile", type=int, default=0)
@@ -845,6 +878,9 @@ def main(argv=None):
     ap.add_argument("--tile-points", type=int, default=-1)
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--workers", type=int, default=0, help="compile processes (sector_batch_specialised)")
+    ap.add_argument("--workload", type=int, default=4, help="4 or 5 (cv_train)")
+    ap.add_argument("--reps", type=int, default=2, help="training runs (cv_train)")
+    ap.add_argument("--sweeps", type=int, default=12, help="ALS sweeps at most (cv_train)")
     ap.add_argument("--out", default=None, help="JSON-lines file of results; a rerun resumes from it "
                                                 "(sector_batch, convergence)")
     args = ap.parse_args(argv)
@@ -862,6 +898,9 @@ def main(argv=None):
                                  shift_tile=args.shift_tile, blocks_per_cu=args.blocks_per_cu)
     elif args.what == "cv_estimate":
         out = cv_estimate()
+    elif args.what == "cv_train":
+        out = cv_train(workload=args.workload, reps=args.reps, max_sweeps=args.sweeps,
+                       log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "allocation_compare":
         out = allocation_compare(count=args.count or 2000)
     elif args.what == "sector_sum":
