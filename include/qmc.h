@@ -250,7 +250,10 @@ typedef enum {
     QMC_BATCH_PERSISTENT = 1, /* CUs x 8 workgroups loop over the work list */
     QMC_BATCH_PER_TILE = 2,   /* one workgroup per tile */
     /* sectors only: one launch per plan of the run-time specialised sector
-       kernel, on one stream, without a graph.  Each distinct exponent
+       kernel (with use_graph: every plan's kernel, finalize and result copy
+       captured into one HIP graph on four parallel chains and replayed by
+       later calls with the same plans, exponent structures and buffers; the
+       coefficients are uploaded before each replay).  Each distinct exponent
        structure is compiled once per process (hipRTC, about 0.1-0.2 s) and
        reused for every later call and coefficient set with that structure, so
        this pays when the same sectors are integrated repeatedly (new
@@ -277,6 +280,17 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
    interleaved (re, im) for complex sectors.  Not filled by the per-plan
    comparison mode. */
 qmc_status qmc_batch_per_shift(uint32_t count, const qmc_plan_t *plans, double *const *per_shift);
+
+/* Autotuner of the batched launch (the table-driven schedules of
+   qmc_integrate_batch): times tile_points in {4096, 8192, 16384, 32768} with
+   the one-workgroup-per-tile and the persistent schedule, each captured into
+   a HIP graph and launched once (device time of the graph, events on the
+   batch stream), and returns the fastest options in best
+   (use_graph = 1) and their time in best_ms (nullable, milliseconds).  The
+   arguments are those of qmc_integrate_batch; the estimates it computes are
+   discarded. */
+qmc_status qmc_batch_autotune(uint32_t count, const qmc_plan_t *plans, qmc_family family,
+                              const void *const *params, qmc_batch_opts *best, double *best_ms);
 
 /* Pick a launch shape for (plan, family, params) by timing candidate shapes
    on the device; the choice is stored in the plan and in the tuning cache

@@ -373,19 +373,184 @@ void plan_release_extra(qmc_plan_s *p) {
 
 // One launch per plan of its run-time specialised sector kernel (each plan's
 // own stream and buffers), then one synchronisation per plan's stream.
+// Launch shape of one plan's specialised sector kernel, as plan_enqueue
+// chooses it (the plan's own configuration, else T = 4 for real sectors of
+// d <= 8, 1 with a deformation, 2 otherwise, and 16 workgroups per CU).
+struct SpecPlan {
+    hipFunction_t fn = nullptr;
+    uint32_t T = 0, bx = 0, tiles = 0;
+};
+
+static qmc_status spec_prepare(qmc_plan_s *p, const Packed &pk, SpecPlan &sp) {
+    const bool wide = !pk.cplx && p->d <= (pk.orders < 2 ? 8u : 6u);
+    sp.T = p->launch.shift_tile ? p->launch.shift_tile : (pk.deform ? 1u : wide ? 4u : 2u);
+    std::string err;
+    sp.fn = jit_kernel(pk.blob, p->d, p->tr, sp.T, pk.cplx, p->device, err);
+    if (!sp.fn) return fail(QMC_EUNSUPPORTED, "specialised sector kernel: %s", err.c_str());
+    if (p->m * pk.np > kMaxRows) return fail(QMC_EUNSUPPORTED, "m * parts > %u", kMaxRows);
+    sp.tiles = (p->m + sp.T - 1) / sp.T;
+    sp.bx = grid_x(p->n, sp.tiles, p->device, p->launch.blocks_per_cu ? p->launch.blocks_per_cu : 16);
+    qmc_status st = plan_upload_params(p, pk);
+    if (!st) st = plan_set_gstep(p, sp.bx * kBlock);
+    if (!st)
+        st = ensure_buffer((void **)&p->d_partials, p->partials_cap, (size_t)p->m * pk.np * sp.bx * sizeof(double2),
+                           "partials");
+    return st;
+}
+
+// lattice kernel, finalize kernel and the copy of the results to the
+// plan's pinned mirror, on stream s
+static hipError_t spec_enqueue(qmc_plan_s *p, const Packed &pk, const SpecPlan &sp, hipStream_t s) {
+    LatticeArgs a{};
+    a.n = p->n;
+    a.d = p->d;
+    a.m = p->m;
+    a.tiles = sp.tiles;
+    a.inv_n = p->inv_n;
+    a.g = p->d_g;
+    a.gstep = p->d_gstep;
+    a.shifts = p->d_shifts;
+    a.params = p->d_params;
+    a.g_stride = a.shift_stride = a.param_stride = 0;
+    a.np = pk.np;
+    a.partials = p->d_partials;
+    hipError_t e = jit_launch(sp.fn, a, dim3(sp.bx, sp.tiles), s);
+    if (e != hipSuccess) return e;
+    FinalizeArgs f{};
+    f.partials = p->d_partials;
+    f.nblk = sp.bx;
+    f.m = p->m;
+    f.np = pk.np;
+    f.n = (double)p->n;
+    f.scale = transform_scale(p->tr, p->d);
+    f.sub = 0.0;
+    f.q = p->d_out;
+    f.res = p->d_out + out_res_offset(p->m);
+    if ((e = launch_finalize(f, 1, s)) != hipSuccess) return e;
+    return hipMemcpyAsync(p->h_out, p->d_out, out_doubles(p->m) * sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+// A captured specialised schedule: the kernels of every plan on kSpecChains
+// parallel chains of one graph, valid while the plans keep the buffers,
+// kernels and launch shapes it was captured with.
+constexpr int kSpecChains = 4;
+struct SpecCtx {
+    std::vector<qmc_plan_s *> plans;
+    std::vector<SpecPlan> sp;
+    std::vector<std::vector<const void *>> bufs;  // per plan: params, partials, out, gstep, g, shifts, h_out
+    hipStream_t stream = nullptr;
+    hipStream_t side[kSpecChains] = {};
+    hipEvent_t fork = nullptr, join[kSpecChains] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~SpecCtx() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (fork) (void)hipEventDestroy(fork);
+        for (int c = 0; c < kSpecChains; ++c) {
+            if (join[c]) (void)hipEventDestroy(join[c]);
+            if (side[c]) (void)hipStreamDestroy(side[c]);
+        }
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+std::vector<std::unique_ptr<SpecCtx>> g_spec;
+
+static std::vector<const void *> spec_buffers(qmc_plan_s *p) {
+    return {p->d_params, p->d_partials, p->d_out, p->d_gstep, p->d_g, p->d_shifts, p->h_out};
+}
+
+static qmc_status spec_capture(SpecCtx &c, const std::vector<Packed> &pk) {
+    hipError_t e = hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.fork, hipEventDisableTiming);
+    for (int k = 0; k < kSpecChains && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&c.side[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c.join[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return hip_fail(e, "specialised batch streams");
+    if ((e = hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "begin capture");
+    hipError_t ce = hipEventRecord(c.fork, c.stream);
+    for (int k = 0; k < kSpecChains && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(c.side[k], c.fork, 0);
+    for (size_t i = 0; i < c.plans.size() && ce == hipSuccess; ++i)
+        ce = spec_enqueue(c.plans[i], pk[i], c.sp[i], c.side[i % kSpecChains]);
+    for (int k = 0; k < kSpecChains && ce == hipSuccess; ++k) {
+        ce = hipEventRecord(c.join[k], c.side[k]);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(c.stream, c.join[k], 0);
+    }
+    e = hipStreamEndCapture(c.stream, &c.graph);
+    if (ce != hipSuccess) return hip_fail(ce, "capture specialised batch");
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    if ((e = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(e, "instantiate graph");
+    return QMC_OK;
+}
+
+// One launch per plan of its run-time specialised kernel (sectors only):
+// without a graph on the plans' own streams, with one a captured graph that
+// later calls with the same plans, structures and buffers replay (the
+// parameter blobs are uploaded before every replay, so new coefficients
+// with the same exponent structure reuse it).
 static qmc_status batch_specialised(uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk,
-                                    qmc_result *out) {
+                                    qmc_result *out, bool use_graph) {
     qmc_status first_bad = QMC_OK;
+    if (!use_graph) {
+        for (uint32_t i = 0; i < count; ++i) {
+            qmc_plan_s *p = plans[i];
+            const int32_t jit = p->jit_mode;
+            p->jit_mode = 2;  // specialised kernel or an error
+            qmc_status st = plan_enqueue(p, pk[i], p->launch.shift_tile, p->launch.blocks_per_cu);
+            p->jit_mode = jit;
+            if (st) return st;
+        }
+        for (uint32_t i = 0; i < count; ++i) {
+            qmc_status st = plan_collect(plans[i], pk[i].np, &out[i], nullptr, pk[i].crossing);
+            if (st == QMC_ENONFINITE || st == QMC_ECONTOUR) {
+                if (!first_bad || st == QMC_ENONFINITE) first_bad = st;
+            } else if (st) {
+                return st;
+            }
+        }
+        return first_bad;
+    }
+    std::vector<SpecPlan> sp(count);
     for (uint32_t i = 0; i < count; ++i) {
-        qmc_plan_s *p = plans[i];
-        const int32_t jit = p->jit_mode;
-        p->jit_mode = 2;  // specialised kernel or an error
-        qmc_status st = plan_enqueue(p, pk[i], p->launch.shift_tile, p->launch.blocks_per_cu);
-        p->jit_mode = jit;
+        qmc_status st = spec_prepare(plans[i], pk[i], sp[i]);
         if (st) return st;
     }
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    SpecCtx *c = nullptr;
+    for (auto &x : g_spec) {
+        if (x->plans.size() != count || !std::equal(x->plans.begin(), x->plans.end(), plans)) continue;
+        bool same = true;
+        for (uint32_t i = 0; i < count && same; ++i)
+            same = x->sp[i].fn == sp[i].fn && x->sp[i].T == sp[i].T && x->sp[i].bx == sp[i].bx &&
+                   x->bufs[i] == spec_buffers(plans[i]);
+        if (same) c = x.get();
+    }
+    if (!c) {
+        auto fresh = std::make_unique<SpecCtx>();
+        fresh->plans.assign(plans, plans + count);
+        fresh->sp = sp;
+        for (uint32_t i = 0; i < count; ++i) fresh->bufs.push_back(spec_buffers(plans[i]));
+        qmc_status st = spec_capture(*fresh, pk);
+        if (st) return st;
+        if (g_spec.size() >= kMaxContexts) g_spec.erase(g_spec.begin());
+        g_spec.push_back(std::move(fresh));
+        c = g_spec.back().get();
+    }
+    // the blobs went up on each plan's own stream in spec_prepare, which
+    // waited for them
+    hipError_t e = hipGraphLaunch(c->exec, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "specialised batch graph");
     for (uint32_t i = 0; i < count; ++i) {
-        qmc_status st = plan_collect(plans[i], pk[i].np, &out[i], nullptr, pk[i].crossing);
+        qmc_plan_s *p = plans[i];
+        p->last_T = sp[i].T;
+        p->last_bx = sp[i].bx;
+        p->last_jit = true;
+        qmc_status st = plan_results(p, pk[i].np, &out[i], nullptr, pk[i].crossing);
         if (st == QMC_ENONFINITE || st == QMC_ECONTOUR) {
             if (!first_bad || st == QMC_ENONFINITE) first_bad = st;
         } else if (st) {
@@ -429,7 +594,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
         if (plans[i]->m * pk[i].np > kMaxRows) return fail(QMC_EUNSUPPORTED, "m * parts > %u", kMaxRows);
     }
 
-    if (specialised) return batch_specialised(count, plans, pk, out);
+    if (specialised) return batch_specialised(count, plans, pk, out, o.use_graph != 0);
 
     std::lock_guard<std::mutex> lock(g_batch_mu);
     BatchCtx *c = nullptr;
@@ -528,6 +693,45 @@ qmc_status qmc_batch_per_shift(uint32_t count, const qmc_plan_t *plans, double *
         return QMC_OK;
     }
     return fail(QMC_EINVAL, "no batch ran with these plans");
+}
+
+qmc_status qmc_batch_autotune(uint32_t count, const qmc_plan_t *plans, qmc_family family, const void *const *params,
+                              qmc_batch_opts *best, double *best_ms) {
+    if (count == 0) return fail(QMC_EINVAL, "count must be >= 1");
+    if (!plans || !params || !best) return fail(QMC_EINVAL, "null argument");
+    if (!plans[0]) return fail(QMC_EINVAL, "plan 0 is NULL");
+    std::vector<qmc_result> out(count);
+    qmc_plan_s *p0 = plans[0];
+    const bool keep_timing = p0->timing;
+    p0->timing = true;
+    double best_t = INFINITY;
+    qmc_batch_opts choice{1, 0, 8192, QMC_BATCH_DEFAULT};
+    qmc_status st = QMC_OK;
+    for (int32_t sched : {QMC_BATCH_DEFAULT, QMC_BATCH_PERSISTENT}) {
+        for (uint32_t tp : {4096u, 8192u, 16384u, 32768u}) {
+            const qmc_batch_opts o{1, 0, tp, sched};
+            // one call per candidate: it captures the graph and launches it;
+            // the events bracket the graph launch alone
+            p0->kernel_ms = 0.0;
+            p0->kernel_launches = 0;
+            st = qmc_integrate_batch(count, plans, family, params, &o, out.data());
+            if (st && st != QMC_ENONFINITE) break;
+            const double t = p0->kernel_launches ? p0->kernel_ms / (double)p0->kernel_launches : INFINITY;
+            if (st && st != QMC_ENONFINITE) break;
+            if (t < best_t) {
+                best_t = t;
+                choice = o;
+            }
+        }
+        if (st && st != QMC_ENONFINITE) break;
+    }
+    p0->timing = keep_timing;
+    p0->kernel_ms = 0.0;
+    p0->kernel_launches = 0;
+    if (st && st != QMC_ENONFINITE) return st;
+    *best = choice;
+    if (best_ms) *best_ms = best_t;
+    return QMC_OK;
 }
 
 }  // extern "C"

@@ -448,6 +448,11 @@ qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per
             p->kernel_launches += 1;
         }
     }
+    return plan_results(p, np, out, per_shift, crossing);
+}
+
+// The result of an estimate whose output is in the plan's pinned mirror.
+qmc_status plan_results(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift, bool crossing) {
     // with a crossing count the last of the np parts is the count, not a
     // value: it is left out of per_shift and of the finiteness check
     const uint32_t nv = crossing ? np - 1 : np;

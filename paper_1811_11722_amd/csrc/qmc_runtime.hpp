@@ -88,6 +88,7 @@ qmc_status plan_upload_params(qmc_plan_s *p, const Packed &pk);
 qmc_status plan_set_gstep(qmc_plan_s *p, uint32_t S);
 qmc_status plan_enqueue(qmc_plan_s *p, const Packed &pk, uint32_t want_T, uint32_t blocks_per_cu);
 qmc_status plan_collect(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift, bool crossing = false);
+qmc_status plan_results(qmc_plan_s *p, uint32_t np, qmc_result *out, double *per_shift, bool crossing);
 void plan_release_extra(qmc_plan_s *p);
 uint32_t padded_rows(uint32_t m);
 std::vector<double> padded_shifts(const std::vector<double> &sh, uint32_t m, uint32_t d, uint32_t rows,

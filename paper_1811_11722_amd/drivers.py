@@ -168,10 +168,12 @@ def _timed(fn, reps: int):
 
 
 def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int = synth.SEED_BASE + 3,
-                 tile_points: int = 8192, reps: int = 3, compare: bool = True) -> dict:
+                 tile_points: int = 8192, reps: int = 3, compare: bool = True, log=None) -> dict:
     """Batched sectors: pilot estimates at n0 = 16381, the error-goal rule for
-    each sector's n, then one graph-replayed persistent launch against one
+    each sector's n, then graph-replayed launches (per-tile and persistent
+    schedules at tile_points, and the tiling the autotuner picks) against one
     launch per sector."""
+    say = log or (lambda msg: None)
     tabs = synth.sector_batch(seed, count)
     gv = GeneratingVectors(seed)
     n0 = LADDER[0]
@@ -192,10 +194,20 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
              for s, (t, n) in enumerate(zip(tabs, ns))]
     t_setup = time.perf_counter() - t0
     evals = int(sum(n * m for n in ns))
+    say(f"  {count} sectors, {evals} evaluations; graph batch")
     res, t_graph = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True,
                                                      tile_points=tile_points), reps)
+    say(f"  graph batch {t_graph:.3f} s; persistent")
     res_ps, t_persist = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True, tile_points=tile_points,
                                                           schedule="persistent"), reps)
+    # the tiling and schedule the autotuner picks
+    say(f"  persistent {t_persist:.3f} s; autotuning")
+    t0 = time.perf_counter()
+    tuned, tuned_device_ms = qmc.batch_autotune(plans, params)
+    t_tune = time.perf_counter() - t0
+    say(f"  autotuner: {tuned} ({t_tune:.1f} s)")
+    _, t_tuned = _timed(lambda: qmc.integrate_batch(plans, params, **tuned), reps)
+    say(f"  tuned batch {t_tuned:.3f} s")
     out = {
         "sectors": count, "m": m, "goal": goal, "tile_points": tile_points,
         "pilot_n": n0, "pilot_seconds": t_pilot,
@@ -204,6 +216,8 @@ def sector_batch(count: int = 2000, m: int = 16, goal: float = 1e-8, seed: int =
         "evals": evals, "setup_seconds": t_setup,
         "graph_seconds": t_graph, "graph_evals_per_s": evals / t_graph,
         "graph_persistent_seconds": t_persist, "graph_persistent_evals_per_s": evals / t_persist,
+        "autotuned": dict(tuned, seconds=t_tuned, evals_per_s=evals / t_tuned, device_ms=tuned_device_ms,
+                          tuning_seconds=t_tune),
         "max_rel_diff_per_tile_vs_persistent": float(max(
             abs(a.mean_re - b.mean_re) / abs(b.mean_re) for a, b in zip(res, res_ps))),
         "rel_err_max": float(max(abs(r.err_re) / abs(r.mean_re) for r in res)),
@@ -338,7 +352,9 @@ def sector_batch_specialised(count: int = 2000, m: int = 16, goal: float = 1e-8,
              for s, (t, n) in enumerate(zip(tabs, ns))]
     evals = int(sum(n * m for n in ns))
     res_sp, t_sp = _timed(lambda: qmc.integrate_batch(plans, params, schedule="specialised"), reps)
-    say(f"  specialised batch {t_sp:.3f} s")
+    say(f"  specialised batch (graph) {t_sp:.3f} s")
+    _, t_sp_eager = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=False, schedule="specialised"), reps)
+    say(f"  specialised batch (launches) {t_sp_eager:.3f} s")
     res_g, t_g = _timed(lambda: qmc.integrate_batch(plans, params, use_graph=True, tile_points=tile_points), reps)
     say(f"  table-driven graph batch {t_g:.3f} s")
     for p in plans:
@@ -346,6 +362,7 @@ def sector_batch_specialised(count: int = 2000, m: int = 16, goal: float = 1e-8,
     return {"sectors": count, "m": m, "goal": goal, "evals": evals, "precompile_workers": workers,
             "precompile_seconds": t_pre, "compile_seconds": t_compile,
             "specialised_seconds": t_sp, "specialised_evals_per_s": evals / t_sp,
+            "specialised_launches_seconds": t_sp_eager,
             "graph_seconds": t_g, "graph_evals_per_s": evals / t_g,
             "max_rel_diff_specialised_vs_graph": float(max(
                 abs(a.mean_re - b.mean_re) / abs(b.mean_re) for a, b in zip(res_sp, res_g)))}
@@ -891,7 +908,7 @@ def main(argv=None):
     elif args.what == "sector_batch":
         out = sector_batch(count=args.count or 2000,
                            tile_points=8192 if args.tile_points < 0 else args.tile_points,
-                           compare=not args.no_compare)
+                           compare=not args.no_compare, log=lambda msg: print(msg, file=sys.stderr, flush=True))
     elif args.what == "product_peak_batch":
         out = product_peak_batch(count=args.count or 512,
                                  tile_points=0 if args.tile_points < 0 else args.tile_points,

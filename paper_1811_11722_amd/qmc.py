@@ -103,6 +103,7 @@ SIGNATURES = {
     "qmc_korobov_vector": (C.c_int, [_u64, _u32, _u64, _vp]),
     "qmc_korobov_search": (C.c_int, [_u64, _u32, _vp, _u32, _vp, _vp, _vp]),
     "qmc_integrate_batch": (C.c_int, [_u32, _vp, C.c_int, _vp, _vp, _vp]),
+    "qmc_batch_autotune": (C.c_int, [_u32, _vp, C.c_int, _vp, _vp, _vp]),
     "qmc_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "qmc_batch_per_shift": (C.c_int, [_u32, _vp, _vp]),
     "qmc_math_eval": (C.c_int, [_i32, _u64, _vp, _vp]),
@@ -518,6 +519,19 @@ def integrate_batch(plans: Sequence[Plan], params: Sequence[Params], use_graph: 
     if not (allow_crossing and st == QMC_ECONTOUR):
         check(st, "qmc_integrate_batch")
     return list(out)
+
+
+def batch_autotune(plans: Sequence[Plan], params: Sequence[Params]):
+    """Fastest table-driven batch options by timing: (dict of
+    integrate_batch keyword arguments, milliseconds)."""
+    fam = params[0].family
+    handles = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+    pp = (C.c_void_p * len(params))(*[p.ptr for p in params])
+    best = qmc_batch_opts()
+    ms = C.c_double()
+    check(lib().qmc_batch_autotune(len(plans), handles, fam, pp, C.byref(best), C.byref(ms)), "qmc_batch_autotune")
+    sched = {v: k for k, v in BATCH_SCHEDULE.items()}[best.schedule]
+    return {"use_graph": bool(best.use_graph), "tile_points": best.tile_points, "schedule": sched}, ms.value
 
 
 def batch_per_shift(plans: Sequence[Plan], complex_parts: bool = False):

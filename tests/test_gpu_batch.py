@@ -213,6 +213,59 @@ def test_batch_specialised_schedule_matches_default(Q):
         p.close()
 
 
+def test_batch_specialised_graph_replays(Q):
+    """The specialised schedule captured into a graph: every replay (with
+    eager work on the same plans between replays, and new coefficients of the
+    same exponent structures, uploaded before a replay) equals the eager
+    launches bit for bit; per-plan standalone calls in between, which move
+    a plan's launch shape, make the next call capture afresh."""
+    import dataclasses
+    tabs = synth.sector_batch(synth.SEED_BASE + 3, 10)
+    plans, params = [], []
+    for s, t in enumerate(tabs):
+        n = 4093 if s % 2 else 16381
+        g = O.korobov_vector(n, t.d, 17364 % n)
+        plans.append(Q.Plan(t.d, n, g, synth.sector_batch_shifts(synth.SEED_BASE + 3, s, 4, t.d), "baker"))
+        params.append(Q.Params("sector", t.d, sector=t))
+    _say("batch specialised graph")
+    key = lambda rs: [(r.mean_re, r.err_re) for r in rs]
+    eager = key(Q.integrate_batch(plans, params, use_graph=False, schedule="specialised"))
+    for rep in range(3):
+        got = key(Q.integrate_batch(plans, params, use_graph=True, schedule="specialised"))
+        assert got == eager, rep
+        # eager work on the same plans between replays
+        for p, pa in zip(plans[:3], params[:3]):
+            p.integrate(pa)
+    # new coefficients, same structures: the graph is replayed with the new blobs
+    scaled = [Q.Params("sector", t.d, sector=dataclasses.replace(t, coef_f=t.coef_f * 1.5)) for t in tabs]
+    eager2 = key(Q.integrate_batch(plans, scaled, use_graph=False, schedule="specialised"))
+    assert eager2 != eager
+    assert key(Q.integrate_batch(plans, scaled, use_graph=True, schedule="specialised")) == eager2
+    # a plan whose launch shape changed: captured again, same results
+    plans[0].set_launch(2, 4)
+    assert key(Q.integrate_batch(plans, scaled, use_graph=True, schedule="specialised")) == \
+        key(Q.integrate_batch(plans, scaled, use_graph=False, schedule="specialised"))
+    for p in plans:
+        p.close()
+
+
+def test_batch_autotune(Q):
+    """The batch autotuner returns a table-driven configuration whose graph
+    batch matches the oracle within 1e-12 per shift."""
+    plans, params, cases = _sector_plans(Q, 24, synth.SEED_BASE + 3, [4093, 16381], 4)
+    _say("batch autotune")
+    opts, ms = Q.batch_autotune(plans, params)
+    assert opts["schedule"] in ("default", "persistent") and opts["use_graph"]
+    assert opts["tile_points"] in (4096, 8192, 16384, 32768) and ms > 0
+    Q.integrate_batch(plans, params, **opts)
+    per = Q.batch_per_shift(plans)
+    for (d, n, g, sh, tab), q in zip(cases, per):
+        est = O.estimate(n, g, sh, O.Params("sector", d, sector=tab), "baker", threads=THREADS)
+        assert np.all(_rel(q, est.q_re) < TOL)
+    for p in plans:
+        p.close()
+
+
 def test_jit_code_object_store(Q, tmp_path):
     """With QMC_JIT_CACHE set, a compiled sector kernel is written to disk and
     a second process loads it: same per-shift sums, bit for bit."""
