@@ -519,6 +519,11 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
     rows_p, cum_p, hit_p = ladder_run(lambda plan: plan.integrate(params)[0], kmax)
 
     say("control variate: training")
+    # the training sampler is specialised to the integrand like the lattice
+    # kernels: compile it outside the timed region
+    warm_train = qmc.Plan(d, ladder[0], gv(ladder[0], d), synth.shifts(seed, 2, d, stream=3), tk, alpha)
+    warm_train.cv_samples(params)
+    warm_train.close()
     train = qmc.Plan(d, n_train, gv(n_train, d), synth.shifts(seed, 2, d, stream=3), tk, alpha)
     _sync()
     t = time.perf_counter()
