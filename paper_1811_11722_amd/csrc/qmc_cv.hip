@@ -450,8 +450,9 @@ __global__ __launch_bounds__(kBlock) void k_cv_gather(const float *partial, uint
 
 // One pass over the training set for the right-hand side of dimension i:
 //   part[split][u] = sum_{j in split} rho_j[r] phi_j[k] e_j,  u = r K + k,
-//   e_j = y_j - sum_{r,k} rho_j[r] phi_j[k] w[r, i, k]   (e_j = y_j when w is null),
-// y_j = yd_j, or yf_j * y_scale when yd is null; FP64 throughout, on
+//   e_j = yf_j y_scale - sum_{r,k} rho_j[r] phi_j[k] w[r, i, k]   (training), or
+//   e_j = yd_j                                                 (NORMAL);
+// FP64 throughout, on
 // v_mfma_f64_16x16x4f64 (A[i][k] and B[k][j] at lane i (or j) + 16 k;
 // output element v of lane l at row 4 v + l / 16, column l % 16).  A wave
 // takes 16 points at a time:
@@ -463,7 +464,8 @@ __global__ __launch_bounds__(kBlock) void k_cv_gather(const float *partial, uint
 //   3. the right-hand side tile accumulates (rho e)^T Phi, 4 points per
 //      instruction: A = rho e as held, B = phi[point 4 g + l / 16][l % 16]
 //      (0 for Legendre indices >= K).
-// Waves take 16-point chunks in turn over the workgroup's range; their tiles
+// Waves take 16-point chunks in turn over the workgroup's range (all the
+// loads of a chunk first, so that it waits on memory once); their tiles
 // are added in wave order.  Entry R K of a split's partials is its sum of
 // e_j^2 (the objective of the current factor).  A set *flag (a converged
 // solve) makes the kernel return at once.
@@ -478,7 +480,7 @@ struct CvPassArgs {
     double *part;             // (splits, R K + 1)
 };
 
-template <int R, int K>
+template <int R, int K, bool NORMAL>
 __global__ __launch_bounds__(kBlock) void k_cv_pass(const CvPassArgs a) {
     constexpr int RT = (R + 15) / 16, KS = (K + 3) / 4;
     static_assert(K <= 16 && RT <= 4, "one B tile of Legendre indices, at most 4 rank tiles");
@@ -487,38 +489,55 @@ __global__ __launch_bounds__(kBlock) void k_cv_pass(const CvPassArgs a) {
     const uint32_t li = lane & 15, lg = lane >> 4;
     const uint32_t j0 = (uint32_t)((uint64_t)a.n * blockIdx.x / a.splits);
     const uint32_t j1 = (uint32_t)((uint64_t)a.n * (blockIdx.x + 1) / a.splits);
-    const bool use_w = a.w != nullptr;
     double wb[RT][KS];
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const uint32_t r = 16 * t + li, k = 4 * s + lg;
-            wb[t][s] = (use_w && r < (uint32_t)R && k < (uint32_t)K) ? a.w[((size_t)r * a.d + a.i) * K + k] : 0.0;
+            wb[t][s] = (!NORMAL && r < (uint32_t)R && k < (uint32_t)K) ? a.w[((size_t)r * a.d + a.i) * K + k] : 0.0;
         }
     cv_d4 acc[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[t] = cv_d4{0.0, 0.0, 0.0, 0.0};
     double e2 = 0.0;  // lanes l < 16 add e^2 of points 4 v + l / 16 ... one lane per point
+    // Every operand of a 16-point chunk is loaded first, branch-free (indices
+    // clamped into the range, values outside it zeroed afterwards), so that
+    // a chunk waits on memory once.
+    const uint32_t rl = li < (uint32_t)R ? li : 0;  // rank lane, clamped (R = 8)
+    const uint32_t kl = li < (uint32_t)K ? li : 0;           // Legendre lane, clamped
     for (uint32_t p0 = j0 + 16 * wave; p0 < j1; p0 += 64) {
-        double rh[RT][4], e[4];
+        double rh[RT][4], y[4], fa[KS], fb[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const uint32_t p = p0 + 4 * v + lg;
+            const uint32_t p = p0 + 4 * v + lg, pc = p < j1 ? p : j1 - 1;
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                const uint32_t r = 16 * t + li;
-                rh[t][v] = (p < j1 && r < (uint32_t)R) ? a.rho[(size_t)p * R + r] : 0.0;
-            }
-            e[v] = p < j1 ? (a.yd ? a.yd[p] : (double)a.yf[p] * a.y_scale) : 0.0;
+            for (int t = 0; t < RT; ++t) rh[t][v] = a.rho[(size_t)pc * R + (16 * t + rl)];
+            y[v] = NORMAL ? a.yd[pc] : (double)a.yf[pc] * a.y_scale;
+            fb[v] = a.phi[(size_t)pc * K + kl];
         }
-        if (use_w) {
-            double fa[KS];
+        {
+            const uint32_t p = p0 + li, pc = p < j1 ? p : j1 - 1;
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
-                const uint32_t p = p0 + li, k = 4 * s + lg;
-                fa[s] = (p < j1 && k < (uint32_t)K) ? a.phi[(size_t)p * K + k] : 0.0;
+                const uint32_t k = 4 * s + lg;
+                fa[s] = a.phi[(size_t)pc * K + (k < (uint32_t)K ? k : 0)];
             }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const bool in = p0 + 4 * v + lg < j1;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) rh[t][v] = (in && 16 * t + li < (uint32_t)R) ? rh[t][v] : 0.0;
+            y[v] = in ? y[v] : 0.0;
+            fb[v] = (in && li < (uint32_t)K) ? fb[v] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) fa[s] = (p0 + li < j1 && 4 * s + lg < (uint32_t)K) ? fa[s] : 0.0;
+        double e[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) e[v] = y[v];
+        if (!NORMAL) {
             double dot[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
@@ -541,10 +560,9 @@ __global__ __launch_bounds__(kBlock) void k_cv_pass(const CvPassArgs a) {
         }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const uint32_t p = p0 + 4 * g + lg;
-            const double fb = (p < j1 && li < (uint32_t)K) ? a.phi[(size_t)p * K + li] : 0.0;
 #pragma unroll
-            for (int t = 0; t < RT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rh[t][g] * e[g], fb, acc[t], 0, 0, 0);
+            for (int t = 0; t < RT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rh[t][g] * e[g], fb[g], acc[t], 0, 0, 0);
         }
     }
     // tiles of the 4 waves, added in wave order; element v of lane l is
@@ -586,6 +604,9 @@ __global__ __launch_bounds__(kBlock) void k_cv_rhs_reduce(const double *part, ui
 }
 
 // ------------------------------------------------------------ the solve
+// Escalation path of the factorisation (the main path is k_cv_chol_diag0 /
+// k_cv_chol_step below; this kernel runs only when that one met a
+// non-positive pivot).
 // (A0 + lam I) = L L^T by a blocked right-looking Cholesky in one workgroup
 // of 512 threads, panels of B columns (B = 32, or 16 when F > 512 so that
 // the panel fits in LDS):
@@ -603,7 +624,8 @@ __global__ __launch_bounds__(kBlock) void k_cv_rhs_reduce(const double *part, ui
 // pivot restarts with a 100x larger ridge (at most three times).  The
 // factor overwrites A (lower triangle), rdiag receives 1 / L_uu, *status the
 // number of escalations (-1: failed), *lam the ridge, and *flag is cleared
-// for the solves that follow.
+// for the solves that follow.  With first > 0 the kernel starts at that
+// attempt (ridge * 100^first) and returns at once unless *status < 0.
 struct CvFactorArgs {
     uint32_t F;
     double ridge;           // relative to the mean diagonal
@@ -613,6 +635,7 @@ struct CvFactorArgs {
     double *lam;
     int *status;
     int *flag;
+    uint32_t first;
 };
 
 constexpr uint32_t kMaxF = 768;  // largest R K compiled: (64, 12)
@@ -639,9 +662,11 @@ __global__ __launch_bounds__(kFactorThreads) void k_cv_factor(const CvFactorArgs
     __shared__ double sdiag[kMaxF];              // the diagonal, for the trace in index order
     __shared__ double s_ridge;
     __shared__ int s_bad;
+    if (a.first > 0 && *a.status >= 0) return;
     double *A = a.A;
     double ridge = a.ridge;
     int attempt = 0;
+    for (; attempt < (int)a.first; ++attempt) ridge *= 100.0;
     for (; attempt < 4; ++attempt, ridge *= 100.0) {
         for (uint32_t u = tid / 32; u < F; u += nt / 32)
             for (uint32_t v = tid % 32; v <= u; v += 32) {
@@ -802,10 +827,333 @@ __global__ __launch_bounds__(kFactorThreads) void k_cv_factor(const CvFactorArgs
     }
 }
 
+// The factorisation on many workgroups: a blocked right-looking Cholesky
+// with 32 x 32 blocks and one launch per panel.
+//   k_cv_chol_diag0: lam (as above), then block (0, 0) of A0 + lam I;
+//   k_cv_chol_step(p), p = 0 .. NB - 2: one workgroup per block (I, J) of
+//     the trailing lower triangle, p < J <= I < NB.  It forms the panel
+//     rows L_Ip = A_Ip W_p^T and L_Jp = A_Jp W_p^T (W_p = L_pp^-1, FP64
+//     MFMA; every workgroup that needs a panel block recomputes it, the
+//     diagonal one (I, I) stores it in the factor), then takes
+//     A_IJ -= L_Ip L_Jp^T into the working copy Aw (A0 + lam I for p = 0).
+//     The workgroup of block (p + 1, p + 1) then factorises that block.
+//     Further workgroups, one per block (I, J) with I > p >= J, carry the
+//     same panel through the block forward substitution L M = I for the
+//     inverse M = L^-1: block row p of M is M_pJ = W_p R_pJ (R = I minus
+//     the updates so far, R_pp = I), and the rows below take
+//     R_IJ -= L_Ip M_pJ; the workgroups of row I = p + 1 store M_p.;
+//   k_cv_chol_last: block row NB - 1 of M;
+//   k_cv_chol_inverse: (A0 + lam I)^-1 = M^T M, both triangles, for the
+//     corrections (k_cv_subst multiplies by it).
+// A diagonal block is factorised by one wave: lanes r < 32 hold row r,
+// lanes 32 + c hold row c of the identity; every column q is scaled by
+// 1 / sqrt(pivot) (hardware reciprocal square root and two Newton steps)
+// and the lanes take the rank-1 update with the column's entries broadcast
+// through LDS (the entry of the next pivot's row by readlane, which is
+// quicker).  The same operations on the identity rows are column-wise
+// forward substitution, so lanes 32 + c end with column c of W = L_pp^-1
+// at no extra latency.  The factor goes to A (lower triangle), 1 / L_uu to
+// rdiag, W_p to Wd; a non-positive pivot sets *status = -1 and the launches
+// left return at once, so that the escalation kernel above takes over.
+struct CvCholArgs {
+    uint32_t F;
+    double ridge;       // relative to the mean diagonal
+    const double *A0;   // (F, F) normal matrix, lower triangle
+    double *Aw;         // (F, F) working copy of the trailing blocks
+    double *A;          // (F, F) factor L, lower triangle
+    double *Wd;         // (F / 32, 32, 32) W_p, row-major
+    double *rdiag;      // (F) 1 / L_uu
+    double *lam;
+    int *status;
+    int *flag;
+    double *Rm;         // (F, F) the substitution's right-hand sides R, blocks below the diagonal
+    double *Mi;         // (F, F) M = L^-1, lower triangle
+    double *Ai;         // (F, F) (A0 + lam I)^-1, both triangles
+};
+
+constexpr uint32_t kCholB = 32;
+constexpr uint32_t kCholDP = kCholB + 1;  // padded LDS row
+
+// Factorises the block held in D (LDS, row-major, rows padded to kCholDP;
+// only the lower triangle is used) on the calling wave (every lane of one
+// wave calls it; D is overwritten with L_pp).  cb: 32 x 64 doubles of LDS
+// for the broadcasts.  c0 = first row of the block, slot = its index p.
+__device__ void chol_diag_block(double *D, double *cb, uint32_t c0, uint32_t slot, const CvCholArgs &a,
+                                uint32_t lane) {
+    constexpr int B = kCholB;
+    const uint32_t r = lane & (B - 1);
+    const bool fac = lane < (uint32_t)B;
+    double x[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) x[c] = fac ? D[r * kCholDP + c] : (c == (int)r ? 1.0 : 0.0);
+    bool bad = false;
+    double rinv = 0.0;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+        const double piv = readlane_d(x[q], q);
+        bad = bad || !(piv > 0.0);
+        const double pv = piv > 0.0 ? piv : 1.0;
+        double rq = __builtin_amdgcn_rsq(pv);
+        rq = fma(0.5 * rq, fma(-(pv * rq), rq, 1.0), rq);
+        rq = fma(0.5 * rq, fma(-(pv * rq), rq, 1.0), rq);
+        const bool own = lane == (uint32_t)q;
+        rinv = own ? rq : rinv;
+        x[q] = own ? pv * rq : x[q] * rq;
+        cb[q * kWave + lane] = x[q];  // unconditional: a branch here lets the updates sink
+        if (q + 1 < B) x[q + 1] = fma(-x[q], readlane_d(x[q], q + 1), x[q + 1]);
+#pragma unroll
+        for (int c = q + 2; c < B; ++c) x[c] = fma(-x[q], cb[q * kWave + c], x[c]);
+        // one column at a time: reads hoisted across columns would take
+        // hundreds of registers
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // W_p: lane 32 + c holds column c, x[q] = W[q][c]
+    double *W = a.Wd + (size_t)slot * B * B;
+    if (!fac) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) W[q * B + r] = x[q];
+    } else {
+#pragma unroll
+        for (int c = 0; c < B; ++c) D[r * kCholDP + c] = x[c];
+        a.rdiag[c0 + r] = rinv;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t t = lane; t < (uint32_t)(B * B); t += kWave) {
+        const uint32_t u = t / B, v = t - u * B;
+        if (v <= u) a.A[(size_t)(c0 + u) * a.F + c0 + v] = D[u * kCholDP + v];
+    }
+    if (bad && lane == 0) *a.status = -1;
+}
+
+__global__ __launch_bounds__(kWave) void k_cv_chol_diag0(const CvCholArgs a) {
+    __shared__ double sdiag[kMaxF];
+    __shared__ double D[kCholB * kCholDP], cb[kCholB * kWave];
+    const uint32_t F = a.F, lane = threadIdx.x;
+    for (uint32_t u = lane; u < F; u += kWave) sdiag[u] = a.A0[(size_t)u * F + u];
+    __syncthreads();
+    double lam = 0.0;
+    if (lane == 0) {
+        // in index order (F is a multiple of 32), 8 reads in flight
+        double t = 0.0;
+        for (uint32_t u = 0; u < F; u += 8) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = sdiag[u + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t += v[k];
+        }
+        lam = a.ridge * t / F + 1e-300;
+        *a.lam = lam;
+        *a.status = 0;
+        *a.flag = 0;
+    }
+    lam = readlane_d(lam, 0);
+    for (uint32_t t = lane; t < kCholB * kCholB; t += kWave) {
+        const uint32_t u = t / kCholB, v = t - u * kCholB;
+        D[u * kCholDP + v] = v <= u ? a.A0[(size_t)u * F + v] + (u == v ? lam : 0.0) : 0.0;
+    }
+    __syncthreads();
+    chol_diag_block(D, cb, 0, 0, a, lane);
+}
+
+// Block (I, J), I > p >= J, of the inverse's substitution in step p (see
+// above): wave w takes the 16 x 16 tiles (w >> 1, w & 1) of L_Ip, M_pJ and
+// R_IJ.
+__device__ void chol_inverse_tile(const CvCholArgs &a, uint32_t p, uint32_t I, uint32_t J, double *LI, double *LM,
+                                  uint32_t tid) {
+    constexpr uint32_t B = kCholB, DP = kCholDP;
+    const uint32_t F = a.F, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t li = lane & 15, lg = lane >> 4, h = wave >> 1, j2 = wave & 1;
+    const double *src = p == 0 ? a.A0 : a.Aw;
+    const double *W = a.Wd + (size_t)p * B * B;
+    const uint32_t c0 = B * p;
+    double old[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        old[v] = p == J ? 0.0 : a.Rm[(size_t)(B * I + 16 * h + 4 * v + lg) * F + B * J + 16 * j2 + li];
+    double ai[B / 4], wl[B / 4], wa[B / 4], rr[B / 4];
+#pragma unroll
+    for (int s = 0; s < (int)B / 4; ++s) {
+        const uint32_t k = 4 * s + lg;
+        ai[s] = src[(size_t)(B * I + 16 * h + li) * F + c0 + k];
+        wl[s] = W[(16 * j2 + li) * B + k];
+        wa[s] = W[(16 * h + li) * B + k];
+        rr[s] = p == J ? (k == 16 * j2 + li ? 1.0 : 0.0) : a.Rm[(size_t)(c0 + k) * F + B * J + 16 * j2 + li];
+    }
+    cv_d4 xl = cv_d4{0.0, 0.0, 0.0, 0.0}, xm = xl;
+#pragma unroll
+    for (int s = 0; s < (int)B / 4; ++s) {
+        xl = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[s], wl[s], xl, 0, 0, 0);  // L_Ip = A_Ip W_p^T
+        xm = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[s], rr[s], xm, 0, 0, 0);  // M_pJ = W_p R_pJ
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        LI[(16 * h + 4 * v + lg) * DP + 16 * j2 + li] = xl[v];
+        LM[(16 * h + 4 * v + lg) * DP + 16 * j2 + li] = xm[v];
+    }
+    __syncthreads();
+    cv_d4 acc = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < (int)B / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(LI[(16 * h + li) * DP + 4 * s + lg],
+                                                  LM[(4 * s + lg) * DP + 16 * j2 + li], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        a.Rm[(size_t)(B * I + 16 * h + 4 * v + lg) * F + B * J + 16 * j2 + li] = old[v] - acc[v];
+    if (I == p + 1) {
+        for (uint32_t e = tid; e < B * B; e += 256) {
+            const uint32_t u = e / B, v = e - u * B;
+            a.Mi[(size_t)(c0 + u) * F + B * J + v] = LM[u * DP + v];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cv_chol_step(const CvCholArgs a, uint32_t p) {
+    if (*a.status < 0) return;
+    constexpr uint32_t B = kCholB, DP = kCholDP;
+    __shared__ double LI[B * DP], LJ[B * DP], D[B * DP], cb[B * kWave];
+    const uint32_t F = a.F, tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t li = lane & 15, lg = lane >> 4;
+    const uint32_t NB = F / B, m = NB - 1 - p, ntrail = m * (m + 1) / 2;
+    if (blockIdx.x >= ntrail) {
+        const uint32_t t = blockIdx.x - ntrail;
+        chol_inverse_tile(a, p, p + 1 + t / (p + 1), t % (p + 1), LI, LJ, tid);
+        return;
+    }
+    // block t -> (ti, tj), tj <= ti, of the trailing triangle
+    const uint32_t t = blockIdx.x;
+    uint32_t ti = (uint32_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > t) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    const uint32_t tj = t - ti * (ti + 1) / 2;
+    const uint32_t I = p + 1 + ti, J = p + 1 + tj;
+    const bool diag = I == J, next = diag && I == p + 1;
+    const double *src = p == 0 ? a.A0 : a.Aw;
+    const double lam = p == 0 ? *a.lam : 0.0;
+    const uint32_t c0 = B * p;
+
+    // wave w: 16 x 16 tile (w >> 1, w & 1) of L_Ip and of L_Jp, and tile
+    // (hI, hJ) = (w >> 1, w & 1) of the update (none above the diagonal)
+    const uint32_t h = wave >> 1, j2 = wave & 1;
+    const bool upd = !(diag && h < j2);
+    double old[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const uint32_t u = B * I + 16 * h + 4 * v + lg, c = B * J + 16 * j2 + li;
+        old[v] = (upd && c <= u) ? src[(size_t)u * F + c] + (u == c ? lam : 0.0) : 0.0;
+    }
+    double ai[B / 4], aj[B / 4], w[B / 4];
+    const double *W = a.Wd + (size_t)p * B * B;
+#pragma unroll
+    for (int s = 0; s < (int)B / 4; ++s) {
+        ai[s] = src[(size_t)(B * I + 16 * h + li) * F + c0 + 4 * s + lg];
+        aj[s] = src[(size_t)(B * J + 16 * h + li) * F + c0 + 4 * s + lg];
+        w[s] = W[(16 * j2 + li) * B + 4 * s + lg];
+    }
+    cv_d4 xi = cv_d4{0.0, 0.0, 0.0, 0.0}, xj = xi;
+#pragma unroll
+    for (int s = 0; s < (int)B / 4; ++s) {
+        xi = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[s], w[s], xi, 0, 0, 0);
+        xj = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[s], w[s], xj, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        LI[(16 * h + 4 * v + lg) * DP + 16 * j2 + li] = xi[v];
+        LJ[(16 * h + 4 * v + lg) * DP + 16 * j2 + li] = xj[v];
+    }
+    __syncthreads();
+    cv_d4 acc = cv_d4{0.0, 0.0, 0.0, 0.0};
+    if (upd) {
+#pragma unroll
+        for (int s = 0; s < (int)B / 4; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(LI[(16 * h + li) * DP + 4 * s + lg],
+                                                      LJ[(16 * j2 + li) * DP + 4 * s + lg], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const uint32_t ru = 16 * h + 4 * v + lg, cu = 16 * j2 + li;
+        const double nv = old[v] - acc[v];
+        if (next) D[ru * DP + cu] = upd ? nv : 0.0;
+        else if (upd && (!diag || cu <= ru)) a.Aw[(size_t)(B * I + ru) * F + B * J + cu] = nv;
+    }
+    if (diag) {
+        // the panel block L_Ip into the factor
+        for (uint32_t e = tid; e < B * B; e += 256) {
+            const uint32_t u = e / B, v = e - u * B;
+            a.A[(size_t)(B * I + u) * F + c0 + v] = LI[u * DP + v];
+        }
+    }
+    if (next) {
+        __syncthreads();
+        if (wave == 0) chol_diag_block(D, cb, B * I, I, a, lane);
+    }
+}
+
+// Block row NB - 1 of M: M_pJ = W_p R_pJ (p = NB - 1), one workgroup per J.
+__global__ __launch_bounds__(256) void k_cv_chol_last(const CvCholArgs a) {
+    if (*a.status < 0) return;
+    constexpr uint32_t B = kCholB;
+    const uint32_t F = a.F, NB = F / B, p = NB - 1, J = blockIdx.x, tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave, li = lane & 15, lg = lane >> 4;
+    const uint32_t h = wave >> 1, j2 = wave & 1, c0 = B * p;
+    const double *W = a.Wd + (size_t)p * B * B;
+    double wa[B / 4], rr[B / 4];
+#pragma unroll
+    for (int s = 0; s < (int)B / 4; ++s) {
+        const uint32_t k = 4 * s + lg;
+        wa[s] = W[(16 * h + li) * B + k];
+        rr[s] = p == J ? (k == 16 * j2 + li ? 1.0 : 0.0) : a.Rm[(size_t)(c0 + k) * F + B * J + 16 * j2 + li];
+    }
+    cv_d4 xm = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < (int)B / 4; ++s) xm = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[s], rr[s], xm, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a.Mi[(size_t)(c0 + 16 * h + 4 * v + lg) * F + B * J + 16 * j2 + li] = xm[v];
+}
+
+// (A0 + lam I)^-1 = M^T M: block (I, J), J <= I, is sum_{K >= I} M_KI^T M_KJ
+// (FP64 MFMA, wave w: tile (w >> 1, w & 1)); written to both triangles.
+__global__ __launch_bounds__(256) void k_cv_chol_inverse(const CvCholArgs a) {
+    if (*a.status < 0) return;
+    constexpr uint32_t B = kCholB;
+    const uint32_t F = a.F, NB = F / B, t = blockIdx.x, tid = threadIdx.x;
+    uint32_t I = (uint32_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const uint32_t J = t - I * (I + 1) / 2;
+    const uint32_t lane = tid & (kWave - 1), wave = tid / kWave, li = lane & 15, lg = lane >> 4;
+    const uint32_t h = wave >> 1, j2 = wave & 1;
+    const double *M = a.Mi;
+    cv_d4 acc = cv_d4{0.0, 0.0, 0.0, 0.0};
+    for (uint32_t K = I; K < NB; ++K) {
+        double x[B / 4], y[B / 4];
+#pragma unroll
+        for (int s = 0; s < (int)B / 4; ++s) {
+            const size_t row = (size_t)(B * K + 4 * s + lg) * F;
+            x[s] = M[row + B * I + 16 * h + li];
+            y[s] = M[row + B * J + 16 * j2 + li];
+        }
+#pragma unroll
+        for (int s = 0; s < (int)B / 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s], y[s], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const uint32_t u = B * I + 16 * h + 4 * v + lg, c = B * J + 16 * j2 + li;
+        a.Ai[(size_t)u * F + c] = acc[v];
+        if (I != J) a.Ai[(size_t)c * F + u] = acc[v];
+    }
+}
+
 // One correction of dimension i's factor from the right-hand side b of the
 // current residual (k_cv_pass): solves L L^T delta = b - lam w and adds
 // delta to w[., i, .] (and its sqrt(2k+1)-scaled copy ws), in one
-// workgroup, blocks of B unknowns:
+// workgroup.  After the many-workgroup factorisation (*status = 0) delta is
+// the product with the explicit inverse (wave w takes rows 2 w, 2 w + 1,
+// then 32 further, ...; lane c columns c, c + 64, ...; a fixed butterfly per
+// row).  After an escalation the factor is solved by substitution, blocks
+// of B unknowns:
 //   forward:  the block's unknowns by wave 0 (lane r holds row r of the
 //             diagonal block, staged through LDS), then every row below
 //             takes the block's contribution (32 lanes per row);
@@ -820,6 +1168,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_cv_factor(const CvFactorArgs
 struct CvSubstArgs {
     uint32_t F, R, K, d, i;
     double tol;
+    const double *Ai;       // (F, F) inverse, both triangles (when *status = 0)
+    const int *status;
     const double *A;        // factor (lower triangle)
     const double *rdiag;    // (F) 1 / L_uu
     const double *b;        // (F + 1) right-hand side of the residual, sum e^2
@@ -843,6 +1193,37 @@ __global__ __launch_bounds__(1024) void k_cv_subst(const CvSubstArgs a) {
         y[u] = gs[u] = a.b[u] - lam * a.w64[((size_t)r * a.d + a.i) * a.K + k];
     }
     const double *A = a.A;
+    if (*a.status == 0) {
+        __syncthreads();
+        constexpr uint32_t RB = 2, NC = kMaxF / kWave;
+        double gk[NC];
+#pragma unroll
+        for (uint32_t m = 0; m < NC; ++m) gk[m] = lane + kWave * m < F ? gs[lane + kWave * m] : 0.0;
+        for (uint32_t u0 = RB * wave; u0 < F; u0 += RB * (nt / kWave)) {
+            double s[RB];
+#pragma unroll
+            for (uint32_t q = 0; q < RB; ++q) {
+                const double *row = a.Ai + (size_t)(u0 + q < F ? u0 + q : 0) * F;
+                double x[NC];
+#pragma unroll
+                for (uint32_t m = 0; m < NC; ++m) x[m] = lane + kWave * m < F ? row[lane + kWave * m] : 0.0;
+                s[q] = 0.0;
+#pragma unroll
+                for (uint32_t m = 0; m < NC; ++m) s[q] = fma(x[m], gk[m], s[q]);
+            }
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1)
+#pragma unroll
+                for (uint32_t q = 0; q < RB; ++q) s[q] += __shfl_xor(s[q], o);
+            if (lane < RB && u0 + lane < F) {
+                double v = s[0];
+#pragma unroll
+                for (uint32_t q = 1; q < RB; ++q) v = lane == q ? s[q] : v;
+                y[u0 + lane] = v;
+            }
+        }
+        __syncthreads();
+    } else {
     // forward substitution L z = y
     for (uint32_t c0 = 0; c0 < F; c0 += B) {
         if (tid < B * B) D[(tid / B) * (B + 1) + tid % B] = tid % B <= tid / B ? A[(size_t)(c0 + tid / B) * F + c0 + tid % B] : 0.0;
@@ -918,6 +1299,7 @@ __global__ __launch_bounds__(1024) void k_cv_subst(const CvSubstArgs a) {
         __syncthreads();
         if (c0 == 0) break;
     }
+    }  // substitution
     // w += delta, and the convergence test
     double dn = 0.0, wn = 0.0;
     for (uint32_t u = tid; u < F; u += nt) {
@@ -1055,7 +1437,9 @@ void launch_loss(uint32_t n, uint32_t d, const float *z, const float *sw, const 
 }
 template <int R, int K>
 void launch_pass(const CvPassArgs &a, uint32_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_cv_pass<R, K>), dim3(blocks), dim3(kBlock), 0, s, a);
+    // targets yd alone (normal equations), or yf and the model w (training)
+    if (a.yd) hipLaunchKernelGGL((k_cv_pass<R, K, true>), dim3(blocks), dim3(kBlock), 0, s, a);
+    else if (a.yf && a.w) hipLaunchKernelGGL((k_cv_pass<R, K, false>), dim3(blocks), dim3(kBlock), 0, s, a);
 }
 // one task per workgroup of 4 waves when the triangle is one task, two
 // per workgroup of 8 waves otherwise (grid.y = tasks / 2)
@@ -1159,7 +1543,9 @@ struct CvTrainer {
     DeviceScratch s;
     float *z = nullptr, *sw = nullptr, *yw = nullptr, *partial = nullptr;
     double *rho = nullptr, *phi = nullptr, *rpart = nullptr, *ydev = nullptr, *ws = nullptr;
-    double *w64 = nullptr, *A0 = nullptr, *A = nullptr, *rdiag = nullptr, *b = nullptr, *lam = nullptr;
+    double *w64 = nullptr, *A0 = nullptr, *A = nullptr, *Aw = nullptr, *Wd = nullptr, *rdiag = nullptr;
+    double *Rm = nullptr, *Mi = nullptr, *Ai = nullptr;
+    double *b = nullptr, *lam = nullptr;
     double *loss_part = nullptr, *abs_part = nullptr;
     int *status = nullptr, *flag = nullptr;
     CvSyrkTask *tasks = nullptr;
@@ -1200,7 +1586,11 @@ struct CvTrainer {
                           (st = take((size_t)rsplits * (F + 1) * 8, rpart)) || (st = take((size_t)n * 8, ydev)))) ||
             (st = take((size_t)R * d * K * 8, ws)) || (st = take((size_t)R * d * K * 8, w64)) ||
             (st = take(tk.size() * sizeof(CvSyrkTask), tasks)) || (st = take((size_t)F * F * 8, A0)) ||
-            (st = take((size_t)F * F * 8, A)) || (st = take((size_t)F * 8, rdiag)) || (st = take((size_t)(F + 1) * 8, b)) ||
+            (st = take((size_t)F * F * 8, A)) || (st = take((size_t)F * F * 8, Aw)) ||
+            (st = take((size_t)F * F * 8, Rm)) || (st = take((size_t)F * F * 8, Mi)) ||
+            (st = take((size_t)F * F * 8, Ai)) ||
+            (st = take((size_t)F * kCholB * 8, Wd)) || (st = take((size_t)F * 8, rdiag)) ||
+            (st = take((size_t)(F + 1) * 8, b)) ||
             (st = take(8, lam)) ||
             (st = take(8, status)) || (st = take(8, flag)) || (st = take((size_t)rblocks * 16, loss_part)) ||
             (st = take((size_t)rblocks * 8, abs_part)))
@@ -1239,9 +1629,9 @@ struct CvTrainer {
                            splits, nslots, R, K, A0);
     }
 
-    // b = sum_j rho_j phi_j^T e_j with e = y - A w (the current factor of
-    // dimension i; e = y when use_w is false), y = yd, or yf * y_scale when
-    // yd is null
+    // b = sum_j rho_j phi_j^T e_j with e = yf * y_scale - A w (use_w: the
+    // current factor of dimension i, yd null) or e = yd (the normal
+    // equations' own right-hand side: use_w false, yd set)
     void rhs(uint32_t i, bool use_w, const float *yf, double y_scale, const double *yd, const int *fl,
              hipStream_t st) {
         const CvPassArgs pa{n, d, i, rsplits, rho, phi, yf, y_scale, yd, use_w ? w64 : nullptr, fl, rpart};
@@ -1250,16 +1640,26 @@ struct CvTrainer {
                            st, (const double *)rpart, rsplits, F + 1, fl, b);
     }
 
-    // L L^T = A0 + lam I; clears the convergence flag
+    // L L^T = A0 + lam I (one launch per panel of 32 columns, then the
+    // escalation kernel, which returns at once unless a pivot failed);
+    // clears the convergence flag
     void factor(double ridge, hipStream_t st) {
-        const CvFactorArgs fa{F, ridge, A0, A, rdiag, lam, status, flag};
+        const CvCholArgs ca{F, ridge, A0, Aw, A, Wd, rdiag, lam, status, flag, Rm, Mi, Ai};
+        hipLaunchKernelGGL(k_cv_chol_diag0, dim3(1), dim3(kWave), 0, st, ca);
+        for (uint32_t p = 0; p + 1 < NB; ++p) {
+            const uint32_t m = NB - 1 - p;
+            hipLaunchKernelGGL(k_cv_chol_step, dim3(m * (m + 1) / 2 + m * (p + 1)), dim3(256), 0, st, ca, p);
+        }
+        hipLaunchKernelGGL(k_cv_chol_last, dim3(NB), dim3(256), 0, st, ca);
+        hipLaunchKernelGGL(k_cv_chol_inverse, dim3(NB * (NB + 1) / 2), dim3(256), 0, st, ca);
+        const CvFactorArgs fa{F, ridge, A0, A, rdiag, lam, status, flag, 1};
         if (F <= 512) hipLaunchKernelGGL(k_cv_factor<32>, dim3(1), dim3(kFactorThreads), 0, st, fa);
         else hipLaunchKernelGGL(k_cv_factor<16>, dim3(1), dim3(kFactorThreads), 0, st, fa);
     }
 
     // w[., i, .] += (L L^T)^-1 (b - lam w[., i, .]); tol as in k_cv_subst
     void subst(uint32_t dd, uint32_t i, double tol, hipStream_t st) {
-        const CvSubstArgs sa{F, R, K, dd, i, tol, A, rdiag, b, lam, w64, ws, flag};
+        const CvSubstArgs sa{F, R, K, dd, i, tol, Ai, status, A, rdiag, b, lam, w64, ws, flag};
         if (F <= 512) hipLaunchKernelGGL(k_cv_subst<32>, dim3(1), dim3(1024), 0, st, sa);
         else hipLaunchKernelGGL(k_cv_subst<16>, dim3(1), dim3(1024), 0, st, sa);
     }
