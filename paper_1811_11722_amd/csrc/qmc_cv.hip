@@ -1150,10 +1150,9 @@ __global__ __launch_bounds__(256) void k_cv_chol_inverse(const CvCholArgs a) {
 // current residual (k_cv_pass): solves L L^T delta = b - lam w and adds
 // delta to w[., i, .] (and its sqrt(2k+1)-scaled copy ws), in one
 // workgroup.  After the many-workgroup factorisation (*status = 0) delta is
-// the product with the explicit inverse (wave w takes rows 2 w, 2 w + 1,
-// then 32 further, ...; lane c columns c, c + 64, ...; a fixed butterfly per
-// row).  After an escalation the factor is solved by substitution, blocks
-// of B unknowns:
+// the product with the explicit inverse, which k_cv_gemv has left in dl.
+// After an escalation the factor is solved by substitution, blocks of B
+// unknowns:
 //   forward:  the block's unknowns by wave 0 (lane r holds row r of the
 //             diagonal block, staged through LDS), then every row below
 //             takes the block's contribution (32 lanes per row);
@@ -1169,6 +1168,7 @@ struct CvSubstArgs {
     uint32_t F, R, K, d, i;
     double tol;
     const double *Ai;       // (F, F) inverse, both triangles (when *status = 0)
+    double *dl;             // (F) the inverse times the right-hand side
     const int *status;
     const double *A;        // factor (lower triangle)
     const double *rdiag;    // (F) 1 / L_uu
@@ -1177,6 +1177,48 @@ struct CvSubstArgs {
     double *w64, *ws;       // (R, d, K)
     int *flag;
 };
+
+// dl = (A0 + lam I)^-1 (b - lam w[., i, .]) after the many-workgroup
+// factorisation: workgroup t takes rows 16 t .. 16 t + 15 (wave w four of
+// them, lane c the columns c, c + 64, ..., c + 64 (NC - 1); a fixed
+// butterfly per row).  Returns at once after an escalation (*status != 0)
+// or once the step has converged (*flag).
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_cv_gemv(const CvSubstArgs a) {
+    if (*a.flag || *a.status != 0) return;
+    const uint32_t F = a.F, tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    __shared__ double g[kMaxF];
+    const double lam = *a.lam;
+    for (uint32_t u = tid; u < F; u += kBlock) {
+        const uint32_t r = u / a.K, k = u - r * a.K;
+        g[u] = a.b[u] - lam * a.w64[((size_t)r * a.d + a.i) * a.K + k];
+    }
+    __syncthreads();
+    double gk[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) gk[m] = lane + kWave * m < F ? g[lane + kWave * m] : 0.0;
+    const uint32_t u0 = 16 * blockIdx.x + 4 * wave;  // F is a multiple of 16
+    double x[4][NC];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            const uint32_t c = lane + kWave * m;
+            x[q][m] = a.Ai[(size_t)(u0 + q) * F + (c < F ? c : 0)];
+        }
+    double sq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sq[q] = 0.0;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) sq[q] = fma(x[q][m], gk[m], sq[q]);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sq[q] += __shfl_xor(sq[q], o);
+    if (lane < 4) a.dl[u0 + lane] = lane == 0 ? sq[0] : lane == 1 ? sq[1] : lane == 2 ? sq[2] : sq[3];
+}
 
 template <int B>
 __global__ __launch_bounds__(1024) void k_cv_subst(const CvSubstArgs a) {
@@ -1194,34 +1236,7 @@ __global__ __launch_bounds__(1024) void k_cv_subst(const CvSubstArgs a) {
     }
     const double *A = a.A;
     if (*a.status == 0) {
-        __syncthreads();
-        constexpr uint32_t RB = 2, NC = kMaxF / kWave;
-        double gk[NC];
-#pragma unroll
-        for (uint32_t m = 0; m < NC; ++m) gk[m] = lane + kWave * m < F ? gs[lane + kWave * m] : 0.0;
-        for (uint32_t u0 = RB * wave; u0 < F; u0 += RB * (nt / kWave)) {
-            double s[RB];
-#pragma unroll
-            for (uint32_t q = 0; q < RB; ++q) {
-                const double *row = a.Ai + (size_t)(u0 + q < F ? u0 + q : 0) * F;
-                double x[NC];
-#pragma unroll
-                for (uint32_t m = 0; m < NC; ++m) x[m] = lane + kWave * m < F ? row[lane + kWave * m] : 0.0;
-                s[q] = 0.0;
-#pragma unroll
-                for (uint32_t m = 0; m < NC; ++m) s[q] = fma(x[m], gk[m], s[q]);
-            }
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1)
-#pragma unroll
-                for (uint32_t q = 0; q < RB; ++q) s[q] += __shfl_xor(s[q], o);
-            if (lane < RB && u0 + lane < F) {
-                double v = s[0];
-#pragma unroll
-                for (uint32_t q = 1; q < RB; ++q) v = lane == q ? s[q] : v;
-                y[u0 + lane] = v;
-            }
-        }
+        for (uint32_t u = tid; u < F; u += nt) y[u] = a.dl[u];
         __syncthreads();
     } else {
     // forward substitution L z = y
@@ -1527,7 +1542,7 @@ double splitmix_uniform(uint64_t &s) {
 }
 
 // workgroups of a right-hand side pass: about 8 per CU, at least 256 points each
-uint32_t rhs_splits(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>(2048, (n + 255) / 256)); }
+uint32_t rhs_splits(uint32_t n) { return std::max<uint32_t>(1, std::min<uint32_t>(1024, (n + 255) / 256)); }
 
 // a correction whose objective decrease is below this fraction of the
 // step's objective ends the step's passes
@@ -1544,7 +1559,7 @@ struct CvTrainer {
     float *z = nullptr, *sw = nullptr, *yw = nullptr, *partial = nullptr;
     double *rho = nullptr, *phi = nullptr, *rpart = nullptr, *ydev = nullptr, *ws = nullptr;
     double *w64 = nullptr, *A0 = nullptr, *A = nullptr, *Aw = nullptr, *Wd = nullptr, *rdiag = nullptr;
-    double *Rm = nullptr, *Mi = nullptr, *Ai = nullptr;
+    double *Rm = nullptr, *Mi = nullptr, *Ai = nullptr, *dl = nullptr;
     double *b = nullptr, *lam = nullptr;
     double *loss_part = nullptr, *abs_part = nullptr;
     int *status = nullptr, *flag = nullptr;
@@ -1588,7 +1603,7 @@ struct CvTrainer {
             (st = take(tk.size() * sizeof(CvSyrkTask), tasks)) || (st = take((size_t)F * F * 8, A0)) ||
             (st = take((size_t)F * F * 8, A)) || (st = take((size_t)F * F * 8, Aw)) ||
             (st = take((size_t)F * F * 8, Rm)) || (st = take((size_t)F * F * 8, Mi)) ||
-            (st = take((size_t)F * F * 8, Ai)) ||
+            (st = take((size_t)F * F * 8, Ai)) || (st = take((size_t)F * 8, dl)) ||
             (st = take((size_t)F * kCholB * 8, Wd)) || (st = take((size_t)F * 8, rdiag)) ||
             (st = take((size_t)(F + 1) * 8, b)) ||
             (st = take(8, lam)) ||
@@ -1659,7 +1674,17 @@ struct CvTrainer {
 
     // w[., i, .] += (L L^T)^-1 (b - lam w[., i, .]); tol as in k_cv_subst
     void subst(uint32_t dd, uint32_t i, double tol, hipStream_t st) {
-        const CvSubstArgs sa{F, R, K, dd, i, tol, Ai, status, A, rdiag, b, lam, w64, ws, flag};
+        const CvSubstArgs sa{F, R, K, dd, i, tol, Ai, dl, status, A, rdiag, b, lam, w64, ws, flag};
+        const dim3 gg(F / 16), gb(kBlock);
+        switch ((F + kWave - 1) / kWave) {  // columns per lane
+            case 1: hipLaunchKernelGGL(k_cv_gemv<1>, gg, gb, 0, st, sa); break;
+            case 2: hipLaunchKernelGGL(k_cv_gemv<2>, gg, gb, 0, st, sa); break;
+            case 3: hipLaunchKernelGGL(k_cv_gemv<3>, gg, gb, 0, st, sa); break;
+            case 4: hipLaunchKernelGGL(k_cv_gemv<4>, gg, gb, 0, st, sa); break;
+            case 6: hipLaunchKernelGGL(k_cv_gemv<6>, gg, gb, 0, st, sa); break;
+            case 8: hipLaunchKernelGGL(k_cv_gemv<8>, gg, gb, 0, st, sa); break;
+            default: hipLaunchKernelGGL(k_cv_gemv<12>, gg, gb, 0, st, sa); break;
+        }
         if (F <= 512) hipLaunchKernelGGL(k_cv_subst<32>, dim3(1), dim3(1024), 0, st, sa);
         else hipLaunchKernelGGL(k_cv_subst<16>, dim3(1), dim3(1024), 0, st, sa);
     }
