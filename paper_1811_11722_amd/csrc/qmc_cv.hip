@@ -31,10 +31,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------- kernels
 // Design-matrix factors of dimension i in FP64:
 //   rho_j[r] = sw_j prod_{i' != i} h_{r,i'}(z_{j,i'}),  phi_j[k] = P~_k(z_{j,i}),
-// h_{r,i'}(z) = sum_k ws[r, i', k] P_k(z) on v_mfma_f64_16x16x4f64, 16 points
-// per wave at a time: A = the Legendre values (lane l: point l % 16, degree
-// 4 s + l / 16, each lane running the recurrence for its point), B = the
-// weights (fragments staged in LDS once per workgroup).  The product over
+// h_{r,i'}(z) = sum_k ws[r, i', k] P_k(z) on v_mfma_f64_16x16x4f64: A = the
+// Legendre values (lane l: point l % 16, degree 4 s + l / 16), B = the
+// weights.  Up to 32 ranks a wave takes 64 points at a time, each lane runs
+// the recurrence of one point and the values reach the A layout through
+// LDS (four 16-point blocks); 64 ranks take 16 points at a time, each lane
+// running the recurrence of its A-operand point, with the weight fragments
+// staged in LDS once per workgroup.  The coordinates of a point are all
+// loaded before the first is used.  The product over
 // dimensions is taken elementwise on the output tiles (element v of lane l:
 // point 4 v + l / 16, rank 16 t + l % 16), which are also the layout of the
 // 128-byte rows of rho the lanes store.
@@ -50,55 +54,153 @@ constexpr uint32_t kCvMaxD = 12;
 
 template <int R, int K>
 __global__ __launch_bounds__(kBlock) void k_cv_rho(const CvRhoArgs a) {
-    constexpr int RT = (R + 15) / 16, KS = (K + 3) / 4;
-    __shared__ double wf[kCvMaxD * RT * KS * kWave];  // ((i RT + t) KS + s) 64 + lane
+    constexpr int RT = (R + 15) / 16, KS = (K + 3) / 4, NP = 4 * KS;
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t li = lane & 15, lg = lane >> 4;
-    for (uint32_t f = tid; f < a.d * RT * KS * kWave; f += kBlock) {
-        const uint32_t fl = f % kWave, idx = f / kWave, s = idx % KS, t = (idx / KS) % RT, i = idx / (KS * RT);
-        const uint32_t r = 16 * t + fl % 16, k = 4 * s + fl / 16;
-        wf[f] = (r < (uint32_t)R && k < (uint32_t)K) ? a.ws[((size_t)r * a.d + i) * K + k] : 0.0;
-    }
-    __syncthreads();
-    const bool s1 = lg == 1, s2 = lg == 2, s3 = lg == 3;
-    for (uint32_t p0 = (blockIdx.x * 4 + wave) * 16; p0 < a.n; p0 += gridDim.x * 64) {
-        cv_d4 prod[RT];
+    if constexpr (R <= 32) {
+        // 64 points per wave at a time: lane l runs the recurrence of point
+        // p0 + l only, and the values reach the operand layout through the
+        // wave's own LDS rows (a wave's LDS accesses complete in order);
+        // the weight fragments come from memory, one dimension ahead
+        constexpr uint32_t LP = NP + 1;  // padded row of a point's values
+        __shared__ double lv[4][kWave * LP];
+        double *lw = lv[wave];
+        auto weights = [&](uint32_t i, double (&wb)[RT][KS]) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) prod[t] = cv_d4{1.0, 1.0, 1.0, 1.0};
-        const uint32_t pa = p0 + li;  // this lane's point in the A operand
-        for (uint32_t i = 0; i < a.d; ++i) {
-            const double zz = pa < a.n ? (double)a.z[(size_t)pa * a.d + i] : 0.5;
-            double pk[4 * KS];
-            legendre_raw<4 * KS, double>(zz, pk);
-            double fa[KS];
-#pragma unroll
-            for (int s = 0; s < KS; ++s) fa[s] = cv_pick4(pk[4 * s], pk[4 * s + 1], pk[4 * s + 2], pk[4 * s + 3], s1, s2, s3);
-            if (i == a.i) {
+            for (int t = 0; t < RT; ++t)
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
-                    const uint32_t k = 4 * s + lg;
-                    if (pa < a.n && k < (uint32_t)K) a.phi[(size_t)pa * K + k] = fa[s] * sqrt((double)(2 * k + 1));
+                    const uint32_t r = 16 * t + li, k = 4 * s + lg;
+                    wb[t][s] = (r < (uint32_t)R && k < (uint32_t)K)
+                                   ? a.ws[((size_t)r * a.d + i) * K + k] : 0.0;
                 }
-                continue;
+        };
+        for (uint32_t p0 = (blockIdx.x * 4 + wave) * 64; p0 < a.n; p0 += gridDim.x * 256) {
+            const uint32_t pm = p0 + lane, pc = pm < a.n ? pm : a.n - 1;
+            float zr[kCvMaxD];
+#pragma unroll
+            for (uint32_t i = 0; i < kCvMaxD; ++i) zr[i] = a.z[(size_t)pc * a.d + (i < a.d ? i : a.d - 1)];
+            cv_d4 prod[4][RT];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int t = 0; t < RT; ++t) prod[c][t] = cv_d4{1.0, 1.0, 1.0, 1.0};
+            double wb[RT][KS];
+            weights(a.i == 0 ? (a.d > 1 ? 1 : 0) : 0, wb);
+#pragma unroll 1
+            for (uint32_t i = 0; i < a.d; ++i) {
+                double pk[NP];
+                legendre_raw<NP, double>(pm < a.n ? (double)zr[i] : 0.5, pk);
+                if (i == a.i) {
+                    if (pm < a.n) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k) a.phi[(size_t)pm * K + k] = pk[k] * sqrt((double)(2 * k + 1));
+                    }
+                    continue;
+                }
+                // the next dimension's weights while this one is computed
+                uint32_t in = i + 1 == a.i ? i + 2 : i + 1;
+                in = in < a.d ? in : i;
+                double wn[RT][KS];
+                weights(in, wn);
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int k = 0; k < NP; ++k) lw[lane * LP + k] = pk[k];
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double fa[KS];
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) fa[s] = lw[(16 * c + li) * LP + 4 * s + lg];
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        cv_d4 h = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int s = 0; s < KS; ++s) h = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s], wb[t][s], h, 0, 0, 0);
+                        prod[c][t] *= h;
+                    }
+                    // one 16-point block at a time: fewer registers live
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) wb[t][s] = wn[t][s];
             }
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                cv_d4 h = cv_d4{0.0, 0.0, 0.0, 0.0};
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int s = 0; s < KS; ++s)
-                    h = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s], wf[((i * RT + t) * KS + s) * kWave + lane], h, 0, 0, 0);
-                prod[t] *= h;
-            }
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t p = p0 + 16 * c + 4 * v + lg;
+                    if (p < a.n) {
+                        const double sw = a.sw[p];
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            const uint32_t r = 16 * t + li;
+                            if (r < (uint32_t)R) a.rho[(size_t)p * R + r] = sw * prod[c][t][v];
+                        }
+                    }
+                }
         }
+    } else {
+        __shared__ double wf[kCvMaxD * RT * KS * kWave];  // ((i RT + t) KS + s) 64 + lane
+        for (uint32_t f = tid; f < a.d * RT * KS * kWave; f += kBlock) {
+            const uint32_t fl = f % kWave, idx = f / kWave, s = idx % KS, t = (idx / KS) % RT, i = idx / (KS * RT);
+            const uint32_t r = 16 * t + fl % 16, k = 4 * s + fl / 16;
+            wf[f] = (r < (uint32_t)R && k < (uint32_t)K) ? a.ws[((size_t)r * a.d + i) * K + k] : 0.0;
+        }
+        __syncthreads();
+        const bool s1 = lg == 1, s2 = lg == 2, s3 = lg == 3;
+        for (uint32_t p0 = (blockIdx.x * 4 + wave) * 16; p0 < a.n; p0 += gridDim.x * 64) {
+            cv_d4 prod[RT];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const uint32_t p = p0 + 4 * v + lg;
-            if (p < a.n) {
-                const double sw = a.sw[p];
+            for (int t = 0; t < RT; ++t) prod[t] = cv_d4{1.0, 1.0, 1.0, 1.0};
+            const uint32_t pa = p0 + li;  // this lane's point in the A operand
+            // the point's coordinates, all loaded before any is used (branch-free:
+            // index clamped, so that the chunk waits on memory once)
+            const uint32_t pc = pa < a.n ? pa : a.n - 1;
+            float zr[kCvMaxD];
+#pragma unroll
+            for (uint32_t i = 0; i < kCvMaxD; ++i) zr[i] = a.z[(size_t)pc * a.d + (i < a.d ? i : a.d - 1)];
+#pragma unroll
+            for (uint32_t i = 0; i < kCvMaxD; ++i) {
+                if (i >= a.d) break;
+                const double zz = pa < a.n ? (double)zr[i] : 0.5;
+                double pk[4 * KS];
+                legendre_raw<4 * KS, double>(zz, pk);
+                double fa[KS];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) fa[s] = cv_pick4(pk[4 * s], pk[4 * s + 1], pk[4 * s + 2], pk[4 * s + 3], s1, s2, s3);
+                if (i == a.i) {
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) {
+                        const uint32_t k = 4 * s + lg;
+                        if (pa < a.n && k < (uint32_t)K) a.phi[(size_t)pa * K + k] = fa[s] * sqrt((double)(2 * k + 1));
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int t = 0; t < RT; ++t) {
-                    const uint32_t r = 16 * t + li;
-                    if (r < (uint32_t)R) a.rho[(size_t)p * R + r] = sw * prod[t][v];
+                    cv_d4 h = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < KS; ++s)
+                        h = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s], wf[((i * RT + t) * KS + s) * kWave + lane], h, 0, 0, 0);
+                    prod[t] *= h;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t p = p0 + 4 * v + lg;
+                if (p < a.n) {
+                    const double sw = a.sw[p];
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        const uint32_t r = 16 * t + li;
+                        if (r < (uint32_t)R) a.rho[(size_t)p * R + r] = sw * prod[t][v];
+                    }
                 }
             }
         }
