@@ -12,8 +12,9 @@ the oracle's FP64 / long-double computation of the same quantity:
   matrix, FP64 for the right-hand side) x the sum of absolute products, at a
   small size in full and at the training size (n = 1048573, d = 8, R = 32,
   K = 12) on sampled entries;
-- the FP64 Cholesky solve: the same matrix on both sides, bound from the
-  condition number and backward stability;
+- the FP64 solve (Cholesky on the oracle side, the explicit inverse from
+  the blocked Cholesky on the GPU): the same matrix on both sides, bound
+  from the condition number and the methods' stability;
 - one whole step with refinement: the exact ridge minimum of the oracle's
   FP64 step and the GPU step's objective (property check, printed).
 Shapes: workload 4 (d = 8, R = 32, K = 12, F = 384), workload 5's model
@@ -219,8 +220,12 @@ def test_solve_matches_oracle(Q, d, R, K, n):
     ev = np.linalg.eigvalsh(G + lamo * np.eye(F))
     kappa = ev[-1] / ev[0]
     rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
-    # both factorisations are backward stable with |dA| <= ~3F u |L||L^T|:
-    # the two solutions differ by at most ~2 kappa 3F u, doubled
+    # the oracle's Cholesky solve is backward stable (|dA| <= ~3F u |L||L^T|),
+    # so it lies within ~3F kappa u of the exact solution; the GPU multiplies
+    # by the explicit inverse M^T M (M = L^-1 by block forward substitution
+    # with the inverted diagonal blocks), whose forward error is of the same
+    # order (each of M's columns a substitution, then one product): the two
+    # differ by at most ~2 kappa 3F u, doubled
     bound = 12 * F * kappa * U64
     print(f"  kappa {kappa:.3g}: |x - x_oracle| / |x| = {rel:.3g} (bound {bound:.3g})")
     assert rel <= bound
