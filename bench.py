@@ -13,7 +13,8 @@ coefficients), baker's transform, n = 16777213 (largest prime < 2^24),
 m = 32 shifts; synthetic seeded inputs.  Prints one JSON line, which also
 carries the metric's other parts, each on its own workload:
 - product_peak_batch512: 512 Genz product-peak instances (d = 4,
-  Korobov weight 3, n = 131071, m = 16) in one launch;
+  Korobov weight 3, n = 131071, m = 16) in one launch, and the latency of
+  one instance (graph replay and plain call, median of 1000);
 - sector_complex_d10: the complex sector (d = 10, U 20 / F 60 monomials,
   mixed-sign F - 0.01i, baker) at n = 1073741789, m = 32;
 - time_to_error: wall time to a relative error of 1e-7 on the d = 8 sector,
@@ -130,6 +131,10 @@ def leg_product_peak_batch(qmc, drivers):
            "seconds": r["seconds"], "evals_per_s": r["evals_per_s"], "device_ms": r["device_seconds"] * 1e3,
            "device_evals_per_s": r["evals"] / r["device_seconds"]}
     out.update(roofline_fields("product_peak", r["evals"], r["device_seconds"]))
+    # one instance: latency of a graph replay and of a plain call, median of 1000
+    lat = drivers.product_peak_latency(reps=1000)
+    out["single_instance"] = {k: lat[k] for k in ("workload", "evals", "reps", "graph_replay", "batch_no_graph",
+                                                   "integrate")}
     return out
 
 

@@ -281,6 +281,16 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
    comparison mode. */
 qmc_status qmc_batch_per_shift(uint32_t count, const qmc_plan_t *plans, double *const *per_shift);
 
+/* Counters of the batch machinery since the library was loaded (all
+   devices): out[0] batch contexts built (buffers, uploads and, with
+   use_graph, a graph captured) for the table-driven schedules, out[1] their
+   graph launches, out[2] specialised-schedule graphs captured, out[3] their
+   graph launches.  A repeated qmc_integrate_batch with the same plans,
+   parameters and options reuses its context and graph (until eight newer
+   contexts displace it), so only the launch counts grow.  out: 4 uint64
+   values, caller-owned.  Errors: EINVAL for a null out. */
+qmc_status qmc_batch_stats(uint64_t *out);
+
 /* Autotuner of the batched launch (the table-driven schedules of
    qmc_integrate_batch): times tile_points in {4096, 8192, 16384, 32768} with
    the one-workgroup-per-tile and the persistent schedule, each captured into

@@ -34,6 +34,8 @@ struct BatchCtx {
     std::vector<std::vector<double>> blobs;
     int key_family = 0;
     uint32_t np = 1, T = 4, tile_points = 0;
+    uint32_t requested_tile_points = 0;  // the caller's option (0 = default): part of the context's key
+    qmc_launch launch0{0, 0};            // the first plan's launch shape when built: part of the key
     int persistent = 0;  // 1: persistent workgroups, 0: one workgroup per tile
     int device = 0;
     hipStream_t stream = nullptr;
@@ -70,6 +72,9 @@ struct BatchCtx {
 };
 
 std::mutex g_batch_mu;
+// qmc_batch_stats: table-driven contexts built, their graph launches,
+// specialised graphs captured, their launches (under g_batch_mu)
+uint64_t g_stats[4] = {0, 0, 0, 0};
 std::vector<std::unique_ptr<BatchCtx>> g_batch;
 constexpr size_t kMaxContexts = 8;
 
@@ -345,13 +350,18 @@ qmc_status run_graph(BatchCtx &c, bool use_graph) {
         if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     }
     e = hipGraphLaunch(c.exec, c.stream);
+    if (e == hipSuccess) ++g_stats[1];
     return e == hipSuccess ? QMC_OK : hip_fail(e, "graph launch");
 }
 
+// A context is reused for the same plans, parameter blobs, requested tile
+// size (which also decides between the uniform and the tiled layout),
+// schedule and first plan's launch shape (the uniform launch takes it).
 bool same_ctx(const BatchCtx &c, uint32_t count, const qmc_plan_t *plans, const std::vector<Packed> &pk,
-              uint32_t tile_points, int persistent) {
-    if (c.plans.size() != count || c.tile_points != tile_points || c.key_family != pk[0].key_family ||
-        c.persistent != persistent)
+              uint32_t requested_tile_points, int persistent) {
+    if (c.plans.size() != count || c.requested_tile_points != requested_tile_points ||
+        c.key_family != pk[0].key_family || c.persistent != persistent ||
+        c.launch0.shift_tile != plans[0]->launch.shift_tile || c.launch0.blocks_per_cu != plans[0]->launch.blocks_per_cu)
         return false;
     for (uint32_t i = 0; i < count; ++i)
         if (c.plans[i] != plans[i] || c.blobs[i] != pk[i].blob) return false;
@@ -536,6 +546,7 @@ static qmc_status batch_specialised(uint32_t count, const qmc_plan_t *plans, con
         for (uint32_t i = 0; i < count; ++i) fresh->bufs.push_back(spec_buffers(plans[i]));
         qmc_status st = spec_capture(*fresh, pk);
         if (st) return st;
+        ++g_stats[2];
         if (g_spec.size() >= kMaxContexts) g_spec.erase(g_spec.begin());
         g_spec.push_back(std::move(fresh));
         c = g_spec.back().get();
@@ -543,6 +554,7 @@ static qmc_status batch_specialised(uint32_t count, const qmc_plan_t *plans, con
     // the blobs went up on each plan's own stream in spec_prepare, which
     // waited for them
     hipError_t e = hipGraphLaunch(c->exec, c->stream);
+    if (e == hipSuccess) ++g_stats[3];
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "specialised batch graph");
     for (uint32_t i = 0; i < count; ++i) {
@@ -599,7 +611,7 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
     std::lock_guard<std::mutex> lock(g_batch_mu);
     BatchCtx *c = nullptr;
     for (auto &x : g_batch)
-        if (same_ctx(*x, count, plans, pk, tile_points, persistent)) c = x.get();
+        if (same_ctx(*x, count, plans, pk, o.tile_points, persistent)) c = x.get();
     if (!c) {
         auto fresh = std::make_unique<BatchCtx>();
         bool uniform = o.tile_points == 0 && count * ((plans[0]->m + 7) / 8) <= 65535;
@@ -609,6 +621,9 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
                                 : build_ctx(*fresh, count, plans, pk, tile_points);
         if (st) return st;
         fresh->persistent = persistent;
+        fresh->requested_tile_points = o.tile_points;
+        fresh->launch0 = plans[0]->launch;
+        ++g_stats[0];
         if (g_batch.size() >= kMaxContexts) g_batch.erase(g_batch.begin());
         g_batch.push_back(std::move(fresh));
         c = g_batch.back().get();
@@ -679,6 +694,13 @@ qmc_status qmc_integrate_batch(uint32_t count, const qmc_plan_t *plans, qmc_fami
         }
     }
     if (any_nonfinite) return fail(QMC_ENONFINITE, "a per-shift sum of some plan is not finite");
+    return QMC_OK;
+}
+
+qmc_status qmc_batch_stats(uint64_t *out) {
+    if (!out) return fail(QMC_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    std::copy(g_stats, g_stats + 4, out);
     return QMC_OK;
 }
 

@@ -7,6 +7,7 @@ and times calls.
 
     python -m paper_1811_11722_amd.drivers sector_batch [--count 2000] [--out rows.jsonl]
     python -m paper_1811_11722_amd.drivers product_peak_batch [--count 512]
+    python -m paper_1811_11722_amd.drivers product_peak_latency [--reps 1000]
     python -m paper_1811_11722_amd.drivers time_to_error
     python -m paper_1811_11722_amd.drivers convergence [--out rows.jsonl]
     python -m paper_1811_11722_amd.drivers cv_estimate
@@ -445,6 +446,48 @@ def product_peak_batch(count: int = 512, n: int = 131071, m: int = 16, d: int = 
     return {"instances": count, "n": n, "m": m, "d": d, "evals": evals, "seconds": t,
             "evals_per_s": evals / t, "device_seconds": kms / max(launches, 1) / 1e3, "generator_a": a,
             "shift_tile": shift_tile, "blocks_per_cu": blocks_per_cu}
+
+
+def product_peak_latency(reps: int = 1000, n: int = 131071, m: int = 16, d: int = 4,
+                         seed: int = synth.SEED_BASE + 1) -> dict:
+    """Latency of one Genz product-peak estimate (config 1, one instance,
+    about 2 million evaluations): the estimate as a graph-replayed batch of
+    one (captured by the first call), as the same batch launched without the
+    graph, and as a plain qmc_integrate call; the wall time of each of
+    `reps` calls (host packing, launch or replay, result copy and
+    synchronisation included; median and 10th / 90th percentiles), and the
+    device time of the replayed graph (HIP events on the batch stream, mean
+    over the calls)."""
+    w = synth.product_peak_workload(n=n, m=m, d=d, seed=seed)
+    a, _, _ = qmc.korobov_search(n, d, w.candidates)
+    plan = qmc.Plan(d, n, qmc.korobov_vector(n, d, a), w.shifts, "korobov", 3)
+    params = qmc.Params("genz_product_peak", d, a=w.genz_a, u=w.genz_u)
+
+    def wall(fn):
+        fn()  # warm-up: uploads, graph capture
+        ts = np.empty(reps)
+        for r in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts[r] = time.perf_counter() - t0
+        return {"median_us": float(np.median(ts)) * 1e6, "p10_us": float(np.percentile(ts, 10)) * 1e6,
+                "p90_us": float(np.percentile(ts, 90)) * 1e6}
+
+    graph = wall(lambda: qmc.integrate_batch([plan], [params]))
+    plan.set_timing(True)
+    plan.kernel_time(reset=True)
+    for _ in range(reps):
+        qmc.integrate_batch([plan], [params])
+    kms, launches = plan.kernel_time()
+    plan.set_timing(False)
+    graph["device_us"] = kms / max(launches, 1) * 1e3
+    batch_direct = wall(lambda: qmc.integrate_batch([plan], [params], use_graph=False))
+    direct = wall(lambda: plan.integrate(params))
+    res, _ = plan.integrate(params)
+    plan.close()
+    return {"workload": f"genz_product_peak_d{d}_korobov3_n{n}_m{m}", "evals": n * m, "reps": reps,
+            "graph_replay": graph, "batch_no_graph": batch_direct, "integrate": direct, "mean": res.mean_re,
+            "err": res.err_re}
 
 
 def _sync():
@@ -889,7 +932,8 @@ def deform(d: int = 6, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "time_to_error", "convergence",
+    ap.add_argument("what", choices=["sector_batch", "product_peak_batch", "product_peak_latency",
+                                     "time_to_error", "convergence",
                                      "cv_estimate", "fig3", "allocation_compare", "deform", "transforms",
                                      "lattices", "sector_batch_specialised", "sector_sum", "cv_train"])
     ap.add_argument("--kmax", type=int, default=0)
@@ -901,7 +945,8 @@ def main(argv=None):
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--workers", type=int, default=0, help="compile processes (sector_batch_specialised)")
     ap.add_argument("--workload", type=int, default=4, help="4 or 5 (cv_train)")
-    ap.add_argument("--reps", type=int, default=2, help="training runs (cv_train)")
+    ap.add_argument("--reps", type=int, default=2,
+                    help="training runs (cv_train); timed calls (product_peak_latency, default 1000)")
     ap.add_argument("--sweeps", type=int, default=12, help="ALS sweeps at most (cv_train)")
     ap.add_argument("--out", default=None, help="JSON-lines file of results; a rerun resumes from it "
                                                 "(sector_batch, convergence)")
@@ -918,6 +963,8 @@ def main(argv=None):
         out = product_peak_batch(count=args.count or 512,
                                  tile_points=0 if args.tile_points < 0 else args.tile_points,
                                  shift_tile=args.shift_tile, blocks_per_cu=args.blocks_per_cu)
+    elif args.what == "product_peak_latency":
+        out = product_peak_latency(reps=args.reps if args.reps > 2 else 1000)
     elif args.what == "cv_estimate":
         out = cv_estimate()
     elif args.what == "cv_train":

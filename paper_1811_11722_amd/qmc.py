@@ -106,6 +106,7 @@ SIGNATURES = {
     "qmc_batch_autotune": (C.c_int, [_u32, _vp, C.c_int, _vp, _vp, _vp]),
     "qmc_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "qmc_batch_per_shift": (C.c_int, [_u32, _vp, _vp]),
+    "qmc_batch_stats": (C.c_int, [_vp]),
     "qmc_math_eval": (C.c_int, [_i32, _u64, _vp, _vp]),
     "qmc_cv_train": (C.c_int, [_vp, C.c_int, _vp, _u32, _u32, _vp, _vp, _vp, _vp]),
     "qmc_cv_integral": (C.c_int, [_u32, _u32, _u32, _vp, _vp, _vp]),
@@ -543,6 +544,14 @@ def batch_per_shift(plans: Sequence[Plan], complex_parts: bool = False):
     if complex_parts:
         return [b[0::2] + 1j * b[1::2] for b in bufs]
     return bufs
+
+
+def batch_stats() -> dict:
+    """Counters of the batch machinery since the library was loaded."""
+    out = np.zeros(4, dtype=np.uint64)
+    check(lib().qmc_batch_stats(_p(out)), "qmc_batch_stats")
+    return {"contexts_built": int(out[0]), "graph_launches": int(out[1]),
+            "specialised_captures": int(out[2]), "specialised_launches": int(out[3])}
 
 
 def cbc_search(n: int, d: int, gamma=None, cand=None):

@@ -104,6 +104,10 @@ def test_null_plan_and_status_strings(Q):
     for s in range(7):
         assert L.qmc_status_string(s) != b"unknown status"
     assert L.qmc_status_string(99) == b"unknown status"
+    assert L.qmc_batch_stats(None) == Q.QMC_EINVAL
+    stats = Q.batch_stats()  # no device work
+    assert set(stats) == {"contexts_built", "graph_launches", "specialised_captures", "specialised_launches"}
+    assert all(isinstance(v, int) and v >= 0 for v in stats.values())
 
 
 def test_construction_and_merge_validation(Q):

@@ -249,6 +249,44 @@ def test_batch_specialised_graph_replays(Q):
         p.close()
 
 
+def test_batch_context_reused(Q):
+    """A repeated batch over the same plans and options replays its context
+    and graph: one context built, one graph launch per call, identical
+    results; another tile-size option or launch shape builds its own.
+    (A context key that never matched once rebuilt buffers and graph on
+    every call.)"""
+    w = synth.product_peak_workload(n=16381, m=8)
+    g = O.korobov_vector(w.n, w.d, 3993)
+    plans, params = [], []
+    for b in range(3):
+        aa, uu = synth.genz_params(synth.SEED_BASE + 1, w.d, stream=16 + b)
+        plans.append(Q.Plan(w.d, w.n, g, w.shifts, "korobov", 3))
+        params.append(Q.Params("genz_product_peak", w.d, a=aa, u=uu))
+    _say("batch context reuse")
+    key = lambda rs: [(r.mean_re, r.err_re) for r in rs]
+    s0 = Q.batch_stats()
+    first = key(Q.integrate_batch(plans, params))
+    for _ in range(3):
+        assert key(Q.integrate_batch(plans, params)) == first
+    s1 = Q.batch_stats()
+    assert s1["contexts_built"] - s0["contexts_built"] == 1
+    assert s1["graph_launches"] - s0["graph_launches"] == 4
+    Q.integrate_batch(plans, params, tile_points=1024)  # tiled layout: its own context
+    Q.integrate_batch(plans, params, tile_points=1024)
+    plans[0].set_launch(2, 4)                            # new launch shape: rebuilt
+    # another grid sums in another order: means within 1e-12; the errors come
+    # from differences of the Q_k (about 1e-6 apart here, each within an ulp
+    # of 2.5e3, so ~3e-7 relative), checked to 1e-5
+    again = np.array(key(Q.integrate_batch(plans, params)))
+    ref = np.array(first)
+    assert np.all(_rel(again[:, 0], ref[:, 0]) < TOL) and np.all(_rel(again[:, 1], ref[:, 1]) < 1e-5)
+    s2 = Q.batch_stats()
+    assert s2["contexts_built"] - s1["contexts_built"] == 2
+    assert s2["graph_launches"] - s1["graph_launches"] == 3
+    for p in plans:
+        p.close()
+
+
 def test_batch_autotune(Q):
     """The batch autotuner returns a table-driven configuration whose graph
     batch matches the oracle within 1e-12 per shift."""
