@@ -57,8 +57,10 @@ __device__ __forceinline__ double cv_pick4(double a, double b, double c, double 
 // l / 16; B = Legendre values: lane l holds column l % 16, inner index
 // l / 16; output element e of lane l is row 4e + l / 16, column l % 16).
 // The product over dimensions is taken elementwise on the output tiles and
-// the sum over ranks by two cross-lane adds.  Each lane reads the z of the 4
-// points its B columns stand for (one per 16-point block) from LDS.
+// the sum over ranks by two cross-lane adds.  Each lane runs the Legendre
+// recurrence of its own point once per dimension; the values reach the B
+// layout (the 4 points a lane's columns stand for, one per 16-point block)
+// through the wave's LDS rows.
 //
 // The weights sit in fragment order at word CvOff of the parameter blob,
 // model after model (D * RB * KS * 64 words each): fragment
@@ -75,6 +77,9 @@ struct FamCvResidual {
     // g of the lane's own point for the model whose fragments start at w
     template <int D>
     __device__ static double model(const double *__restrict__ w, const double *zw, uint32_t lane) {
+        constexpr int NPK = 4 * KS, LP = NPK + 1;  // Legendre values per point, padded LDS row
+        __shared__ double lvs[kBlock / kWave][kWave * LP];
+        double *lw = lvs[threadIdx.x / kWave];
         const uint32_t grp = lane >> 4, col = lane & 15;
         const bool s1 = grp == 1, s2 = grp == 2, s3 = grp == 3;
         cv_d4 prod[RB][4];
@@ -96,16 +101,22 @@ struct FamCvResidual {
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) wn[rb][ks] = w[((inext * RB + rb) * KS + ks) * kWave];
+            // the lane's own point's Legendre values, through the wave's LDS
+            // rows to the B layout (a wave's LDS accesses complete in order)
+            double pk[NPK];
+            legendre_raw<NPK, double>(zw[lane * D + i], pk);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < NPK; ++k) lw[lane * LP + k] = pk[k];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             double bk[4][KS];
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb) {
-                const double zp = zw[(16 * pb + col) * D + i];
-                double pk[4 * KS];
-                legendre_raw<4 * KS, double>(zp, pk);
+            for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-                    bk[pb][ks] = cv_pick4(pk[4 * ks], pk[4 * ks + 1], pk[4 * ks + 2], pk[4 * ks + 3], s1, s2, s3);
-            }
+                for (int ks = 0; ks < KS; ++ks) bk[pb][ks] = lw[(16 * pb + col) * LP + 4 * ks + grp];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             // RB x 4 independent accumulation chains, interleaved over ks
             cv_d4 acc[RB][4];
 #pragma unroll
