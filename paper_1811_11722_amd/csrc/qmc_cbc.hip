@@ -48,18 +48,26 @@ __global__ __launch_bounds__(kBlock) void k_cbc_eval(const CbcArgs a) {
         for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) tile[i] = a.prod[base + i];
         __syncthreads();
         uint32_t idx = (uint32_t)(((uint64_t)base * c) % a.n);
-        double s = 0.0;
-        for (uint32_t i = 0; i < cnt; ++i) {
+        // 1 + w B2(x) = w x (x - 1) + (1 + w / 6): two FMAs per point
+        const double w6 = 1.0 + a.w / 6.0;
+        auto pair = [&](uint32_t i, double &s) {
             const double x = (double)idx * a.inv_n;
-            const double b2 = fma_(x, x - 1.0, 1.0 / 6.0);
-            s = fma_(tile[i], fma_(a.w, b2, 1.0), s);
+            s = fma_(tile[i], fma_(x, fma_(a.w, x, -a.w), w6), s);
             idx += c;
             idx = idx >= a.n ? idx - a.n : idx;
-            if ((i & 7u) == 7u) {
-                dd_accumulate(acc.hi, acc.lo, s);
-                s = 0.0;
-            }
+        };
+        // groups of 8 points into one plain sum, then the double-double fold
+        // (written as a loop over whole groups: a fold guarded inside the
+        // point loop was if-converted and ran at every unrolled step)
+        uint32_t i = 0;
+        for (; i + 8 <= cnt; i += 8) {
+            double s = 0.0;
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) pair(i + u, s);
+            dd_accumulate(acc.hi, acc.lo, s);
         }
+        double s = 0.0;
+        for (; i < cnt; ++i) pair(i, s);
         dd_accumulate(acc.hi, acc.lo, s);
     }
     if (live) a.partial[(size_t)blockIdx.y * a.ncand + t] = make_double2(acc.hi, acc.lo);
