@@ -3,15 +3,20 @@
 
 namespace qmc {
 
+// Threads of a finalize block: 16 waves, so that m = 32 rows take two
+// rounds of loads (each row's partials are a dependent read per wave).
+constexpr uint32_t kFinalizeThreads = 1024;
+
 // One block per instance.  Wave w adds block pairs of (k, p) rows in a fixed
-// strided order and reduces them with the butterfly; thread 0 forms the mean
-// and the two-pass error of eq. (3) for each part.
-__global__ __launch_bounds__(kBlock) void k_finalize(const FinalizeArgs a) {
+// strided order and reduces them with the butterfly (the same order whatever
+// the number of waves); thread 0 forms the mean and the two-pass error of
+// eq. (3) for each part.
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const FinalizeArgs a) {
     __shared__ double qs[kMaxRows];
     const uint32_t inst = blockIdx.x;
     const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const uint32_t rows = a.m * a.np;
-    for (uint32_t r = wave; r < rows; r += kBlock / kWave) {
+    for (uint32_t r = wave; r < rows; r += kFinalizeThreads / kWave) {
         const double2 *src = a.partials + ((size_t)inst * rows + r) * a.nblk;
         dd acc{0.0, 0.0};
         for (uint32_t b = lane; b < a.nblk; b += kWave) acc = dd_add(acc, dd{src[b].x, src[b].y});
@@ -116,12 +121,12 @@ hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t s) {
 
 // One block per plan of a batch: adds the plan's tile slots of every
 // (shift, part) row in slot order, then forms Q_k, the mean and the error.
-__global__ __launch_bounds__(kBlock) void k_finalize_batch(const FinalizeBatchArgs a) {
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize_batch(const FinalizeBatchArgs a) {
     __shared__ double qs[kMaxRows];
     const BatchSector sc = a.sectors[blockIdx.x];
     const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const uint32_t rows = sc.m * a.np, width = a.T * a.np;
-    for (uint32_t r = wave; r < rows; r += kBlock / kWave) {
+    for (uint32_t r = wave; r < rows; r += kFinalizeThreads / kWave) {
         const uint32_t k = r / a.np, p = r - k * a.np;
         const uint32_t kt = k / a.T, col = (k - kt * a.T) * a.np + p;
         const double2 *src = a.partials + ((size_t)sc.slot_base + (size_t)kt * sc.jtiles) * width + col;
@@ -156,12 +161,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(const FinalizeBatchAr
 }
 
 hipError_t launch_finalize_batch(const FinalizeBatchArgs &a, uint32_t count, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_batch, dim3(count), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(count), dim3(kFinalizeThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t ninst, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(ninst), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(ninst), dim3(kFinalizeThreads), 0, s, a);
     return hipGetLastError();
 }
 
