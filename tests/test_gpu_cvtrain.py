@@ -206,7 +206,8 @@ def test_normal_equations_training_size_sampled(Q):
     assert np.all(eb <= bb * ba)
 
 
-@pytest.mark.parametrize("d,R,K,n", [(8, 32, 12, 16381), (10, 64, 12, 4093), (5, 8, 4, 2039)])
+@pytest.mark.parametrize("d,R,K,n", [(8, 32, 12, 16381), (10, 64, 12, 4093), (5, 8, 4, 2039), (6, 16, 8, 4093),
+                                     (6, 32, 16, 8191)])
 def test_solve_matches_oracle(Q, d, R, K, n):
     rho, phi, y = _design_inputs(d, R, K, n, 75)
     G, b, _, _ = O.cv_normal(rho, phi, y, threads=THREADS)
