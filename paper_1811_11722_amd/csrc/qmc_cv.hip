@@ -9,13 +9,15 @@
 // rho_j[r] = sw_j prod_{i' != i} h_{r,i'}(z_{j,i'}),  phi_j[k] = P~_k(z_{j,i}).
 // A^T A has Kronecker structure: its (k, k') block is
 //   sum_j phi_j[k] phi_j[k'] rho_j rho_j^T,
-// a rank-N sum of R x R outer products, which k_cv_syrk accumulates with
-// BF16 MFMA (v_mfma_f32_32x32x16_bf16: 32 x 32 tiles, 16 points per
-// instruction, FP32 accumulation).  The per-split tiles are added in a fixed
-// order in FP64 and factorised in FP64 on the device (k_cv_factor).  That
-// factor preconditions passes against the FP64 design matrix (k_cv_pass,
-// FP64 MFMA, and k_cv_subst), so each step converges to the FP64 ridge
-// solution.  The trained model is evaluated in FP64 inside the estimator.
+// a rank-N sum of R x R outer products, which k_cv_syrk2 / k_cv_syrk
+// accumulate with BF16 MFMA (v_mfma_f32_32x32x16_bf16: 32 x 32 tiles, 16
+// points per instruction, FP32 accumulation).  The per-split tiles are added
+// in a fixed order in FP64, factorised in FP64 by a blocked Cholesky over
+// many workgroups (k_cv_chol_*), which also forms the explicit inverse.  That
+// inverse preconditions passes against the FP64 design matrix (k_cv_pass,
+// FP64 MFMA; k_cv_gemv and k_cv_subst apply the correction), so each step
+// converges to the FP64 ridge solution.  The trained model is evaluated in
+// FP64 inside the estimator.
 #include <cmath>
 #include <cstring>
 #include <type_traits>
