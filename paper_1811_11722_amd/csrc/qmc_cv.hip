@@ -564,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_cv_gather(const float *partial, uint
 //      phi[point l % 16][4 s + l / 16], B: the weights, kept in registers),
 //      so lane l holds H at point 4 v + l / 16 and rank 16 t + l % 16;
 //   2. rho is read in that layout (128-byte rows), and the 16 lanes of a
-//      point add rho H with a butterfly: e of the point;
+//      point add rho H (row16_sum): e of the point;
 //   3. the right-hand side tile accumulates (rho e)^T Phi, 4 points per
 //      instruction: A = rho e as held, B = phi[point 4 g + l / 16][l % 16]
 //      (0 for Legendre indices >= K).
@@ -573,6 +573,25 @@ __global__ __launch_bounds__(kBlock) void k_cv_gather(const float *partial, uint
 // are added in wave order.  Entry R K of a split's partials is its sum of
 // e_j^2 (the objective of the current factor).  A set *flag (a converged
 // solve) makes the kernel return at once.
+// Sum over the 16 lanes of a row (every lane gets it) with DPP moves: xor 1
+// and xor 2 within quads, then the half-row and row mirrors, which pair each
+// quad with its partner quad as the xor-4 and xor-8 butterfly does (the
+// partner's quad sums are uniform), so the result equals that butterfly's bit
+// for bit; cross-lane moves at VALU latency instead of LDS permutes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    return v;
+}
+
 struct CvPassArgs {
     uint32_t n, d, i, splits;
     const double *rho, *phi;  // (n, R), (n, K)
@@ -652,11 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_cv_pass(const CvPassArgs a) {
                 for (int v = 0; v < 4; ++v) dot[v] = fma(rh[t][v], h[v], dot[v]);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-#pragma unroll
-                for (int o = 1; o < 16; o <<= 1) dot[v] += __shfl_xor(dot[v], o);
-                e[v] -= dot[v];
-            }
+            for (int v = 0; v < 4; ++v) e[v] -= row16_sum(dot[v]);
         }
         if (li == 0) {
 #pragma unroll
