@@ -42,7 +42,7 @@ CPU_THREADS_MAX = 16            # the host CPU share of one GPU on the measureme
 # wave-evaluation, rocprofv3 --pmc on the same launches; profiles/ holds the
 # runs), per workload.
 FLOPS_MODEL = {"sector": 280.0, "product_peak": 91.0, "sector_complex": 540.0}
-FLOPS_COUNTED = {"sector": 165.9, "product_peak": 80.6, "sector_complex": 374.1}
+FLOPS_COUNTED = {"sector": 165.9, "product_peak": 76.6, "sector_complex": 374.1}
 # engine cycles of one launch of the headline kernel: GRBM_GUI_ACTIVE per XCD
 # (rocprofv3 --pmc, profiles/); divided by the kernel time measured here it
 # gives the clock the kernel ran at

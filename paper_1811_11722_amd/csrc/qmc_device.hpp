@@ -49,6 +49,18 @@ __device__ __forceinline__ uint32_t walk(uint32_t idx, uint32_t step, uint32_t n
 __device__ __forceinline__ double fract(double x) { return __builtin_amdgcn_fract(x); }
 
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// c in a scalar / vector register pair that the compiler cannot see through:
+// a loop-invariant FP64 constant then stays in registers set up once (the
+// empty asm has no side effects, so it is hoisted and merged) instead of
+// being rebuilt as a literal before each use.
+__device__ __forceinline__ double sreg_const(double c) {
+    asm("" : "+s"(c));
+    return c;
+}
+__device__ __forceinline__ double vreg_const(double c) {
+    asm("" : "+v"(c));
+    return c;
+}
 
 // 1/b: hardware reciprocal estimate refined by two Newton steps.
 __device__ __forceinline__ double recip(double b) {

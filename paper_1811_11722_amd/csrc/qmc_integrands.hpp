@@ -42,51 +42,62 @@ constexpr double cpow4(int e) {  // 4^e for e <= 0
     return e == 0 ? 1.0 : 0.25 * cpow4(e + 1);
 }
 
-// Korobov transform of weight A, eq. (4): w(x) = C_A x^A (1-x)^A with
-// C_A = (2A+1)!/(A!)^2, z(x) = int_0^x w.  With t = x - 1/2 the weight is
-// C_A (1/4 - t^2)^A and z = 1/2 + t * sum_j c_j t^(2j), where expanding the
-// binomial and integrating term by term gives
-// c_j = C_A binom(A, j) 4^(j-A) (-1)^j / (2j + 1).  This odd polynomial in t
-// has small coefficients, so it avoids the cancellation of the expanded form
-// in x near x = 1.  The constant C_A^d of prod_i w_i is applied once to
-// the final sums.
+// Korobov transform of weight A, eq. (4): w(x) = C_A u^A with u = x (1 - x)
+// and C_A = (2A+1)!/(A!)^2, z(x) = int_0^x w.  With t = x - 1/2,
+//   z = 1/2 + t * H(u),  H(u) = sum_{k=0..A} binom(2k, k) u^k.
+// Differentiating (u' = -2t, t^2 = 1/4 - u), the terms of u^k from the k-th
+// and (k+1)-th summands cancel because (k+1) binom(2k+2, k+1) = 2 (2k+1)
+// binom(2k, k), which leaves (2A+1) binom(2A, A) u^A = C_A u^A; z(0) = 0.
+// The coefficients 1, 2, 6, 20, 70, ... are positive integers and
+// u <= 1/4, so every term of H lies in [0, 1] and Horner's rule sums
+// positive values (no cancellation anywhere in [0, 1]).  u is needed for
+// the Jacobian anyway, so z costs no separate t^2.  The constant C_A^d of
+// prod_i w_i is applied once to the final sums.
 template <int A>
 struct TrKorobov {
     static_assert(A >= 1 && A <= 6, "Korobov weight 1..6");
     static constexpr bool kJac = true;
     static constexpr double kC = cfact(2 * A + 1) / (cfact(A) * cfact(A));
-    // the c_j as a table evaluated by the compiler: calling the recursive
-    // helpers from device code would leave them as run-time calls
+    // binom(2k, k) as a table evaluated by the compiler: calling the
+    // recursive helpers from device code would leave them as run-time calls
     struct Coefs {
         double c[A + 1];
     };
     static constexpr Coefs make_coefs() {
         Coefs r{};
-        for (int j = 0; j <= A; ++j)
-            r.c[j] = kC * cbinom(A, j) * cpow4(j - A) * ((j & 1) ? -1.0 : 1.0) / (2 * j + 1);
+        for (int k = 0; k <= A; ++k) r.c[k] = cbinom(2 * k, k);
         return r;
     }
     static constexpr Coefs kCoef = make_coefs();
-    // h(t^2) = sum_j c_j t^(2j), Horner from the top coefficient
-    __device__ static double h(double t2) {
-        double r = kCoef.c[A];
+    // H(u), Horner from the top coefficient.  From A = 3 on the first step
+    // multiplies and adds two constants that are not inline operands (20u + 6
+    // at A = 3); as literals the compiler re-creates the addend with two
+    // v_mov_b32 before every use, so both come from registers set once per
+    // thread: the factor from an SGPR pair, the addend from a VGPR pair (one
+    // FMA per use, within the one-SGPR operand limit of VOP3).
+    __device__ static double h(double u) {
+        double r;
+        if constexpr (A == 1)
+            r = fma_(u, kCoef.c[1], kCoef.c[0]);
+        else if constexpr (A == 2)
+            r = fma_(u, sreg_const(kCoef.c[2]), kCoef.c[1]);
+        else
+            r = fma_(u, sreg_const(kCoef.c[A]), vreg_const(kCoef.c[A - 1]));
 #pragma unroll
-        for (int j = A - 1; j >= 0; --j) r = fma_(r, t2, kCoef.c[j]);
+        for (int k = A - 2; k >= 0; --k) r = fma_(r, u, kCoef.c[k]);
         return r;
     }
     // z and u = x (1 - x) = 1/4 - t^2
     __device__ static double z(double x, double &u) {
         const double t = x - 0.5;
-        const double t2 = t * t;
         u = fma_(-t, t, 0.25);
-        return fma_(t, h(t2), 0.5);
+        return fma_(t, h(u), 0.5);
     }
     // z - c, given hmc = 1/2 - c, and u
     __device__ static double z_minus(double x, double hmc, double &u) {
         const double t = x - 0.5;
-        const double t2 = t * t;
         u = fma_(-t, t, 0.25);
-        return fma_(t, h(t2), hmc);
+        return fma_(t, h(u), hmc);
     }
     // prod_i w_i / C_A^d = (prod_i u_i)^A
     __device__ static double jac(double pu) {
