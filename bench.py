@@ -42,16 +42,16 @@ CPU_THREADS_MAX = 16            # the host CPU share of one GPU on the measureme
 # wave-evaluation, rocprofv3 --pmc on the same launches; profiles/ holds the
 # runs), per workload.
 FLOPS_MODEL = {"sector": 280.0, "product_peak": 91.0, "sector_complex": 540.0}
-FLOPS_COUNTED = {"sector": 165.9, "product_peak": 76.6, "sector_complex": 374.1}
+FLOPS_COUNTED = {"sector": 163.95, "product_peak": 76.6, "sector_complex": 371.8}
 # engine cycles of one launch of the headline kernel: GRBM_GUI_ACTIVE per XCD
 # (rocprofv3 --pmc, profiles/); divided by the kernel time measured here it
 # gives the clock the kernel ran at
-CYCLES_PER_XCD = {"sector": 4.79e6}
+CYCLES_PER_XCD = {"sector": 4.634e6}
 
 # HBM bytes per lattice-kernel launch from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy of known size); recorded for
 # the kernel as profiled (profiles/k_lattice_sector_jit_d6_n16777213_m32.md).
-TRAFFIC_BYTES = {"sector": 803840}
+TRAFFIC_BYTES = {"sector": 803226}
 
 
 def make_workload(name: str):

@@ -642,8 +642,10 @@ __device__ __forceinline__ double qlog(double x) {
     constexpr double kLn2Lo = 1.90821492927058770002e-10;
     const double m = __builtin_amdgcn_frexp_mant(x);
     const double e = (double)__builtin_amdgcn_frexp_exp(x);
-    // (m - 1/2) * 512 is exact; the clamp keeps inf and NaN inputs in bounds
-    const int j = min(max((int)fma_(m, 512.0, -256.0), 0), 255);
+    // j = floor((m - 1/2) 512) is the top 8 bits of m's fraction field, bits
+    // 12..19 of its high word (one bit-field extract; any input, NaN and inf
+    // included, gives a j in 0..255)
+    const int j = (int)__builtin_amdgcn_ubfe((uint32_t)__double2hiint(m), 12, 8);
     const double ic = kMathTab[2 * j], nl = kMathTab[2 * j + 1];
     const double r = fma_(m, ic, -1.0);
     // ln(1 + r) = r - r^2 (1/2 - r/3 + r^2/4 - r^3/5)
@@ -653,7 +655,10 @@ __device__ __forceinline__ double qlog(double x) {
     q = fma_(q, r, 0.5);
     const double lr = fma_(-r * r, q, r);
     const double res = fma_(e, kLn2Hi, nl + fma_(e, kLn2Lo, lr));
-    return (x > 0.0 && x < __builtin_inf()) ? res : __builtin_nan("");
+    // NaN unless x is positive and finite: only the high word is replaced
+    // (0x7ff80000 there makes a quiet NaN whatever the low word holds)
+    const bool ok = x > 0.0 && x < __builtin_inf();
+    return __hiloint2double(ok ? __double2hiint(res) : 0x7ff80000, __double2loint(res));
 }
 
 // ------------------------------------------------- FP64 atan2 and sincos
