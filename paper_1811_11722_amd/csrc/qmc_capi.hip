@@ -925,6 +925,20 @@ qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint
     a.param_stride = 0;
     a.np = 1;
     a.partials = (double2 *)s.ptr[4];
+    // The point n - j is the mirror 1 - x of the point j and B2(1 - x) =
+    // B2(x), so for odd n the sum S over all points is 2 sum_{j <= n/2} -
+    // term(0), term(0) = (1 + pi^2/3)^d (formed as the kernel forms it: q(0)
+    // is exactly that constant, multiplied up in order).  For even n the
+    // self-mirrored point n/2 depends on each candidate, and all n points
+    // are summed.
+    const bool half = (n & 1) == 1;
+    double t0 = 0.0;
+    if (half) {
+        const double c0 = 1.0 + 9.869604401089358 / 3.0;
+        t0 = c0;
+        for (uint32_t i = 1; i < d; ++i) t0 *= c0;
+    }
+    a.jend = half ? (uint32_t)(n / 2 + 1) : 0;
     if ((e = fn(a, dim3(bx, ncand), stream)) != hipSuccess) return hip_fail(e, "launch P2 kernel");
     FinalizeArgs f{};
     f.partials = a.partials;
@@ -932,8 +946,9 @@ qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint
     f.m = 1;
     f.np = 1;
     f.n = (double)n;
-    f.scale = 1.0;
-    f.sub = (double)n;
+    // q = (S - n) / n = ((sum - (n + t0) / 2) 2) / n
+    f.scale = half ? 2.0 : 1.0;
+    f.sub = half ? ((double)n + t0) / 2.0 : (double)n;
     f.q = (double *)s.ptr[5];
     f.res = (double *)s.ptr[6];
     if ((e = launch_finalize(f, ncand, stream)) != hipSuccess) return hip_fail(e, "launch finalize");

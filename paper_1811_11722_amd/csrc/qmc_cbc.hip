@@ -3,14 +3,18 @@
 // search, with product weights).  For component s every admissible candidate
 // c needs
 //   S(c) = sum_{j<n} p_j (1 + w_s B2({j c / n})),   w_s = 2 pi^2 gamma_s,
-// with p_j the product over the components already chosen.  One thread owns
+// with p_j the product over the components already chosen.  B2(1 - x) =
+// B2(x), so the point n - j contributes what j does (p_j inherits the
+// symmetry from the chosen components), and only j <= n/2 is summed:
+// S(c) = 2 sum_{j <= n/2} - term(0) - [n even] term(n/2).  One thread owns
 // one candidate and walks its index j c mod n exactly (u32 add and
 // conditional subtract); the p_j are staged through LDS in tiles that every
 // thread of the block reads in the same order (broadcast reads), and the
 // point range is split over grid.y so that small candidate sets still fill
 // the chip.  Partial sums are double-double; a second kernel folds them in
-// a fixed order into e^2(c) = (S(c) - n) / n.  The argmin runs on the host,
-// then p_j is multiplied by the chosen factor.
+// a fixed order, restores the full sum and forms e^2(c) = (S(c) - n) / n.
+// The argmin runs on the host, then p_j (j <= n/2) is multiplied by the
+// chosen factor.
 #include <algorithm>
 #include <cmath>
 
@@ -25,6 +29,7 @@ constexpr uint32_t kCbcTile = 2048;  // doubles of p_j per LDS tile (16 KB)
 
 struct CbcArgs {
     uint32_t n;
+    uint32_t jend;    // points j < jend are summed (n/2 + 1)
     uint32_t ncand;
     uint32_t jchunk;  // points per grid.y slice
     double inv_n;
@@ -40,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_cbc_eval(const CbcArgs a) {
     const bool live = t < a.ncand;
     const uint32_t c = live ? a.cand[t] : 1u;
     const uint32_t j0 = blockIdx.y * a.jchunk;
-    const uint32_t j1 = min(a.n, j0 + a.jchunk);
+    const uint32_t j1 = min(a.jend, j0 + a.jchunk);
     dd acc{0.0, 0.0};
     for (uint32_t base = j0; base < j1; base += kCbcTile) {
         const uint32_t cnt = min(kCbcTile, j1 - base);
@@ -73,9 +78,12 @@ __global__ __launch_bounds__(kBlock) void k_cbc_eval(const CbcArgs a) {
     if (live) a.partial[(size_t)blockIdx.y * a.ncand + t] = make_double2(acc.hi, acc.lo);
 }
 
-// e2[t] = (sum over slices - n) / n, slices folded in order
+// e2[t] = (S - n) / n with S = 2 (sum over slices) - term(0) - [n even]
+// term(n/2), slices folded in order; the two terms are formed as k_cbc_eval
+// forms them (x = idx / n through inv_n)
 __global__ __launch_bounds__(kBlock) void k_cbc_reduce(const double2 *partial, uint32_t slices, uint32_t ncand,
-                                                       double n, double *e2) {
+                                                       uint32_t n, double inv_n, double w, const double *prod,
+                                                       double *e2) {
     const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= ncand) return;
     dd acc{0.0, 0.0};
@@ -83,13 +91,21 @@ __global__ __launch_bounds__(kBlock) void k_cbc_reduce(const double2 *partial, u
         const double2 v = partial[(size_t)y * ncand + t];
         acc = dd_add(acc, dd{v.x, v.y});
     }
-    e2[t] = ((acc.hi - n) + acc.lo) / n;
+    acc = dd{2.0 * acc.hi, 2.0 * acc.lo};
+    const double w6 = 1.0 + w / 6.0;
+    acc = dd_add(acc, dd{-(prod[0] * w6), 0.0});
+    if ((n & 1u) == 0) {  // j = n/2 is its own mirror; c is odd, so idx = n/2
+        const double x = (double)(n / 2) * inv_n;
+        acc = dd_add(acc, dd{-(prod[n / 2] * fma_(x, fma_(w, x, -w), w6)), 0.0});
+    }
+    e2[t] = ((acc.hi - (double)n) + acc.lo) / (double)n;
 }
 
-// p_j *= 1 + w B2({j z / n})
-__global__ __launch_bounds__(kBlock) void k_cbc_update(double *prod, uint32_t n, double inv_n, uint32_t z, double w) {
+// p_j *= 1 + w B2({j z / n}) for j < jend
+__global__ __launch_bounds__(kBlock) void k_cbc_update(double *prod, uint32_t n, uint32_t jend, double inv_n,
+                                                       uint32_t z, double w) {
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
+    if (j >= jend) return;
     const uint32_t idx = (uint32_t)(((uint64_t)j * z) % n);
     const double x = (double)idx * inv_n;
     prod[j] = prod[j] * fma_(w, fma_(x, x - 1.0, 1.0 / 6.0), 1.0);
@@ -155,11 +171,12 @@ extern "C" qmc_status qmc_cbc_search(uint64_t n, uint32_t d, const double *gamma
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     const uint32_t bx = (nc + kBlock - 1) / kBlock;
     const uint32_t want = 8u * (uint32_t)device_cu_count(dev);
-    const uint32_t max_slices = (uint32_t)std::max<uint64_t>(1, n / kCbcTile);
+    const uint32_t jend = (uint32_t)(n / 2 + 1);  // j <= n/2 (mirror symmetry j <-> n - j)
+    const uint32_t max_slices = std::max<uint32_t>(1, jend / kCbcTile);
     const uint32_t slices = std::min(max_slices, std::max(1u, (want + bx - 1) / bx));
     DeviceScratch s;
     qmc_status st;
-    if ((st = s.alloc((size_t)n * 8)) || (st = s.alloc((size_t)nc * 4)) ||
+    if ((st = s.alloc((size_t)jend * 8)) || (st = s.alloc((size_t)nc * 4)) ||
         (st = s.alloc((size_t)slices * nc * sizeof(double2))) || (st = s.alloc((size_t)nc * 8)) ||
         (st = s.alloc(4)))
         return st;
@@ -172,8 +189,8 @@ extern "C" qmc_status qmc_cbc_search(uint64_t n, uint32_t d, const double *gamma
     if ((e = hipMemcpy(dcand, cs.data(), (size_t)nc * 4, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(one, &one_h, 4, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "cbc upload");
-    const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kBlock), 0, nullptr, prod, (uint32_t)n, 1.0);
+    const uint32_t nb = (jend + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kBlock), 0, nullptr, prod, jend, 1.0);
     const double inv_n = 1.0 / (double)n;
     const double two_pi2 = 2.0 * 3.141592653589793 * 3.141592653589793;
     std::vector<double> h(nc);
@@ -184,11 +201,11 @@ extern "C" qmc_status qmc_cbc_search(uint64_t n, uint32_t d, const double *gamma
         const uint32_t cnt = first ? 1u : nc;
         const uint32_t cbx = first ? 1u : bx;
         const uint32_t csl = first ? std::min(max_slices, want) : slices;
-        const uint32_t cch = (uint32_t)((n + csl - 1) / csl);
-        CbcArgs a{(uint32_t)n, cnt, cch, inv_n, w, prod, first ? one : dcand, partial};
+        const uint32_t cch = (jend + csl - 1) / csl;
+        CbcArgs a{(uint32_t)n, jend, cnt, cch, inv_n, w, prod, first ? one : dcand, partial};
         hipLaunchKernelGGL(k_cbc_eval, dim3(cbx, csl), dim3(kBlock), 0, nullptr, a);
         hipLaunchKernelGGL(k_cbc_reduce, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, nullptr,
-                           (const double2 *)partial, csl, cnt, (double)n, e2);
+                           (const double2 *)partial, csl, cnt, (uint32_t)n, inv_n, w, (const double *)prod, e2);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch CBC kernels");
         if ((e = hipMemcpy(h.data(), e2, (size_t)cnt * 8, hipMemcpyDeviceToHost)) != hipSuccess)
             return hip_fail(e, "cbc download");
@@ -205,7 +222,7 @@ extern "C" qmc_status qmc_cbc_search(uint64_t n, uint32_t d, const double *gamma
         const uint32_t z = first ? 1u : cs[best];
         z_out[comp] = z;
         e2_out[comp] = h[best];
-        hipLaunchKernelGGL(k_cbc_update, dim3(nb), dim3(kBlock), 0, nullptr, prod, (uint32_t)n, inv_n, z, w);
+        hipLaunchKernelGGL(k_cbc_update, dim3(nb), dim3(kBlock), 0, nullptr, prod, (uint32_t)n, jend, inv_n, z, w);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "launch CBC update");
     }
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "cbc synchronize");

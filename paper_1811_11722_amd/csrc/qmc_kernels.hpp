@@ -33,6 +33,9 @@ struct LatticeArgs {
     uint32_t g_stride, shift_stride, param_stride;
     uint32_t np;            // 1 real, 2 complex
     double2 *partials;      // (inst, m, np, gridDim.x) of (hi, lo)
+    uint32_t jend;          // points j < jend are summed; 0 means all n (only
+                            // the P2 search, whose sum is symmetric in j and
+                            // n - j, sets n/2 + 1)
 };
 
 constexpr int kChunk = 8;  // points per plain-FP64 partial before the TwoSum fold
@@ -182,7 +185,8 @@ __device__ __forceinline__ void lattice_body(const LatticeArgs &a) {
     for (int k = 0; k < T; ++k)
 #pragma unroll
         for (int p = 0; p < NP; ++p) hi[k][p] = lo[k][p] = 0.0;
-    walk_points<Fam, Tr, D, T>(blockIdx.x * kBlock + threadIdx.x, a.n, gridDim.x * kBlock, a.n, a.inv_n, g, gs,
+    const uint32_t j1 = a.jend ? a.jend : a.n;
+    walk_points<Fam, Tr, D, T>(blockIdx.x * kBlock + threadIdx.x, j1, gridDim.x * kBlock, a.n, a.inv_n, g, gs,
                                sh + (size_t)k0 * D, prm, hi, lo);
 
     __shared__ dd red[kBlock / kWave][T * NP];

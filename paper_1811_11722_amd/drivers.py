@@ -815,6 +815,10 @@ def lattice_study(n: int = 1048573, d: int = 10, m: int = 32, seed: int = synth.
     w = synth.sector_workload(n=n, m=m, d=d, n_u=20, n_f=60, seed=seed, complex_kinematics=True)
     params = qmc.Params("sector", d, sector=w.sector)
     vecs = []
+    # the process's first library call loads the code objects: keep it out of
+    # the construction times
+    qmc.korobov_search(n, d, synth.korobov_candidates(seed, n, 1))
+    _sync()
     t = time.perf_counter()
     a, p2k, _ = qmc.korobov_search(n, d, synth.korobov_candidates(seed, n, 64))
     vecs.append(("korobov_p2_64", qmc.korobov_vector(n, d, a), time.perf_counter() - t, p2k))
