@@ -42,7 +42,7 @@ CPU_THREADS_MAX = 16            # the host CPU share of one GPU on the measureme
 # wave-evaluation, rocprofv3 --pmc on the same launches; profiles/ holds the
 # runs), per workload.
 FLOPS_MODEL = {"sector": 280.0, "product_peak": 91.0, "sector_complex": 540.0}
-FLOPS_COUNTED = {"sector": 163.95, "product_peak": 76.6, "sector_complex": 371.8}
+FLOPS_COUNTED = {"sector": 163.95, "product_peak": 71.4, "sector_complex": 371.8}
 # engine cycles of one launch of the headline kernel: GRBM_GUI_ACTIVE per XCD
 # (rocprofv3 --pmc, profiles/); divided by the kernel time measured here it
 # gives the clock the kernel ran at

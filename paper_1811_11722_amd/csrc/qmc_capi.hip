@@ -123,6 +123,19 @@ qmc_status pack_params(int family, uint32_t d, const void *params, Packed &pk) {
             for (uint32_t i = 0; i < D; ++i) pk.blob.push_back(1.0 / (p->a[i] * p->a[i]));
             for (uint32_t i = 0; i < D; ++i) pk.blob.push_back(p->u[i]);
             for (uint32_t i = 0; i < D; ++i) pk.blob.push_back(0.5 - p->u[i]);
+            // tile flag: one reciprocal may serve a thread's shifts if every
+            // denominator prod_i q_i, a^-2 <= q_i <= a^-2 + max(u^2, (1-u)^2),
+            // lies within 2^-62 .. 2^62 (products of up to 16 of them then stay
+            // within 2^-1000 .. 2^1000)
+            double lg_lo = 0.0, lg_hi = 0.0;
+            for (uint32_t i = 0; i < d; ++i) {
+                const double a2 = 1.0 / (p->a[i] * p->a[i]);
+                const double s2 = std::max(p->u[i] * p->u[i], (1.0 - p->u[i]) * (1.0 - p->u[i]));
+                lg_lo += std::log2(a2);
+                lg_hi += std::log2(a2 + s2);
+            }
+            pk.blob.push_back(std::isfinite(lg_lo) && std::isfinite(lg_hi) && lg_lo >= -62.0 && lg_hi <= 62.0 ? 1.0
+                                                                                                                : 0.0);
         } else if (family == QMC_F_GENZ_OSCILLATORY) {
             for (uint32_t i = 0; i < D; ++i) pk.blob.push_back(p->a[i]);
             pk.blob.push_back(2.0 * M_PI * p->u[0]);
