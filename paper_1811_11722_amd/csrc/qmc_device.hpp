@@ -71,6 +71,25 @@ __device__ __forceinline__ double recip(double b) {
     return fma_(r, e, r);
 }
 
+// r_k = 1 / b_k for T values from one reciprocal (v_rcp_f64 issues at a
+// quarter of the FP64 rate): prefix products, the reciprocal of their total,
+// then two multiplies back per value.  The caller guarantees that every
+// product of the b_k is a normal number.
+template <int T>
+__device__ __forceinline__ void recip_tile(const double (&b)[T], double (&r)[T]) {
+    double pre[T];
+    pre[0] = b[0];
+#pragma unroll
+    for (int k = 1; k < T; ++k) pre[k] = pre[k - 1] * b[k];
+    double inv = recip(pre[T - 1]);  // 1 / (b_0 ... b_{T-1})
+#pragma unroll
+    for (int k = T - 1; k > 0; --k) {
+        r[k] = inv * pre[k - 1];
+        inv *= b[k];  // 1 / (b_0 ... b_{k-1})
+    }
+    r[0] = inv;
+}
+
 // a / b via the refined reciprocal and one residual correction.
 __device__ __forceinline__ double divide(double a, double b) {
     const double r = recip(b);

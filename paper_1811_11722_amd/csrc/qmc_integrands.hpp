@@ -321,17 +321,10 @@ struct FamGenzProductPeak {
         }
         if constexpr (T > 1) {
             if (p[3 * D] != 0.0) {  // the same for every thread of the launch's instance
-                double pre[T];
-                pre[0] = den[0];
+                double r[T];
+                recip_tile<T>(den, r);
 #pragma unroll
-                for (int k = 1; k < T; ++k) pre[k] = pre[k - 1] * den[k];
-                double inv = recip(pre[T - 1]);  // 1 / (den_0 ... den_{T-1})
-#pragma unroll
-                for (int k = T - 1; k > 0; --k) {
-                    v[k][0] = w[k] * (inv * pre[k - 1]);
-                    inv *= den[k];  // 1 / (den_0 ... den_{k-1})
-                }
-                v[0][0] = w[0] * inv;
+                for (int k = 0; k < T; ++k) v[k][0] = w[k] * r[k];
                 return;
             }
         }

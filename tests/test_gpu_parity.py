@@ -303,6 +303,36 @@ def test_sector_real_shapes(Q, d, n_u, n_f, jit):
     assert np.all(_rel(q, est.q_re) < TOL)
 
 
+@pytest.mark.parametrize("jit", [0, 2])
+@pytest.mark.parametrize("u_case", ["bounded", "no_constant_term", "negative_coefficient"])
+def test_sector_u_edge_cases(Q, u_case, jit):
+    """U^-2 where U is bounded away from 0 (non-negative coefficients, a
+    positive constant term), where it vanishes at a corner (no constant
+    term) and with a negative coefficient.  Each against the oracle, per
+    shift, at shift tile 4."""
+    import dataclasses
+    d, n, m = 6, 16381, 8
+    tab = synth.sector_tables(101, d, 12, 30)
+    eu = np.asarray(tab.exp_u).reshape(tab.n_u, d)
+    const = [t for t in range(tab.n_u) if not eu[t].any()]
+    assert const, "the synthetic U has a constant term"
+    if u_case == "no_constant_term":
+        keep = [t for t in range(tab.n_u) if t not in const]
+        tab = dataclasses.replace(tab, coef_u=np.asarray(tab.coef_u)[keep], exp_u=eu[keep])
+    elif u_case == "negative_coefficient":
+        cu = np.array(tab.coef_u, dtype=np.float64)
+        t = next(t for t in range(tab.n_u) if t not in const)
+        cu[t] = -0.01 * cu[t]
+        tab = dataclasses.replace(tab, coef_u=cu)
+    g = O.korobov_vector(n, d, 5029)
+    sh = synth.shifts(56, m, d)
+    _say(f"sector U edge case {u_case} jit={jit}")
+    res, q, est = _both(Q, "sector", d, n, g, sh, "baker", launch=(4, 0), jit=jit, sector=tab)
+    rel = _rel(q, est.q_re)
+    print(f"max relative difference {rel.max():.2e}")
+    assert np.all(rel < TOL), rel.max()
+
+
 def test_sector_same_structure_new_values(Q):
     """One plan, one specialised kernel (found by the monomial structure),
     three integrands that share it: new coefficients and powers, and the
