@@ -19,7 +19,9 @@ carries the metric's other parts, each on its own workload:
   mixed-sign F - 0.01i, baker) at n = 1073741789, m = 32;
 - time_to_error: wall time to a relative error of 1e-7 on the d = 8 sector,
   plain estimator against the learned control variate, with the transform
-  picked automatically;
+  picked automatically (the control variate's ladder runs the plain kernel
+  once two consecutive rungs have fallen back; `cv_pass` marks the rungs
+  that ran the residual pass);
 - cpu_baseline: the CPU oracle at 1 thread and at the machine's CPU share.
 """
 from __future__ import annotations
@@ -179,8 +181,9 @@ def leg_time_to_error(drivers, goal: float):
             "transform_choice": tte["transform_choice"],
             "plain": {k: tte["plain"][k] for k in keep},
             "cv": dict({k: tte["cv"][k] for k in keep},
-                       **{k: tte["cv"][k] for k in ("train_seconds", "train_rel_loss", "R", "K")},
-                       used_cv=[r["used_cv"] for r in tte["cv"]["rungs"]])}
+                       **{k: tte["cv"][k] for k in ("train_seconds", "train_rel_loss", "R", "K", "drop_after")},
+                       used_cv=[r["used_cv"] for r in tte["cv"]["rungs"]],
+                       cv_pass=[int(r["cv_pass"]) for r in tte["cv"]["rungs"]])}
 
 
 def main():

@@ -498,7 +498,8 @@ def _sync():
 def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 4,
                   goal: float = 1e-7, m: int = 32, R: int = 32, K: int = 12, n_train: int = 1048573,
                   kmin: int = 14, kmax: int = 30, cv_kmax: int = 28, max_sweeps: int = 12, transform=None,
-                  pilot_n: int = 65521, candidates: int = 64, choices=None, log=None) -> dict:
+                  pilot_n: int = 65521, candidates: int = 64, choices=None, cv_drop_after: int = 2,
+                  log=None) -> dict:
     """Time to a relative error goal, plain estimator against the control
     variate (real sector integrand).  The periodising transform is
     `transform` = (kind, alpha), or (None) the one choose_transform picks on
@@ -512,7 +513,10 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
     in practice) and their time is reported on its own; the first call of
     each form compiles its specialised kernel and is not timed.  choices:
     the candidate transforms (None: every transform choose_transform
-    knows)."""
+    knows).  cv_drop_after: once that many consecutive rungs of the CV form
+    have fallen back to the plain estimate (the model no longer lowers the
+    error at that resolution), its later rungs run the plain kernel instead
+    of the residual pass (0: never); each rung records which it ran."""
     tab = synth.sector_tables(seed, d, n_u, n_f)
     params = qmc.Params("sector", d, sector=tab)
     ladder = synth.prime_ladder(kmin, kmax)
@@ -551,7 +555,7 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
             cum += t
             rel = abs(res.err_re) / abs(res.mean_re)
             rows.append({"n": n, "mean": res.mean_re, "err": res.err_re, "rel_err": rel,
-                         "seconds": t, "used_cv": res.used_cv})
+                         "seconds": t, "used_cv": res.used_cv, "cv_pass": getattr(res, "cv_pass", False)})
             say(f"  n={n} mean={res.mean_re!r} rel_err={rel:.3e} used_cv={res.used_cv} {t * 1e3:.2f} ms")
             if rel <= goal:
                 hit = rows[-1]
@@ -578,7 +582,17 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
     warm.integrate_cv(params, W, c)
     warm.close()
     say("control variate: ladder")
-    rows_c, cum_c, hit_c = ladder_run(lambda plan: plan.integrate_cv(params, W, c)[0], cv_kmax)
+    fallbacks = [0]
+
+    def cv_step(plan):
+        if cv_drop_after and fallbacks[0] >= cv_drop_after:
+            return plan.integrate(params)[0]
+        res = plan.integrate_cv(params, W, c)[0]
+        res.cv_pass = True
+        fallbacks[0] = 0 if res.used_cv else fallbacks[0] + 1
+        return res
+
+    rows_c, cum_c, hit_c = ladder_run(cv_step, cv_kmax)
 
     def summary(rows, cum, hit, extra):
         return {"goal_met": hit is not None, "n": (hit or rows[-1])["n"],
@@ -593,7 +607,8 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
             "generating_vector_search_seconds": t_search,
             "plain": summary(rows_p, cum_p, hit_p, 0.0),
             "cv": dict(summary(rows_c, cum_c, hit_c, t_train), R=R, K=K, n_train=n_train,
-                       train_seconds=t_train, train_sweeps=rep.sweeps, train_rel_loss=rep.rel_loss)}
+                       train_seconds=t_train, train_sweeps=rep.sweeps, train_rel_loss=rep.rel_loss,
+                       drop_after=cv_drop_after)}
 
 
 def convergence(d: int = 10, n_u: int = 20, n_f: int = 60, seed: int = synth.SEED_BASE + 5, m: int = 32,
