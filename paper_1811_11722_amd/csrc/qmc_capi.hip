@@ -284,10 +284,17 @@ uint32_t default_tile(int key_family) {
     }
 }
 
+// Workgroups along the points: about blocks_per_cu (default 8) per CU over
+// all shift tiles, and at most one per kBlock x kMinPointsPerThread points.
+// Below that floor a thread would walk one or two points and the launch
+// would be all block reductions and partials (one instance of n = 131071,
+// m = 16: 17.4 us -> 13.2 us per kernel with the floor).
+constexpr uint64_t kMinPointsPerThread = 4;
+
 uint32_t grid_x(uint32_t n, uint32_t tiles_total, int dev, uint32_t blocks_per_cu) {
     const uint64_t target = (uint64_t)device_cu_count(dev) * (blocks_per_cu ? blocks_per_cu : 8);
     uint64_t bx = std::max<uint64_t>(1, target / std::max<uint32_t>(1, tiles_total));
-    const uint64_t cap = (n + kBlock - 1) / kBlock;
+    const uint64_t cap = (n + kBlock * kMinPointsPerThread - 1) / (kBlock * kMinPointsPerThread);
     bx = std::min(bx, cap);
     return (uint32_t)std::max<uint64_t>(bx, 1);
 }
