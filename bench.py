@@ -48,7 +48,7 @@ FLOPS_COUNTED = {"sector": 163.95, "product_peak": 71.4, "sector_complex": 371.8
 # engine cycles of one launch of the headline kernel: GRBM_GUI_ACTIVE per XCD
 # (rocprofv3 --pmc, profiles/); divided by the kernel time measured here it
 # gives the clock the kernel ran at
-CYCLES_PER_XCD = {"sector": 4.634e6}
+CYCLES_PER_XCD = {"sector": 4.678e6}
 
 # HBM bytes per lattice-kernel launch from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 256 MiB copy of known size); recorded for
