@@ -495,6 +495,23 @@ def _sync():
     torch.cuda.synchronize()  # the library calls return synchronously; kept as a guard
 
 
+class CvLadderPolicy:
+    """Which pass a rung of the control variate's ladder runs: the residual
+    pass until `drop_after` consecutive rungs have fallen back to the plain
+    estimate (the model no longer lowers the error at that resolution), the
+    plain kernel from then on; drop_after = 0 keeps the residual pass."""
+
+    def __init__(self, drop_after: int):
+        self.drop_after = drop_after
+        self.fallbacks = 0
+
+    def residual_pass(self) -> bool:
+        return not (self.drop_after and self.fallbacks >= self.drop_after)
+
+    def record(self, used_cv: bool) -> None:
+        self.fallbacks = 0 if used_cv else self.fallbacks + 1
+
+
 def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SEED_BASE + 4,
                   goal: float = 1e-7, m: int = 32, R: int = 32, K: int = 12, n_train: int = 1048573,
                   kmin: int = 14, kmax: int = 30, cv_kmax: int = 28, max_sweeps: int = 12, transform=None,
@@ -582,14 +599,14 @@ def time_to_error(d: int = 8, n_u: int = 12, n_f: int = 30, seed: int = synth.SE
     warm.integrate_cv(params, W, c)
     warm.close()
     say("control variate: ladder")
-    fallbacks = [0]
+    policy = CvLadderPolicy(cv_drop_after)
 
     def cv_step(plan):
-        if cv_drop_after and fallbacks[0] >= cv_drop_after:
+        if not policy.residual_pass():
             return plan.integrate(params)[0]
         res = plan.integrate_cv(params, W, c)[0]
         res.cv_pass = True
-        fallbacks[0] = 0 if res.used_cv else fallbacks[0] + 1
+        policy.record(bool(res.used_cv))
         return res
 
     rows_c, cum_c, hit_c = ladder_run(cv_step, cv_kmax)
