@@ -92,6 +92,30 @@ struct FamCvResidual {
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) wa[rb][ks] = w[(rb * KS + ks) * kWave];
+        // the lane's own point's Legendre values of dimension i, through the
+        // wave's LDS rows to the B layout (a wave's LDS accesses complete in
+        // order)
+        auto legendre_b = [&](int i, double (&bk)[4][KS]) {
+            double pk[NPK];
+            legendre_raw<NPK, double>(zw[lane * D + i], pk);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < NPK; ++k) lw[lane * LP + k] = pk[k];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) bk[pb][ks] = lw[(16 * pb + col) * LP + 4 * ks + grp];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+        double bk[4][KS];
+        legendre_b(0, bk);
+        // software-pipelined over the dimensions: dimension i's matrix
+        // instructions are issued first, and the next dimension's Legendre
+        // values (VALU and LDS work, independent of them) are formed while
+        // they run
 #pragma unroll 1
         for (int i = 0; i < D; ++i) {
             // weights of the next dimension, loaded while this one computes
@@ -101,22 +125,6 @@ struct FamCvResidual {
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) wn[rb][ks] = w[((inext * RB + rb) * KS + ks) * kWave];
-            // the lane's own point's Legendre values, through the wave's LDS
-            // rows to the B layout (a wave's LDS accesses complete in order)
-            double pk[NPK];
-            legendre_raw<NPK, double>(zw[lane * D + i], pk);
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int k = 0; k < NPK; ++k) lw[lane * LP + k] = pk[k];
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            double bk[4][KS];
-#pragma unroll
-            for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) bk[pb][ks] = lw[(16 * pb + col) * LP + 4 * ks + grp];
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
             // RB x 4 independent accumulation chains, interleaved over ks
             cv_d4 acc[RB][4];
 #pragma unroll
@@ -130,6 +138,7 @@ struct FamCvResidual {
 #pragma unroll
                     for (int pb = 0; pb < 4; ++pb)
                         acc[rb][pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[rb][ks], bk[pb][ks], acc[rb][pb], 0, 0, 0);
+            if (i + 1 < D) legendre_b(i + 1, bk);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
