@@ -228,7 +228,9 @@ qmc_status qmc_korobov_vector(uint64_t n, uint32_t d, uint64_t a, uint64_t *g);
    as an unshifted lattice rule; returns the minimiser (ties: smaller P2, then
    smaller a).  p2_all (nullable) receives all ncand values.  The generating
    vector itself is not fixed by the paper (Sec. 2 only names it); this is
-   the standard worst-case-error choice.  n <= 2^31, d <= 16, ncand <= 4096. */
+   the standard worst-case-error choice.  For odd n the sum runs over
+   j <= n/2 and is doubled less the j = 0 term (the point n - j mirrors the
+   point j, and B2(1 - x) = B2(x)).  n <= 2^31, d <= 16, ncand <= 4096. */
 qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint32_t ncand,
                               uint64_t *a_best, double *p2_best, double *p2_all);
 
@@ -509,7 +511,9 @@ qmc_status qmc_deform_select(qmc_plan_t plan, const qmc_sector_params *params, d
    cand: ncand candidates, each a unit mod n (NULL: every unit in [1, n/2]);
    values within 1e-13 (1 + e^2) of the minimum are ties (lattice symmetries
    make exact ties common: c and c^-1 in two dimensions), and ties go to the
-   smaller c.  z_out: d values; e2_out: d values, e_s^2(z_s)
+   smaller c.  The sum over j is formed from j <= n/2 (the points j and
+   n - j contribute equally) as twice that sum less the self-mirrored terms
+   j = 0 and, for even n, j = n/2.  z_out: d values; e2_out: d values, e_s^2(z_s)
    after each component (host memory, caller-owned).  n in [2, 2^31],
    d <= 16; EUNSUPPORTED when candidates x n exceeds 2^44 (pass a subset).
    Runs on the current device, synchronously. */
