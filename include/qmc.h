@@ -228,9 +228,10 @@ qmc_status qmc_korobov_vector(uint64_t n, uint32_t d, uint64_t a, uint64_t *g);
    as an unshifted lattice rule; returns the minimiser (ties: smaller P2, then
    smaller a).  p2_all (nullable) receives all ncand values.  The generating
    vector itself is not fixed by the paper (Sec. 2 only names it); this is
-   the standard worst-case-error choice.  For odd n the sum runs over
-   j <= n/2 and is doubled less the j = 0 term (the point n - j mirrors the
-   point j, and B2(1 - x) = B2(x)).  n <= 2^31, d <= 16, ncand <= 4096. */
+   the standard worst-case-error choice.  For odd n, and for even n when
+   every candidate is odd, the sum runs over j <= n/2 and is doubled less the
+   self-mirrored terms j = 0 and (even n) j = n/2: the point n - j mirrors
+   the point j, and B2(1 - x) = B2(x).  n <= 2^31, d <= 16, ncand <= 4096. */
 qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint32_t ncand,
                               uint64_t *a_best, double *p2_best, double *p2_all);
 

@@ -946,17 +946,29 @@ qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint
     a.np = 1;
     a.partials = (double2 *)s.ptr[4];
     // The point n - j is the mirror 1 - x of the point j and B2(1 - x) =
-    // B2(x), so for odd n the sum S over all points is 2 sum_{j <= n/2} -
-    // term(0), term(0) = (1 + pi^2/3)^d (formed as the kernel forms it: q(0)
-    // is exactly that constant, multiplied up in order).  For even n the
-    // self-mirrored point n/2 depends on each candidate, and all n points
-    // are summed.
-    const bool half = (n & 1) == 1;
+    // B2(x), so the sum S over all points is 2 sum_{j <= n/2} - term(0) -
+    // [n even] term(n/2), term(0) = (1 + pi^2/3)^d.  For even n and odd
+    // candidates every g_i is odd and the point n/2 is (1/2, ..., 1/2) for
+    // all of them; an even candidate puts 0 in some coordinates there, and
+    // then all n points are summed.  Both terms are formed as the kernel
+    // forms them (q(0) is exactly the constant; x = (n/2) / n through 1/n),
+    // multiplied up in order.
+    bool half = true;
+    if ((n & 1) == 0)
+        for (uint32_t c = 0; c < ncand; ++c) half = half && (cand[c] % n) % 2 == 1;
     double t0 = 0.0;
     if (half) {
-        const double c0 = 1.0 + 9.869604401089358 / 3.0;
+        const double c2 = 2.0 * 9.869604401089358, c0 = 1.0 + 9.869604401089358 / 3.0;
+        double th = 1.0;
+        if ((n & 1) == 0) {
+            const double x = (double)(n / 2) * (1.0 / (double)n);
+            const double q = std::fma(std::fma(c2, x, -c2), x, c0);
+            th = q;
+            for (uint32_t i = 1; i < d; ++i) th *= q;
+        }
         t0 = c0;
         for (uint32_t i = 1; i < d; ++i) t0 *= c0;
+        if ((n & 1) == 0) t0 += th;  // both self-mirrored terms
     }
     a.jend = half ? (uint32_t)(n / 2 + 1) : 0;
     if ((e = fn(a, dim3(bx, ncand), stream)) != hipSuccess) return hip_fail(e, "launch P2 kernel");
@@ -966,7 +978,7 @@ qmc_status qmc_korobov_search(uint64_t n, uint32_t d, const uint64_t *cand, uint
     f.m = 1;
     f.np = 1;
     f.n = (double)n;
-    // q = (S - n) / n = ((sum - (n + t0) / 2) 2) / n
+    // q = (S - n) / n = ((sum - (n + t0) / 2) 2) / n, t0 the self-mirrored terms
     f.scale = half ? 2.0 : 1.0;
     f.sub = half ? ((double)n + t0) / 2.0 : (double)n;
     f.q = (double *)s.ptr[5];

@@ -170,6 +170,22 @@ def test_korobov_search_config_product_peak(Q):
     assert p2_gpu == all_gpu.min()
 
 
+@pytest.mark.parametrize("n,cands", [(4093, [3, 17, 76, 1234, 2001]), (4096, [3, 17, 77, 1235, 2001]),
+                                     (4096, [3, 18, 77, 1234]), (2, [1]), (3, [1, 2])])
+def test_korobov_search_half_range(Q, n, cands):
+    """The P2 sum formed from j <= n/2 (odd n; even n with odd candidates,
+    whose point n/2 is (1/2, ..., 1/2)) and over all n points (even n with an
+    even candidate) against the oracle's plain sum over all points."""
+    d = 5
+    c = np.array(cands, dtype=np.uint64)
+    _say(f"korobov search n={n} candidates={cands}")
+    _, _, all_gpu = Q.korobov_search(n, d, c)
+    _, _, all_or = O.korobov_search(n, d, c, threads=THREADS)
+    rel = _rel(all_gpu, all_or)
+    print(f"max relative difference {rel.max():.2e}")
+    assert np.all(rel < 1e-12), rel.max()
+
+
 # ------------------------------------------------------------- estimates
 def test_product_peak_config(Q):
     """Genz product peak, d = 4, Korobov 3, n = 131071, m = 16."""
