@@ -104,11 +104,17 @@ def test_genz_batch(Q):
 
 @pytest.mark.parametrize("use_graph", [True, False])
 def test_uniform_batch_instances(Q, use_graph):
-    """Plans with one (d, n, m) run as instances of a single lattice launch."""
+    """Plans with one (d, n, m) run as instances of a single lattice launch.
+    Every third instance has its a scaled by 1e-4 and every third by 100, so
+    that instances whose shifts share one reciprocal and instances with one
+    reciprocal per shift run in the same launch.  (A scale of 1e3 makes the
+    peaks so sharp, a up to 8000, that one rounding of z moves f by about
+    a x 1e-16 per dimension, above the 1e-12 bar whichever path runs.)"""
     d, n, m = 4, 16381, 16
     plans, params, cases = [], [], []
     for b in range(40):
         a, u = synth.genz_params(2000 + b, d)
+        a = a * (1.0, 1e-4, 100.0)[b % 3]
         g = O.korobov_vector(n, d, 76 + 2 * b)
         sh = synth.shifts(2000 + b, m, d)
         plans.append(Q.Plan(d, n, g, sh, "korobov", 3))

@@ -212,15 +212,15 @@ def test_product_peak_launch_shapes(Q, launch):
     assert np.all(_rel(q, est.q_re) < TOL)
 
 
-@pytest.mark.parametrize("a_scale", [1e-4, 1.0, 1e3])
+@pytest.mark.parametrize("a_scale", [1e-4, 1.0, 100.0])
 @pytest.mark.parametrize("launch", [(8, 1), (4, 3), (2, 2)])
 def test_product_peak_tile_reciprocal(Q, a_scale, launch):
     """The shifts of a tile share one reciprocal of their denominators'
     product unless a denominator could leave 2^-62 .. 2^62.  With a in
     2..8 scaled by 1e-4 the four factors a^-2 + s^2 multiply to about 2^90,
-    scaled by 1e3 to at least 2^-96, so those take one reciprocal per shift;
-    unscaled (2^-16 .. 2^-1.4) they share one.  Both against the oracle, per
-    shift."""
+    scaled by 100 the lower bound a^-2 of each multiplies to 2^-69, so those
+    take one reciprocal per shift; unscaled (2^-16 .. 2^-1.4) they share one.
+    Both against the oracle, per shift."""
     w = synth.product_peak_workload(n=16381, m=11)
     g = O.korobov_vector(w.n, w.d, 1234)
     a = w.genz_a * a_scale
