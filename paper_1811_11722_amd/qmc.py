@@ -214,10 +214,13 @@ class Params:
             self.n_orders = int(orders[0]) if orders else 0
         else:
             self.struct = qmc_genz_params(_p(keep(a, np.float64)), _p(keep(u, np.float64)))
+        # the struct's address, formed once: a batch passes hundreds of these
+        # per call, and a ctypes cast per parameter block cost about 1 us each
+        self._addr = None if self.struct is None else C.addressof(self.struct)
 
     @property
     def ptr(self):
-        return None if self.struct is None else C.cast(C.pointer(self.struct), C.c_void_p)
+        return self._addr
 
     @property
     def is_complex(self) -> bool:
