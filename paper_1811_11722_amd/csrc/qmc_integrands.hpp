@@ -421,27 +421,36 @@ struct FamGenzCornerPeak {
 // factors of variable i.  The code and the coefficient are wave-uniform, so
 // the factor loop and the variable selection below become scalar branches;
 // only the multiplications run on the vector unit, once per shift.
+// Runs f(i) for the one variable i = v in [LO, HI), choosing it by halving
+// the range: ceil(log2 D) uniform branches instead of one test per variable.
+template <int LO, int HI, int D, int T, class Fn>
+__device__ __forceinline__ void pick_var(uint32_t v, Fn &&f) {
+    if constexpr (HI - LO == 1) {
+        f(LO);
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (v < (uint32_t)MID)
+            pick_var<LO, MID, D, T>(v, f);
+        else
+            pick_var<MID, HI, D, T>(v, f);
+    }
+}
+
 template <int D, int T>
 __device__ __forceinline__ void mul_var(double (&q)[T], const double (&z)[T][D], uint32_t v) {
+    pick_var<0, D, D, T>(v, [&](int i) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        if (v == (uint32_t)i) {
-#pragma unroll
-            for (int k = 0; k < T; ++k) q[k] *= z[k][i];
-        }
-    }
+        for (int k = 0; k < T; ++k) q[k] *= z[k][i];
+    });
 }
 
 template <int D, int T>
 __device__ __forceinline__ void scale_var(double (&q)[T], double c, const double (&z)[T][D],
                                           uint32_t v) {
+    pick_var<0, D, D, T>(v, [&](int i) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        if (v == (uint32_t)i) {
-#pragma unroll
-            for (int k = 0; k < T; ++k) q[k] = c * z[k][i];
-        }
-    }
+        for (int k = 0; k < T; ++k) q[k] = c * z[k][i];
+    });
 }
 
 // out[k] = sum_t coef[t] * prod_f z[k][var_f(t)]
